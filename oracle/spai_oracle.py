@@ -1,0 +1,482 @@
+"""Plain FP64 CPU oracle for the global SPAI iterations and the SPAI-preconditioned CG.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this module: only the tests, the smoke check of ``__graft_entry__`` and
+the ``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+library and imports nothing from the package.
+
+Everything is float64 with ``scipy.sparse`` matrices.  Library primitives
+(sparse product, sparse sum, transpose, sort) serve as single steps; there is no
+blocking, fusion or reordering beyond the algorithms as the paper states them.
+Iterates are kept column-compressed (CSC) because columns are the independent
+unit of the objective (Section 2).  Support means the set of nonzero entries,
+as in the definitions of supp(P) and supp(M) (Section 6.1, Appendix A): stored
+zeros are removed.
+
+Readings of points the paper leaves open (each is an argument, shared with the
+GPU library's options):
+
+* M_0 = (tr A / tr A^2) I, the Frobenius-optimal multiple of the identity
+  (Section 2 says only "given an initial iterate").
+* Explicit residual R_{i+1} = I - A M_{i+1} whenever dropping is active
+  (Section 6.2); the implicit update is available for dropping-free runs.
+* Drop rule on M (Appendix A, steps 1-3, with the cap of step 3 taken as the
+  hard thresholding of Section 6.1, which is what the dropping experiments of
+  Section 7.2 use): symmetrize, remove off-diagonal |m| < u, then cap.  The
+  diagonal is never dropped and counts toward the cap.
+* Drop rule on P (Section 6.1): hard thresholding with the same cap, no
+  diagonal exemption.  MR's search direction P = R is not dropped.
+* Ties: eq. (hard thresholding) has no unique minimiser when magnitudes tie at
+  the cut.  With t the (b+1)-th largest candidate magnitude (b = budget), keep
+  exactly the entries with |x| > t (1 + eta).  This never exceeds the budget,
+  keeps symmetric pairs together and equals the textbook top-b whenever the
+  b-th largest magnitude exceeds t (1 + eta).
+* Per-column cap (not in the paper, whose caps are global): column j keeps at
+  most k_j entries; on the symmetrized M an off-diagonal (r, c) survives only if
+  it passes both column thresholds, which keeps M symmetric.
+* LOMR degeneracy: when c_i <= 1e-14 (AR,AR)(AP,AP) (Theorem 4.2's c_i is a
+  2x2 Gram determinant) take the MR step (gamma = 0).
+* Stop when ||I - A M_i||_F / sqrt(n) <= tol (the "backward error" of
+  Section 7.2; Tables 5-6 are consistent with this scaling).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+__all__ = [
+    "frob", "fnorm", "initial_iterate", "residual", "DropRule", "cap_counts",
+    "drop_main", "drop_direction", "mr", "cg", "lomr", "run", "pcg", "pcg_block",
+    "loss", "loss_grad", "OracleBreakdown",
+]
+
+UNIT_ROUNDOFF = 2.0 ** -53
+LOMR_DEGENERACY = 1e-14
+
+
+class OracleBreakdown(RuntimeError):
+    """Raised when a step size is undefined (e.g. (P, AP)_F <= 0 in CG)."""
+
+
+# ----------------------------------------------------------------------------
+# basic operations (Section 2)
+# ----------------------------------------------------------------------------
+
+def _csc(X) -> sp.csc_matrix:
+    X = sp.csc_matrix(X, dtype=np.float64)
+    X.sum_duplicates()
+    X.eliminate_zeros()
+    X.sort_indices()
+    return X
+
+
+def frob(X, Y) -> float:
+    """Frobenius inner product (X, Y)_F = tr(X^T Y) (Section 2)."""
+    return float(sp.csc_matrix(X).multiply(sp.csc_matrix(Y)).sum())
+
+
+def fnorm(X) -> float:
+    """Frobenius norm ||X||_F = (X, X)_F^(1/2) (Section 2)."""
+    return math.sqrt(frob(X, X))
+
+
+def initial_iterate(A) -> tuple[float, sp.csc_matrix]:
+    """M_0 = c I with c = tr(A) / tr(A^2), i.e. argmin_c ||I - c A||_F."""
+    A = sp.csr_matrix(A)
+    t1 = float(A.diagonal().sum())
+    t2 = float(A.multiply(A.T).sum())          # tr(A A) = sum_ij a_ij a_ji
+    c = t1 / t2
+    n = A.shape[0]
+    return c, _csc(c * sp.identity(n, format="csc"))
+
+
+def residual(A, M) -> sp.csc_matrix:
+    """R = I - A M (the objective's residual, Section 2; explicit update, Section 6.2)."""
+    n = A.shape[0]
+    return _csc(sp.identity(n, format="csc") - sp.csr_matrix(A) @ sp.csc_matrix(M))
+
+
+# ----------------------------------------------------------------------------
+# dropping (Section 6.1 hard thresholding; Appendix A steps 1-3)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class DropRule:
+    """What the drop operators D_M and D_P do.
+
+    mode: "none" | "global" | "column".  ``m`` is the global count cap and
+    ``k`` the per-column caps (array of length n), as produced by
+    :func:`cap_counts`.  ``u`` is the small-entry threshold of Appendix A
+    step 2 (0 disables it), ``eta`` the tie band, ``symmetrize`` Appendix A
+    step 1.
+    """
+    mode: str = "none"
+    m: int = 0
+    k: np.ndarray | None = None
+    u: float = UNIT_ROUNDOFF
+    eta: float = 1e-9
+    symmetrize: bool = True
+
+    @staticmethod
+    def no_drop() -> "DropRule":
+        return DropRule(mode="none", u=0.0, symmetrize=False)
+
+
+def cap_counts(A, mode: str, value: float, relative: bool):
+    """Turn a cap spec into counts: global m, or per-column k_j.
+
+    relative global: m = round(value * nnz(A)); relative column:
+    k_j = round(value * nnz(A e_j)); otherwise the value itself.
+    """
+    A = sp.csc_matrix(A)
+    if mode == "global":
+        return int(round(value * A.nnz)) if relative else int(round(value))
+    if mode == "column":
+        counts = np.diff(A.indptr).astype(np.float64)
+        if relative:
+            return np.rint(value * counts).astype(np.int64)
+        return np.full(A.shape[1], int(round(value)), dtype=np.int64)
+    return None
+
+
+def _entries(X: sp.csc_matrix):
+    cols = np.repeat(np.arange(X.shape[1]), np.diff(X.indptr))
+    return X.indices.astype(np.int64), cols, X.data.copy()
+
+
+def _kth_largest_per_column(cols, mags, ncols, kk):
+    """t_c = (kk_c + 1)-th largest of mags in column c, or 0 if there are <= kk_c."""
+    t = np.zeros(ncols)
+    if len(mags) == 0:
+        return t
+    # scatter each column's magnitudes into one row of a padded table, sort rows
+    order = np.argsort(cols, kind="stable")
+    sc, sm = cols[order], mags[order]
+    count = np.bincount(sc, minlength=ncols)
+    start = np.concatenate(([0], np.cumsum(count)[:-1]))
+    pos = np.arange(len(sc)) - start[sc]
+    table = np.full((ncols, int(count.max())), -np.inf)
+    table[sc, pos] = sm
+    table = -np.sort(-table, axis=1)                 # each row in descending order
+    has = count > kk
+    t[has] = table[np.nonzero(has)[0], kk[has]]
+    return t
+
+
+def _from_entries(rows, cols, vals, shape):
+    return _csc(sp.csc_matrix((vals, (rows, cols)), shape=shape))
+
+
+def drop_main(X, rule: DropRule) -> sp.csc_matrix:
+    """D_M: the drop rule on the main iterate (Appendix A steps 1-3 + Section 6.1)."""
+    X = _csc(X)
+    n = X.shape[0]
+    if rule.symmetrize:                                  # step 1: M := (M + M^T) / 2
+        X = _csc((X + X.T.tocsc()) * 0.5)
+    rows, cols, vals = _entries(X)
+    diag = rows == cols
+    keep = vals != 0.0
+    if rule.u > 0.0:                                     # step 2: off-diagonal |m| < u
+        keep &= diag | (np.abs(vals) >= rule.u)
+    if rule.mode == "global":                            # step 3: cap |supp(M)| <= m
+        if keep.sum() > rule.m:
+            ndiag = int((keep & diag).sum())
+            b = rule.m - ndiag
+            if b < 0:
+                raise ValueError("cap below the number of diagonal entries")
+            mags = np.abs(vals[keep & ~diag])
+            if len(mags) > b:
+                t = np.sort(mags)[::-1][b]
+                keep &= diag | (np.abs(vals) > t * (1.0 + rule.eta))
+    elif rule.mode == "column":
+        k = np.asarray(rule.k, dtype=np.int64)
+        if np.any(k < 1):
+            raise ValueError("column cap below one (the diagonal)")
+        off = keep & ~diag
+        t = _kth_largest_per_column(cols[off], np.abs(vals[off]), n, k - 1)
+        thr = np.maximum(t[rows], t[cols]) if rule.symmetrize else t[cols]
+        keep &= diag | (np.abs(vals) > thr * (1.0 + rule.eta))
+    return _from_entries(rows[keep], cols[keep], vals[keep], X.shape)
+
+
+def drop_direction(X, rule: DropRule) -> sp.csc_matrix:
+    """D_P: hard thresholding of a search direction (Section 6.1), no diagonal exemption."""
+    X = _csc(X)
+    rows, cols, vals = _entries(X)
+    keep = vals != 0.0
+    if rule.mode == "global":
+        if keep.sum() > rule.m:
+            mags = np.abs(vals[keep])
+            t = np.sort(mags)[::-1][rule.m]
+            keep &= np.abs(vals) > t * (1.0 + rule.eta)
+    elif rule.mode == "column":
+        k = np.asarray(rule.k, dtype=np.int64)
+        t = _kth_largest_per_column(cols[keep], np.abs(vals[keep]), X.shape[1], k)
+        keep &= np.abs(vals) > t[cols] * (1.0 + rule.eta)
+    return _from_entries(rows[keep], cols[keep], vals[keep], X.shape)
+
+
+# ----------------------------------------------------------------------------
+# the three global iterations
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Result:
+    M: sp.csc_matrix
+    P: sp.csc_matrix | None
+    resid: list = field(default_factory=list)     # ||R_i||_F, i = 0..iters
+    scalars: list = field(default_factory=list)   # per iteration dict
+    nnz_m: list = field(default_factory=list)
+    nnz_p: list = field(default_factory=list)
+    iters: int = 0
+    status: str = "maxiter"
+    c: float = 0.0
+
+
+def _converged(rnorm, n, tol):
+    return tol > 0.0 and rnorm / math.sqrt(n) <= tol
+
+
+def mr(A, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = True,
+       M0=None) -> Result:
+    """Minimal residual with matrix iterates (Algorithm 1).
+
+    alpha_i = (R_i, A R_i)_F / ||A R_i||_F^2 ; M_{i+1} = D_M(M_i + alpha_i R_i).
+    """
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    c, Minit = initial_iterate(A)
+    M = Minit if M0 is None else _csc(M0)
+    R = residual(A, M)
+    out = Result(M, None, c=c)
+    out.resid.append(fnorm(R))
+    out.nnz_m.append(M.nnz)
+    if _converged(out.resid[-1], n, tol):
+        out.status = "converged"
+        return out
+    for i in range(max_iter):
+        AR = _csc(A @ R)
+        ar_ar = frob(AR, AR)
+        if ar_ar == 0.0:
+            out.status = "converged"
+            break
+        r_ar = frob(R, AR)
+        alpha = r_ar / ar_ar
+        M = drop_main(M + alpha * R, rule)
+        R = residual(A, M) if explicit else _csc(R - alpha * AR)
+        out.scalars.append({"alpha": alpha, "r_ar": r_ar, "ar_ar": ar_ar})
+        out.resid.append(fnorm(R))
+        out.nnz_m.append(M.nnz)
+        out.iters = i + 1
+        if _converged(out.resid[-1], n, tol):
+            out.status = "converged"
+            break
+    out.M = M
+    return out
+
+
+def cg(A, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = True,
+       M0=None) -> Result:
+    """Conjugate gradient with matrix iterates (Algorithm 3).
+
+    P_0 = D_P(R_0); alpha_i = ||R_i||^2 / (P_i, A P_i); M_{i+1} = D_M(M_i + alpha_i P_i);
+    beta_{i+1} = ||R_{i+1}||^2 / ||R_i||^2; P_{i+1} = D_P(R_{i+1} + beta_{i+1} P_i).
+    """
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    c, Minit = initial_iterate(A)
+    M = Minit if M0 is None else _csc(M0)
+    R = residual(A, M)
+    P = drop_direction(R, rule)
+    rr = frob(R, R)
+    out = Result(M, P, c=c)
+    out.resid.append(math.sqrt(rr))
+    out.nnz_m.append(M.nnz)
+    out.nnz_p.append(P.nnz)
+    if _converged(out.resid[-1], n, tol):
+        out.status = "converged"
+        return out
+    for i in range(max_iter):
+        if rr == 0.0:
+            out.status = "converged"
+            break
+        AP = _csc(A @ P)
+        p_ap = frob(P, AP)
+        if not p_ap > 0.0:
+            out.status = "breakdown"
+            break
+        alpha = rr / p_ap
+        M = drop_main(M + alpha * P, rule)
+        R = residual(A, M) if explicit else _csc(R - alpha * AP)
+        rr_new = frob(R, R)
+        beta = rr_new / rr
+        P = drop_direction(R + beta * P, rule)
+        out.scalars.append({"alpha": alpha, "beta": beta, "p_ap": p_ap, "rr": rr})
+        rr = rr_new
+        out.resid.append(math.sqrt(rr))
+        out.nnz_m.append(M.nnz)
+        out.nnz_p.append(P.nnz)
+        out.iters = i + 1
+        if _converged(out.resid[-1], n, tol):
+            out.status = "converged"
+            break
+    out.M, out.P = M, P
+    return out
+
+
+def lomr_coefficients(r_ar, ar_ar, ar_ap, r_ap, ap_ap, first: bool):
+    """(delta_i, gamma_i) of Theorem 4.2 / Algorithm 4, with the MR step when degenerate."""
+    if first:
+        return r_ar / ar_ar, 1.0, False
+    c = ar_ar * ap_ap - ar_ap * ar_ap
+    if not c > LOMR_DEGENERACY * ar_ar * ap_ap:
+        return r_ar / ar_ar, 0.0, True
+    delta = (ap_ap * r_ar - ar_ap * r_ap) / c
+    gamma = (ar_ar * r_ap - ar_ap * r_ar) / c
+    return delta, gamma, False
+
+
+def lomr(A, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = True,
+         M0=None) -> Result:
+    """Locally optimal minimal residual (Definition 4.1, Theorem 4.2, Algorithm 4).
+
+    M_{i+1} = D_M(M_i + delta_i R_i + gamma_i P_{i-1}), P_i = D_P(delta_i R_i + gamma_i P_{i-1}),
+    with P_{-1} = 0 and the MR step at i = 0.
+    """
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    c, Minit = initial_iterate(A)
+    M = Minit if M0 is None else _csc(M0)
+    R = residual(A, M)
+    P = _csc(sp.csc_matrix((n, n)))
+    out = Result(M, P, c=c)
+    out.resid.append(fnorm(R))
+    out.nnz_m.append(M.nnz)
+    out.nnz_p.append(0)
+    if _converged(out.resid[-1], n, tol):
+        out.status = "converged"
+        return out
+    for i in range(max_iter):
+        AR = _csc(A @ R)
+        AP = _csc(A @ P)
+        ar_ar = frob(AR, AR)
+        if ar_ar == 0.0:
+            out.status = "converged"
+            break
+        r_ar = frob(R, AR)
+        ar_ap = frob(AR, AP)
+        r_ap = frob(R, AP)
+        ap_ap = frob(AP, AP)
+        delta, gamma, fell_back = lomr_coefficients(r_ar, ar_ar, ar_ap, r_ap, ap_ap, i == 0)
+        M = drop_main(M + delta * R + gamma * P, rule)
+        Rnew = residual(A, M) if explicit else _csc(R - delta * AR - gamma * AP)
+        P = drop_direction(delta * R + gamma * P, rule)
+        R = Rnew
+        out.scalars.append({"delta": delta, "gamma": gamma, "r_ar": r_ar, "ar_ar": ar_ar,
+                            "ar_ap": ar_ap, "r_ap": r_ap, "ap_ap": ap_ap,
+                            "mr_fallback": fell_back})
+        out.resid.append(fnorm(R))
+        out.nnz_m.append(M.nnz)
+        out.nnz_p.append(P.nnz)
+        out.iters = i + 1
+        if _converged(out.resid[-1], n, tol):
+            out.status = "converged"
+            break
+    out.M, out.P = M, P
+    return out
+
+
+def run(method: str, A, rule: DropRule, max_iter: int, tol: float = 0.0, **kw) -> Result:
+    return {"mr": mr, "cg": cg, "lomr": lomr}[method](A, rule, max_iter, tol, **kw)
+
+
+# ----------------------------------------------------------------------------
+# vector PCG with the SPAI as preconditioner (Sections 1 and 7, Experiments 04/06)
+# ----------------------------------------------------------------------------
+
+def pcg(A, M, b, rtol: float = 1e-8, max_iter: int = 10000):
+    """Textbook preconditioned CG for one right-hand side, z = M r, x_0 = 0.
+
+    Stops when ||r||_2 <= rtol ||b||_2 on the recursively updated residual.
+    Returns (x, iterations, status) with status "converged", "maxiter" or
+    "indefinite" ((r, z) <= 0 or (p, A p) <= 0).
+    """
+    A = sp.csr_matrix(A)
+    M = sp.csr_matrix(M)
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    bnorm = float(np.sqrt(b @ b))
+    if bnorm == 0.0:
+        return x, 0, "converged"
+    r = b.copy()
+    z = M @ r
+    rz = float(r @ z)
+    p = z.copy()
+    for it in range(1, max_iter + 1):
+        if not rz > 0.0:
+            return x, it - 1, "indefinite"
+        q = A @ p
+        pq = float(p @ q)
+        if not pq > 0.0:
+            return x, it - 1, "indefinite"
+        alpha = rz / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        if float(np.sqrt(r @ r)) <= rtol * bnorm:
+            return x, it, "converged"
+        z = M @ r
+        rz_new = float(r @ z)
+        beta = rz_new / rz
+        rz = rz_new
+        p = z + beta * p
+    return x, max_iter, "maxiter"
+
+
+def pcg_block(A, M, B, rtol: float = 1e-8, max_iter: int = 10000):
+    """Run :func:`pcg` independently on each column of B (shape n x nrhs)."""
+    B = np.asarray(B, dtype=np.float64)
+    X = np.zeros_like(B)
+    iters, status = [], []
+    for j in range(B.shape[1]):
+        x, it, st = pcg(A, M, B[:, j], rtol, max_iter)
+        X[:, j] = x
+        iters.append(it)
+        status.append(st)
+    return X, np.array(iters), status
+
+
+# ----------------------------------------------------------------------------
+# differentiable objective f(M) = ||I - A M||_F^2 (Section 2 and its gradient)
+# ----------------------------------------------------------------------------
+
+def loss(A, M) -> float:
+    """f(M) = ||I - A M||_F^2 (the objective of Section 2)."""
+    return frob(residual(A, M), residual(A, M))
+
+
+def loss_grad(A, M):
+    """Gradients of f in the stored values of M and of A.
+
+    With R = I - A M: df = -2 (R, dA M + A dM)_F, so df/dM = -2 A^T R and
+    df/dA = -2 R M^T; each is restricted to the pattern of its argument and
+    returned as a CSR matrix on that pattern (A's and M's patterns as given).
+    For symmetric A the first is the gradient of Section 2.
+    """
+    A = sp.csr_matrix(A)
+    M = sp.csr_matrix(M)
+    R = residual(A, M)
+    GM = -2.0 * (A.T @ R)
+    GA = -2.0 * (R @ M.T)
+    return _on_pattern(GA, A), _on_pattern(GM, M)
+
+
+def _on_pattern(G, P):
+    P = sp.csr_matrix(P)
+    P.sort_indices()
+    G = sp.csr_matrix(G)
+    rows = np.repeat(np.arange(P.shape[0]), np.diff(P.indptr))
+    vals = np.asarray(G[rows, P.indices]).ravel()
+    return sp.csr_matrix((vals, P.indices.copy(), P.indptr.copy()), shape=P.shape)

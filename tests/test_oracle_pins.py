@@ -1,0 +1,480 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these retype the oracle's step formulas: they use closed forms
+(eigenvalues of the Dirichlet Laplacian, exact traces), optimality properties
+solved by dense least squares, theorems (contraction, finite termination,
+orthogonality), brute-force subset enumeration for the drop rule, a library CG
+and finite differences.
+"""
+import csv
+import itertools
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import spai_oracle as O
+from paper_2511_09753_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dirichlet_eigs(N):
+    """Eigenvalues of the 5-point Dirichlet Laplacian (diag 4, -1) on N x N, closed form."""
+    th = np.arange(1, N + 1) * np.pi / (N + 1)
+    l1 = 2.0 - 2.0 * np.cos(th)
+    return (l1[:, None] + l1[None, :]).ravel()
+
+
+def random_spd(n, seed, cond=10.0, density=None):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.linspace(1.0, cond, n)
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    return sp.csr_matrix(A), lam
+
+
+# ----------------------------------------------------------------------------
+# P1, P2: closed forms of R_0 and of the first MR step (32 x 32 Laplacian)
+# ----------------------------------------------------------------------------
+
+def test_initial_residual_closed_form_laplace32():
+    # tr(A) = 4 n and tr(A^2) = 16 n + (number of off-diagonal -1 entries), exactly
+    N = 32
+    n = N * N
+    offdiag = 2 * (2 * N * (N - 1))
+    t1 = Fraction(4 * n)
+    t2 = Fraction(16 * n + offdiag)
+    c_exact = t1 / t2
+    r0sq_exact = n - t1 * t1 / t2
+    assert c_exact == Fraction(32, 159)
+    assert r0sq_exact == Fraction(31744, 159)
+    A = W.laplace2d(N)
+    c, M0 = O.initial_iterate(A)
+    assert c == pytest.approx(float(c_exact), rel=1e-15)
+    R0 = O.residual(A, M0)
+    assert O.fnorm(R0) ** 2 == pytest.approx(float(r0sq_exact), rel=1e-13)
+
+
+def test_first_mr_step_by_traces_laplace32():
+    """alpha_0 and ||R_1|| from tr(A^k), k = 1..4, via the closed-form spectrum.
+
+    With M_0 = cI, R_0 = I - cA, (R_0, A R_0) = t1 - 2c t2 + c^2 t3 and
+    ||A R_0||^2 = t2 - 2c t3 + c^2 t4.  M_1 = cI + alpha_0 R_0 has exactly A's
+    pattern (= the cap nnz(A)), so this also pins the first capped iterate.
+    """
+    N = 32
+    lam = dirichlet_eigs(N)
+    t = [float(np.sum(lam ** k)) for k in range(5)]
+    assert t[1] == pytest.approx(4096, rel=1e-14)
+    assert t[2] == pytest.approx(20352, rel=1e-13)
+    c = t[1] / t[2]
+    r_ar = t[1] - 2 * c * t[2] + c * c * t[3]
+    ar_ar = t[2] - 2 * c * t[3] + c * c * t[4]
+    alpha0 = r_ar / ar_ar
+    r0sq = t[0] - 2 * c * t[1] + c * c * t[2]
+    r1 = math.sqrt(r0sq - alpha0 * r_ar)
+    A = W.laplace2d(N)
+    rule = O.DropRule(mode="global", m=A.nnz)
+    res = O.mr(A, rule, 1)
+    assert res.scalars[0]["alpha"] == pytest.approx(alpha0, rel=1e-12)
+    assert res.resid[1] == pytest.approx(r1, rel=1e-12)
+    assert res.nnz_m[1] == A.nnz
+    assert abs(alpha0 - 0.215571491620124) < 1e-12
+    assert abs(r1 - 9.727452876828) < 1e-9
+
+
+# ----------------------------------------------------------------------------
+# step optimality by dense least squares (eq. descent-opt, Definition 4.1)
+# ----------------------------------------------------------------------------
+
+def _dense(X):
+    return np.asarray(sp.csc_matrix(X).todense())
+
+
+def _lstsq_steps(A, M, dirs):
+    """argmin_c ||I - A (M + sum c_k D_k)||_F by dense least squares on vec form."""
+    Ad = _dense(A)
+    n = Ad.shape[0]
+    R = np.eye(n) - Ad @ _dense(M)
+    cols = np.stack([(Ad @ _dense(D)).ravel() for D in dirs], axis=1)
+    coef, *_ = np.linalg.lstsq(cols, R.ravel(), rcond=None)
+    return coef
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_mr_step_is_least_squares_optimal(seed):
+    A, _ = random_spd(12, seed, cond=20.0)
+    rng = np.random.default_rng(seed + 10)
+    M = sp.csc_matrix(rng.standard_normal((12, 12)) * 0.05)
+    for _ in range(4):
+        R = O.residual(A, M)
+        res = O.mr(A, O.DropRule.no_drop(), 1, M0=M)
+        (alpha_ls,) = _lstsq_steps(A, M, [R])
+        assert res.scalars[0]["alpha"] == pytest.approx(alpha_ls, rel=1e-10)
+        M = res.M
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_lomr_step_is_two_dim_least_squares_optimal(seed):
+    """(delta_i, gamma_i) solve min over M_i + span{R_i, P_{i-1}} (Definition 4.1)."""
+    A, _ = random_spd(10, seed, cond=50.0)
+    res = O.lomr(A, O.DropRule.no_drop(), 6)
+    # replay the iterates and check each (delta, gamma) against dense least squares
+    c, M = O.initial_iterate(A)
+    P = sp.csc_matrix((10, 10))
+    for i, s in enumerate(res.scalars):
+        R = O.residual(A, M)
+        if i == 0:
+            (d_ls,) = _lstsq_steps(A, M, [R])
+            assert s["delta"] == pytest.approx(d_ls, rel=1e-9)
+            dM = s["delta"] * R
+        else:
+            d_ls, g_ls = _lstsq_steps(A, M, [R, P])
+            assert s["delta"] == pytest.approx(d_ls, rel=1e-7)
+            assert s["gamma"] == pytest.approx(g_ls, rel=1e-7, abs=1e-12)
+            dM = s["delta"] * R + s["gamma"] * P
+        M = sp.csc_matrix(M + dM)
+        P = sp.csc_matrix(dM)
+
+
+def test_lomr_not_worse_than_mr_step():
+    """eq. (LOMR <= MR <= ||R_i||) from the same iterate, no dropping."""
+    A = W.laplace2d(6)
+    res = O.lomr(A, O.DropRule.no_drop(), 12)
+    c, M = O.initial_iterate(A)
+    P = sp.csc_matrix(A.shape)
+    for s, rnext in zip(res.scalars, res.resid[1:]):
+        R = O.residual(A, M)
+        (alpha,) = _lstsq_steps(A, M, [R])
+        mr_next = O.fnorm(O.residual(A, M + alpha * R))
+        assert rnext <= mr_next * (1 + 1e-12) + 1e-14
+        assert mr_next <= O.fnorm(R) * (1 + 1e-14)
+        dM = s["delta"] * R + s["gamma"] * P
+        M = sp.csc_matrix(M + dM)
+        P = sp.csc_matrix(dM)
+
+
+# ----------------------------------------------------------------------------
+# CG: Krylov optimality (Theorem 3.4), orthogonality (Prop. 3.2), finite
+# termination (Theorem 3.5)
+# ----------------------------------------------------------------------------
+
+def test_cg_minimises_a_norm_error_over_krylov_space():
+    A, _ = random_spd(9, 7, cond=8.0)
+    Ad = _dense(A)
+    n = Ad.shape[0]
+    L = np.linalg.cholesky(Ad)
+    Ainv = np.linalg.inv(Ad)
+    res = O.cg(A, O.DropRule.no_drop(), 4)
+    c, M0 = O.initial_iterate(A)
+    R0 = np.eye(n) - Ad @ _dense(M0)
+    for i in range(1, 5):
+        # basis of K_i(A, R_0) and the A-weighted least-squares minimiser
+        basis = [np.linalg.matrix_power(Ad, k) @ R0 for k in range(i)]
+        cols = np.stack([(L.T @ B).ravel() for B in basis], axis=1)
+        target = (L.T @ (Ainv - _dense(M0))).ravel()
+        coef, *_ = np.linalg.lstsq(cols, target, rcond=None)
+        M_best = _dense(M0) + sum(cf * B for cf, B in zip(coef, basis))
+        oracle_M = _dense(O.cg(A, O.DropRule.no_drop(), i).M)
+        assert np.max(np.abs(oracle_M - M_best)) <= 1e-8 * np.max(np.abs(M_best))
+    assert res.iters == 4
+
+
+def test_cg_orthogonality():
+    A = W.laplace2d(5)
+    rule = O.DropRule.no_drop()
+    Rs, Ps = [], []
+    c, M = O.initial_iterate(A)
+    R = O.residual(A, M)
+    P = R
+    for i in range(5):
+        Rs.append(R)
+        Ps.append(P)
+        res = O.cg(A, rule, i + 1)
+        R = O.residual(A, res.M)
+        P = res.P
+    Rs.append(R)
+    Ps.append(P)
+    scale = O.fnorm(Rs[0]) ** 2
+    for i in range(1, 6):
+        for j in range(i):
+            assert abs(O.frob(Rs[i], Rs[j])) <= 1e-10 * scale
+            assert abs(O.frob(Rs[i], Ps[j])) <= 1e-10 * scale
+            assert abs(O.frob(Ps[i], A @ Ps[j])) <= 1e-10 * scale * 8
+
+
+def test_cg_finite_termination_distinct_eigenvalues():
+    """The 4 x 4 Dirichlet Laplacian has 9 distinct eigenvalues: CG ends at step 9."""
+    lam = dirichlet_eigs(4)
+    assert len(np.unique(np.round(lam, 12))) == 9
+    A = W.laplace2d(4)
+    res = O.cg(A, O.DropRule.no_drop(), 9)
+    assert res.resid[8] > 1e-6
+    assert res.resid[9] < 1e-10
+    # diagonal A with 3 distinct values: 3 steps
+    D = sp.diags(np.array([1.0, 2.0, 5.0, 1.0, 2.0, 5.0, 5.0]))
+    res = O.cg(D, O.DropRule.no_drop(), 3)
+    assert res.resid[2] > 1e-6 and res.resid[3] < 1e-12
+
+
+def test_cg_converges_to_inverse_no_drop():
+    A, _ = random_spd(8, 11, cond=5.0)
+    res = O.cg(A, O.DropRule.no_drop(), 8)
+    assert np.max(np.abs(_dense(res.M) - np.linalg.inv(_dense(A)))) < 1e-9
+
+
+# ----------------------------------------------------------------------------
+# MR: Theorem 2.1 contraction for any M_0, monotone residuals (no dropping)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_mr_contraction_any_initial_guess(seed):
+    A, lam = random_spd(4, seed, cond=1.5)
+    C = math.sqrt(1.0 - np.linalg.eigvalsh(_dense(A)).min() ** 2 / O.frob(A, A))
+    assert C < 0.95
+    rng = np.random.default_rng(seed)
+    M0 = sp.csc_matrix(rng.standard_normal((4, 4)))
+    res = O.mr(A, O.DropRule.no_drop(), 200, M0=M0)
+    for a, b in zip(res.resid[:-1], res.resid[1:]):
+        assert b <= C * a * (1 + 1e-12) + 1e-14 * res.resid[0]
+    assert np.max(np.abs(_dense(res.M) - np.linalg.inv(_dense(A)))) < 1e-3
+
+
+@pytest.mark.parametrize("method", ["mr", "lomr"])
+def test_monotone_residual_without_dropping(method):
+    A = W.laplace2d(8)
+    res = O.run(method, A, O.DropRule.no_drop(), 25)
+    assert all(b <= a * (1 + 1e-13) for a, b in zip(res.resid[:-1], res.resid[1:]))
+
+
+def test_implicit_and_explicit_residuals_agree_without_dropping():
+    A = W.laplace2d(6)
+    for meth in ("mr", "cg", "lomr"):
+        e = O.run(meth, A, O.DropRule.no_drop(), 8, explicit=True)
+        i = O.run(meth, A, O.DropRule.no_drop(), 8, explicit=False)
+        assert np.allclose(e.resid, i.resid, rtol=1e-9, atol=1e-12)
+
+
+def test_special_cases():
+    # A = I: M_0 = I is the inverse, residual 0
+    I = sp.identity(5, format="csr")
+    c, M0 = O.initial_iterate(I)
+    assert c == 1.0 and O.fnorm(O.residual(I, M0)) == 0.0
+    res = O.lomr(I, O.DropRule.no_drop(), 3, tol=1e-12)
+    assert res.status == "converged" and res.iters == 0
+    # n = 1
+    a = sp.csr_matrix(np.array([[3.0]]))
+    c, M0 = O.initial_iterate(a)
+    assert c == pytest.approx(1 / 3) and O.fnorm(O.residual(a, M0)) < 1e-15
+    # diagonal A: every iterate stays diagonal and the columns decouple
+    D = sp.diags(np.array([1.0, 3.0, 7.0]))
+    res = O.mr(D, O.DropRule.no_drop(), 5)
+    Md = _dense(res.M)
+    assert np.count_nonzero(Md - np.diag(np.diag(Md))) == 0
+    # one MR step from M = 0 is the scaled identity c I
+    A = W.laplace2d(4)
+    res = O.mr(A, O.DropRule.no_drop(), 1, M0=sp.csc_matrix(A.shape))
+    c, M0 = O.initial_iterate(A)
+    assert np.allclose(_dense(res.M), _dense(M0), rtol=1e-14)
+
+
+# ----------------------------------------------------------------------------
+# drop rule (Section 6.1, Appendix A)
+# ----------------------------------------------------------------------------
+
+def _brute_force_keep(vals, budget, exempt):
+    """eq. (hard thresholding) by enumeration: drop the set S of minimal total |value|
+    with |supp| - |S| = budget (exempt entries are never in S)."""
+    cand = [i for i in range(len(vals)) if not exempt[i] and vals[i] != 0]
+    nz = [i for i in range(len(vals)) if vals[i] != 0]
+    ndrop = len(nz) - budget
+    if ndrop <= 0:
+        return set(nz)
+    best, best_set = None, None
+    for S in itertools.combinations(cand, ndrop):
+        s = sum(abs(vals[i]) for i in S)
+        if best is None or s < best:
+            best, best_set = s, set(S)
+    return set(nz) - best_set
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_direction_drop_equals_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    X = sp.random(5, 5, density=0.5, random_state=rng, format="csc")
+    X.data = rng.standard_normal(X.nnz)
+    m = max(1, X.nnz // 2)
+    kept = O.drop_direction(X, O.DropRule(mode="global", m=m, u=0.0))
+    rows, cols, vals = O._entries(O._csc(X))
+    want = _brute_force_keep(list(vals), m, [False] * len(vals))
+    got = set(zip(kept.tocoo().row, kept.tocoo().col))
+    assert got == {(rows[i], cols[i]) for i in want}
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_main_drop_equals_brute_force_with_diagonal_exempt(seed):
+    rng = np.random.default_rng(100 + seed)
+    B = rng.standard_normal((5, 5))
+    B[rng.random((5, 5)) < 0.4] = 0.0
+    X = sp.csc_matrix(B + B.T + np.diag(rng.uniform(1, 2, 5)))
+    m = 5 + 4
+    kept = O.drop_main(X, O.DropRule(mode="global", m=m, u=0.0, symmetrize=True))
+    rows, cols, vals = O._entries(O._csc(X))
+    want = _brute_force_keep(list(vals), m, list(rows == cols))
+    got = set(zip(kept.tocoo().row, kept.tocoo().col))
+    # pairs tie exactly (symmetric input): the tie band drops the whole cut pair
+    assert got <= {(rows[i], cols[i]) for i in want}
+    assert kept.nnz <= m
+    assert all((c, r) in got for (r, c) in got)
+
+
+def test_drop_rule_properties():
+    rng = np.random.default_rng(7)
+    B = sp.random(40, 40, density=0.3, random_state=rng, format="csc")
+    B.data = rng.standard_normal(B.nnz)
+    X = B + B.T + sp.identity(40) * 3.0
+    rule = O.DropRule(mode="global", m=200)
+    M1 = O.drop_main(X, rule)
+    assert M1.nnz <= 200
+    assert np.all(M1.diagonal() != 0)
+    assert (abs(M1 - M1.T)).nnz == 0                      # exactly symmetric
+    M2 = O.drop_main(M1, rule)                            # idempotent under the cap
+    assert (abs(M2 - M1)).nnz == 0
+    # per-column caps, symmetric intersection reading
+    k = np.full(40, 4)
+    M3 = O.drop_main(X, O.DropRule(mode="column", k=k))
+    assert np.all(np.diff(M3.indptr) <= 4)
+    assert (abs(M3 - M3.T)).nnz == 0
+    P3 = O.drop_direction(X, O.DropRule(mode="column", k=k))
+    assert np.all(np.diff(P3.indptr) <= 4)
+    # u-drop: off-diagonal entries below u vanish, diagonal ones stay
+    T = sp.csc_matrix(np.array([[1e-20, 1e-17], [1e-17, 2.0]]))
+    T2 = O.drop_main(T, O.DropRule(mode="none", u=O.UNIT_ROUNDOFF))
+    assert T2.nnz == 2 and T2[0, 0] == 1e-20
+
+
+def test_tie_band_drops_whole_tie_cluster():
+    vals = np.array([5.0, 3.0, 2.0, 2.0, 2.0 * (1 + 1e-12), 1.0])
+    X = sp.csc_matrix((vals, (np.arange(6), np.zeros(6, dtype=int))), shape=(6, 1))
+    P = O.drop_direction(X, O.DropRule(mode="global", m=3))
+    assert sorted(P.data.tolist()) == [3.0, 5.0]           # the near-tie cluster at the cut goes
+    P = O.drop_direction(X, O.DropRule(mode="global", m=2))
+    assert sorted(P.data.tolist()) == [3.0, 5.0]           # exactly the textbook top-2
+    P = O.drop_direction(X, O.DropRule(mode="global", m=5))
+    assert sorted(P.data.tolist()) == sorted(vals[:5].tolist())
+
+
+def test_cap_counts():
+    A = W.aniso2d(8)
+    k = O.cap_counts(A, "column", 3.0, True)
+    counts = np.diff(sp.csc_matrix(A).indptr)
+    assert np.array_equal(k, 3 * counts)
+    assert set(k.tolist()) == {9, 12, 15}
+    assert O.cap_counts(A, "global", 2.0, True) == 2 * A.nnz
+
+
+# ----------------------------------------------------------------------------
+# stopping rule reading against Tables 5-6
+# ----------------------------------------------------------------------------
+
+def test_backward_error_reading_matches_tables_5_6():
+    rows = []
+    with open(os.path.join(GOLDEN, "table5_6_backward_error.csv")) as f:
+        for r in csv.DictReader(line for line in f if not line.startswith("#")):
+            rows.append((int(r["n"]), float(r["resid_fro"]), int(r["iters"])))
+    early = [r for r in rows if r[2] not in (5, 20, 100)]
+    snap = [r for r in rows if r[2] in (5, 20, 100)]
+    assert len(early) == 7
+    # the scaled reading classifies every row as the tables report it ...
+    assert all(O._converged(res, n, 1e-6) for n, res, _ in early)
+    assert not any(O._converged(res, n, 1e-6) for n, res, _ in snap)
+    # ... while the unscaled and the 1/n readings do not
+    assert not all(res <= 1e-6 for _, res, _ in early)
+    assert any(res / n <= 1e-6 for n, res, _ in snap)
+
+
+# ----------------------------------------------------------------------------
+# PCG (vector iteration with the SPAI as preconditioner)
+# ----------------------------------------------------------------------------
+
+def test_pcg_matches_library_cg_and_special_cases():
+    A = W.laplace2d(16)
+    n = A.shape[0]
+    b = W.rhs(n, 1, 1)[:, 0]
+    x, it, st = O.pcg(A, sp.identity(n), b, rtol=1e-8)
+    count = [0]
+
+    def cb(_):
+        count[0] += 1
+
+    xl, info = spla.cg(A, b, rtol=1e-8, atol=0.0, maxiter=1000, callback=cb)
+    assert st == "converged" and info == 0
+    assert abs(it - count[0]) <= 1
+    xd = np.linalg.solve(A.toarray(), b)
+    assert np.linalg.norm(x - xd) <= 1e-6 * np.linalg.norm(xd)
+    # exact inverse as preconditioner: one step
+    Minv = sp.csr_matrix(np.linalg.inv(A.toarray()))
+    x, it, st = O.pcg(A, Minv, b, rtol=1e-8)
+    assert it == 1 and st == "converged"
+    # diagonal A with 4 distinct values: at most 4 steps with M = I
+    D = sp.diags(np.repeat([1.0, 2.0, 3.0, 9.0], 10))
+    x, it, st = O.pcg(D, sp.identity(40), np.ones(40), rtol=1e-12)
+    assert it <= 4 and st == "converged"
+    # indefinite preconditioner is reported
+    x, it, st = O.pcg(A, -sp.identity(n), b)
+    assert st == "indefinite"
+
+
+# ----------------------------------------------------------------------------
+# loss and its gradients
+# ----------------------------------------------------------------------------
+
+def test_loss_gradients_finite_differences_and_closed_form():
+    A = W.grid9(5, 55)
+    pat = W.square_pattern(A)
+    M = W.loss_m_values(A, pat, 56)
+    GA, GM = O.loss_grad(A, M)
+    h = 1e-6
+    rng = np.random.default_rng(0)
+    M = sp.csr_matrix(M)
+    A = sp.csr_matrix(A)
+    for which, X, G in (("M", M, GM), ("A", A, GA)):
+        for e in rng.choice(X.nnz, 12, replace=False):
+            Xp, Xm = X.copy(), X.copy()
+            Xp.data[e] += h
+            Xm.data[e] -= h
+            if which == "M":
+                fp, fm = O.loss(A, Xp), O.loss(A, Xm)
+            else:
+                fp, fm = O.loss(Xp, M), O.loss(Xm, M)
+            fd = (fp - fm) / (2 * h)
+            assert fd == pytest.approx(G.data[e], rel=1e-6, abs=1e-7)
+    # closed form of Section 2 for symmetric A: -2 A R on the pattern of M
+    R = O.residual(A, M)
+    full = (-2.0 * (A @ R)).toarray()
+    Md = sp.csr_matrix(M).tocoo()
+    assert np.allclose(GM.tocoo().data, full[Md.row, Md.col], rtol=1e-12, atol=1e-14)
+
+
+# ----------------------------------------------------------------------------
+# workload generators
+# ----------------------------------------------------------------------------
+
+def test_workload_shapes():
+    assert W.laplace2d(32).nnz == 4992
+    assert W.aniso2d(256).nnz == 326656
+    A3 = W.lognormal3d(8, 3000)
+    assert A3.nnz == 8 ** 3 + 2 * 3 * 7 * 64
+    assert abs(A3 - A3.T).max() == 0
+    A5 = W.grid9(16, 5000)
+    assert abs(A5 - A5.T).max() == 0
+    assert np.all(A5.diagonal() > -A5.sum(axis=1).A.ravel() + A5.diagonal() - 1e-12)
+    G = W.geometric_graph(1000, 9)
+    assert abs(G - G.T).max() == 0
+    assert 6.0 < G.nnz / 1000 - 1 < 10.0
