@@ -1,0 +1,231 @@
+/*
+ * spai.h — C ABI of libspai: global short-recurrence sparse approximate inverses
+ * (MR, CG and LOMR with sparse matrix iterates and Frobenius inner products) of a
+ * symmetric positive definite matrix on an AMD Instinct MI355X (gfx950), and the
+ * preconditioned CG solve that applies the result.
+ *
+ * Method source: Venkovic & Anzt, "Global Iterative Methods for Sparse Approximate
+ * Inverses of Symmetric Positive Definite Matrices" — MR (Algorithm 1), CG with
+ * matrix iterates (Definition 3.1, Proposition 3.2, Algorithm 3), LOMR
+ * (Definition 4.1, Theorem 4.2, Algorithm 4), hard thresholding (Section 6.1),
+ * the explicit residual (Section 6.2) and the main-iterate drop steps of Appendix A.
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns an int status: 0 = SPAI_OK, > 0 an informational
+ *    outcome, < 0 an error.  No C++ exception and no abort crosses the ABI.  After
+ *    an error, spai_last_error() returns a message for the calling thread.
+ *  - Sparse inputs are CSR with int64 row pointers (n + 1 entries, rowptr[0] = 0,
+ *    nondecreasing), int32 column indices sorted ascending and unique within each
+ *    row, and float64 values.  "on_device" = 1 means the three arrays are device
+ *    pointers valid on the current HIP device, 0 means host memory.  Inputs are
+ *    borrowed for the duration of the call only: they are copied.
+ *  - A must be exactly symmetric (pattern and values, bitwise), have a strictly
+ *    positive diagonal stored explicitly and only finite values; violations
+ *    return SPAI_ERR_NOT_SYMMETRIC, SPAI_ERR_NOT_SPD or SPAI_ERR_NONFINITE.
+ *  - All device work is enqueued on opts->stream (a hipStream_t; NULL = the null
+ *    stream).  Calls that return host results synchronise that stream.
+ *  - Floating point: reductions (Frobenius inner products, norms, step sizes,
+ *    PCG scalars) are always float64.  Iterate values are stored in float64 or,
+ *    with SPAI_PREC_MIXED, float32.
+ *  - Results are deterministic: the same inputs on the same device give bitwise
+ *    identical iterates and scalars on every run.
+ */
+#ifndef SPAI_H
+#define SPAI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+enum {
+  SPAI_OK = 0,
+  SPAI_CONVERGED = 1,       /* stopped because ||I - A M||_F / sqrt(n) <= tol   */
+  SPAI_MAXITER = 2,         /* the requested iterations ran without converging  */
+  SPAI_BREAKDOWN = 3,       /* a step size is undefined: CG (P, AP)_F <= 0      */
+  PCG_INDEFINITE = 4,       /* PCG met (r, z) <= 0 or (p, A p) <= 0 on some RHS  */
+  SPAI_ERR_ARG = -1,        /* bad shape, pointer, cap, method or option        */
+  SPAI_ERR_NOT_SYMMETRIC = -2,
+  SPAI_ERR_NOT_SPD = -3,    /* a diagonal entry is missing or not positive      */
+  SPAI_ERR_NONFINITE = -4,
+  SPAI_ERR_NOMEM = -5,      /* device allocation failed or exceeds the pool cap */
+  SPAI_ERR_HIP = -6,        /* a HIP runtime call failed                        */
+  SPAI_ERR_CAPACITY = -7    /* a column exceeded the largest per-column tile    */
+};
+
+enum { SPAI_MR = 0, SPAI_CG = 1, SPAI_LOMR = 2 };
+enum { SPAI_PREC_F64 = 0, SPAI_PREC_MIXED = 1 };
+enum { SPAI_CAP_NONE = 0, SPAI_CAP_GLOBAL = 1, SPAI_CAP_COLUMN = 2 };
+
+typedef struct spai_handle spai_handle_t;
+
+/* Borrowed CSR matrix (see conventions above). */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t* rowptr;   /* [n + 1] */
+  const int32_t* colind;   /* [nnz]   */
+  const double* val;       /* [nnz]   */
+  int on_device;
+} spai_csr_t;
+
+/* Density cap of the drop rule.
+ *  SPAI_CAP_GLOBAL: |supp(M)| <= m and |supp(P)| <= m (Section 6.1, eq. of hard
+ *    thresholding), m = value (relative = 0) or round(value * nnz(A)) (relative = 1).
+ *    On M the diagonal is never dropped and counts toward m (Appendix A).
+ *  SPAI_CAP_COLUMN: column j of M and of P keeps at most k_j entries, k_j = value
+ *    or round(value * nnz(A e_j)); on M this includes the diagonal, and an
+ *    off-diagonal entry of the symmetrized M survives only if it passes both its
+ *    row's and its column's threshold, so M stays symmetric.
+ *  SPAI_CAP_NONE: no count cap (the other drop steps still apply).
+ * Ties: with t the (b+1)-th largest candidate magnitude for a budget b, the kept
+ * entries are exactly those with |x| > t (1 + tie_eta). */
+typedef struct {
+  int mode;
+  int relative;
+  double value;
+} spai_cap_t;
+
+/* Options.  Pass NULL for the defaults shown. */
+typedef struct {
+  int precision;            /* SPAI_PREC_F64 (default) or SPAI_PREC_MIXED: M, P and R
+                               values stored in float32, A read as float32, every
+                               sum accumulated in float64                          */
+  int symmetrize;           /* 1: M := (M + M^T) / 2 before dropping (Appendix A
+                               step 1), default 1                                  */
+  double drop_tol;          /* u of Appendix A step 2: off-diagonal |m| < u of M is
+                               dropped; default 2^-53; 0 disables                 */
+  double tie_eta;           /* tie band of the cap, default 1e-9                  */
+  void* stream;             /* hipStream_t, default NULL                           */
+  int64_t device_pool_limit;/* bytes; 0 = no limit.  Exceeding it at create time
+                               returns SPAI_ERR_NOMEM                             */
+} spai_opts_t;
+
+/* Fill *opts with the defaults. */
+void spai_default_opts(spai_opts_t* opts);
+
+/*
+ * spai_create — validate A, upload it, and form the initial iterate
+ *   M_0 = (tr A / tr A^2) I  and  R_0 = I - A M_0 (Algorithms 1, 3, 4, first line;
+ *   the paper leaves M_0 open, this is the Frobenius-optimal multiple of I).
+ *   CG also forms P_0 = D_P(R_0); LOMR sets P_{-1} = 0.
+ * method: SPAI_MR, SPAI_CG or SPAI_LOMR.
+ * max_iter: upper bound on the total iterations this handle will run (sizes the
+ *   residual history); must be >= 0.
+ * tol: stop when ||I - A M_i||_F / sqrt(n) <= tol (0 disables the test).
+ * out: receives the new handle; on error *out is left NULL.
+ * Errors: SPAI_ERR_ARG (n < 1, null pointers, method, cap below the diagonal
+ *   count for M, cap mode other than NONE with value <= 0), SPAI_ERR_NOT_SYMMETRIC,
+ *   SPAI_ERR_NOT_SPD, SPAI_ERR_NONFINITE, SPAI_ERR_NOMEM, SPAI_ERR_HIP.
+ * The handle owns every device buffer; release it with spai_destroy.
+ */
+int spai_create(const spai_csr_t* A, int method, spai_cap_t cap, int max_iter,
+                double tol, const spai_opts_t* opts, spai_handle_t** out);
+
+/*
+ * spai_iterate — run up to n_iter further iterations of the handle's method, each
+ *   SpGEMM + Frobenius dots -> step sizes -> merge (SpGEAM) -> drop rule -> explicit
+ *   residual R = I - A M with ||R||_F, all on the device with no host round trip.
+ * iters_done (may be NULL): iterations actually run in this call.
+ * resid_hist (may be NULL): host array of n_iter doubles; entry t receives
+ *   ||I - A M||_F after the t-th iteration of this call (entries past iters_done
+ *   are left untouched).
+ * Returns SPAI_OK (all n_iter ran), SPAI_CONVERGED, SPAI_BREAKDOWN, or an error.
+ * Iterating past max_iter total iterations returns SPAI_ERR_ARG.
+ * Synchronises the stream once at the end.
+ */
+int spai_iterate(spai_handle_t* h, int n_iter, int* iters_done, double* resid_hist);
+
+/* Output CSR buffers for spai_get (caller-allocated). */
+typedef struct {
+  int64_t n;
+  int64_t nnz;        /* set by spai_get: number of stored entries of M         */
+  int64_t capacity;   /* entries the colind / val arrays can hold               */
+  int64_t* rowptr;    /* [n + 1]                                                */
+  int32_t* colind;    /* [capacity]                                             */
+  double* val;        /* [capacity] (float32 iterates are widened exactly)      */
+  int on_device;      /* 1: the arrays are device pointers; 0: host             */
+} spai_csr_out_t;
+
+/*
+ * spai_get — export the current iterate M as CSR (rows sorted, no stored zeros).
+ *   Two-call protocol: with rowptr == NULL (or capacity too small) only M->nnz is
+ *   set and SPAI_OK / SPAI_ERR_ARG returned respectively; then call again with
+ *   buffers.  Synchronises the stream.
+ */
+int spai_get(spai_handle_t* h, spai_csr_out_t* M);
+
+/*
+ * spai_stats — scalar state: iterations run so far, ||I - A M||_F, nnz(M), nnz(P)
+ *   and the last step sizes (MR: alpha; CG: alpha, beta; LOMR: delta, gamma) and
+ *   LOMR's count of degenerate steps taken as MR steps.  Any pointer may be NULL.
+ */
+int spai_stats(spai_handle_t* h, int* iters, double* resid_fro, int64_t* nnz_m,
+               int64_t* nnz_p, double* step1, double* step2, int* mr_fallbacks);
+
+/* Release every device buffer of the handle.  NULL is accepted. */
+int spai_destroy(spai_handle_t* h);
+
+/*
+ * pcg_solve — preconditioned CG for A X = B with the SPAI M as preconditioner
+ *   (z = M r), one independent recurrence per right-hand side, all in float64,
+ *   x_0 = 0, stopping when ||r||_2 <= rtol ||b||_2 on the recursively updated
+ *   residual (the vector solves of Section 7, Experiments 04 and 06).
+ * A, M: CSR as above; M need not be symmetric but must be square of the same n.
+ * B, X: dense n x nrhs, row-major (the nrhs values of one row are contiguous),
+ *   float64, device pointers when A->on_device, else host.  X is overwritten.
+ * iters, relres (may be NULL): host arrays of nrhs: iterations taken, and the
+ *   true relative residual ||b - A x||_2 / ||b||_2 at exit.
+ * Returns SPAI_OK when every RHS converged, SPAI_MAXITER when some did not,
+ *   PCG_INDEFINITE when some RHS met (r, z) <= 0 or (p, A p) <= 0, or an error.
+ * Synchronises the stream.
+ */
+int pcg_solve(const spai_csr_t* A, const spai_csr_t* M, int nrhs, const double* B,
+              double* X, double rtol, int max_iter, int* iters, double* relres,
+              const spai_opts_t* opts);
+
+/*
+ * spai_loss_fwd — f(M) = ||I - A M||_F^2 (Section 2) for CSR A and M of the same n,
+ *   without storing A M.  Values are read as float32 when opts->precision is
+ *   SPAI_PREC_MIXED, else float64; the sum is float64.  *L is a host double.
+ */
+int spai_loss_fwd(const spai_csr_t* A, const spai_csr_t* M, double* L,
+                  const spai_opts_t* opts);
+
+/*
+ * spai_loss_bwd — gradients of f in the stored values of A and of M:
+ *   gA = dL * (-2 R M^T) on the pattern of A, gM = dL * (-2 A^T R) on the pattern
+ *   of M, R = I - A M recomputed per column (for symmetric A, gM is the gradient
+ *   -2 A R of Section 2).  gA, gM: arrays of nnz(A), nnz(M) doubles in the CSR
+ *   order of A and M, on the device when A->on_device.  Either may be NULL.
+ *   The patterns of A and M must be symmetric (values need not be).
+ */
+int spai_loss_bwd(const spai_csr_t* A, const spai_csr_t* M, double dL, double* gA,
+                  double* gM, const spai_opts_t* opts);
+
+/*
+ * spai_create_batched — many independent SPD matrices treated as one
+ *   block-diagonal problem: one launch per step covers every matrix, while the
+ *   Frobenius dots, step sizes, stopping test and residual history are kept per
+ *   matrix.  As_host: array of nb CSR descriptors (all host or all device).
+ *   Only SPAI_CAP_NONE and SPAI_CAP_COLUMN are accepted (a column cap involves no
+ *   cross-matrix selection).  The iteration sequence is captured once in a HIP
+ *   graph and replayed by spai_iterate.  spai_get on a batched handle returns
+ *   the block-diagonal M; spai_batched_resid returns ||I - A_b M_b||_F per matrix.
+ */
+int spai_create_batched(const spai_csr_t* As, int nb, int method, spai_cap_t cap,
+                        int max_iter, double tol, const spai_opts_t* opts,
+                        spai_handle_t** out);
+int spai_batched_resid(spai_handle_t* h, double* resid /* [nb], host */);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* spai_last_error(void);
+/* Static name of a status code. */
+const char* spai_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPAI_H */

@@ -1,0 +1,742 @@
+// spai_api.hip — C ABI and host driver of libspai (see include/spai.h).
+//
+// The driver validates A once, sizes every device pool for the worst case the cap
+// allows (so an iteration never needs the host), and enqueues each iteration as a
+// fixed sequence of kernels on the caller's stream.  All step sizes, stopping
+// decisions and buffer parities live in device memory; the host synchronises only
+// when it returns host results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "spai.h"
+#include "spai_kern.hpp"
+#include "spai_host.hpp"
+
+using namespace spai;
+
+namespace spai {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int fetch_csr(const spai_csr_t* A, HostCsr& h) {
+  if (!A || A->n < 1 || A->nnz < 0 || !A->rowptr || (A->nnz > 0 && (!A->colind || !A->val)))
+    return fail(SPAI_ERR_ARG, "CSR: bad shape or null pointer");
+  if (A->n > INT32_MAX - 1) return fail(SPAI_ERR_ARG, "CSR: n exceeds the int32 index range");
+  h.n = A->n;
+  h.nnz = A->nnz;
+  h.rowptr.resize(A->n + 1);
+  h.col.resize(A->nnz);
+  h.val.resize(A->nnz);
+  if (A->on_device) {
+    HIPCHK(hipMemcpy(h.rowptr.data(), A->rowptr, sizeof(int64_t) * (A->n + 1), hipMemcpyDeviceToHost));
+    if (A->nnz) {
+      HIPCHK(hipMemcpy(h.col.data(), A->colind, sizeof(int32_t) * A->nnz, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(h.val.data(), A->val, sizeof(double) * A->nnz, hipMemcpyDeviceToHost));
+    }
+  } else {
+    std::memcpy(h.rowptr.data(), A->rowptr, sizeof(int64_t) * (A->n + 1));
+    if (A->nnz) {
+      std::memcpy(h.col.data(), A->colind, sizeof(int32_t) * A->nnz);
+      std::memcpy(h.val.data(), A->val, sizeof(double) * A->nnz);
+    }
+  }
+  // structure
+  if (h.rowptr[0] != 0 || h.rowptr[h.n] != h.nnz) return fail(SPAI_ERR_ARG, "CSR: bad row pointers");
+  for (int64_t i = 0; i < h.n; ++i) {
+    if (h.rowptr[i + 1] < h.rowptr[i]) return fail(SPAI_ERR_ARG, "CSR: row pointers decrease");
+    for (int64_t q = h.rowptr[i]; q < h.rowptr[i + 1]; ++q) {
+      const int32_t c = h.col[q];
+      if (c < 0 || c >= h.n) return fail(SPAI_ERR_ARG, "CSR: column index out of range");
+      if (q > h.rowptr[i] && c <= h.col[q - 1])
+        return fail(SPAI_ERR_ARG, "CSR: column indices not sorted and unique");
+    }
+  }
+  for (int64_t q = 0; q < h.nnz; ++q)
+    if (!std::isfinite(h.val[q])) return fail(SPAI_ERR_NONFINITE, "CSR: non-finite value");
+  return SPAI_OK;
+}
+
+int64_t find_entry(const HostCsr& h, int64_t i, int32_t j) {
+  const int32_t* b = h.col.data() + h.rowptr[i];
+  const int32_t* e = h.col.data() + h.rowptr[i + 1];
+  const int32_t* p = std::lower_bound(b, e, j);
+  return (p != e && *p == j) ? (int64_t)(p - h.col.data()) : -1;
+}
+
+int check_spd_symmetric(const HostCsr& h) {
+  for (int64_t i = 0; i < h.n; ++i) {
+    bool diag = false;
+    for (int64_t q = h.rowptr[i]; q < h.rowptr[i + 1]; ++q) {
+      const int32_t j = h.col[q];
+      if (j == i) {
+        diag = true;
+        if (!(h.val[q] > 0.0)) return fail(SPAI_ERR_NOT_SPD, "A: non-positive diagonal entry");
+        continue;
+      }
+      const int64_t t = find_entry(h, j, (int32_t)i);
+      if (t < 0 || std::memcmp(&h.val[t], &h.val[q], sizeof(double)) != 0)
+        return fail(SPAI_ERR_NOT_SYMMETRIC, "A: not exactly symmetric");
+    }
+    if (!diag) return fail(SPAI_ERR_NOT_SPD, "A: missing diagonal entry");
+  }
+  return SPAI_OK;
+}
+
+int check_symmetric_pattern(const HostCsr& h) {
+  for (int64_t i = 0; i < h.n; ++i)
+    for (int64_t q = h.rowptr[i]; q < h.rowptr[i + 1]; ++q)
+      if (find_entry(h, h.col[q], (int32_t)i) < 0)
+        return fail(SPAI_ERR_ARG, "pattern is not symmetric");
+  return SPAI_OK;
+}
+
+int DevPool::alloc_bytes(void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (limit > 0 && used + bytes > (size_t)limit)
+    return fail(SPAI_ERR_NOMEM, "device pool limit exceeded");
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(SPAI_ERR_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  ptrs.push_back(*p);
+  used += bytes;
+  return SPAI_OK;
+}
+
+DevPool::~DevPool() {
+  for (void* p : ptrs) (void)hipFree(p);
+}
+
+}  // namespace spai
+
+// ============================================================================
+// engine: one handle's device state and iteration sequence
+// ============================================================================
+
+namespace {
+
+struct EngineBase {
+  virtual ~EngineBase() {}
+  virtual int iterate(int k, int* done, double* hist) = 0;
+  virtual int get(spai_csr_out_t* M) = 0;
+  virtual int stats(int* iters, double* resid, int64_t* nnz_m, int64_t* nnz_p, double* s1,
+                    double* s2, int* fb) = 0;
+  virtual int batched_resid(double* out) = 0;
+};
+
+template <typename T>
+struct Engine : EngineBase {
+  // configuration
+  int method = 0;
+  int64_t n = 0;
+  int nseg = 1;
+  spai_cap_t cap{};
+  spai_opts_t opts{};
+  double tol = 0.0;
+  int max_iter = 0;
+  hipStream_t s = nullptr;
+  bool global = false, colcap = false;
+  int64_t m_global = 0;
+  bool batched_graph = false;
+  // host mirror of A
+  HostCsr hA;
+  std::vector<int64_t> seg_beg_h;
+  // device
+  DevPool pool;
+  Csr A;
+  Pair<T> M, P, PT;
+  Cols<T> R;
+  int64_t *ub = nullptr, *off = nullptr, *total = nullptr, *scantmp = nullptr;
+  double *colpart = nullptr, *colnorm = nullptr, *red = nullptr, *red_rr = nullptr;
+  double *blockpart = nullptr, *cvec = nullptr, *hist = nullptr;
+  int32_t* kcol = nullptr;
+  double *tM = nullptr, *tP = nullptr;
+  BigList big[3];
+  unsigned long long *selhist = nullptr, *selbuf = nullptr;
+  DevState* st = nullptr;
+  SegState* segst = nullptr;
+  int* seg_of = nullptr;
+  int64_t* seg_beg = nullptr;
+  Seg seg;
+  Tile tRs{128, 512}, tRl{1024, 4096}, tDs{256, 1024}, tDl{1024, 4096}, tUs{384, 512},
+      tUl{2048, 2048};
+  int hist_cap = 0;
+  int iters_host = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t own_stream = nullptr;
+
+  ~Engine() override {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (own_stream) {
+      (void)hipStreamSynchronize(own_stream);
+      (void)hipStreamDestroy(own_stream);
+    }
+  }
+
+  template <typename U>
+  int dalloc(U** p, int64_t count) {
+    return pool.alloc_bytes((void**)p, sizeof(U) * (size_t)std::max<int64_t>(count, 1));
+  }
+
+  int alloc_cols(Cols<T>& c, int64_t capacity) {
+    int rc;
+    if ((rc = dalloc(&c.beg, n))) return rc;
+    if ((rc = dalloc(&c.len, n))) return rc;
+    if ((rc = dalloc(&c.idx, capacity))) return rc;
+    if ((rc = dalloc(&c.val, capacity))) return rc;
+    c.cap = capacity;
+    return SPAI_OK;
+  }
+
+  int setup(const std::vector<int64_t>& segs) {
+    int rc;
+    seg_beg_h = segs;
+    nseg = (int)segs.size() - 1;
+    global = cap.mode == SPAI_CAP_GLOBAL;
+    colcap = cap.mode == SPAI_CAP_COLUMN;
+    s = (hipStream_t)opts.stream;
+    if (batched_graph && !s) {          // graphs cannot be captured on the null stream
+      HIPCHK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+      s = own_stream;
+    }
+    pool.limit = opts.device_pool_limit;
+    // ---- caps and worst-case sizes
+    int64_t maxdeg = 0;
+    for (int64_t i = 0; i < n; ++i) maxdeg = std::max(maxdeg, hA.rowptr[i + 1] - hA.rowptr[i]);
+    const double n2 = (double)n * (double)n;
+    double nnzM_max = n2;
+    std::vector<int32_t> kc;
+    if (global) {
+      const double mv = cap.relative ? cap.value * (double)hA.nnz : cap.value;
+      if (!(mv >= (double)n)) return fail(SPAI_ERR_ARG, "global cap below the diagonal count n");
+      m_global = (int64_t)std::llround(mv);
+      nnzM_max = std::min(n2, (double)m_global);
+    } else if (colcap) {
+      kc.resize(n);
+      double sum = 0.0;
+      for (int64_t j = 0; j < n; ++j) {
+        const double deg = (double)(hA.rowptr[j + 1] - hA.rowptr[j]);
+        const double kv = cap.relative ? cap.value * deg : cap.value;
+        const int64_t k = (int64_t)std::llround(kv);
+        if (k < 1) return fail(SPAI_ERR_ARG, "column cap below one (the diagonal)");
+        kc[j] = (int32_t)std::min<int64_t>(k, n);
+        sum += kc[j];
+      }
+      nnzM_max = std::min(n2, sum);
+    } else if (cap.mode != SPAI_CAP_NONE) {
+      return fail(SPAI_ERR_ARG, "unknown cap mode");
+    }
+    const double nnzP_max = method == SPAI_MR ? 0.0 : nnzM_max;
+    // offsets come from per-column bounds that count duplicate products, so the pools
+    // hold the sum of the bounds (not the number of distinct entries)
+    const double capR_d = (double)n + nnzM_max * (double)maxdeg;
+    const double capU_d = (double)n + nnzM_max + capR_d + 2.0 * nnzP_max + nnzM_max * (double)maxdeg;
+    if (capU_d > 4.0e9) return fail(SPAI_ERR_NOMEM, "worst-case pattern too large (set a cap)");
+    const int64_t capR = (int64_t)capR_d, capU = (int64_t)capU_d;
+    // ---- A
+    int64_t* d_rowptr;
+    int32_t* d_col;
+    double* d_val;
+    if ((rc = dalloc(&d_rowptr, n + 1)) || (rc = dalloc(&d_col, hA.nnz)) || (rc = dalloc(&d_val, hA.nnz)))
+      return rc;
+    HIPCHK(hipMemcpyAsync(d_rowptr, hA.rowptr.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_col, hA.col.data(), sizeof(int32_t) * hA.nnz, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_val, hA.val.data(), sizeof(double) * hA.nnz, hipMemcpyHostToDevice, s));
+    A.n = n;
+    A.nnz = hA.nnz;
+    A.rowptr = d_rowptr;
+    A.col = d_col;
+    A.val = d_val;
+    std::vector<float> v32;
+    if (opts.precision == SPAI_PREC_MIXED) {
+      float* d_v32;
+      if ((rc = dalloc(&d_v32, hA.nnz))) return rc;
+      v32.resize(hA.nnz);
+      for (int64_t q = 0; q < hA.nnz; ++q) v32[q] = (float)hA.val[q];
+      HIPCHK(hipMemcpyAsync(d_v32, v32.data(), sizeof(float) * hA.nnz, hipMemcpyHostToDevice, s));
+      A.val32 = d_v32;
+    }
+    // ---- state
+    if ((rc = dalloc(&st, 1)) || (rc = dalloc(&segst, nseg)) || (rc = dalloc(&seg_beg, nseg + 1)))
+      return rc;
+    HIPCHK(hipMemsetAsync(st, 0, sizeof(DevState), s));
+    HIPCHK(hipMemsetAsync(segst, 0, sizeof(SegState) * nseg, s));
+    HIPCHK(hipMemcpyAsync(seg_beg, seg_beg_h.data(), sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice, s));
+    std::vector<int> segof_h;
+    if (nseg > 1) {
+      if ((rc = dalloc(&seg_of, n))) return rc;
+      segof_h.resize(n);
+      for (int g = 0; g < nseg; ++g)
+        for (int64_t j = seg_beg_h[g]; j < seg_beg_h[g + 1]; ++j) segof_h[j] = g;
+      HIPCHK(hipMemcpyAsync(seg_of, segof_h.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    }
+    seg.nseg = nseg;
+    seg.of = seg_of;
+    seg.st = segst;
+    // ---- iterate pools
+    const int64_t capP = method == SPAI_MR ? 1 : capU;
+    for (int b = 0; b < 2; ++b) {
+      if ((rc = alloc_cols(M.b[b], capU))) return rc;
+      if ((rc = alloc_cols(P.b[b], capP))) return rc;
+      if ((rc = alloc_cols(PT.b[b], capP))) return rc;
+    }
+    if ((rc = alloc_cols(R, capR))) return rc;
+    M.cur = &st->curM;
+    P.cur = &st->curP;
+    PT.cur = &st->curP;
+    if ((rc = dalloc(&ub, n)) || (rc = dalloc(&off, n)) || (rc = dalloc(&total, 1)) ||
+        (rc = dalloc(&scantmp, scan_tmp_elems(n))))
+      return rc;
+    if ((rc = dalloc(&colpart, n * kND)) || (rc = dalloc(&colnorm, n)) ||
+        (rc = dalloc(&red, (int64_t)nseg * kND)) || (rc = dalloc(&red_rr, nseg)) ||
+        (rc = dalloc(&blockpart, 1024 * kND)) || (rc = dalloc(&cvec, nseg)))
+      return rc;
+    hist_cap = std::max(max_iter, 1);
+    if ((rc = dalloc(&hist, (int64_t)nseg * hist_cap))) return rc;
+    if (colcap) {
+      if ((rc = dalloc(&kcol, n)) || (rc = dalloc(&tM, n)) || (rc = dalloc(&tP, n))) return rc;
+      HIPCHK(hipMemcpyAsync(kcol, kc.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    }
+    for (int b = 0; b < 3; ++b)
+      if ((rc = dalloc(&big[b].list, n)) || (rc = dalloc(&big[b].count, 1))) return rc;
+    if (global) {
+      if ((rc = dalloc(&selhist, 8192)) || (rc = dalloc(&selbuf, capU))) return rc;
+    }
+    // ---- M_0 = c I, R_0, and CG's P_0
+    launch_trace_parts(A, colpart, s);
+    launch_reduce(colpart, 2, n, seg, nseg > 1 ? seg_beg : nullptr, red, blockpart, s);
+    launch_init_state(seg, red, nseg > 1 ? seg_beg : nullptr, n, cvec, method, st, s);
+    launch_init_m<T>(n, M.b[0], cvec, seg, s);
+    if (method != SPAI_MR)
+      for (int b = 0; b < 2; ++b) {
+        launch_zero_cols<T>(n, P.b[b], s);
+        launch_zero_cols<T>(n, PT.b[b], s);
+      }
+    resid_step(1);
+    if (method == SPAI_CG) p_update_step();
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return check_err();
+  }
+
+  UpdMode mode(int doM, int x1, int x2, int doP) const {
+    UpdMode md{};
+    md.doM = doM;
+    md.x1 = x1;
+    md.x2 = x2;
+    md.doP = doP;
+    md.pR = 1;
+    md.pP = 1;
+    md.sym = opts.symmetrize ? 1 : 0;
+    md.colcap = colcap ? 1 : 0;
+    md.u = opts.drop_tol;
+    return md;
+  }
+
+  void resid_step(int setup) {
+    launch_bound_resid<T>(A, M, ub, n, st, s);
+    launch_scan(ub, off, total, n, scantmp, s);
+    launch_resid<T>(A, M, R, off, total, colnorm, big[0], st, tRs, tRl, s);
+    launch_reduce(colnorm, 1, n, seg, nseg > 1 ? seg_beg : nullptr, red_rr, blockpart, s);
+    launch_scal_post(method, seg, red_rr, tol, hist, hist_cap, setup, st, s);
+  }
+
+  void dots_step(int useR, int useP) {
+    launch_dots<T>(A, R, P, useR, useP, colpart, big[1], st, tDs, tDl, s);
+    launch_reduce(colpart, kND, n, seg, nseg > 1 ? seg_beg : nullptr, red, blockpart, s);
+    launch_scal_step(method, seg, red, st, s);
+  }
+
+  void update_step(UpdMode md) {
+    launch_bound_update<T>(A, M, R, P, PT, md, ub, n, st, s);
+    launch_scan(ub, off, total, n, scantmp, s);
+    launch_update<T>(A, M, R, P, PT, md, off, total, kcol, tM, tP, big[2], seg, st, tUs, tUl, s);
+    if (global) {
+      if (md.doM) launch_global_select<T>(M, 1, m_global, opts.tie_eta, 0, selhist, selbuf, n, st, s);
+      if (md.doP) launch_global_select<T>(P, 0, m_global, opts.tie_eta, 1, selhist, selbuf, n, st, s);
+    }
+    if (md.doM) {
+      launch_compact<T>(M, 0, colcap, md.sym, global, tM, opts.tie_eta, n, st, s);
+      launch_flip(0, st, s);
+    }
+    if (md.doP) {
+      launch_compact<T>(P, 1, colcap, 0, global, tP, opts.tie_eta, n, st, s);
+      launch_compact<T>(PT, 2, colcap, 0, global, tP, opts.tie_eta, n, st, s);
+      launch_flip(1, st, s);
+    }
+  }
+
+  void p_update_step() { update_step(mode(0, 0, 0, 1)); }
+
+  // one iteration of the handle's method, entirely on the device
+  void enqueue_iteration() {
+    if (method == SPAI_MR) {
+      dots_step(1, 0);
+      update_step(mode(1, 1, 0, 0));
+      resid_step(0);
+    } else if (method == SPAI_CG) {
+      dots_step(0, 1);
+      update_step(mode(1, 2, 0, 0));
+      resid_step(0);
+      p_update_step();
+    } else {
+      dots_step(1, 1);
+      update_step(mode(1, 1, 2, 1));
+      resid_step(0);
+    }
+  }
+
+  int check_err() {
+    DevState h;
+    HIPCHK(hipMemcpy(&h, st, sizeof(DevState), hipMemcpyDeviceToHost));
+    if (h.err & 1) return fail(SPAI_ERR_CAPACITY, "a column exceeded the largest per-column tile");
+    if (h.err & 2) return fail(SPAI_ERR_NOMEM, "an iterate exceeded its device pool");
+    return SPAI_OK;
+  }
+
+  int read_segs(std::vector<SegState>& v) {
+    v.resize(nseg);
+    HIPCHK(hipMemcpy(v.data(), segst, sizeof(SegState) * nseg, hipMemcpyDeviceToHost));
+    return SPAI_OK;
+  }
+
+  int iterate(int k, int* done, double* hout) override {
+    if (k < 0) return fail(SPAI_ERR_ARG, "negative iteration count");
+    if (iters_host + k > max_iter) return fail(SPAI_ERR_ARG, "iterations beyond max_iter");
+    int rc;
+    std::vector<SegState> before;
+    if ((rc = read_segs(before))) return rc;
+    if (batched_graph && k > 0) {
+      if (!graph_exec) {
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        enqueue_iteration();
+        HIPCHK(hipStreamEndCapture(s, &graph));
+        HIPCHK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+      }
+      for (int t = 0; t < k; ++t) HIPCHK(hipGraphLaunch(graph_exec, s));
+    } else {
+      for (int t = 0; t < k; ++t) enqueue_iteration();
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    if ((rc = check_err())) return rc;
+    std::vector<SegState> after;
+    if ((rc = read_segs(after))) return rc;
+    const int d0 = after[0].iters - before[0].iters;
+    iters_host += k;
+    if (done) *done = d0;
+    if (hout && d0 > 0)
+      HIPCHK(hipMemcpy(hout, hist + before[0].iters, sizeof(double) * d0, hipMemcpyDeviceToHost));
+    if (nseg == 1) {
+      if (after[0].status == 3) return SPAI_BREAKDOWN;
+      if (after[0].status == 1) return SPAI_CONVERGED;
+      return SPAI_OK;
+    }
+    bool all_conv = true, any_break = false;
+    for (auto& g : after) {
+      all_conv = all_conv && g.status == 1;
+      any_break = any_break || g.status == 3;
+    }
+    if (any_break) return SPAI_BREAKDOWN;
+    if (all_conv) return SPAI_CONVERGED;
+    return SPAI_OK;
+  }
+
+  int get(spai_csr_out_t* out) override {
+    if (!out) return fail(SPAI_ERR_ARG, "null output");
+    HIPCHK(hipStreamSynchronize(s));
+    DevState h;
+    HIPCHK(hipMemcpy(&h, st, sizeof(DevState), hipMemcpyDeviceToHost));
+    const Cols<T>& C = M.b[h.curM];
+    std::vector<int64_t> beg(n);
+    std::vector<int32_t> len(n);
+    HIPCHK(hipMemcpy(beg.data(), C.beg, sizeof(int64_t) * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(len.data(), C.len, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    int64_t nnz = 0;
+    for (int64_t j = 0; j < n; ++j) nnz += len[j];
+    out->n = n;
+    out->nnz = nnz;
+    if (!out->rowptr) return SPAI_OK;
+    if (out->capacity < nnz) return fail(SPAI_ERR_ARG, "output capacity below nnz(M)");
+    // gather the columns (CSC), then transpose to CSR on the host
+    std::vector<int32_t> ci(nnz);
+    std::vector<T> cv(nnz);
+    int64_t o = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (len[j]) {
+        HIPCHK(hipMemcpy(ci.data() + o, C.idx + beg[j], sizeof(int32_t) * len[j], hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(cv.data() + o, C.val + beg[j], sizeof(T) * len[j], hipMemcpyDeviceToHost));
+      }
+      o += len[j];
+    }
+    std::vector<int64_t> rp(n + 1, 0);
+    for (int64_t q = 0; q < nnz; ++q) rp[ci[q] + 1]++;
+    for (int64_t i = 0; i < n; ++i) rp[i + 1] += rp[i];
+    std::vector<int64_t> cur(rp.begin(), rp.end() - 1);
+    std::vector<int32_t> rc_col(nnz);
+    std::vector<double> rc_val(nnz);
+    o = 0;
+    for (int64_t j = 0; j < n; ++j)
+      for (int e = 0; e < len[j]; ++e, ++o) {
+        const int64_t p = cur[ci[o]]++;
+        rc_col[p] = (int32_t)j;
+        rc_val[p] = (double)cv[o];
+      }
+    if (out->on_device) {
+      HIPCHK(hipMemcpy(out->rowptr, rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+      if (nnz) {
+        HIPCHK(hipMemcpy(out->colind, rc_col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(out->val, rc_val.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
+      }
+    } else {
+      std::memcpy(out->rowptr, rp.data(), sizeof(int64_t) * (n + 1));
+      if (nnz) {
+        std::memcpy(out->colind, rc_col.data(), sizeof(int32_t) * nnz);
+        std::memcpy(out->val, rc_val.data(), sizeof(double) * nnz);
+      }
+    }
+    return SPAI_OK;
+  }
+
+  int stats(int* iters, double* resid, int64_t* nnz_m, int64_t* nnz_p, double* s1, double* s2,
+            int* fb) override {
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<SegState> g;
+    int rc;
+    if ((rc = read_segs(g))) return rc;
+    DevState h;
+    HIPCHK(hipMemcpy(&h, st, sizeof(DevState), hipMemcpyDeviceToHost));
+    if (iters) *iters = g[0].iters;
+    if (resid) *resid = std::sqrt(g[0].rr);
+    if (s1) *s1 = g[0].step1;
+    if (s2) *s2 = g[0].step2;
+    if (fb) *fb = g[0].mr_fallbacks;
+    if (nnz_m || nnz_p) {
+      auto count = [&](const Cols<T>& C, int64_t* out) -> int {
+        std::vector<int32_t> len(n);
+        HIPCHK(hipMemcpy(len.data(), C.len, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+        int64_t t = 0;
+        for (auto v : len) t += v;
+        *out = t;
+        return SPAI_OK;
+      };
+      if (nnz_m && (rc = count(M.b[h.curM], nnz_m))) return rc;
+      if (nnz_p) {
+        if (method == SPAI_MR) *nnz_p = 0;
+        else if ((rc = count(P.b[h.curP], nnz_p))) return rc;
+      }
+    }
+    return SPAI_OK;
+  }
+
+  int batched_resid(double* out) override {
+    if (!out) return fail(SPAI_ERR_ARG, "null output");
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<SegState> g;
+    int rc;
+    if ((rc = read_segs(g))) return rc;
+    for (int i = 0; i < nseg; ++i) out[i] = std::sqrt(g[i].rr);
+    return SPAI_OK;
+  }
+};
+
+}  // namespace
+
+struct spai_handle {
+  std::unique_ptr<EngineBase> eng;
+};
+
+static void fill_defaults(spai_opts_t* o) {
+  o->precision = SPAI_PREC_F64;
+  o->symmetrize = 1;
+  o->drop_tol = std::ldexp(1.0, -53);
+  o->tie_eta = 1e-9;
+  o->stream = nullptr;
+  o->device_pool_limit = 0;
+}
+
+template <typename T>
+static int make_engine(HostCsr&& hA, const std::vector<int64_t>& segs, int method, spai_cap_t cap,
+                       int max_iter, double tol, const spai_opts_t& o, bool graph,
+                       spai_handle_t** out) {
+  auto e = std::make_unique<Engine<T>>();
+  e->method = method;
+  e->n = hA.n;
+  e->cap = cap;
+  e->opts = o;
+  e->tol = tol;
+  e->max_iter = max_iter;
+  e->hA = std::move(hA);
+  e->batched_graph = graph;
+  int rc = e->setup(segs);
+  if (rc) return rc;
+  auto* h = new (std::nothrow) spai_handle;
+  if (!h) return fail(SPAI_ERR_NOMEM, "host allocation failed");
+  h->eng = std::move(e);
+  *out = h;
+  return SPAI_OK;
+}
+
+static int check_common(int method, spai_cap_t cap, int max_iter, double tol,
+                        const spai_opts_t* opts, spai_opts_t& o) {
+  if (method != SPAI_MR && method != SPAI_CG && method != SPAI_LOMR)
+    return fail(SPAI_ERR_ARG, "unknown method");
+  if (max_iter < 0 || !(tol >= 0.0)) return fail(SPAI_ERR_ARG, "bad max_iter or tol");
+  if (cap.mode != SPAI_CAP_NONE && !(cap.value > 0.0)) return fail(SPAI_ERR_ARG, "cap value <= 0");
+  fill_defaults(&o);
+  if (opts) o = *opts;
+  if (o.precision != SPAI_PREC_F64 && o.precision != SPAI_PREC_MIXED)
+    return fail(SPAI_ERR_ARG, "unknown precision");
+  if (!(o.drop_tol >= 0.0) || !(o.tie_eta >= 0.0)) return fail(SPAI_ERR_ARG, "bad drop_tol / tie_eta");
+  return SPAI_OK;
+}
+
+extern "C" {
+
+void spai_default_opts(spai_opts_t* opts) {
+  if (opts) fill_defaults(opts);
+}
+
+int spai_create(const spai_csr_t* A, int method, spai_cap_t cap, int max_iter, double tol,
+                const spai_opts_t* opts, spai_handle_t** out) {
+  try {
+    if (!out) return fail(SPAI_ERR_ARG, "null handle pointer");
+    *out = nullptr;
+    spai_opts_t o;
+    int rc = check_common(method, cap, max_iter, tol, opts, o);
+    if (rc) return rc;
+    HostCsr hA;
+    if ((rc = fetch_csr(A, hA))) return rc;
+    if ((rc = check_spd_symmetric(hA))) return rc;
+    std::vector<int64_t> segs{0, hA.n};
+    if (o.precision == SPAI_PREC_MIXED)
+      return make_engine<float>(std::move(hA), segs, method, cap, max_iter, tol, o, false, out);
+    return make_engine<double>(std::move(hA), segs, method, cap, max_iter, tol, o, false, out);
+  } catch (const std::bad_alloc&) {
+    return fail(SPAI_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_create_batched(const spai_csr_t* As, int nb, int method, spai_cap_t cap, int max_iter,
+                        double tol, const spai_opts_t* opts, spai_handle_t** out) {
+  try {
+    if (!out || !As || nb < 1) return fail(SPAI_ERR_ARG, "bad batch arguments");
+    *out = nullptr;
+    spai_opts_t o;
+    int rc = check_common(method, cap, max_iter, tol, opts, o);
+    if (rc) return rc;
+    if (cap.mode == SPAI_CAP_GLOBAL) return fail(SPAI_ERR_ARG, "batched handles take column caps only");
+    // block-diagonal assembly
+    HostCsr big;
+    big.n = 0;
+    big.nnz = 0;
+    std::vector<int64_t> segs{0};
+    big.rowptr.push_back(0);
+    for (int b = 0; b < nb; ++b) {
+      HostCsr h;
+      if ((rc = fetch_csr(&As[b], h))) return rc;
+      if ((rc = check_spd_symmetric(h))) return rc;
+      const int64_t base = big.n;
+      for (int64_t i = 0; i < h.n; ++i) big.rowptr.push_back(big.nnz + h.rowptr[i + 1]);
+      for (int64_t q = 0; q < h.nnz; ++q) {
+        big.col.push_back((int32_t)(h.col[q] + base));
+        big.val.push_back(h.val[q]);
+      }
+      big.n += h.n;
+      big.nnz += h.nnz;
+      segs.push_back(big.n);
+      if (big.n > INT32_MAX - 1) return fail(SPAI_ERR_ARG, "batch exceeds the int32 index range");
+    }
+    if (o.precision == SPAI_PREC_MIXED)
+      return make_engine<float>(std::move(big), segs, method, cap, max_iter, tol, o, true, out);
+    return make_engine<double>(std::move(big), segs, method, cap, max_iter, tol, o, true, out);
+  } catch (const std::bad_alloc&) {
+    return fail(SPAI_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_iterate(spai_handle_t* h, int n_iter, int* iters_done, double* resid_hist) {
+  if (!h) return fail(SPAI_ERR_ARG, "null handle");
+  try {
+    return h->eng->iterate(n_iter, iters_done, resid_hist);
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_get(spai_handle_t* h, spai_csr_out_t* M) {
+  if (!h) return fail(SPAI_ERR_ARG, "null handle");
+  try {
+    return h->eng->get(M);
+  } catch (const std::bad_alloc&) {
+    return fail(SPAI_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_stats(spai_handle_t* h, int* iters, double* resid_fro, int64_t* nnz_m, int64_t* nnz_p,
+               double* step1, double* step2, int* mr_fallbacks) {
+  if (!h) return fail(SPAI_ERR_ARG, "null handle");
+  try {
+    return h->eng->stats(iters, resid_fro, nnz_m, nnz_p, step1, step2, mr_fallbacks);
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_batched_resid(spai_handle_t* h, double* resid) {
+  if (!h) return fail(SPAI_ERR_ARG, "null handle");
+  try {
+    return h->eng->batched_resid(resid);
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_destroy(spai_handle_t* h) {
+  delete h;
+  return SPAI_OK;
+}
+
+const char* spai_last_error(void) { return g_last_error.c_str(); }
+
+const char* spai_status_string(int status) {
+  switch (status) {
+    case SPAI_OK: return "SPAI_OK";
+    case SPAI_CONVERGED: return "SPAI_CONVERGED";
+    case SPAI_MAXITER: return "SPAI_MAXITER";
+    case SPAI_BREAKDOWN: return "SPAI_BREAKDOWN";
+    case PCG_INDEFINITE: return "PCG_INDEFINITE";
+    case SPAI_ERR_ARG: return "SPAI_ERR_ARG";
+    case SPAI_ERR_NOT_SYMMETRIC: return "SPAI_ERR_NOT_SYMMETRIC";
+    case SPAI_ERR_NOT_SPD: return "SPAI_ERR_NOT_SPD";
+    case SPAI_ERR_NONFINITE: return "SPAI_ERR_NONFINITE";
+    case SPAI_ERR_NOMEM: return "SPAI_ERR_NOMEM";
+    case SPAI_ERR_HIP: return "SPAI_ERR_HIP";
+    case SPAI_ERR_CAPACITY: return "SPAI_ERR_CAPACITY";
+    default: return "SPAI_UNKNOWN";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// spai_host.hpp — host-side helpers of libspai: error reporting, CSR intake, device pool.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "spai.h"
+
+namespace spai {
+
+extern thread_local std::string g_last_error;
+int fail(int code, const std::string& msg);
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) {                                                                \
+      (void)hipGetLastError();                                                             \
+      return ::spai::fail(SPAI_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_));  \
+    }                                                                                      \
+  } while (0)
+
+struct HostCsr {
+  int64_t n = 0, nnz = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+// copy a borrowed CSR to the host and check its structure and finiteness
+int fetch_csr(const spai_csr_t* A, HostCsr& h);
+// exact symmetry (bitwise values) and a positive stored diagonal
+int check_spd_symmetric(const HostCsr& h);
+// symmetric pattern (values free)
+int check_symmetric_pattern(const HostCsr& h);
+// position of entry (i, j) or -1
+int64_t find_entry(const HostCsr& h, int64_t i, int32_t j);
+
+// owner of a handle's or a call's device allocations
+struct DevPool {
+  std::vector<void*> ptrs;
+  size_t used = 0;
+  int64_t limit = 0;
+  int alloc_bytes(void** p, size_t bytes);
+  template <typename U>
+  int alloc(U** p, int64_t count) {
+    return alloc_bytes((void**)p, sizeof(U) * (size_t)(count > 0 ? count : 1));
+  }
+  ~DevPool();
+};
+
+}  // namespace spai

@@ -1,0 +1,140 @@
+// spai_kern.hpp — device state and kernel launchers of libspai (host-visible declarations).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spai_dev.hpp"
+
+namespace spai {
+
+enum : int { kMR = 0, kCG = 1, kLOMR = 2 };
+
+// Frobenius dots produced per column by the SpGEMM-dots kernel:
+// 0 (R,AR)  1 (AR,AR)  2 (AR,AP)  3 (R,AP)  4 (AP,AP)  5 (P,AP)
+constexpr int kND = 6;
+
+// Per-matrix ("segment") scalar state; a single segment unless the handle is batched.
+struct SegState {
+  double dots[kND];   // reduced dots of the current iteration
+  double rr;          // ||R_i||_F^2 of the current iterate
+  double coef[4];     // a1, a2 (M + a1 X1 + a2 X2), c1, c2 (P = c1 R + c2 P)
+  double step1, step2;// last step sizes (MR alpha | CG alpha, beta | LOMR delta, gamma)
+  double inv_sqrt_n;  // 1 / sqrt(rows of this matrix)
+  double last_resid;  // ||R||_F after the last completed iteration
+  int iters;          // iterations completed
+  int stop;           // 1 once converged or broken down
+  int status;         // 0 running, 1 converged, 3 breakdown
+  int first;          // LOMR: the next step is the first (MR) step
+  int mr_fallbacks;   // LOMR degenerate steps taken as MR steps
+  int pad;
+};
+
+// Global device state of a handle.
+struct DevState {
+  int any_active;     // 0 once every segment has stopped: kernels return at once
+  int err;            // bit 0: a column exceeded the largest tile; bit 1: buffer overflow
+  int curM, curP;     // which of the two buffers holds the current M / (P, P^T)
+  int big_count[4];   // overflow-column list lengths (resid, dots, update)
+  unsigned long long nnz_m, nnz_p;
+  // global-cap radix selection
+  double thrM, thrP;              // keep |x| > thr (thr already includes 1 + eta)
+  unsigned long long sel_count;   // keys in the selection buffer
+  unsigned long long sel_prefix;  // key bits fixed so far
+  long long sel_rank;             // 1-based rank still to find inside the prefix
+  long long sel_diag;             // diagonal candidates (excluded, always kept)
+  int sel_done;                   // 1: threshold known
+  int iter_active;                // 1: the current iteration runs (set by the step kernel)
+};
+
+struct Seg {                       // column -> matrix map for batched handles
+  int nseg = 1;
+  const int* of = nullptr;         // [n] matrix of each column (null when nseg == 1)
+  SegState* st = nullptr;          // [nseg]
+  __device__ __forceinline__ int segof(int64_t j) const { return nseg > 1 ? of[j] : 0; }
+};
+
+template <typename T>
+struct Pair {                      // ping-pong pair of column buffers
+  Cols<T> b[2];
+  const int* cur = nullptr;        // device index of the current buffer
+  __device__ __forceinline__ Cols<T> now() const { return b[*cur]; }
+  __device__ __forceinline__ Cols<T> nxt() const { return b[*cur ^ 1]; }
+};
+
+struct BigList {
+  int* list = nullptr;             // columns left to the large-tile pass
+  int* count = nullptr;
+};
+
+struct Tile { int L, H; };         // per-column LDS tile: list entries and hash slots
+
+struct UpdMode {
+  int doM;       // form the (symmetrized, small-dropped) M candidates
+  int x1, x2;    // lists added to M: 0 none, 1 R, 2 P, with coef[0], coef[1]
+  int doP;       // form P and P^T candidates coef[2] R + coef[3] P
+  int pR, pP;    // R / P take part in the P candidates
+  int sym;       // symmetrize M
+  int colcap;    // per-column caps: compute per-column thresholds
+  double u;      // small-entry threshold on off-diagonal M (0 = off)
+};
+
+// ---------------- launchers (all enqueue on `s`) -----------------------------
+int64_t scan_tmp_elems(int64_t n);
+void launch_scan(const int64_t* in, int64_t* out, int64_t* total, int64_t n, int64_t* tmp,
+                 hipStream_t s);
+
+// per-segment sums of colpart[j * nd + d] in a fixed order -> red[seg * nd + d]
+void launch_reduce(const double* colpart, int nd, int64_t n, const Seg& seg,
+                   const int64_t* seg_beg, double* red, double* blockpart, hipStream_t s);
+
+void launch_trace_parts(const Csr& A, double* colpart, hipStream_t s);
+void launch_init_state(const Seg& seg, const double* red_tr, const int64_t* seg_beg, int64_t n,
+                       double* cvec, int method, DevState* st, hipStream_t s);
+
+template <typename T>
+void launch_init_m(int64_t n, Cols<T> M, const double* cvec, const Seg& seg, hipStream_t s);
+
+template <typename T>
+void launch_zero_cols(int64_t n, Cols<T> X, hipStream_t s);
+
+template <typename T>
+void launch_bound_resid(const Csr& A, Pair<T> M, int64_t* ub, int64_t n, const DevState* st,
+                        hipStream_t s);
+template <typename T>
+void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const int64_t* total,
+                  double* colnorm, BigList big, DevState* st, Tile small, Tile large,
+                  hipStream_t s);
+
+template <typename T>
+void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, double* colpart,
+                 BigList big, DevState* st, Tile small, Tile large, hipStream_t s);
+
+template <typename T>
+void launch_bound_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, UpdMode md,
+                         int64_t* ub, int64_t n, const DevState* st, hipStream_t s);
+template <typename T>
+void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, UpdMode md,
+                   const int64_t* off, const int64_t* total, const int32_t* kcol, double* tM,
+                   double* tP, BigList big, const Seg& seg, DevState* st, Tile small,
+                   Tile large, hipStream_t s);
+
+// global cap: exact (b+1)-th largest magnitude among the candidates in X.nxt()
+template <typename T>
+void launch_global_select(Pair<T> X, int exclude_diag, int64_t m, double eta, int which,
+                          unsigned long long* hist, unsigned long long* selbuf, int64_t n,
+                          DevState* st, hipStream_t s);
+
+// keep rule + in-place compaction of the candidates in X.nxt();
+// kind 0: M (diagonal kept), 1: P (column threshold tcol[j]), 2: P^T (tcol[row])
+template <typename T>
+void launch_compact(Pair<T> X, int kind, int colcap, int sym, int global, const double* tcol,
+                    double eta, int64_t n, DevState* st, hipStream_t s);
+
+void launch_scal_step(int method, const Seg& seg, const double* red, DevState* st,
+                      hipStream_t s);
+void launch_scal_post(int method, const Seg& seg, const double* red, double tol, double* hist,
+                      int hist_cap, int setup, DevState* st, hipStream_t s);
+extern int g_grid_cols;   // persistent grid of the per-column kernels (multiple of 8)
+void launch_flip(int which, DevState* st, hipStream_t s);   // 0: curM, 1: curP
+
+}  // namespace spai

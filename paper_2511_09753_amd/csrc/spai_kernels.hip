@@ -1,0 +1,1315 @@
+// spai_kernels.hip — HIP kernels of the global SPAI iterations for gfx950.
+//
+// Method: Venkovic & Anzt, MR (Algorithm 1), CG with matrix iterates (Algorithm 3),
+// LOMR (Theorem 4.2, Algorithm 4), hard thresholding (Section 6.1), explicit residual
+// (Section 6.2) and the main-iterate drop steps of Appendix A.
+//
+// Storage: every iterate is column-compressed with padded columns (see Cols): column
+// j is an independent unit of f(M) = sum_j ||e_j - A m_j||^2 (Section 2), so each
+// per-column kernel gives one column to one 64-lane wavefront and keeps that column's
+// working set (input lists, hash set of output rows, sorted keys) in LDS.  A is
+// symmetric, so row k of A is also column k.
+//
+// Determinism: no floating-point atomics.  Every output value is a sum taken in a
+// fixed order (ascending row index of A's row, or of the key set), every per-column
+// Frobenius partial is a fixed-tree wave sum, and the cross-column reductions run
+// in a fixed order (launch_reduce).  The set of keys in the LDS hash is independent
+// of insertion order and is sorted before use.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "spai_dev.hpp"
+#include "spai_kern.hpp"
+
+namespace spai {
+
+__device__ __forceinline__ double aval(const Csr& A, int64_t q) {
+  return A.val32 ? (double)A.val32[q] : A.val[q];
+}
+
+// 8-byte aligned carve-up of the dynamic LDS of a per-column kernel
+struct Carve {
+  char* p;
+  __device__ explicit Carve(char* base) : p(base) {}
+  template <typename U> __device__ U* take(int count) {
+    uintptr_t a = ((uintptr_t)p + 7) & ~(uintptr_t)7;
+    U* r = (U*)a;
+    p = (char*)(a + sizeof(U) * (size_t)count);
+    return r;
+  }
+};
+
+// Degree prefix of the rows rows[0..cnt): pre[e] = sum_{f<=e} deg(rows[f]); returns the total.
+__device__ inline int degree_prefix(const Csr& A, const int* rows, int cnt, int* pre) {
+  const int lane = lane_id();
+  int run = 0;
+  for (int base = 0; base < cnt; base += SPAI_WAVE) {
+    const int e = base + lane;
+    int d = 0;
+    if (e < cnt) {
+      const int l = rows[e];
+      d = (int)(A.rowptr[l + 1] - A.rowptr[l]);
+    }
+    const int inc = wave_incl_scan(d);
+    if (e < cnt) pre[e] = run + inc;
+    run += __shfl(inc, SPAI_WAVE - 1, SPAI_WAVE);
+  }
+  return run;
+}
+
+// Insert the column index of every nonzero of the rows rows[0..cnt) of A into the key set.
+__device__ inline void insert_products(const Csr& A, const int* rows, int cnt, const int* pre,
+                                       int total, int* keys, int H) {
+  for (int p = lane_id(); p < total; p += SPAI_WAVE) {
+    const int e = upper_bound_int(pre, cnt, p);
+    const int before = e ? pre[e - 1] : 0;
+    const int64_t q = A.rowptr[rows[e]] + (p - before);
+    ks_insert(keys, H, A.col[q]);
+  }
+}
+
+// ============================================================================
+// small utilities: exclusive scan, fixed-order reductions
+// ============================================================================
+
+// counters are cleared by a kernel, never by a memset node, so that the
+// iteration sequence can be captured in a HIP graph
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline int64_t block_excl_scan_i64(int64_t v, int64_t* sh, int64_t* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int d = 1; d < (int)blockDim.x; d <<= 1) {
+    int64_t add = (t >= d) ? sh[t - d] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  int64_t incl = sh[t];
+  *total = sh[blockDim.x - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int64_t* in, int64_t* out,
+                                                             int64_t n, int64_t* tile_sums) {
+  __shared__ int64_t sh[kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int64_t loc[kScanItems];
+  int64_t run = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t g = base + i;
+    const int64_t v = g < n ? in[g] : 0;
+    loc[i] = run;
+    run += v;
+  }
+  int64_t tot;
+  const int64_t off = block_excl_scan_i64(run, sh, &tot);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t g = base + i;
+    if (g < n) out[g] = off + loc[i];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(int64_t* tile_sums, int64_t ntiles,
+                                                    int64_t* total) {
+  __shared__ int64_t sh[1024];
+  const int per = (int)((ntiles + 1023) / 1024);
+  const int64_t b = (int64_t)threadIdx.x * per;
+  int64_t run = 0;
+  for (int i = 0; i < per; ++i)
+    if (b + i < ntiles) run += tile_sums[b + i];
+  int64_t tot;
+  const int64_t off = block_excl_scan_i64(run, sh, &tot);
+  int64_t acc = off;
+  for (int i = 0; i < per; ++i)
+    if (b + i < ntiles) {
+      const int64_t v = tile_sums[b + i];
+      tile_sums[b + i] = acc;
+      acc += v;
+    }
+  if (threadIdx.x == 0 && total) *total = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int64_t* out, int64_t n,
+                                                           const int64_t* tile_off) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  const int64_t add = tile_off[blockIdx.x];
+  for (int i = threadIdx.x; i < kScanTile; i += kScanThreads) {
+    const int64_t g = base + i;
+    if (g < n) out[g] += add;
+  }
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+void launch_scan(const int64_t* in, int64_t* out, int64_t* total, int64_t n, int64_t* tmp,
+                 hipStream_t s) {
+  const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in, out, n,
+                     tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, tmp, ntiles, total);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, out, n, tmp);
+}
+
+// ---- fixed-order reduction of per-column partials ---------------------------
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+
+// one block per chunk of columns (single segment) or per segment (batched)
+__global__ __launch_bounds__(kRedThreads) void k_reduce_chunks(const double* colpart, int nd,
+                                                               int64_t n, int64_t chunk,
+                                                               const int64_t* seg_beg,
+                                                               double* out) {
+  __shared__ double sh[kRedThreads];
+  int64_t lo, hi;
+  if (seg_beg) {
+    lo = seg_beg[blockIdx.x];
+    hi = seg_beg[blockIdx.x + 1];
+  } else {
+    lo = (int64_t)blockIdx.x * chunk;
+    hi = lo + chunk < n ? lo + chunk : n;
+  }
+  for (int d = 0; d < nd; ++d) {
+    double acc = 0.0;
+    for (int64_t j = lo + threadIdx.x; j < hi; j += kRedThreads) acc += colpart[j * nd + d];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * nd + d] = sh[0];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* part, int nd,
+                                                              int nparts, double* out) {
+  __shared__ double sh[kRedThreads];
+  for (int d = 0; d < nd; ++d) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kRedThreads) acc += part[(int64_t)b * nd + d];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[d] = sh[0];
+    __syncthreads();
+  }
+}
+
+void launch_reduce(const double* colpart, int nd, int64_t n, const Seg& seg,
+                   const int64_t* seg_beg, double* red, double* blockpart, hipStream_t s) {
+  if (seg.nseg > 1) {
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(seg.nseg), dim3(kRedThreads), 0, s, colpart, nd, n,
+                       (int64_t)0, seg_beg, red);
+    return;
+  }
+  const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
+  const int nb = (int)((n + chunk - 1) / chunk);
+  hipLaunchKernelGGL(k_reduce_chunks, dim3(nb), dim3(kRedThreads), 0, s, colpart, nd, n, chunk,
+                     (const int64_t*)nullptr, blockpart);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, s, blockpart, nd, nb, red);
+}
+
+// ============================================================================
+// setup: traces, M_0 = c I
+// ============================================================================
+
+// per row k: a_kk and sum_l a_kl^2 (tr A and tr A^2 = ||A||_F^2 for symmetric A)
+__global__ void k_trace_parts(Csr A, double* colpart) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= A.n) return;
+  double d = 0.0, s2 = 0.0;
+  for (int64_t q = A.rowptr[k]; q < A.rowptr[k + 1]; ++q) {
+    const double v = A.val[q];
+    if (A.col[q] == k) d = v;
+    s2 += v * v;
+  }
+  colpart[2 * k] = d;
+  colpart[2 * k + 1] = s2;
+}
+
+void launch_trace_parts(const Csr& A, double* colpart, hipStream_t s) {
+  hipLaunchKernelGGL(k_trace_parts, dim3((unsigned)((A.n + 255) / 256)), dim3(256), 0, s, A,
+                     colpart);
+}
+
+// c = tr A / tr A^2 per segment; segment bookkeeping
+__global__ void k_init_state(Seg seg, const double* red_tr, const int64_t* seg_beg, int64_t n,
+                             double* cvec, int method, DevState* st) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < seg.nseg) {
+    SegState& g = seg.st[s];
+    cvec[s] = red_tr[2 * s] / red_tr[2 * s + 1];
+    const int64_t ns = seg_beg ? seg_beg[s + 1] - seg_beg[s] : n;
+    g.inv_sqrt_n = 1.0 / sqrt((double)ns);
+    g.rr = 0.0;
+    g.last_resid = 0.0;
+    for (int d = 0; d < kND; ++d) g.dots[d] = 0.0;
+    g.coef[0] = g.coef[1] = g.coef[2] = g.coef[3] = 0.0;
+    g.step1 = g.step2 = 0.0;
+    g.iters = 0;
+    g.stop = 0;
+    g.status = 0;
+    g.first = (method == kLOMR) ? 1 : 0;
+    g.mr_fallbacks = 0;
+  }
+  if (s == 0) {
+    st->any_active = 1;
+    st->err = 0;
+    st->curM = 0;
+    st->curP = 0;
+    st->iter_active = 1;
+  }
+}
+
+void launch_init_state(const Seg& seg, const double* red_tr, const int64_t* seg_beg, int64_t n,
+                       double* cvec, int method, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_state, dim3((seg.nseg + 255) / 256), dim3(256), 0, s, seg, red_tr,
+                     seg_beg, n, cvec, method, st);
+}
+
+template <typename T>
+__global__ void k_init_m(int64_t n, Cols<T> M, const double* cvec, Seg seg) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  M.beg[j] = j;
+  M.len[j] = 1;
+  M.idx[j] = (int32_t)j;
+  M.val[j] = (T)cvec[seg.segof(j)];
+}
+
+template <typename T>
+void launch_init_m(int64_t n, Cols<T> M, const double* cvec, const Seg& seg, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_m<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, M, cvec,
+                     seg);
+}
+
+template <typename T>
+__global__ void k_zero_cols(int64_t n, Cols<T> X) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  X.beg[j] = 0;
+  X.len[j] = 0;
+}
+
+template <typename T>
+void launch_zero_cols(int64_t n, Cols<T> X, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_cols<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, X);
+}
+
+// ============================================================================
+// R = I - A M (explicit residual, Section 6.2) with ||r_j||^2 per column
+// ============================================================================
+
+// upper bound of nnz(r_j): 1 + sum_{l in supp(m_j)} deg(l)
+template <typename T>
+__global__ void k_bound_resid(Csr A, Pair<T> Mp, int64_t* ub, int64_t n, const DevState* st) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  if (!st->any_active) return;
+  const Cols<T> M = Mp.now();
+  const int64_t b = M.beg[j];
+  const int lm = M.len[j];
+  int64_t s = 1;
+  for (int e = 0; e < lm; ++e) {
+    const int l = M.idx[b + e];
+    s += A.rowptr[l + 1] - A.rowptr[l];
+  }
+  ub[j] = s;
+}
+
+template <typename T>
+void launch_bound_resid(const Csr& A, Pair<T> M, int64_t* ub, int64_t n, const DevState* st,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_bound_resid<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, M,
+                     ub, n, st);
+}
+
+template <typename T>
+__global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> R,
+                                                     const int64_t* off, const int64_t* total,
+                                                     double* colnorm, BigList big, DevState* st,
+                                                     int tier, int L, int H) {
+  if (!st->any_active) return;
+  extern __shared__ char smem[];
+  Carve cv(smem);
+  int* s_mi = cv.take<int>(L);
+  int* s_pre = cv.take<int>(L);
+  int* s_keys = cv.take<int>(H);
+  int* s_sorted = cv.take<int>(H);
+  double* s_mv = cv.take<double>(L);
+  const int lane = lane_id();
+  const Cols<T> M = Mp.now();
+  const bool overflow = *total > R.cap;
+
+  auto body = [&](int64_t j) {
+    const int64_t mb = M.beg[j];
+    const int lm = M.len[j];
+    if (lm > L) {
+      if (tier == 0) {
+        if (lane == 0) big.list[atomicAdd(big.count, 1)] = (int)j;
+      } else if (lane == 0) {
+        atomicOr(&st->err, 1);
+      }
+      return;
+    }
+    for (int e = lane; e < lm; e += SPAI_WAVE) {
+      s_mi[e] = M.idx[mb + e];
+      s_mv[e] = (double)M.val[mb + e];
+    }
+    __syncthreads();
+    const int tot = degree_prefix(A, s_mi, lm, s_pre);
+    if (tot + 1 >= H) {            // keys must stay below the slot count
+      if (tier == 0) {
+        if (lane == 0) big.list[atomicAdd(big.count, 1)] = (int)j;
+      } else if (lane == 0) {
+        atomicOr(&st->err, 1);
+      }
+      __syncthreads();
+      return;
+    }
+    if (overflow) {
+      if (lane == 0) atomicOr(&st->err, 2);
+      __syncthreads();
+      return;
+    }
+    ks_clear(s_keys, H);
+    __syncthreads();
+    if (lane == 0) ks_insert(s_keys, H, (int)j);
+    insert_products(A, s_mi, lm, s_pre, tot, s_keys, H);
+    __syncthreads();
+    const int nu = ks_sorted(s_keys, H, s_sorted);
+    __syncthreads();
+    const int64_t ob = off[j];
+    double acc = 0.0;
+    for (int t = lane; t < nu; t += SPAI_WAVE) {
+      const int u = s_sorted[t];
+      double sum = 0.0;
+      for (int64_t q = A.rowptr[u]; q < A.rowptr[u + 1]; ++q) {
+        const int e = bsearch_idx(s_mi, lm, A.col[q]);
+        if (e >= 0) sum += aval(A, q) * s_mv[e];
+      }
+      const double r = ((u == (int)j) ? 1.0 : 0.0) - sum;
+      const T rt = (T)r;
+      R.idx[ob + t] = u;
+      R.val[ob + t] = rt;
+      acc += (double)rt * (double)rt;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      colnorm[j] = acc;
+      R.beg[j] = ob;
+      R.len[j] = nu;
+    }
+    __syncthreads();
+  };
+
+  if (tier == 0) {
+    ColumnWalk w(A.n, blockIdx.x, gridDim.x);
+    for (int64_t j = w.begin; j < w.end; j += w.step) body(j);
+  } else {
+    const int cnt = *big.count;
+    for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list[t]);
+  }
+}
+
+static size_t resid_lds(Tile t) {
+  return (size_t)t.L * 4 * 2 + (size_t)t.H * 4 * 2 + (size_t)t.L * 8 + 64;
+}
+
+int g_grid_cols = 2048;   // persistent grid of the per-column kernels (multiple of 8)
+
+template <typename T>
+void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const int64_t* total,
+                  double* colnorm, BigList big, DevState* st, Tile small, Tile large,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
+  hipLaunchKernelGGL(k_resid<T>, dim3(g_grid_cols), dim3(SPAI_WAVE), resid_lds(small), s, A, M, R,
+                     off, total, colnorm, big, st, 0, small.L, small.H);
+  hipLaunchKernelGGL(k_resid<T>, dim3(256), dim3(SPAI_WAVE), resid_lds(large), s, A, M, R, off,
+                     total, colnorm, big, st, 1, large.L, large.H);
+}
+
+// ============================================================================
+// SpGEMM fused with Frobenius dots: A r_j and A p_j in LDS, never stored
+// ============================================================================
+
+template <typename T>
+__global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp, int useR,
+                                                    int useP, double* colpart, BigList big,
+                                                    DevState* st, int tier, int L, int H) {
+  if (!st->any_active || !st->iter_active) return;
+  extern __shared__ char smem[];
+  Carve cv(smem);
+  int* s_li = cv.take<int>(L);
+  int* s_pre = cv.take<int>(L);
+  int* s_keys = cv.take<int>(H);
+  int* s_sorted = cv.take<int>(H);
+  double* s_lv = cv.take<double>(L);
+  const int lane = lane_id();
+  const Cols<T> P = Pp.now();
+
+  auto body = [&](int64_t j) {
+    const int lr = useR ? R.len[j] : 0;
+    const int lp = useP ? P.len[j] : 0;
+    if (lr + lp > L) {
+      if (tier == 0) {
+        if (lane == 0) big.list[atomicAdd(big.count, 1)] = (int)j;
+      } else if (lane == 0) {
+        atomicOr(&st->err, 1);
+      }
+      return;
+    }
+    const int64_t rb = useR ? R.beg[j] : 0;
+    const int64_t pb = useP ? P.beg[j] : 0;
+    for (int e = lane; e < lr; e += SPAI_WAVE) {
+      s_li[e] = R.idx[rb + e];
+      s_lv[e] = (double)R.val[rb + e];
+    }
+    for (int e = lane; e < lp; e += SPAI_WAVE) {
+      s_li[lr + e] = P.idx[pb + e];
+      s_lv[lr + e] = (double)P.val[pb + e];
+    }
+    __syncthreads();
+    const int tot = degree_prefix(A, s_li, lr + lp, s_pre);
+    if (tot + 1 >= H) {
+      if (tier == 0) {
+        if (lane == 0) big.list[atomicAdd(big.count, 1)] = (int)j;
+      } else if (lane == 0) {
+        atomicOr(&st->err, 1);
+      }
+      __syncthreads();
+      return;
+    }
+    ks_clear(s_keys, H);
+    __syncthreads();
+    insert_products(A, s_li, lr + lp, s_pre, tot, s_keys, H);
+    __syncthreads();
+    const int nu = ks_sorted(s_keys, H, s_sorted);
+    __syncthreads();
+    const int* ri = s_li;
+    const double* rv = s_lv;
+    const int* pi = s_li + lr;
+    const double* pv = s_lv + lr;
+    double d0 = 0, d1 = 0, d2 = 0, d3 = 0, d4 = 0, d5 = 0;
+    for (int t = lane; t < nu; t += SPAI_WAVE) {
+      const int u = s_sorted[t];
+      double ar = 0.0, ap = 0.0;
+      for (int64_t q = A.rowptr[u]; q < A.rowptr[u + 1]; ++q) {
+        const int l = A.col[q];
+        const double a = aval(A, q);
+        if (lr) {
+          const int e = bsearch_idx(ri, lr, l);
+          if (e >= 0) ar += a * rv[e];
+        }
+        if (lp) {
+          const int e = bsearch_idx(pi, lp, l);
+          if (e >= 0) ap += a * pv[e];
+        }
+      }
+      double ru = 0.0, pu = 0.0;
+      if (lr) {
+        const int e = bsearch_idx(ri, lr, u);
+        if (e >= 0) ru = rv[e];
+      }
+      if (lp) {
+        const int e = bsearch_idx(pi, lp, u);
+        if (e >= 0) pu = pv[e];
+      }
+      d0 += ru * ar;
+      d1 += ar * ar;
+      d2 += ar * ap;
+      d3 += ru * ap;
+      d4 += ap * ap;
+      d5 += pu * ap;
+    }
+    d0 = wave_sum(d0);
+    d1 = wave_sum(d1);
+    d2 = wave_sum(d2);
+    d3 = wave_sum(d3);
+    d4 = wave_sum(d4);
+    d5 = wave_sum(d5);
+    if (lane == 0) {
+      double* o = colpart + j * kND;
+      o[0] = d0; o[1] = d1; o[2] = d2; o[3] = d3; o[4] = d4; o[5] = d5;
+    }
+    __syncthreads();
+  };
+
+  if (tier == 0) {
+    ColumnWalk w(A.n, blockIdx.x, gridDim.x);
+    for (int64_t j = w.begin; j < w.end; j += w.step) body(j);
+  } else {
+    const int cnt = *big.count;
+    for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list[t]);
+  }
+}
+
+static size_t dots_lds(Tile t) {
+  return (size_t)t.L * 4 * 2 + (size_t)t.H * 4 * 2 + (size_t)t.L * 8 + 64;
+}
+
+template <typename T>
+void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, double* colpart,
+                 BigList big, DevState* st, Tile small, Tile large, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
+  hipLaunchKernelGGL(k_dots<T>, dim3(g_grid_cols), dim3(SPAI_WAVE), dots_lds(small), s, A, R, P,
+                     useR, useP, colpart, big, st, 0, small.L, small.H);
+  hipLaunchKernelGGL(k_dots<T>, dim3(256), dim3(SPAI_WAVE), dots_lds(large), s, A, R, P, useR,
+                     useP, colpart, big, st, 1, large.L, large.H);
+}
+
+// ============================================================================
+// merge (SpGEAM) + symmetrize + small-entry drop + per-column thresholds
+// ============================================================================
+//
+// Column j of the candidates:
+//   x  = (m_j + a1 X1(:,j)) + a2 X2(:,j)           (M_i + alpha R_i, M_i + alpha P_i or
+//                                                   M_i + delta R_i + gamma P_{i-1})
+//   y  = (m_j + a1 X1^T(:,j)) + a2 X2^T(:,j)       (row j of the same sum)
+//   M candidate = (x + y) / 2                      (Appendix A step 1)
+//   P candidate = c1 R(:,j) + c2 P(:,j), and the same from R^T, P^T for P^T.
+// R^T(:,j) = e_j - M a_j is recomputed from the neighbour columns m_l, l in N(j):
+// with M and A exactly symmetric and both sums taken over l ascending, it equals
+// the transposed R bitwise, so the symmetrized M is exactly symmetric and the P^T
+// candidates are exactly the transposed P candidates.
+
+// upper bound of the union of the lists of column j
+template <typename T>
+__global__ void k_bound_update(Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp, Pair<T> PTp, UpdMode md,
+                               int64_t* ub, int64_t n, const DevState* st) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  if (!st->any_active || !st->iter_active) return;
+  const Cols<T> M = Mp.now();
+  const Cols<T> P = Pp.now();
+  const Cols<T> PT = PTp.now();
+  const bool needR = (md.doM && (md.x1 == 1 || md.x2 == 1)) || (md.doP && md.pR);
+  const bool needP = (md.doM && (md.x1 == 2 || md.x2 == 2)) || (md.doP && md.pP);
+  const bool mirror = md.sym != 0;   // R^T, P^T serve only the symmetrization
+  int64_t s = 1;
+  if (md.doM) s += M.len[j];
+  if (needR) s += R.len[j];
+  if (needP) s += P.len[j];
+  if (needP && mirror) s += PT.len[j];
+  if (needR && mirror)
+    for (int64_t q = A.rowptr[j]; q < A.rowptr[j + 1]; ++q) s += M.len[A.col[q]];
+  ub[j] = s;
+}
+
+template <typename T>
+void launch_bound_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, UpdMode md,
+                         int64_t* ub, int64_t n, const DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_bound_update<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, M,
+                     R, P, PT, md, ub, n, st);
+}
+
+// (b+1)-th largest of the magnitudes v[0..cnt) in LDS (0 if cnt <= b), same on all lanes
+__device__ inline double kth_largest(const double* v, int cnt, int b) {
+  double t = 0.0;
+  if (cnt > b) {
+    for (int e = lane_id(); e < cnt; e += SPAI_WAVE) {
+      const double x = v[e];
+      int r = 0;
+      for (int f = 0; f < cnt; ++f) {
+        const double y = v[f];
+        r += (y > x) || (y == x && f < e);
+      }
+      if (r == b) t = x;
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) t = fmax(t, __shfl_xor(t, d, SPAI_WAVE));
+  return t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp,
+                                                      Pair<T> PTp, UpdMode md, const int64_t* off,
+                                                      const int64_t* total, const int32_t* kcol,
+                                                      double* tM, double* tP, BigList big,
+                                                      Seg seg, DevState* st, int tier, int L,
+                                                      int H, int DG) {
+  if (!st->any_active || !st->iter_active) return;
+  extern __shared__ char smem[];
+  Carve cv(smem);
+  int* s_li = cv.take<int>(L);
+  int* s_keys = cv.take<int>(H);        // reused for M candidate magnitudes (H/2 doubles)
+  int* s_sorted = cv.take<int>(H);
+  int* s_nbcol = cv.take<int>(DG);
+  int* s_nboff = cv.take<int>(DG + 1);
+  double* s_lv = cv.take<double>(L);
+  double* s_nbval = cv.take<double>(DG);
+  double* s_candP = cv.take<double>(H / 2);
+  double* s_candM = (double*)s_keys;
+  const int lane = lane_id();
+
+  const Cols<T> M = Mp.now();
+  const Cols<T> Mo = Mp.nxt();
+  const Cols<T> P = Pp.now();
+  const Cols<T> Po = Pp.nxt();
+  const Cols<T> PT = PTp.now();
+  const Cols<T> PTo = PTp.nxt();
+  const bool needR = (md.doM && (md.x1 == 1 || md.x2 == 1)) || (md.doP && md.pR);
+  const bool needP = (md.doM && (md.x1 == 2 || md.x2 == 2)) || (md.doP && md.pP);
+  const bool mirror = md.sym != 0;   // R^T, P^T serve only the symmetrization
+  const bool needRT = needR && mirror;
+  const bool needPT = needP && mirror;
+  const bool overflow = *total > Mo.cap || (md.doP && (*total > Po.cap || *total > PTo.cap));
+
+  auto body = [&](int64_t j) {
+    const SegState& g = seg.st[seg.segof(j)];
+    const double a1 = g.coef[0], a2 = g.coef[1], c1 = g.coef[2], c2 = g.coef[3];
+    // ---- sizes and fit test
+    const int lm = md.doM ? M.len[j] : 0;
+    const int lr = needR ? R.len[j] : 0;
+    const int lp = needP ? P.len[j] : 0;
+    const int lpt = needPT ? PT.len[j] : 0;
+    const int64_t qa = A.rowptr[j];
+    const int deg = needRT ? (int)(A.rowptr[j + 1] - qa) : 0;
+    int nbtot = 0;
+    for (int t = lane; t < deg; t += SPAI_WAVE) nbtot += M.len[A.col[qa + t]];
+    nbtot = wave_sum_int(nbtot);
+    const int ltot = lm + lr + lp + lpt + nbtot;
+    if (ltot > L || ltot + 2 >= H / 2 || deg > DG) {
+      if (tier == 0) {
+        if (lane == 0) big.list[atomicAdd(big.count, 1)] = (int)j;
+      } else if (lane == 0) {
+        atomicOr(&st->err, 1);
+      }
+      return;
+    }
+    if (overflow) {
+      if (lane == 0) atomicOr(&st->err, 2);
+      return;
+    }
+    // ---- load the lists: m_j | r_j | p_j | pT_j | m_l for l in N(j)
+    const int om = 0, orr = lm, op = lm + lr, opt = lm + lr + lp, onb = lm + lr + lp + lpt;
+    {
+      const int64_t b = md.doM ? M.beg[j] : 0;
+      for (int e = lane; e < lm; e += SPAI_WAVE) {
+        s_li[om + e] = M.idx[b + e];
+        s_lv[om + e] = (double)M.val[b + e];
+      }
+    }
+    if (lr) {
+      const int64_t b = R.beg[j];
+      for (int e = lane; e < lr; e += SPAI_WAVE) {
+        s_li[orr + e] = R.idx[b + e];
+        s_lv[orr + e] = (double)R.val[b + e];
+      }
+    }
+    if (lp) {
+      const int64_t b = P.beg[j];
+      for (int e = lane; e < lp; e += SPAI_WAVE) {
+        s_li[op + e] = P.idx[b + e];
+        s_lv[op + e] = (double)P.val[b + e];
+      }
+    }
+    if (lpt) {
+      const int64_t b = PT.beg[j];
+      for (int e = lane; e < lpt; e += SPAI_WAVE) {
+        s_li[opt + e] = PT.idx[b + e];
+        s_lv[opt + e] = (double)PT.val[b + e];
+      }
+    }
+    if (deg) {
+      // neighbour offsets (prefix of their lengths), then their entries
+      int run = 0;
+      for (int base = 0; base < deg; base += SPAI_WAVE) {
+        const int t = base + lane;
+        int len = 0;
+        if (t < deg) {
+          const int l = A.col[qa + t];
+          len = M.len[l];
+          s_nbcol[t] = l;
+          s_nbval[t] = aval(A, qa + t);
+        }
+        const int inc = wave_incl_scan(len);
+        if (t < deg) s_nboff[t] = onb + run + inc - len;
+        run += __shfl(inc, SPAI_WAVE - 1, SPAI_WAVE);
+      }
+      if (lane == 0) s_nboff[deg] = onb + run;
+      __syncthreads();
+      for (int t = 0; t < deg; ++t) {
+        const int l = s_nbcol[t];
+        const int64_t b = M.beg[l];
+        const int len = M.len[l];
+        const int o = s_nboff[t];
+        for (int e = lane; e < len; e += SPAI_WAVE) {
+          s_li[o + e] = M.idx[b + e];
+          s_lv[o + e] = (double)M.val[b + e];
+        }
+      }
+    }
+    __syncthreads();
+    // ---- key union
+    ks_clear(s_keys, H);
+    __syncthreads();
+    if (lane == 0) ks_insert(s_keys, H, (int)j);
+    for (int e = lane; e < ltot; e += SPAI_WAVE) ks_insert(s_keys, H, s_li[e]);
+    __syncthreads();
+    const int nk = ks_sorted(s_keys, H, s_sorted);
+    __syncthreads();
+    // ---- values, candidates
+    const int64_t ob = off[j];
+    int cntM = 0, cntMo = 0, cntP = 0, cntPT = 0;
+    for (int base = 0; base < nk; base += SPAI_WAVE) {
+      const int t = base + lane;
+      const bool valid = t < nk;
+      const int k = valid ? s_sorted[t] : 0;
+      double mv = 0.0, rv = 0.0, rtv = 0.0, pv = 0.0, ptv = 0.0;
+      if (valid) {
+        if (lm) { const int e = bsearch_idx(s_li + om, lm, k); if (e >= 0) mv = s_lv[om + e]; }
+        if (lr) { const int e = bsearch_idx(s_li + orr, lr, k); if (e >= 0) rv = s_lv[orr + e]; }
+        if (lp) { const int e = bsearch_idx(s_li + op, lp, k); if (e >= 0) pv = s_lv[op + e]; }
+        if (lpt) { const int e = bsearch_idx(s_li + opt, lpt, k); if (e >= 0) ptv = s_lv[opt + e]; }
+        if (needRT) {
+          double sum = 0.0;
+          for (int t2 = 0; t2 < deg; ++t2) {
+            const int o = s_nboff[t2];
+            const int e = bsearch_idx(s_li + o, s_nboff[t2 + 1] - o, k);
+            if (e >= 0) sum += s_nbval[t2] * s_lv[o + e];
+          }
+          rtv = (double)(T)(((k == (int)j) ? 1.0 : 0.0) - sum);
+        }
+      }
+      // M candidate
+      bool keepM = false, offM = false;
+      T mt = (T)0;
+      if (md.doM) {
+        const double v1 = md.x1 == 1 ? rv : (md.x1 == 2 ? pv : 0.0);
+        const double v2 = md.x2 == 1 ? rv : (md.x2 == 2 ? pv : 0.0);
+        const double x = (mv + a1 * v1) + a2 * v2;
+        double sv = x;
+        if (md.sym) {
+          const double w1 = md.x1 == 1 ? rtv : (md.x1 == 2 ? ptv : 0.0);
+          const double w2 = md.x2 == 1 ? rtv : (md.x2 == 2 ? ptv : 0.0);
+          const double y = (mv + a1 * w1) + a2 * w2;
+          sv = (x + y) * 0.5;
+        }
+        mt = (T)sv;
+        const double sd = (double)mt;
+        keepM = valid && sd != 0.0 && (k == (int)j || fabs(sd) >= md.u);
+        offM = keepM && k != (int)j;
+      }
+      // P and P^T candidates
+      bool keepP = false, keepPT = false;
+      T pt = (T)0, ptt = (T)0;
+      if (md.doP) {
+        const double x = (md.pR ? c1 * rv : 0.0) + (md.pP ? c2 * pv : 0.0);
+        const double y = (md.pR ? c1 * rtv : 0.0) + (md.pP ? c2 * ptv : 0.0);
+        pt = (T)x;
+        ptt = (T)y;
+        keepP = valid && (double)pt != 0.0;
+        keepPT = valid && (double)ptt != 0.0;
+      }
+      const unsigned long long bm = __ballot(keepM);
+      const unsigned long long bmo = __ballot(offM);
+      const unsigned long long bp = __ballot(keepP);
+      const unsigned long long bpt = __ballot(keepPT);
+      const unsigned long long lt = lanemask_lt();
+      if (keepM) {
+        const int64_t pos = ob + cntM + __popcll(bm & lt);
+        Mo.idx[pos] = k;
+        Mo.val[pos] = mt;
+      }
+      if (md.colcap && offM) s_candM[cntMo + __popcll(bmo & lt)] = fabs((double)mt);
+      if (keepP) {
+        const int64_t pos = ob + cntP + __popcll(bp & lt);
+        Po.idx[pos] = k;
+        Po.val[pos] = pt;
+        if (md.colcap) s_candP[cntP + __popcll(bp & lt)] = fabs((double)pt);
+      }
+      if (keepPT) {
+        const int64_t pos = ob + cntPT + __popcll(bpt & lt);
+        PTo.idx[pos] = k;
+        PTo.val[pos] = ptt;
+      }
+      cntM += __popcll(bm);
+      cntMo += __popcll(bmo);
+      cntP += __popcll(bp);
+      cntPT += __popcll(bpt);
+    }
+    __syncthreads();
+    if (lane == 0) {
+      if (md.doM) { Mo.beg[j] = ob; Mo.len[j] = cntM; }
+      if (md.doP) {
+        Po.beg[j] = ob; Po.len[j] = cntP;
+        PTo.beg[j] = ob; PTo.len[j] = cntPT;
+      }
+    }
+    if (md.colcap) {
+      const int k = kcol[j];
+      if (md.doM) {
+        const double t = kth_largest(s_candM, cntMo, k - 1);
+        if (lane == 0) tM[j] = t;
+      }
+      if (md.doP) {
+        const double t = kth_largest(s_candP, cntP, k);
+        if (lane == 0) tP[j] = t;
+      }
+    }
+    __syncthreads();
+  };
+
+  if (tier == 0) {
+    ColumnWalk w(A.n, blockIdx.x, gridDim.x);
+    for (int64_t j = w.begin; j < w.end; j += w.step) body(j);
+  } else {
+    const int cnt = *big.count;
+    for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list[t]);
+  }
+}
+
+static int update_deg(Tile t) { return t.L >= 2048 ? 512 : 64; }
+
+static size_t update_lds(Tile t) {
+  const int DG = update_deg(t);
+  return (size_t)t.L * 4 + (size_t)t.H * 4 * 2 + (size_t)DG * 4 * 2 + 4 + (size_t)t.L * 8 +
+         (size_t)DG * 8 + (size_t)(t.H / 2) * 8 + 64;
+}
+
+template <typename T>
+void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, UpdMode md,
+                   const int64_t* off, const int64_t* total, const int32_t* kcol, double* tM,
+                   double* tP, BigList big, const Seg& seg, DevState* st, Tile small, Tile large,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
+  hipLaunchKernelGGL(k_update<T>, dim3(g_grid_cols), dim3(SPAI_WAVE), update_lds(small), s, A, M,
+                     R, P, PT, md, off, total, kcol, tM, tP, big, seg, st, 0, small.L, small.H,
+                     update_deg(small));
+  hipLaunchKernelGGL(k_update<T>, dim3(256), dim3(SPAI_WAVE), update_lds(large), s, A, M, R, P,
+                     PT, md, off, total, kcol, tM, tP, big, seg, st, 1, large.L, large.H,
+                     update_deg(large));
+}
+
+// ============================================================================
+// global cap: exact (b+1)-th largest candidate magnitude by radix selection on the
+// bits of |x| (positive doubles order like their bit patterns)
+// ============================================================================
+
+constexpr int kSelThreads = 256;
+constexpr int kSelGrid = 1024;
+
+__device__ __forceinline__ unsigned long long mag_key(double v) {
+  return (unsigned long long)__double_as_longlong(fabs(v));
+}
+
+// exponent histogram (bits 62..52) of the candidates; counts diagonal entries apart
+template <typename T>
+__global__ __launch_bounds__(kSelThreads) void k_sel_hist_exp(Pair<T> Xp, int excl_diag,
+                                                              unsigned long long* hist, int64_t n,
+                                                              DevState* st) {
+  if (!st->any_active || !st->iter_active) return;
+  __shared__ unsigned int h[2048];
+  for (int i = threadIdx.x; i < 2048; i += kSelThreads) h[i] = 0;
+  __syncthreads();
+  const Cols<T> X = Xp.nxt();
+  const int wid = threadIdx.x / SPAI_WAVE;
+  const int lane = lane_id();
+  ColumnWalk w(n, (int64_t)wid * gridDim.x + blockIdx.x, (int64_t)gridDim.x * (kSelThreads / 64));
+  long long diag = 0;
+  for (int64_t j = w.begin; j < w.end; j += w.step) {
+    const int64_t b = X.beg[j];
+    const int len = X.len[j];
+    for (int e = lane; e < len; e += SPAI_WAVE) {
+      if (excl_diag && X.idx[b + e] == (int)j) { ++diag; continue; }
+      const unsigned long long key = mag_key((double)X.val[b + e]);
+      atomicAdd(&h[(int)(key >> 52)], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2048; i += kSelThreads)
+    if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
+  diag = wave_sum_ll(diag);
+  if (lane == 0 && diag) atomicAdd((unsigned long long*)&st->sel_diag, (unsigned long long)diag);
+}
+
+// find the exponent bin of the (b+1)-th largest; b = m - (diagonal count if excluded)
+__global__ void k_sel_find_exp(const unsigned long long* hist, int excl_diag, int64_t m,
+                               double* thr, DevState* st) {
+  if (!st->any_active || !st->iter_active) return;
+  if (threadIdx.x != 0) return;
+  long long total = 0;
+  for (int i = 0; i < 2048; ++i) total += (long long)hist[i];
+  const long long b = m - (excl_diag ? st->sel_diag : 0);
+  st->sel_count = 0;
+  if (b < 0) {                      // cap below the diagonal count: keep only the diagonal
+    st->sel_done = 1;
+    *thr = INFINITY;
+    return;
+  }
+  if (total <= b) {                  // |supp| within the cap: nothing to drop
+    st->sel_done = 1;
+    *thr = 0.0;
+    return;
+  }
+  long long acc = 0;
+  for (int i = 2047; i >= 0; --i) {
+    const long long c = (long long)hist[i];
+    if (acc + c >= b + 1) {
+      st->sel_prefix = (unsigned long long)i << 52;
+      st->sel_rank = (b + 1) - acc;
+      break;
+    }
+    acc += c;
+  }
+  st->sel_done = 0;
+}
+
+// gather the keys inside the selected exponent bin
+template <typename T>
+__global__ __launch_bounds__(kSelThreads) void k_sel_collect(Pair<T> Xp, int excl_diag,
+                                                             unsigned long long* selbuf,
+                                                             int64_t n, DevState* st) {
+  if (!st->any_active || !st->iter_active || st->sel_done) return;
+  const Cols<T> X = Xp.nxt();
+  const unsigned long long want = st->sel_prefix >> 52;
+  const int wid = threadIdx.x / SPAI_WAVE;
+  const int lane = lane_id();
+  ColumnWalk w(n, (int64_t)wid * gridDim.x + blockIdx.x, (int64_t)gridDim.x * (kSelThreads / 64));
+  for (int64_t j = w.begin; j < w.end; j += w.step) {
+    const int64_t b = X.beg[j];
+    const int len = X.len[j];
+    for (int base = 0; base < len; base += SPAI_WAVE) {
+      const int e = base + lane;
+      bool take = false;
+      unsigned long long key = 0;
+      if (e < len && !(excl_diag && X.idx[b + e] == (int)j)) {
+        key = mag_key((double)X.val[b + e]);
+        take = (key >> 52) == want;
+      }
+      const unsigned long long bal = __ballot(take);
+      if (bal) {
+        unsigned long long basepos = 0;
+        if (lane == 0) basepos = atomicAdd(&st->sel_count, (unsigned long long)__popcll(bal));
+        basepos = __shfl(basepos, 0, SPAI_WAVE);
+        if (take) selbuf[basepos + __popcll(bal & lanemask_lt())] = key;
+      }
+    }
+  }
+}
+
+// histogram of 13 key bits at `shift` among the collected keys matching the prefix above
+__global__ __launch_bounds__(kSelThreads) void k_sel_hist_buf(const unsigned long long* selbuf,
+                                                              int shift,
+                                                              unsigned long long* hist,
+                                                              DevState* st) {
+  if (!st->any_active || !st->iter_active || st->sel_done) return;
+  __shared__ unsigned int h[8192];
+  for (int i = threadIdx.x; i < 8192; i += kSelThreads) h[i] = 0;
+  __syncthreads();
+  const unsigned long long cnt = st->sel_count;
+  const int hi = shift + 13;
+  const unsigned long long pre = st->sel_prefix >> hi;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * kSelThreads + threadIdx.x; i < cnt;
+       i += (unsigned long long)gridDim.x * kSelThreads) {
+    const unsigned long long key = selbuf[i];
+    if ((key >> hi) == pre) atomicAdd(&h[(int)((key >> shift) & 8191ull)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 8192; i += kSelThreads)
+    if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
+}
+
+__global__ void k_sel_find_buf(const unsigned long long* hist, int shift, double eta,
+                               double* thr, DevState* st) {
+  if (!st->any_active || !st->iter_active || st->sel_done) return;
+  if (threadIdx.x != 0) return;
+  long long acc = 0;
+  const long long rank = st->sel_rank;
+  for (int i = 8191; i >= 0; --i) {
+    const long long c = (long long)hist[i];
+    if (acc + c >= rank) {
+      st->sel_prefix |= (unsigned long long)i << shift;
+      st->sel_rank = rank - acc;
+      break;
+    }
+    acc += c;
+  }
+  if (shift == 0) {
+    const double t = __longlong_as_double((long long)st->sel_prefix);
+    *thr = t * (1.0 + eta);
+    st->sel_done = 1;
+  }
+}
+
+__global__ void k_sel_reset(unsigned long long* hist, int nbins, DevState* st) {
+  for (int i = threadIdx.x; i < nbins; i += blockDim.x) hist[i] = 0;
+  if (threadIdx.x == 0) {
+    st->sel_diag = 0;
+    st->sel_count = 0;
+    st->sel_done = 0;
+  }
+}
+
+__global__ void k_hist_clear(unsigned long long* hist, int nbins, const DevState* st) {
+  if (st->sel_done) return;
+  for (int i = threadIdx.x; i < nbins; i += blockDim.x) hist[i] = 0;
+}
+
+template <typename T>
+void launch_global_select(Pair<T> X, int exclude_diag, int64_t m, double eta, int which,
+                          unsigned long long* hist, unsigned long long* selbuf, int64_t n,
+                          DevState* st, hipStream_t s) {
+  double* thr = which == 0 ? &st->thrM : &st->thrP;
+  hipLaunchKernelGGL(k_sel_reset, dim3(1), dim3(1024), 0, s, hist, 8192, st);
+  hipLaunchKernelGGL(k_sel_hist_exp<T>, dim3(kSelGrid), dim3(kSelThreads), 0, s, X, exclude_diag,
+                     hist, n, st);
+  hipLaunchKernelGGL(k_sel_find_exp, dim3(1), dim3(64), 0, s, hist, exclude_diag, m, thr, st);
+  hipLaunchKernelGGL(k_sel_collect<T>, dim3(kSelGrid), dim3(kSelThreads), 0, s, X, exclude_diag,
+                     selbuf, n, st);
+  for (int shift = 39; shift >= 0; shift -= 13) {
+    hipLaunchKernelGGL(k_hist_clear, dim3(1), dim3(1024), 0, s, hist, 8192, st);
+    hipLaunchKernelGGL(k_sel_hist_buf, dim3(256), dim3(kSelThreads), 0, s, selbuf, shift, hist,
+                       st);
+    hipLaunchKernelGGL(k_sel_find_buf, dim3(1), dim3(64), 0, s, hist, shift, eta, thr, st);
+  }
+}
+
+// ============================================================================
+// keep rule + in-place compaction
+// ============================================================================
+
+template <typename T>
+__global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int colcap, int sym,
+                                                       int global, const double* tcol,
+                                                       const double* gthr, double eta, int64_t n,
+                                                       DevState* st) {
+  if (!st->any_active || !st->iter_active) return;
+  const Cols<T> X = Xp.nxt();
+  const int lane = lane_id();
+  const double g = global ? *gthr : 0.0;
+  unsigned long long kept = 0;
+  ColumnWalk w(n, blockIdx.x, gridDim.x);
+  for (int64_t j = w.begin; j < w.end; j += w.step) {
+    const int64_t b = X.beg[j];
+    const int len = X.len[j];
+    const double tj = colcap ? tcol[j] : 0.0;
+    int cnt = 0;
+    for (int base = 0; base < len; base += SPAI_WAVE) {
+      const int e = base + lane;
+      bool keep = false;
+      int k = 0;
+      T v = (T)0;
+      if (e < len) {
+        k = X.idx[b + e];
+        v = X.val[b + e];
+        const double a = fabs((double)v);
+        if (kind == 0 && k == (int)j) {
+          keep = true;
+        } else if (global) {
+          keep = a > g;
+        } else if (colcap) {
+          double t = tj;
+          if (kind == 0 && sym) t = fmax(t, tcol[k]);
+          if (kind == 2) t = tcol[k];
+          keep = a > t * (1.0 + eta);
+        } else {
+          keep = true;
+        }
+      }
+      const unsigned long long bal = __ballot(keep);
+      if (keep) {
+        const int64_t pos = b + cnt + __popcll(bal & lanemask_lt());
+        X.idx[pos] = k;
+        X.val[pos] = v;
+      }
+      cnt += __popcll(bal);
+    }
+    if (lane == 0) X.len[j] = cnt;
+    kept += (unsigned long long)cnt;
+  }
+  if (lane == 0 && kept) {
+    unsigned long long* dst = (kind == 0) ? &st->nnz_m : (kind == 1 ? &st->nnz_p : nullptr);
+    if (dst) atomicAdd(dst, kept);
+  }
+}
+
+template <typename T>
+void launch_compact(Pair<T> X, int kind, int colcap, int sym, int global, const double* tcol,
+                    double eta, int64_t n, DevState* st, hipStream_t s) {
+  const double* gthr = kind == 0 ? &st->thrM : &st->thrP;
+  hipLaunchKernelGGL(k_compact<T>, dim3(g_grid_cols), dim3(SPAI_WAVE), 0, s, X, kind, colcap, sym,
+                     global, tcol, gthr, eta, n, st);
+}
+
+// ============================================================================
+// scalar steps (one thread per segment)
+// ============================================================================
+
+// step sizes from the reduced dots; decides whether this iteration runs
+__global__ void k_scal_step(int method, Seg seg, const double* red, DevState* st) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= seg.nseg) return;
+  SegState& g = seg.st[s];
+  const double* d = red + (int64_t)s * kND;
+  for (int i = 0; i < kND; ++i) g.dots[i] = d[i];
+  if (!g.stop) {
+    if (method == kMR) {
+      if (!(d[1] > 0.0)) {              // A R = 0: R = 0, converged
+        g.stop = 1;
+        g.status = 1;
+      } else {
+        const double alpha = d[0] / d[1];
+        g.coef[0] = alpha; g.coef[1] = 0.0; g.coef[2] = 0.0; g.coef[3] = 0.0;
+        g.step1 = alpha;
+        g.step2 = 0.0;
+      }
+    } else if (method == kCG) {
+      if (!(g.rr > 0.0)) {
+        g.stop = 1;
+        g.status = 1;
+      } else if (!(d[5] > 0.0)) {       // (P, A P) <= 0: A is not SPD, or P = 0
+        g.stop = 1;
+        g.status = 3;
+      } else {
+        const double alpha = g.rr / d[5];
+        g.coef[0] = alpha; g.coef[1] = 0.0;
+        g.step1 = alpha;
+      }
+    } else {  // LOMR (Theorem 4.2)
+      const double r_ar = d[0], ar_ar = d[1], ar_ap = d[2], r_ap = d[3], ap_ap = d[4];
+      if (!(ar_ar > 0.0)) {
+        g.stop = 1;
+        g.status = 1;
+      } else {
+        double delta, gamma;
+        if (g.first) {
+          delta = r_ar / ar_ar;
+          gamma = 1.0;
+          g.first = 0;
+        } else {
+          const double c = ar_ar * ap_ap - ar_ap * ar_ap;
+          if (!(c > 1e-14 * ar_ar * ap_ap)) {
+            delta = r_ar / ar_ar;
+            gamma = 0.0;
+            g.mr_fallbacks += 1;
+          } else {
+            delta = (ap_ap * r_ar - ar_ap * r_ap) / c;
+            gamma = (ar_ar * r_ap - ar_ap * r_ar) / c;
+          }
+        }
+        g.coef[0] = delta; g.coef[1] = gamma; g.coef[2] = delta; g.coef[3] = gamma;
+        g.step1 = delta;
+        g.step2 = gamma;
+      }
+    }
+  }
+  if (g.stop) {                         // carry a stopped matrix through unchanged
+    g.coef[0] = 0.0; g.coef[1] = 0.0; g.coef[2] = 0.0; g.coef[3] = 1.0;
+  }
+}
+
+// any segment still running -> the iteration runs
+__global__ void k_any_active(Seg seg, DevState* st) {
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int s = threadIdx.x; s < seg.nseg; s += blockDim.x)
+    if (!seg.st[s].stop) atomicOr(&any, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->iter_active = any;
+    st->any_active = any;
+    st->nnz_m = 0;
+    st->nnz_p = 0;
+  }
+}
+
+void launch_scal_step(int method, const Seg& seg, const double* red, DevState* st,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_scal_step, dim3((seg.nseg + 255) / 256), dim3(256), 0, s, method, seg, red,
+                     st);
+  hipLaunchKernelGGL(k_any_active, dim3(1), dim3(256), 0, s, seg, st);
+}
+
+// after R_{i+1}: record ||R||, test the stopping rule, CG's beta
+__global__ void k_scal_post(int method, Seg seg, const double* red, double tol, double* hist,
+                            int hist_cap, int setup, DevState* st) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= seg.nseg) return;
+  if (!st->iter_active) return;
+  SegState& g = seg.st[s];
+  const double rr_new = red[s];
+  const double rn = sqrt(rr_new);
+  if (setup) {                          // R_0: no iteration counted
+    g.rr = rr_new;
+    g.last_resid = rn;
+    g.coef[0] = 0.0; g.coef[1] = 0.0; g.coef[2] = 1.0; g.coef[3] = 0.0;   // CG: P_0 = R_0
+    if (tol > 0.0 && rn * g.inv_sqrt_n <= tol) { g.stop = 1; g.status = 1; }
+    return;
+  }
+  if (g.stop) return;
+  g.last_resid = rn;
+  if (hist && g.iters < hist_cap) hist[(int64_t)s * hist_cap + g.iters] = rn;
+  g.iters += 1;
+  if (method == kCG) {
+    const double beta = g.rr > 0.0 ? rr_new / g.rr : 0.0;
+    g.coef[2] = 1.0;
+    g.coef[3] = beta;
+    g.step2 = beta;
+  }
+  g.rr = rr_new;
+  if (tol > 0.0 && rn * g.inv_sqrt_n <= tol) {
+    g.stop = 1;
+    g.status = 1;
+  }
+}
+
+void launch_scal_post(int method, const Seg& seg, const double* red, double tol, double* hist,
+                      int hist_cap, int setup, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_scal_post, dim3((seg.nseg + 255) / 256), dim3(256), 0, s, method, seg, red,
+                     tol, hist, hist_cap, setup, st);
+}
+
+__global__ void k_flip(int which, DevState* st) {
+  if (!st->iter_active) return;
+  if (which == 0) st->curM ^= 1; else st->curP ^= 1;
+}
+
+void launch_flip(int which, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_flip, dim3(1), dim3(1), 0, s, which, st);
+}
+
+// ---- explicit instantiations
+#define SPAI_INST(T)                                                                               \
+  template void launch_init_m<T>(int64_t, Cols<T>, const double*, const Seg&, hipStream_t);       \
+  template void launch_zero_cols<T>(int64_t, Cols<T>, hipStream_t);                               \
+  template void launch_bound_resid<T>(const Csr&, Pair<T>, int64_t*, int64_t, const DevState*,    \
+                                      hipStream_t);                                               \
+  template void launch_resid<T>(const Csr&, Pair<T>, Cols<T>, const int64_t*, const int64_t*,    \
+                                double*, BigList, DevState*, Tile, Tile, hipStream_t);            \
+  template void launch_dots<T>(const Csr&, Cols<T>, Pair<T>, int, int, double*, BigList,          \
+                               DevState*, Tile, Tile, hipStream_t);                               \
+  template void launch_bound_update<T>(const Csr&, Pair<T>, Cols<T>, Pair<T>, Pair<T>, UpdMode,   \
+                                       int64_t*, int64_t, const DevState*, hipStream_t);          \
+  template void launch_update<T>(const Csr&, Pair<T>, Cols<T>, Pair<T>, Pair<T>, UpdMode,         \
+                                 const int64_t*, const int64_t*, const int32_t*, double*,         \
+                                 double*, BigList, const Seg&, DevState*, Tile, Tile,             \
+                                 hipStream_t);                                                    \
+  template void launch_global_select<T>(Pair<T>, int, int64_t, double, int, unsigned long long*,  \
+                                        unsigned long long*, int64_t, DevState*, hipStream_t);    \
+  template void launch_compact<T>(Pair<T>, int, int, int, int, const double*, double, int64_t,    \
+                                  DevState*, hipStream_t);
+
+SPAI_INST(double)
+SPAI_INST(float)
+
+}  // namespace spai

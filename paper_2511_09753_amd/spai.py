@@ -1,0 +1,368 @@
+"""Python binding of libspai: argument marshalling only.
+
+Every step of the method runs in the HIP library; this module turns scipy / torch
+matrices into the C structs of ``include/spai.h``, calls the entry point of the
+same name and raises :class:`SpaiError` on an error status.  It fails loudly when
+the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspai.so")
+
+SPAI_OK, SPAI_CONVERGED, SPAI_MAXITER, SPAI_BREAKDOWN, PCG_INDEFINITE = 0, 1, 2, 3, 4
+METHODS = {"mr": 0, "cg": 1, "lomr": 2}
+CAP_MODES = {"none": 0, "global": 1, "column": 2}
+PRECISIONS = {"f64": 0, "mixed": 1}
+
+
+class SpaiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class CsrT(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("colind", C.c_void_p), ("val", C.c_void_p), ("on_device", C.c_int)]
+
+
+class CsrOutT(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("capacity", C.c_int64),
+                ("rowptr", C.c_void_p), ("colind", C.c_void_p), ("val", C.c_void_p),
+                ("on_device", C.c_int)]
+
+
+class CapT(C.Structure):
+    _fields_ = [("mode", C.c_int), ("relative", C.c_int), ("value", C.c_double)]
+
+
+class OptsT(C.Structure):
+    _fields_ = [("precision", C.c_int), ("symmetrize", C.c_int), ("drop_tol", C.c_double),
+                ("tie_eta", C.c_double), ("stream", C.c_void_p),
+                ("device_pool_limit", C.c_int64)]
+
+
+EXPORTS = [
+    "spai_default_opts", "spai_create", "spai_iterate", "spai_get", "spai_stats",
+    "spai_destroy", "pcg_solve", "spai_loss_fwd", "spai_loss_bwd", "spai_create_batched",
+    "spai_batched_resid", "spai_last_error", "spai_status_string",
+]
+
+_lib = None
+
+
+def load():
+    """Load libspai.so (built by ``paper_2511_09753_amd.build``); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libspai.so is not built ({LIB_PATH}); run paper_2511_09753_amd/build.py")
+    # torch ships its own HIP runtime under the same soname; load it first so that
+    # libspai binds to that one and the process holds a single HIP runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    lib.spai_default_opts.argtypes = [C.POINTER(OptsT)]
+    lib.spai_default_opts.restype = None
+    lib.spai_create.argtypes = [C.POINTER(CsrT), C.c_int, CapT, C.c_int, C.c_double,
+                                C.POINTER(OptsT), C.POINTER(P)]
+    lib.spai_create_batched.argtypes = [C.POINTER(CsrT), C.c_int, C.c_int, CapT, C.c_int,
+                                        C.c_double, C.POINTER(OptsT), C.POINTER(P)]
+    lib.spai_iterate.argtypes = [P, C.c_int, C.POINTER(C.c_int), P]
+    lib.spai_get.argtypes = [P, C.POINTER(CsrOutT)]
+    lib.spai_stats.argtypes = [P, C.POINTER(C.c_int), C.POINTER(C.c_double),
+                               C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                               C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    lib.spai_destroy.argtypes = [P]
+    lib.spai_batched_resid.argtypes = [P, P]
+    lib.pcg_solve.argtypes = [C.POINTER(CsrT), C.POINTER(CsrT), C.c_int, P, P, C.c_double,
+                              C.c_int, P, P, C.POINTER(OptsT)]
+    lib.spai_loss_fwd.argtypes = [C.POINTER(CsrT), C.POINTER(CsrT), C.POINTER(C.c_double),
+                                  C.POINTER(OptsT)]
+    lib.spai_loss_bwd.argtypes = [C.POINTER(CsrT), C.POINTER(CsrT), C.c_double, P, P,
+                                  C.POINTER(OptsT)]
+    lib.spai_last_error.restype = C.c_char_p
+    lib.spai_status_string.restype = C.c_char_p
+    lib.spai_status_string.argtypes = [C.c_int]
+    for name in EXPORTS:
+        if name not in ("spai_default_opts", "spai_last_error", "spai_status_string"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc, allowed=(SPAI_OK,)):
+    if rc in allowed:
+        return rc
+    lib = load()
+    raise SpaiError(rc, f"{lib.spai_status_string(rc).decode()}: {lib.spai_last_error().decode()}")
+
+
+# ----------------------------------------------------------------------------
+# argument marshalling
+# ----------------------------------------------------------------------------
+
+class _Csr:
+    """Keeps the arrays of a CsrT alive for the duration of a call."""
+
+    def __init__(self, A):
+        import scipy.sparse as sp
+        self.keep = []
+        if _is_torch_csr(A):
+            rp = A.crow_indices().to(dtype=_torch().int64).contiguous()
+            ci = A.col_indices().to(dtype=_torch().int32).contiguous()
+            va = A.values().to(dtype=_torch().float64).contiguous()
+            self.keep = [rp, ci, va]
+            self.c = CsrT(A.shape[0], va.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr(),
+                          1 if A.is_cuda else 0)
+            self.device = A.is_cuda
+        else:
+            A = sp.csr_matrix(A)
+            rp = np.ascontiguousarray(A.indptr, dtype=np.int64)
+            ci = np.ascontiguousarray(A.indices, dtype=np.int32)
+            va = np.ascontiguousarray(A.data, dtype=np.float64)
+            self.keep = [rp, ci, va]
+            self.c = CsrT(A.shape[0], A.nnz, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, 0)
+            self.device = False
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _is_torch_csr(A):
+    try:
+        import torch
+    except ImportError:
+        return False
+    return isinstance(A, torch.Tensor) and A.layout == torch.sparse_csr
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return None
+    return C.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+@dataclass
+class Options:
+    precision: str = "f64"
+    symmetrize: bool = True
+    drop_tol: float = 2.0 ** -53
+    tie_eta: float = 1e-9
+    stream: object = None
+    device_pool_limit: int = 0
+
+    def c(self):
+        o = OptsT()
+        load().spai_default_opts(C.byref(o))
+        o.precision = PRECISIONS[self.precision]
+        o.symmetrize = 1 if self.symmetrize else 0
+        o.drop_tol = self.drop_tol
+        o.tie_eta = self.tie_eta
+        o.stream = _stream_ptr(self.stream)
+        o.device_pool_limit = int(self.device_pool_limit)
+        return o
+
+
+def cap(mode="none", value=0.0, relative=False):
+    return CapT(CAP_MODES[mode], 1 if relative else 0, float(value))
+
+
+# ----------------------------------------------------------------------------
+# entry points
+# ----------------------------------------------------------------------------
+
+class SPAI:
+    """Handle over ``spai_create`` / ``spai_iterate`` / ``spai_get`` / ``spai_destroy``."""
+
+    def __init__(self, A, method="lomr", cap_mode="none", cap_value=0.0, cap_relative=False,
+                 max_iter=100, tol=0.0, options: Options | None = None, batch=None):
+        lib = load()
+        self.options = options or Options()
+        self._opts = self.options.c()
+        h = C.c_void_p()
+        c = cap(cap_mode, cap_value, cap_relative)
+        if batch is None:
+            a = _Csr(A)
+            self.n = a.c.n
+            rc = lib.spai_create(C.byref(a.c), METHODS[method], c, int(max_iter), float(tol),
+                                 C.byref(self._opts), C.byref(h))
+            self.nseg = 1
+        else:
+            mats = [_Csr(x) for x in batch]
+            arr = (CsrT * len(mats))(*[m.c for m in mats])
+            self.n = sum(m.c.n for m in mats)
+            rc = lib.spai_create_batched(arr, len(mats), METHODS[method], c, int(max_iter),
+                                         float(tol), C.byref(self._opts), C.byref(h))
+            self.nseg = len(mats)
+        _check(rc)
+        self.h = h
+        self.method = method
+
+    def iterate(self, k):
+        """Run up to k iterations; returns (iterations run, residual history, status)."""
+        done = C.c_int(0)
+        hist = np.zeros(max(int(k), 1), dtype=np.float64)
+        rc = load().spai_iterate(self.h, int(k), C.byref(done), hist.ctypes.data)
+        _check(rc, (SPAI_OK, SPAI_CONVERGED, SPAI_BREAKDOWN))
+        return done.value, hist[: done.value].copy(), rc
+
+    def get(self):
+        """Current iterate M as scipy CSR (float64)."""
+        import scipy.sparse as sp
+        out = CsrOutT()
+        out.n = self.n
+        _check(load().spai_get(self.h, C.byref(out)))
+        nnz = out.nnz
+        rp = np.zeros(self.n + 1, dtype=np.int64)
+        ci = np.zeros(max(nnz, 1), dtype=np.int32)
+        va = np.zeros(max(nnz, 1), dtype=np.float64)
+        out.capacity = nnz
+        out.rowptr, out.colind, out.val = rp.ctypes.data, ci.ctypes.data, va.ctypes.data
+        out.on_device = 0
+        _check(load().spai_get(self.h, C.byref(out)))
+        return sp.csr_matrix((va[:nnz], ci[:nnz], rp), shape=(self.n, self.n))
+
+    def stats(self):
+        it, fb = C.c_int(), C.c_int()
+        res, s1, s2 = C.c_double(), C.c_double(), C.c_double()
+        nm, npp = C.c_int64(), C.c_int64()
+        _check(load().spai_stats(self.h, C.byref(it), C.byref(res), C.byref(nm), C.byref(npp),
+                                 C.byref(s1), C.byref(s2), C.byref(fb)))
+        return {"iters": it.value, "resid": res.value, "nnz_m": nm.value, "nnz_p": npp.value,
+                "step1": s1.value, "step2": s2.value, "mr_fallbacks": fb.value}
+
+    def batched_resid(self):
+        out = np.zeros(self.nseg, dtype=np.float64)
+        _check(load().spai_batched_resid(self.h, out.ctypes.data))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().spai_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pcg_solve(A, M, B, rtol=1e-8, max_iter=10000, options: Options | None = None):
+    """PCG with preconditioner M on every column of B (n x nrhs).
+
+    Host numpy B -> host X; a torch CUDA tensor B (with torch CSR A, M on the device)
+    -> a torch CUDA X.  Returns (X, iterations, true relative residuals, status).
+    """
+    lib = load()
+    opts = (options or Options()).c()
+    a, m = _Csr(A), _Csr(M)
+    torch_in = _is_torch_csr(A)
+    if torch_in:
+        torch = _torch()
+        Bt = B.to(dtype=torch.float64).contiguous()
+        if Bt.dim() == 1:
+            Bt = Bt[:, None]
+        X = torch.empty_like(Bt)
+        nrhs = Bt.shape[1]
+        bptr, xptr = Bt.data_ptr(), X.data_ptr()
+    else:
+        Bn = np.ascontiguousarray(B, dtype=np.float64)
+        if Bn.ndim == 1:
+            Bn = Bn[:, None]
+        X = np.zeros_like(Bn)
+        nrhs = Bn.shape[1]
+        bptr, xptr = Bn.ctypes.data, X.ctypes.data
+    iters = np.zeros(nrhs, dtype=np.int32)
+    relres = np.zeros(nrhs, dtype=np.float64)
+    rc = lib.pcg_solve(C.byref(a.c), C.byref(m.c), int(nrhs), bptr, xptr, float(rtol),
+                       int(max_iter), iters.ctypes.data, relres.ctypes.data, C.byref(opts))
+    _check(rc, (SPAI_OK, SPAI_MAXITER, PCG_INDEFINITE))
+    return X, iters, relres, rc
+
+
+def loss_fwd(A, M, options: Options | None = None) -> float:
+    """f(M) = ||I - A M||_F^2 (A, M: scipy CSR on the host or torch CSR on the device)."""
+    out = C.c_double()
+    opts = (options or Options()).c()
+    a, m = _Csr(A), _Csr(M)
+    _check(load().spai_loss_fwd(C.byref(a.c), C.byref(m.c), C.byref(out), C.byref(opts)))
+    return out.value
+
+
+def loss_bwd(A, M, dL=1.0, want_a=True, want_m=True, options: Options | None = None):
+    """Gradients of f in the stored values of A and M (arrays in their CSR order)."""
+    opts = (options or Options()).c()
+    a, m = _Csr(A), _Csr(M)
+    if a.device:
+        torch = _torch()
+        dev = A.values().device
+        gA = torch.empty(a.c.nnz, dtype=torch.float64, device=dev) if want_a else None
+        gM = torch.empty(m.c.nnz, dtype=torch.float64, device=dev) if want_m else None
+        pa = gA.data_ptr() if want_a else None
+        pm = gM.data_ptr() if want_m else None
+    else:
+        gA = np.zeros(a.c.nnz) if want_a else None
+        gM = np.zeros(m.c.nnz) if want_m else None
+        pa = gA.ctypes.data if want_a else None
+        pm = gM.ctypes.data if want_m else None
+    _check(load().spai_loss_bwd(C.byref(a.c), C.byref(m.c), float(dL), pa, pm, C.byref(opts)))
+    return gA, gM
+
+
+def fro_loss_function():
+    """torch.autograd.Function for f = ||I - A M||_F^2 over the values of A and M.
+
+    ``FroLoss.apply(a_vals, m_vals, A_pattern, M_pattern, options)`` where the patterns
+    are torch CSR tensors on the device (their values are ignored) and a_vals, m_vals
+    are 1-D tensors of the stored values in CSR order.
+    """
+    torch = _torch()
+
+    def _with(pattern, vals):
+        return torch.sparse_csr_tensor(pattern.crow_indices(), pattern.col_indices(),
+                                       vals.detach().to(torch.float64), size=pattern.shape)
+
+    class FroLoss(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, a_vals, m_vals, A_pattern, M_pattern, options=None):
+            A = _with(A_pattern, a_vals)
+            M = _with(M_pattern, m_vals)
+            ctx.save_for_backward(a_vals, m_vals)
+            ctx.pats = (A_pattern, M_pattern, options)
+            return torch.tensor(loss_fwd(A, M, options), dtype=torch.float64,
+                                device=a_vals.device)
+
+        @staticmethod
+        def backward(ctx, grad):
+            a_vals, m_vals = ctx.saved_tensors
+            A_pattern, M_pattern, options = ctx.pats
+            A = _with(A_pattern, a_vals)
+            M = _with(M_pattern, m_vals)
+            gA, gM = loss_bwd(A, M, float(grad), ctx.needs_input_grad[0],
+                              ctx.needs_input_grad[1], options)
+            out_a = gA.to(a_vals.dtype) if gA is not None else None
+            out_m = gM.to(m_vals.dtype) if gM is not None else None
+            return out_a, out_m, None, None, None
+
+    return FroLoss

@@ -1,0 +1,60 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry point,
+and rejects bad inputs on the host before touching the device."""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from tests.helpers import ROOT
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "spai.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2511_09753_amd import spai as S
+    if not os.path.exists(S.LIB_PATH):
+        from paper_2511_09753_amd import build
+        build.build()
+    S.load()
+    return S
+
+
+def test_exports_every_declared_symbol(S):
+    names = _declared()
+    assert len(names) >= 13
+    lib = S.load()
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) <= set(S.EXPORTS)
+
+
+def test_status_strings(S):
+    lib = S.load()
+    assert lib.spai_status_string(0) == b"SPAI_OK"
+    assert lib.spai_status_string(-2) == b"SPAI_ERR_NOT_SYMMETRIC"
+
+
+def _expect(S, code, fn):
+    with pytest.raises(S.SpaiError) as e:
+        fn()
+    assert e.value.code == code
+
+
+def test_host_side_errors(S):
+    A = sp.csr_matrix(np.array([[2.0, 1.0], [0.5, 2.0]]))
+    _expect(S, -2, lambda: S.SPAI(A, "mr"))                            # not symmetric
+    B = sp.csr_matrix(np.array([[-1.0, 0.0], [0.0, 2.0]]))
+    _expect(S, -3, lambda: S.SPAI(B, "mr"))                            # not SPD diagonal
+    Cm = sp.csr_matrix(np.array([[2.0, np.nan], [np.nan, 2.0]]))
+    _expect(S, -4, lambda: S.SPAI(Cm, "mr"))                           # non-finite
+    D = sp.identity(4, format="csr") * 2.0
+    _expect(S, -1, lambda: S.SPAI(D, "mr", "global", 3, False))        # cap below diagonal count
+    _expect(S, -1, lambda: S.SPAI(D, "mr", "column", 0.2, False))      # column cap below one
+    _expect(S, -1, lambda: S.SPAI(D, "lomr", "global", 0.0, False))

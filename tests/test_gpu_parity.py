@@ -1,0 +1,227 @@
+"""HIP path vs the CPU oracle, element by element, on the same seeded inputs.
+
+Small sizes span several per-column tiles and ragged columns; the full-size
+configurations compare against stored oracle runs (tests/golden/make_golden.py).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import spai_oracle as O
+from paper_2511_09753_amd import workloads as W
+from tests.helpers import (GOLDEN, TOL_F64, TOL_MIXED, oracle_rule, pattern_diff, rel_err,
+                           require_gpu, value_err)
+
+pytestmark = pytest.mark.gpu
+
+
+def _spai():
+    require_gpu()
+    from paper_2511_09753_amd import spai as S
+    S.load()
+    return S
+
+
+def _run_gpu(S, A, method, mode, value, relative, iters, precision="f64", tol=0.0,
+             symmetrize=True):
+    h = S.SPAI(A, method, mode, value, relative, max_iter=iters, tol=tol,
+               options=S.Options(precision=precision, symmetrize=symmetrize))
+    r0 = h.stats()["resid"]
+    done, hist, rc = h.iterate(iters)
+    M = h.get()
+    st = h.stats()
+    h.close()
+    return r0, hist, M, st, rc
+
+
+SMALL = [
+    ("laplace8", lambda: W.laplace2d(8)),
+    ("aniso24", lambda: W.aniso2d(24, 1.0, 0.01)),
+    ("lognormal9", lambda: W.lognormal3d(9, 77)),
+    ("geo700", lambda: W.geometric_graph(700, 5)),
+]
+
+
+@pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
+@pytest.mark.parametrize("mode,value,relative", [("global", 2.0, True), ("column", 3.0, True),
+                                                 ("column", 4.0, False)])
+@pytest.mark.parametrize("name,make", SMALL)
+def test_small_parity_f64(name, make, method, mode, value, relative):
+    S = _spai()
+    A = make()
+    iters = 12
+    r0, hist, Mg, st, rc = _run_gpu(S, A, method, mode, value, relative, iters)
+    ref = O.run(method, A, oracle_rule(A, mode, value, relative), iters)
+    print(name, method, mode, "gpu", hist[-3:], "oracle", ref.resid[-3:])
+    assert r0 == pytest.approx(ref.resid[0], rel=1e-14)
+    assert len(hist) == ref.iters
+    assert rel_err(hist, ref.resid[1:]) <= TOL_F64
+    only_g, only_o = pattern_diff(Mg, ref.M)
+    assert not only_g and not only_o, (len(only_g), len(only_o))
+    assert value_err(Mg, ref.M) <= 1e-9
+    assert st["nnz_m"] == ref.M.nnz
+    # exactly symmetric iterate
+    assert abs(Mg - Mg.T).nnz == 0
+
+
+@pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
+def test_no_drop_parity_and_theory(method):
+    """No cap, no small-entry drop: the GPU follows the oracle, and LOMR/MR decrease."""
+    S = _spai()
+    A = W.laplace2d(6)
+    h = S.SPAI(A, method, "none", 0, False, max_iter=10,
+               options=S.Options(drop_tol=0.0))
+    _, hist, _ = h.iterate(10)
+    Mg = h.get()
+    h.close()
+    ref = O.run(method, A, O.DropRule(mode="none", u=0.0, symmetrize=True), 10)
+    assert rel_err(hist, ref.resid[1:len(hist) + 1]) <= 1e-9
+    if method != "cg":
+        assert all(b <= a * (1 + 1e-12) for a, b in zip(hist[:-1], hist[1:]))
+    assert value_err(Mg, ref.M) <= 1e-8
+
+
+def test_laplace32_first_iterate_closed_form():
+    """Setup and the first capped MR iterate against the closed forms of the traces."""
+    S = _spai()
+    A = W.laplace2d(32)
+    h = S.SPAI(A, "mr", "global", A.nnz, False, max_iter=20)
+    assert h.stats()["resid"] ** 2 == pytest.approx(31744 / 159, rel=1e-13)
+    done, hist, _ = h.iterate(1)
+    assert hist[0] == pytest.approx(9.727452876828249, rel=1e-12)
+    M1 = h.get()
+    assert M1.nnz == A.nnz
+    h.close()
+
+
+def test_laplace32_full_mr_and_pcg():
+    """The 32x32 Laplacian workload: MR 20 iterations, then PCG on one RHS to 1e-8."""
+    S = _spai()
+    wl = W.workload("laplace32")
+    A = wl.A
+    r0, hist, Mg, st, _ = _run_gpu(S, A, "mr", "global", A.nnz, False, 20)
+    ref = O.mr(A, oracle_rule(A, "global", A.nnz, False), 20)
+    assert rel_err(hist, ref.resid[1:]) <= TOL_F64
+    assert pattern_diff(Mg, ref.M) == (set(), set())
+    b = W.rhs(A.shape[0], 1, W.seed_for(1, 1))
+    # GPU PCG with the oracle's M against the oracle PCG with the same M
+    X, it, relres, rc = S.pcg_solve(A, ref.M, b, rtol=1e-8)
+    xo, ito, sto = O.pcg(A, ref.M, b[:, 0], rtol=1e-8)
+    assert rc == S.SPAI_OK and sto == "converged"
+    assert it[0] == ito
+    assert np.max(np.abs(X[:, 0] - xo)) <= 1e-10 * np.max(np.abs(xo))
+    assert relres[0] <= 1.01e-8
+    # end to end: GPU SPAI + GPU PCG vs oracle SPAI + oracle PCG
+    X2, it2, _, _ = S.pcg_solve(A, Mg, b, rtol=1e-8)
+    assert it2[0] == ito
+
+
+@pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
+def test_aniso256_full_against_stored_oracle(method):
+    path = os.path.join(GOLDEN, "aniso256.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle run not generated")
+    gold = json.load(open(path))["methods"][method]
+    S = _spai()
+    wl = W.workload("aniso256")
+    r0, hist, Mg, st, _ = _run_gpu(S, wl.A, method, "column", 3.0, True, wl.iters)
+    assert r0 == pytest.approx(gold["resid"][0], rel=1e-14)
+    assert rel_err(hist, gold["resid"][1:]) <= TOL_F64
+    assert st["nnz_m"] == gold["nnz_m"][-1]
+    if method != "mr":
+        assert st["nnz_p"] == gold["nnz_p"][-1]
+
+
+def test_pcg_multi_rhs_aniso():
+    S = _spai()
+    A = W.aniso2d(64, 1.0, 0.01)
+    ref = O.lomr(A, oracle_rule(A, "column", 3.0, True), 10)
+    B = W.rhs(A.shape[0], 4, W.seed_for(2, 1))
+    X, it, relres, rc = S.pcg_solve(A, ref.M, B, rtol=1e-8)
+    Xo, ito, sto = O.pcg_block(A, ref.M, B, rtol=1e-8)
+    assert rc == S.SPAI_OK
+    assert list(it) == list(ito)
+    assert np.max(np.abs(X - Xo)) <= 1e-9 * np.max(np.abs(Xo))
+    # Jacobi preconditioner and the identity as special cases
+    D = sp.diags(1.0 / A.diagonal()).tocsr()
+    X, it, _, _ = S.pcg_solve(A, D, B, rtol=1e-8)
+    _, ito, _ = O.pcg_block(A, D, B, rtol=1e-8)
+    assert list(it) == list(ito)
+    # an indefinite preconditioner is reported
+    _, _, _, rc = S.pcg_solve(A, -sp.identity(A.shape[0], format="csr"), B, rtol=1e-8)
+    assert rc == S.PCG_INDEFINITE
+
+
+def test_determinism():
+    S = _spai()
+    A = W.lognormal3d(10, 3)
+    outs = []
+    for _ in range(2):
+        _, hist, M, _, _ = _run_gpu(S, A, "lomr", "global", 2.0, True, 8)
+        outs.append((hist, M))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert (outs[0][1] != outs[1][1]).nnz == 0
+
+
+def test_mixed_precision_against_f64_oracle():
+    S = _spai()
+    A = W.lognormal3d(12, 3000)
+    iters = 15
+    r0, hist, Mg, st, _ = _run_gpu(S, A, "lomr", "global", 2.0, True, iters, precision="mixed")
+    ref = O.lomr(A, oracle_rule(A, "global", 2.0, True), iters)
+    err = rel_err(hist, ref.resid[1:])
+    print("mixed vs f64 oracle, max rel err in ||R||_F over the iterations:", err)
+    assert err <= TOL_MIXED
+    # the reported residual is the residual of the returned (float32-valued) M
+    R = sp.identity(A.shape[0]) - A @ Mg
+    assert np.sqrt((R.multiply(R)).sum()) == pytest.approx(hist[-1], rel=1e-6)
+
+
+def test_stopping_tolerance():
+    S = _spai()
+    A = W.geometric_graph(600, 2, shift=4.0)
+    ref = O.lomr(A, oracle_rule(A, "global", 8.0, True), 40, tol=1e-3)
+    assert ref.status == "converged"
+    h = S.SPAI(A, "lomr", "global", 8.0, True, max_iter=40, tol=1e-3)
+    done, hist, rc = h.iterate(40)
+    h.close()
+    assert rc == S.SPAI_CONVERGED
+    assert done == ref.iters
+    assert hist[-1] / np.sqrt(A.shape[0]) <= 1e-3
+
+
+def test_loss_and_gradients():
+    S = _spai()
+    A = W.grid9(24, 11)
+    M = W.loss_m_values(A, W.square_pattern(A), 12)
+    L = S.loss_fwd(A, M)
+    assert L == pytest.approx(O.loss(A, M), rel=1e-12)
+    gA, gM = S.loss_bwd(A, M, dL=1.0)
+    oA, oM = O.loss_grad(A, M)
+    assert np.max(np.abs(gA - oA.data)) <= 1e-11 * np.max(np.abs(oA.data))
+    assert np.max(np.abs(gM - oM.data)) <= 1e-11 * np.max(np.abs(oM.data))
+    # FP32 values, FP64 sums
+    L32 = S.loss_fwd(A, M, S.Options(precision="mixed"))
+    assert L32 == pytest.approx(O.loss(A, M), rel=1e-5)
+
+
+def test_batched_per_matrix_parity():
+    S = _spai()
+    mats = W.batch_geometric(6, 404, 500, 1500)
+    iters = 10
+    h = S.SPAI(None, "mr", "column", 4.0, False, max_iter=iters, batch=mats)
+    done, hist, rc = h.iterate(iters)
+    res = h.batched_resid()
+    Mg = h.get()
+    h.close()
+    off = 0
+    for b, A in enumerate(mats):
+        ref = O.mr(A, oracle_rule(A, "column", 4.0, False), iters)
+        assert res[b] == pytest.approx(ref.resid[-1], rel=TOL_F64)
+        n = A.shape[0]
+        blk = Mg[off:off + n, off:off + n]
+        assert pattern_diff(blk, ref.M) == (set(), set())
+        off += n
