@@ -101,6 +101,8 @@ typedef struct {
   void* stream;             /* hipStream_t, default NULL                           */
   int64_t device_pool_limit;/* bytes; 0 = no limit.  Exceeding it at create time
                                returns SPAI_ERR_NOMEM                             */
+  int profile;              /* 1: time every phase of an iteration with HIP events
+                               on the handle's stream (see spai_profile), default 0 */
 } spai_opts_t;
 
 /* Fill *opts with the defaults. */
@@ -167,6 +169,49 @@ int spai_stats(spai_handle_t* h, int* iters, double* resid_fro, int64_t* nnz_m,
 
 /* Release every device buffer of the handle.  NULL is accepted. */
 int spai_destroy(spai_handle_t* h);
+
+/*
+ * spai_reset — restart the handle from M_0 = (tr A / tr A^2) I (and R_0, P_0) with
+ *   the same A, method, cap and options, reusing its device pools; the iteration
+ *   budget max_iter starts again.  Synchronises the stream.
+ */
+int spai_reset(spai_handle_t* h);
+
+/*
+ * spai_pcg — pcg_solve with the handle's own A and its current iterate M, both
+ *   already in device memory (no copy, no conversion).  Requires symmetrize = 1 (M
+ *   exactly symmetric, so its column storage is also its row storage).  B, X: dense
+ *   n x nrhs row-major float64, device pointers when on_device = 1, else host.
+ *   For a batched handle the block-diagonal system is solved.  Returns as pcg_solve.
+ */
+int spai_pcg(spai_handle_t* h, int nrhs, const double* B, double* X, double rtol,
+             int max_iter, int* iters, double* relres, int on_device);
+
+/* Phases timed when opts.profile = 1, and traffic counters (cumulative since create). */
+enum {
+  SPAI_PH_DOTS = 0,     /* SpGEMM fused with the Frobenius dots (A R, A P)          */
+  SPAI_PH_UPDATE = 1,   /* merge + symmetrize + small-entry drop (+ column thresholds) */
+  SPAI_PH_RESID = 2,    /* explicit residual R = I - A M with ||R||_F               */
+  SPAI_PH_SELECT = 3,   /* global-cap radix selection                               */
+  SPAI_PH_COMPACT = 4,  /* keep rule and in-place compaction                        */
+  SPAI_PH_BOUNDS = 5,   /* per-column output bounds and their prefix sums           */
+  SPAI_PH_SCALAR = 6,   /* fixed-order reductions and step sizes                    */
+  SPAI_PH_PCG = 7,      /* spai_pcg                                                 */
+  SPAI_NPHASES = 8
+};
+enum {
+  SPAI_CNT_CAND_M = 0, SPAI_CNT_CAND_P = 1, SPAI_CNT_CAND_PT = 2,   /* candidates formed */
+  SPAI_CNT_KEPT_M = 3, SPAI_CNT_KEPT_P = 4, SPAI_CNT_KEPT_PT = 5,   /* entries kept      */
+  SPAI_CNT_RESID = 6,   /* residual entries written                                  */
+  SPAI_CNT_ITERS = 7,   /* iterations run                                            */
+  SPAI_NCOUNTS = 8
+};
+/*
+ * spai_profile — accumulated milliseconds and launch counts per phase (zeros unless
+ *   opts.profile = 1) and the traffic counters.  Any pointer may be NULL; arrays
+ *   hold SPAI_NPHASES / SPAI_NCOUNTS entries.  Synchronises the stream.
+ */
+int spai_profile(spai_handle_t* h, double* phase_ms, int64_t* phase_calls, int64_t* counts);
 
 /*
  * pcg_solve — preconditioned CG for A X = B with the SPAI M as preconditioner

@@ -136,6 +136,10 @@ struct EngineBase {
   virtual int stats(int* iters, double* resid, int64_t* nnz_m, int64_t* nnz_p, double* s1,
                     double* s2, int* fb) = 0;
   virtual int batched_resid(double* out) = 0;
+  virtual int reset() = 0;
+  virtual int pcg(int nrhs, const double* B, double* X, double rtol, int max_iter, int* iters,
+                  double* relres, int on_device) = 0;
+  virtual int profile(double* ms, int64_t* calls, int64_t* counts) = 0;
 };
 
 template <typename T>
@@ -168,19 +172,75 @@ struct Engine : EngineBase {
   BigList big[3];
   unsigned long long *selhist = nullptr, *selbuf = nullptr;
   DevState* st = nullptr;
+  unsigned long long* cnt = nullptr;
   SegState* segst = nullptr;
   int* seg_of = nullptr;
   int64_t* seg_beg = nullptr;
   Seg seg;
-  Tile tRs{128, 512}, tRl{1024, 4096}, tDs{256, 1024}, tDl{1024, 4096}, tUs{384, 512},
-      tUl{2048, 2048};
+  Tile tRs{128, 512}, tRl{1024, 4096}, tDs{256, 512}, tDl{1024, 4096}, tUs{384, 512},
+      tUl{2048, 4096};
   int hist_cap = 0;
   int iters_host = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t own_stream = nullptr;
+  // phase timing (opts.profile)
+  bool prof = false;
+  double ph_ms[SPAI_NPHASES] = {};
+  int64_t ph_calls[SPAI_NPHASES] = {};
+  int64_t total_iters = 0;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  hipEvent_t ev_open = nullptr;
+  int ph_open = -1;
+
+  hipEvent_t ev_get() {
+    hipEvent_t e = nullptr;
+    if (!ev_free.empty()) {
+      e = ev_free.back();
+      ev_free.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return e;
+  }
+  void tb(int ph) {
+    if (!prof) return;
+    ev_open = ev_get();
+    ph_open = ph;
+    if (ev_open) (void)hipEventRecord(ev_open, s);
+  }
+  void te() {
+    if (!prof || !ev_open) return;
+    hipEvent_t b = ev_get();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    ev_pending.push_back({ph_open, {ev_open, b}});
+    ev_open = nullptr;
+  }
+  void collect() {                     // after a synchronisation
+    for (auto& p : ev_pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+        ph_ms[p.first] += ms;
+        ph_calls[p.first] += 1;
+      } else {
+        (void)hipGetLastError();
+      }
+      ev_free.push_back(p.second.first);
+      ev_free.push_back(p.second.second);
+    }
+    ev_pending.clear();
+  }
 
   ~Engine() override {
+    if (s) (void)hipStreamSynchronize(s);
+    for (auto& p : ev_pending) {
+      (void)hipEventDestroy(p.second.first);
+      (void)hipEventDestroy(p.second.second);
+    }
+    for (auto e : ev_free) (void)hipEventDestroy(e);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (own_stream) {
@@ -273,9 +333,13 @@ struct Engine : EngineBase {
       A.val32 = d_v32;
     }
     // ---- state
-    if ((rc = dalloc(&st, 1)) || (rc = dalloc(&segst, nseg)) || (rc = dalloc(&seg_beg, nseg + 1)))
+    if ((rc = dalloc(&st, 1)) || (rc = dalloc(&segst, nseg)) || (rc = dalloc(&seg_beg, nseg + 1)) ||
+        (rc = dalloc(&cnt, (int64_t)kNCnt * kCntSlots)))
       return rc;
     HIPCHK(hipMemsetAsync(st, 0, sizeof(DevState), s));
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * kNCnt * kCntSlots, s));
+    HIPCHK(hipMemcpyAsync(&st->cnt, &cnt, sizeof(cnt), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipMemsetAsync(segst, 0, sizeof(SegState) * nseg, s));
     HIPCHK(hipMemcpyAsync(seg_beg, seg_beg_h.data(), sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice, s));
     std::vector<int> segof_h;
@@ -318,7 +382,12 @@ struct Engine : EngineBase {
     if (global) {
       if ((rc = dalloc(&selhist, 8192)) || (rc = dalloc(&selbuf, capU))) return rc;
     }
-    // ---- M_0 = c I, R_0, and CG's P_0
+    prof = opts.profile != 0 && !batched_graph;
+    return init_iterate();
+  }
+
+  // M_0 = c I, R_0, and CG's P_0
+  int init_iterate() {
     launch_trace_parts(A, colpart, s);
     launch_reduce(colpart, 2, n, seg, nseg > 1 ? seg_beg : nullptr, red, blockpart, s);
     launch_init_state(seg, red, nseg > 1 ? seg_beg : nullptr, n, cvec, method, st, s);
@@ -332,7 +401,77 @@ struct Engine : EngineBase {
     if (method == SPAI_CG) p_update_step();
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
+    collect();
+    iters_host = 0;
     return check_err();
+  }
+
+  int reset() override { return init_iterate(); }
+
+  int pcg(int nrhs, const double* B, double* X, double rtol, int max_iter, int* iters,
+          double* relres, int on_device) override {
+    if (!opts.symmetrize) return fail(SPAI_ERR_ARG, "spai_pcg needs a symmetrized iterate");
+    if (nrhs < 1 || !B || !X || !(rtol >= 0.0) || max_iter < 0)
+      return fail(SPAI_ERR_ARG, "spai_pcg: bad arguments");
+    HIPCHK(hipStreamSynchronize(s));
+    DevState h;
+    HIPCHK(hipMemcpy(&h, st, sizeof(DevState), hipMemcpyDeviceToHost));
+    const Cols<T>& C = M.b[h.curM];
+    PcgMat pa, pm;
+    pa.n = n;
+    pa.rowptr = A.rowptr;
+    pa.col = A.col;
+    pa.val = A.val;
+    pm.n = n;
+    pm.beg = C.beg;
+    pm.len = C.len;
+    pm.col = C.idx;
+    if (sizeof(T) == 4) pm.val32 = (const float*)C.val; else pm.val = (const double*)C.val;
+    DevPool tmp;
+    int rc;
+    const int64_t tot = n * (int64_t)nrhs;
+    const double* dB = B;
+    double* dX = X;
+    if (!on_device) {
+      double *b2, *x2;
+      if ((rc = tmp.alloc(&b2, tot)) || (rc = tmp.alloc(&x2, tot))) return rc;
+      HIPCHK(hipMemcpyAsync(b2, B, sizeof(double) * tot, hipMemcpyHostToDevice, s));
+      dB = b2;
+      dX = x2;
+    }
+    tb(SPAI_PH_PCG);
+    rc = pcg_run(pa, pm, nrhs, dB, dX, rtol, max_iter, iters, relres, s);
+    te();
+    if (rc < 0) return rc;
+    if (!on_device) {
+      HIPCHK(hipMemcpyAsync(X, dX, sizeof(double) * tot, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    collect();
+    return rc;
+  }
+
+  int profile(double* ms, int64_t* calls, int64_t* counts) override {
+    HIPCHK(hipStreamSynchronize(s));
+    collect();
+    for (int i = 0; i < SPAI_NPHASES; ++i) {
+      if (ms) ms[i] = ph_ms[i];
+      if (calls) calls[i] = ph_calls[i];
+    }
+    if (counts) {
+      std::vector<unsigned long long> c((size_t)kNCnt * kCntSlots);
+      HIPCHK(hipMemcpy(c.data(), cnt, sizeof(unsigned long long) * c.size(), hipMemcpyDeviceToHost));
+      int64_t sums[kNCnt] = {};
+      for (int k = 0; k < kNCnt; ++k)
+        for (int b = 0; b < kCntSlots; ++b) sums[k] += (int64_t)c[(size_t)k * kCntSlots + b];
+      for (int k = 0; k < 3; ++k) {
+        counts[SPAI_CNT_CAND_M + k] = sums[k];
+        counts[SPAI_CNT_KEPT_M + k] = sums[3 + k];
+      }
+      counts[SPAI_CNT_RESID] = sums[6];
+      counts[SPAI_CNT_ITERS] = total_iters;
+    }
+    return SPAI_OK;
   }
 
   UpdMode mode(int doM, int x1, int x2, int doP) const {
@@ -350,27 +489,44 @@ struct Engine : EngineBase {
   }
 
   void resid_step(int setup) {
+    tb(SPAI_PH_BOUNDS);
     launch_bound_resid<T>(A, M, ub, n, st, s);
     launch_scan(ub, off, total, n, scantmp, s);
+    te();
+    tb(SPAI_PH_RESID);
     launch_resid<T>(A, M, R, off, total, colnorm, big[0], st, tRs, tRl, s);
+    te();
+    tb(SPAI_PH_SCALAR);
     launch_reduce(colnorm, 1, n, seg, nseg > 1 ? seg_beg : nullptr, red_rr, blockpart, s);
     launch_scal_post(method, seg, red_rr, tol, hist, hist_cap, setup, st, s);
+    te();
   }
 
   void dots_step(int useR, int useP) {
+    tb(SPAI_PH_DOTS);
     launch_dots<T>(A, R, P, useR, useP, colpart, big[1], st, tDs, tDl, s);
+    te();
+    tb(SPAI_PH_SCALAR);
     launch_reduce(colpart, kND, n, seg, nseg > 1 ? seg_beg : nullptr, red, blockpart, s);
     launch_scal_step(method, seg, red, st, s);
+    te();
   }
 
   void update_step(UpdMode md) {
+    tb(SPAI_PH_BOUNDS);
     launch_bound_update<T>(A, M, R, P, PT, md, ub, n, st, s);
     launch_scan(ub, off, total, n, scantmp, s);
+    te();
+    tb(SPAI_PH_UPDATE);
     launch_update<T>(A, M, R, P, PT, md, off, total, kcol, tM, tP, big[2], seg, st, tUs, tUl, s);
+    te();
     if (global) {
+      tb(SPAI_PH_SELECT);
       if (md.doM) launch_global_select<T>(M, 1, m_global, opts.tie_eta, 0, selhist, selbuf, n, st, s);
       if (md.doP) launch_global_select<T>(P, 0, m_global, opts.tie_eta, 1, selhist, selbuf, n, st, s);
+      te();
     }
+    tb(SPAI_PH_COMPACT);
     if (md.doM) {
       launch_compact<T>(M, 0, colcap, md.sym, global, tM, opts.tie_eta, n, st, s);
       launch_flip(0, st, s);
@@ -380,6 +536,7 @@ struct Engine : EngineBase {
       launch_compact<T>(PT, 2, colcap, 0, global, tP, opts.tie_eta, n, st, s);
       launch_flip(1, st, s);
     }
+    te();
   }
 
   void p_update_step() { update_step(mode(0, 0, 0, 1)); }
@@ -435,11 +592,13 @@ struct Engine : EngineBase {
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
+    collect();
     if ((rc = check_err())) return rc;
     std::vector<SegState> after;
     if ((rc = read_segs(after))) return rc;
     const int d0 = after[0].iters - before[0].iters;
     iters_host += k;
+    total_iters += d0;
     if (done) *done = d0;
     if (hout && d0 > 0)
       HIPCHK(hipMemcpy(hout, hist + before[0].iters, sizeof(double) * d0, hipMemcpyDeviceToHost));
@@ -569,6 +728,7 @@ static void fill_defaults(spai_opts_t* o) {
   o->tie_eta = 1e-9;
   o->stream = nullptr;
   o->device_pool_limit = 0;
+  o->profile = 0;
 }
 
 template <typename T>
@@ -717,6 +877,36 @@ int spai_batched_resid(spai_handle_t* h, double* resid) {
 int spai_destroy(spai_handle_t* h) {
   delete h;
   return SPAI_OK;
+}
+
+int spai_reset(spai_handle_t* h) {
+  if (!h) return fail(SPAI_ERR_ARG, "null handle");
+  try {
+    return h->eng->reset();
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_pcg(spai_handle_t* h, int nrhs, const double* B, double* X, double rtol, int max_iter,
+             int* iters, double* relres, int on_device) {
+  if (!h) return fail(SPAI_ERR_ARG, "null handle");
+  try {
+    return h->eng->pcg(nrhs, B, X, rtol, max_iter, iters, relres, on_device);
+  } catch (const std::bad_alloc&) {
+    return fail(SPAI_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_profile(spai_handle_t* h, double* phase_ms, int64_t* phase_calls, int64_t* counts) {
+  if (!h) return fail(SPAI_ERR_ARG, "null handle");
+  try {
+    return h->eng->profile(phase_ms, phase_calls, counts);
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
 }
 
 const char* spai_last_error(void) { return g_last_error.c_str(); }

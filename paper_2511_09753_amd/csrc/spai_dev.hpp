@@ -93,6 +93,28 @@ __device__ __forceinline__ void ks_insert(int* keys, int H, int key) {
   }
 }
 
+// Insert with a bound on the number of distinct keys: `cnt` counts the keys placed,
+// and once it reaches `limit` further inserts are refused and `*over` is set.  With
+// limit + 64 < H (at most 64 lanes insert at once) an empty slot always exists, so
+// probing terminates.
+__device__ __forceinline__ void ks_insert_bounded(int* keys, int H, int key, int* cnt, int limit,
+                                                  int* over) {
+  if (*((volatile int*)cnt) >= limit) {
+    *over = 1;
+    return;
+  }
+  unsigned h = hash_key(key) & (unsigned)(H - 1);
+  while (true) {
+    int prev = atomicCAS(&keys[h], -1, key);
+    if (prev == -1) {
+      if (atomicAdd(cnt, 1) + 1 > limit) *over = 1;
+      return;
+    }
+    if (prev == key) return;
+    h = (h + 1) & (unsigned)(H - 1);
+  }
+}
+
 __device__ __forceinline__ int next_pow2(int x) {
   int p = 1;
   while (p < x) p <<= 1;
@@ -114,6 +136,27 @@ __device__ inline void bitonic_sort_int(int* a, int S) {
       __syncthreads();
     }
   }
+}
+
+// Sort the keys of the set in place: keys[0..cnt) ascending, returns cnt.  The
+// compaction writes slot s to position <= s after the whole 64-slot chunk has been
+// read, so it can run in place; the tail up to next_pow2(cnt) is padded for the sort.
+__device__ inline int ks_sort_inplace(int* keys, int H) {
+  int cnt = 0;
+  for (int base = 0; base < H; base += SPAI_WAVE) {
+    int k = keys[base + lane_id()];
+    bool occ = k != -1;
+    unsigned long long m = __ballot(occ);
+    __syncthreads();
+    if (occ) keys[cnt + __popcll(m & lanemask_lt())] = k;
+    cnt += __popcll(m);
+    __syncthreads();
+  }
+  int S = next_pow2(cnt > 0 ? cnt : 1);
+  for (int i = cnt + lane_id(); i < S; i += SPAI_WAVE) keys[i] = INT_MAX;
+  __syncthreads();
+  if (cnt > 1) bitonic_sort_int(keys, S);
+  return cnt;
 }
 
 // Gather the keys of the set into out[0..cnt) in ascending order; returns cnt.

@@ -52,4 +52,25 @@ struct DevPool {
   ~DevPool();
 };
 
+// matrix operand of the PCG kernels: CSR (rowptr) or padded columns (beg, len), with
+// float64 or float32 values
+struct PcgMat {
+  int64_t n = 0;
+  const int64_t* rowptr = nullptr;
+  const int64_t* beg = nullptr;
+  const int32_t* len = nullptr;
+  const int32_t* col = nullptr;
+  const double* val = nullptr;
+  const float* val32 = nullptr;
+  __device__ __forceinline__ int64_t row_begin(int64_t i) const { return beg ? beg[i] : rowptr[i]; }
+  __device__ __forceinline__ int64_t row_end(int64_t i) const {
+    return beg ? beg[i] + len[i] : rowptr[i + 1];
+  }
+  __device__ __forceinline__ double v(int64_t q) const { return val32 ? (double)val32[q] : val[q]; }
+};
+
+// preconditioned CG on device-resident operands (B, X on the device)
+int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double* dX, double rtol,
+            int max_iter, int* iters, double* relres, hipStream_t s);
+
 }  // namespace spai

@@ -12,6 +12,8 @@ enum : int { kMR = 0, kCG = 1, kLOMR = 2 };
 // Frobenius dots produced per column by the SpGEMM-dots kernel:
 // 0 (R,AR)  1 (AR,AR)  2 (AR,AP)  3 (R,AP)  4 (AP,AP)  5 (P,AP)
 constexpr int kND = 6;
+constexpr int kCntSlots = 65536;   // workgroup slots per traffic counter
+constexpr int kNCnt = 7;
 
 // Per-matrix ("segment") scalar state; a single segment unless the handle is batched.
 struct SegState {
@@ -36,6 +38,10 @@ struct DevState {
   int curM, curP;     // which of the two buffers holds the current M / (P, P^T)
   int big_count[4];   // overflow-column list lengths (resid, dots, update)
   unsigned long long nnz_m, nnz_p;
+  // cumulative entry counts for traffic accounting, one slot per workgroup and
+  // counter (no contended atomics): counter c of workgroup b at cnt[c * kCntSlots + b];
+  // counters 0-2 candidates in (M, P, P^T), 3-5 kept, 6 residual entries written
+  unsigned long long* cnt;
   // global-cap radix selection
   double thrM, thrP;              // keep |x| > thr (thr already includes 1 + eta)
   unsigned long long sel_count;   // keys in the selection buffer

@@ -20,6 +20,11 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "spai_dev.hpp"
 #include "spai_kern.hpp"
 
@@ -61,12 +66,21 @@ __device__ inline int degree_prefix(const Csr& A, const int* rows, int cnt, int*
 
 // Insert the column index of every nonzero of the rows rows[0..cnt) of A into the key set.
 __device__ inline void insert_products(const Csr& A, const int* rows, int cnt, const int* pre,
-                                       int total, int* keys, int H) {
+                                       int total, int* keys, int H, int* kc, int limit,
+                                       int* over) {
   for (int p = lane_id(); p < total; p += SPAI_WAVE) {
     const int e = upper_bound_int(pre, cnt, p);
     const int before = e ? pre[e - 1] : 0;
     const int64_t q = A.rowptr[rows[e]] + (p - before);
-    ks_insert(keys, H, A.col[q]);
+    ks_insert_bounded(keys, H, A.col[q], kc, limit, over);
+  }
+}
+
+// a column that does not fit its tile: hand it to the large tile, or flag it there
+__device__ inline void defer_column(int tier, BigList big, DevState* st, int64_t j) {
+  if (lane_id() == 0) {
+    if (tier == 0) big.list[atomicAdd(big.count, 1)] = (int)j;
+    else atomicOr(&st->err, 1);
   }
 }
 
@@ -350,12 +364,14 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> 
   Carve cv(smem);
   int* s_mi = cv.take<int>(L);
   int* s_pre = cv.take<int>(L);
-  int* s_keys = cv.take<int>(H);
-  int* s_sorted = cv.take<int>(H);
+  int* s_keys = cv.take<int>(H);         // hash set, then the sorted keys
+  int* s_sorted = s_keys;
+  int* s_kc = cv.take<int>(2);           // distinct-key count, overflow flag
   double* s_mv = cv.take<double>(L);
   const int lane = lane_id();
   const Cols<T> M = Mp.now();
   const bool overflow = *total > R.cap;
+  unsigned long long outcnt = 0;
 
   auto body = [&](int64_t j) {
     const int64_t mb = M.beg[j];
@@ -374,26 +390,23 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> 
     }
     __syncthreads();
     const int tot = degree_prefix(A, s_mi, lm, s_pre);
-    if (tot + 1 >= H) {            // keys must stay below the slot count
-      if (tier == 0) {
-        if (lane == 0) big.list[atomicAdd(big.count, 1)] = (int)j;
-      } else if (lane == 0) {
-        atomicOr(&st->err, 1);
-      }
-      __syncthreads();
-      return;
-    }
     if (overflow) {
       if (lane == 0) atomicOr(&st->err, 2);
       __syncthreads();
       return;
     }
     ks_clear(s_keys, H);
+    if (lane == 0) { s_kc[0] = 0; s_kc[1] = 0; }
     __syncthreads();
-    if (lane == 0) ks_insert(s_keys, H, (int)j);
-    insert_products(A, s_mi, lm, s_pre, tot, s_keys, H);
+    if (lane == 0) ks_insert_bounded(s_keys, H, (int)j, s_kc, H / 2, s_kc + 1);
+    insert_products(A, s_mi, lm, s_pre, tot, s_keys, H, s_kc, H / 2, s_kc + 1);
     __syncthreads();
-    const int nu = ks_sorted(s_keys, H, s_sorted);
+    if (s_kc[1]) {                 // more distinct rows than the tile holds
+      defer_column(tier, big, st, j);
+      __syncthreads();
+      return;
+    }
+    const int nu = ks_sort_inplace(s_keys, H);
     __syncthreads();
     const int64_t ob = off[j];
     double acc = 0.0;
@@ -416,6 +429,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> 
       R.beg[j] = ob;
       R.len[j] = nu;
     }
+    outcnt += (unsigned long long)nu;
     __syncthreads();
   };
 
@@ -426,20 +440,48 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> 
     const int cnt = *big.count;
     for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list[t]);
   }
+  if (lane == 0 && tier == 0 && blockIdx.x < kCntSlots) st->cnt[6 * kCntSlots + blockIdx.x] += outcnt;
+  if (lane == 0 && tier == 1 && outcnt) atomicAdd(&st->cnt[6 * kCntSlots + kCntSlots - 1], outcnt);
 }
 
 static size_t resid_lds(Tile t) {
-  return (size_t)t.L * 4 * 2 + (size_t)t.H * 4 * 2 + (size_t)t.L * 8 + 64;
+  return (size_t)t.L * 4 * 2 + (size_t)t.H * 4 + 8 + (size_t)t.L * 8 + 64;
 }
 
-int g_grid_cols = 2048;   // persistent grid of the per-column kernels (multiple of 8)
+int g_grid_cols = 2048;   // fallback persistent grid of the per-column kernels
+
+// Persistent grid for a per-column kernel: as many one-wave workgroups as can be
+// resident at once given its LDS tile (queried once per kernel and tile), rounded
+// down to a multiple of the 8 XCDs.
+template <typename K>
+static int resident_grid(K kernel, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, size_t>, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_pair((const void*)kernel, lds);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0, per = 0;
+  int grid = g_grid_cols;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, SPAI_WAVE, lds) == hipSuccess &&
+      per > 0 && cus > 0) {
+    grid = std::max(8, (per * cus) / 8 * 8);
+  } else {
+    (void)hipGetLastError();
+  }
+  cache[key] = grid;
+  return grid;
+}
 
 template <typename T>
 void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const int64_t* total,
                   double* colnorm, BigList big, DevState* st, Tile small, Tile large,
                   hipStream_t s) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
-  hipLaunchKernelGGL(k_resid<T>, dim3(g_grid_cols), dim3(SPAI_WAVE), resid_lds(small), s, A, M, R,
+  hipLaunchKernelGGL(k_resid<T>, dim3(resident_grid(k_resid<T>, resid_lds(small))), dim3(SPAI_WAVE),
+                     resid_lds(small), s, A, M, R,
                      off, total, colnorm, big, st, 0, small.L, small.H);
   hipLaunchKernelGGL(k_resid<T>, dim3(256), dim3(SPAI_WAVE), resid_lds(large), s, A, M, R, off,
                      total, colnorm, big, st, 1, large.L, large.H);
@@ -459,7 +501,8 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
   int* s_li = cv.take<int>(L);
   int* s_pre = cv.take<int>(L);
   int* s_keys = cv.take<int>(H);
-  int* s_sorted = cv.take<int>(H);
+  int* s_sorted = s_keys;
+  int* s_kc = cv.take<int>(2);
   double* s_lv = cv.take<double>(L);
   const int lane = lane_id();
   const Cols<T> P = Pp.now();
@@ -487,20 +530,17 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
     }
     __syncthreads();
     const int tot = degree_prefix(A, s_li, lr + lp, s_pre);
-    if (tot + 1 >= H) {
-      if (tier == 0) {
-        if (lane == 0) big.list[atomicAdd(big.count, 1)] = (int)j;
-      } else if (lane == 0) {
-        atomicOr(&st->err, 1);
-      }
+    ks_clear(s_keys, H);
+    if (lane == 0) { s_kc[0] = 0; s_kc[1] = 0; }
+    __syncthreads();
+    insert_products(A, s_li, lr + lp, s_pre, tot, s_keys, H, s_kc, H / 2, s_kc + 1);
+    __syncthreads();
+    if (s_kc[1]) {
+      defer_column(tier, big, st, j);
       __syncthreads();
       return;
     }
-    ks_clear(s_keys, H);
-    __syncthreads();
-    insert_products(A, s_li, lr + lp, s_pre, tot, s_keys, H);
-    __syncthreads();
-    const int nu = ks_sorted(s_keys, H, s_sorted);
+    const int nu = ks_sort_inplace(s_keys, H);
     __syncthreads();
     const int* ri = s_li;
     const double* rv = s_lv;
@@ -561,14 +601,15 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
 }
 
 static size_t dots_lds(Tile t) {
-  return (size_t)t.L * 4 * 2 + (size_t)t.H * 4 * 2 + (size_t)t.L * 8 + 64;
+  return (size_t)t.L * 4 * 2 + (size_t)t.H * 4 + 8 + (size_t)t.L * 8 + 64;
 }
 
 template <typename T>
 void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, double* colpart,
                  BigList big, DevState* st, Tile small, Tile large, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
-  hipLaunchKernelGGL(k_dots<T>, dim3(g_grid_cols), dim3(SPAI_WAVE), dots_lds(small), s, A, R, P,
+  hipLaunchKernelGGL(k_dots<T>, dim3(resident_grid(k_dots<T>, dots_lds(small))), dim3(SPAI_WAVE),
+                     dots_lds(small), s, A, R, P,
                      useR, useP, colpart, big, st, 0, small.L, small.H);
   hipLaunchKernelGGL(k_dots<T>, dim3(256), dim3(SPAI_WAVE), dots_lds(large), s, A, R, P, useR,
                      useP, colpart, big, st, 1, large.L, large.H);
@@ -638,6 +679,32 @@ __device__ inline double kth_largest(const double* v, int cnt, int b) {
   return t;
 }
 
+// the same from a candidate column in global memory, skipping the entry with row `skip`
+template <typename T>
+__device__ inline double kth_largest_cols(const int32_t* idx, const T* val, int cnt, int skip,
+                                          int b) {
+  int m = 0;
+  for (int e = lane_id(); e < cnt; e += SPAI_WAVE) m += idx[e] != skip;
+  m = wave_sum_int(m);
+  double t = 0.0;
+  if (m > b) {
+    for (int e = lane_id(); e < cnt; e += SPAI_WAVE) {
+      if (idx[e] == skip) continue;
+      const double x = fabs((double)val[e]);
+      int r = 0;
+      for (int f = 0; f < cnt; ++f) {
+        if (idx[f] == skip) continue;
+        const double y = fabs((double)val[f]);
+        r += (y > x) || (y == x && f < e);
+      }
+      if (r == b) t = x;
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) t = fmax(t, __shfl_xor(t, d, SPAI_WAVE));
+  return t;
+}
+
 template <typename T>
 __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp,
                                                       Pair<T> PTp, UpdMode md, const int64_t* off,
@@ -649,14 +716,17 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
   extern __shared__ char smem[];
   Carve cv(smem);
   int* s_li = cv.take<int>(L);
-  int* s_keys = cv.take<int>(H);        // reused for M candidate magnitudes (H/2 doubles)
-  int* s_sorted = cv.take<int>(H);
+  int* s_keys = cv.take<int>(H);        // hash set, then the sorted keys
+  int* s_sorted = s_keys;
   int* s_nbcol = cv.take<int>(DG);
   int* s_nboff = cv.take<int>(DG + 1);
+  int* s_kc = cv.take<int>(2);
   double* s_lv = cv.take<double>(L);
   double* s_nbval = cv.take<double>(DG);
-  double* s_candP = cv.take<double>(H / 2);
-  double* s_candM = (double*)s_keys;
+  // small tile: the neighbour columns m_l sit in LDS; large tile: they stay in global
+  // memory and are searched in place (s_nbbeg / s_nboff hold their start and length)
+  const bool nb_lds = tier == 0;
+  int64_t* s_nbbeg = nb_lds ? nullptr : cv.take<int64_t>(DG);
   const int lane = lane_id();
 
   const Cols<T> M = Mp.now();
@@ -685,13 +755,10 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
     int nbtot = 0;
     for (int t = lane; t < deg; t += SPAI_WAVE) nbtot += M.len[A.col[qa + t]];
     nbtot = wave_sum_int(nbtot);
-    const int ltot = lm + lr + lp + lpt + nbtot;
-    if (ltot > L || ltot + 2 >= H / 2 || deg > DG) {
-      if (tier == 0) {
-        if (lane == 0) big.list[atomicAdd(big.count, 1)] = (int)j;
-      } else if (lane == 0) {
-        atomicOr(&st->err, 1);
-      }
+    const int lown = lm + lr + lp + lpt;
+    const int ltot = lown + (nb_lds ? nbtot : 0);
+    if (ltot > L || deg > DG) {
+      defer_column(tier, big, st, j);
       return;
     }
     if (overflow) {
@@ -728,7 +795,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
         s_lv[opt + e] = (double)PT.val[b + e];
       }
     }
-    if (deg) {
+    if (deg && nb_lds) {
       // neighbour offsets (prefix of their lengths), then their entries
       int run = 0;
       for (int base = 0; base < deg; base += SPAI_WAVE) {
@@ -756,15 +823,37 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
           s_lv[o + e] = (double)M.val[b + e];
         }
       }
+    } else if (deg) {
+      for (int t = lane; t < deg; t += SPAI_WAVE) {
+        const int l = A.col[qa + t];
+        s_nbcol[t] = l;
+        s_nbval[t] = aval(A, qa + t);
+        s_nbbeg[t] = M.beg[l];
+        s_nboff[t] = M.len[l];
+      }
     }
     __syncthreads();
-    // ---- key union
+    // ---- key union (at most H / 2 - 1 distinct keys)
     ks_clear(s_keys, H);
+    if (lane == 0) { s_kc[0] = 0; s_kc[1] = 0; }
     __syncthreads();
-    if (lane == 0) ks_insert(s_keys, H, (int)j);
-    for (int e = lane; e < ltot; e += SPAI_WAVE) ks_insert(s_keys, H, s_li[e]);
+    const int klim = H / 2 - 1;
+    if (lane == 0) ks_insert_bounded(s_keys, H, (int)j, s_kc, klim, s_kc + 1);
+    for (int e = lane; e < ltot; e += SPAI_WAVE) ks_insert_bounded(s_keys, H, s_li[e], s_kc, klim, s_kc + 1);
+    if (!nb_lds)
+      for (int t = 0; t < deg; ++t) {
+        const int64_t b = s_nbbeg[t];
+        const int len = s_nboff[t];
+        for (int e = lane; e < len; e += SPAI_WAVE)
+          ks_insert_bounded(s_keys, H, M.idx[b + e], s_kc, klim, s_kc + 1);
+      }
     __syncthreads();
-    const int nk = ks_sorted(s_keys, H, s_sorted);
+    if (s_kc[1]) {
+      defer_column(tier, big, st, j);
+      __syncthreads();
+      return;
+    }
+    const int nk = ks_sort_inplace(s_keys, H);
     __syncthreads();
     // ---- values, candidates
     const int64_t ob = off[j];
@@ -782,9 +871,15 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
         if (needRT) {
           double sum = 0.0;
           for (int t2 = 0; t2 < deg; ++t2) {
-            const int o = s_nboff[t2];
-            const int e = bsearch_idx(s_li + o, s_nboff[t2 + 1] - o, k);
-            if (e >= 0) sum += s_nbval[t2] * s_lv[o + e];
+            if (nb_lds) {
+              const int o = s_nboff[t2];
+              const int e = bsearch_idx(s_li + o, s_nboff[t2 + 1] - o, k);
+              if (e >= 0) sum += s_nbval[t2] * s_lv[o + e];
+            } else {
+              const int64_t b = s_nbbeg[t2];
+              const int e = bsearch_idx(M.idx + b, s_nboff[t2], k);
+              if (e >= 0) sum += s_nbval[t2] * (double)M.val[b + e];
+            }
           }
           rtv = (double)(T)(((k == (int)j) ? 1.0 : 0.0) - sum);
         }
@@ -829,12 +924,10 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
         Mo.idx[pos] = k;
         Mo.val[pos] = mt;
       }
-      if (md.colcap && offM) s_candM[cntMo + __popcll(bmo & lt)] = fabs((double)mt);
       if (keepP) {
         const int64_t pos = ob + cntP + __popcll(bp & lt);
         Po.idx[pos] = k;
         Po.val[pos] = pt;
-        if (md.colcap) s_candP[cntP + __popcll(bp & lt)] = fabs((double)pt);
       }
       if (keepPT) {
         const int64_t pos = ob + cntPT + __popcll(bpt & lt);
@@ -855,13 +948,16 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
       }
     }
     if (md.colcap) {
+      // thresholds from the candidates this wave has just written (L1/L2 resident)
       const int k = kcol[j];
+      __threadfence_block();
+      __syncthreads();
       if (md.doM) {
-        const double t = kth_largest(s_candM, cntMo, k - 1);
+        const double t = kth_largest_cols(Mo.idx + ob, Mo.val + ob, cntM, (int)j, k - 1);
         if (lane == 0) tM[j] = t;
       }
       if (md.doP) {
-        const double t = kth_largest(s_candP, cntP, k);
+        const double t = kth_largest_cols(Po.idx + ob, Po.val + ob, cntP, -1, k);
         if (lane == 0) tP[j] = t;
       }
     }
@@ -877,12 +973,12 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
   }
 }
 
-static int update_deg(Tile t) { return t.L >= 2048 ? 512 : 64; }
+static int update_deg(Tile t) { return t.L >= 2048 ? 256 : 64; }
 
-static size_t update_lds(Tile t) {
+static size_t update_lds(Tile t, bool small) {
   const int DG = update_deg(t);
-  return (size_t)t.L * 4 + (size_t)t.H * 4 * 2 + (size_t)DG * 4 * 2 + 4 + (size_t)t.L * 8 +
-         (size_t)DG * 8 + (size_t)(t.H / 2) * 8 + 64;
+  return (size_t)t.L * 4 + (size_t)t.H * 4 + (size_t)DG * 4 * 2 + 4 + 8 + (size_t)t.L * 8 +
+         (size_t)DG * 8 + (small ? 0 : (size_t)DG * 8) + 96;
 }
 
 template <typename T>
@@ -891,10 +987,11 @@ void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, Up
                    double* tP, BigList big, const Seg& seg, DevState* st, Tile small, Tile large,
                    hipStream_t s) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
-  hipLaunchKernelGGL(k_update<T>, dim3(g_grid_cols), dim3(SPAI_WAVE), update_lds(small), s, A, M,
+  hipLaunchKernelGGL(k_update<T>, dim3(resident_grid(k_update<T>, update_lds(small, true))),
+                     dim3(SPAI_WAVE), update_lds(small, true), s, A, M,
                      R, P, PT, md, off, total, kcol, tM, tP, big, seg, st, 0, small.L, small.H,
                      update_deg(small));
-  hipLaunchKernelGGL(k_update<T>, dim3(256), dim3(SPAI_WAVE), update_lds(large), s, A, M, R, P,
+  hipLaunchKernelGGL(k_update<T>, dim3(256), dim3(SPAI_WAVE), update_lds(large, false), s, A, M, R, P,
                      PT, md, off, total, kcol, tM, tP, big, seg, st, 1, large.L, large.H,
                      update_deg(large));
 }
@@ -941,14 +1038,47 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist_exp(Pair<T> Xp, int ex
   if (lane == 0 && diag) atomicAdd((unsigned long long*)&st->sel_diag, (unsigned long long)diag);
 }
 
+// Find, with one 1024-thread block, the bin i holding the rank-th largest key of a
+// histogram counted from the top bin down: *bin = i, *above = keys in bins above i.
+// Each thread owns nbins / 1024 consecutive bins (thread 0 the highest).
+__device__ inline void find_bin_desc(const unsigned long long* hist, int nbins, long long rank,
+                                     long long* total, int* bin, long long* above) {
+  __shared__ int64_t sh[1024];
+  __shared__ int s_bin;
+  __shared__ long long s_above, s_total;
+  const int t = threadIdx.x;
+  const int per = nbins / 1024;
+  const int hi = nbins - 1 - t * per;            // this thread's bins: hi, hi-1, ..., hi-per+1
+  long long loc = 0;
+  for (int k = 0; k < per; ++k) loc += (long long)hist[hi - k];
+  int64_t tot;
+  const int64_t before = block_excl_scan_i64(loc, sh, &tot);
+  if (t == 0) { s_total = tot; s_bin = -1; s_above = 0; }
+  __syncthreads();
+  if (rank >= 1 && before < rank && before + loc >= rank) {
+    long long acc = before;
+    for (int k = 0; k < per; ++k) {
+      const long long c = (long long)hist[hi - k];
+      if (acc + c >= rank) { s_bin = hi - k; s_above = acc; break; }
+      acc += c;
+    }
+  }
+  __syncthreads();
+  *total = s_total;
+  *bin = s_bin;
+  *above = s_above;
+}
+
 // find the exponent bin of the (b+1)-th largest; b = m - (diagonal count if excluded)
-__global__ void k_sel_find_exp(const unsigned long long* hist, int excl_diag, int64_t m,
-                               double* thr, DevState* st) {
+__global__ __launch_bounds__(1024) void k_sel_find_exp(const unsigned long long* hist,
+                                                       int excl_diag, int64_t m, double* thr,
+                                                       DevState* st) {
   if (!st->any_active || !st->iter_active) return;
-  if (threadIdx.x != 0) return;
-  long long total = 0;
-  for (int i = 0; i < 2048; ++i) total += (long long)hist[i];
   const long long b = m - (excl_diag ? st->sel_diag : 0);
+  long long total, above;
+  int bin;
+  find_bin_desc(hist, 2048, b + 1, &total, &bin, &above);
+  if (threadIdx.x != 0) return;
   st->sel_count = 0;
   if (b < 0) {                      // cap below the diagonal count: keep only the diagonal
     st->sel_done = 1;
@@ -960,49 +1090,77 @@ __global__ void k_sel_find_exp(const unsigned long long* hist, int excl_diag, in
     *thr = 0.0;
     return;
   }
-  long long acc = 0;
-  for (int i = 2047; i >= 0; --i) {
-    const long long c = (long long)hist[i];
-    if (acc + c >= b + 1) {
-      st->sel_prefix = (unsigned long long)i << 52;
-      st->sel_rank = (b + 1) - acc;
-      break;
-    }
-    acc += c;
-  }
+  st->sel_prefix = (unsigned long long)bin << 52;
+  st->sel_rank = (b + 1) - above;
   st->sel_done = 0;
 }
 
-// gather the keys inside the selected exponent bin
+// gather the keys inside the selected exponent bin: each workgroup stages its keys
+// in LDS and reserves global space with one atomic per flush
+constexpr int kStage = 2048;
 template <typename T>
 __global__ __launch_bounds__(kSelThreads) void k_sel_collect(Pair<T> Xp, int excl_diag,
                                                              unsigned long long* selbuf,
                                                              int64_t n, DevState* st) {
   if (!st->any_active || !st->iter_active || st->sel_done) return;
+  __shared__ unsigned long long stage[kStage];
+  __shared__ int s_cnt;
+  __shared__ unsigned long long s_base;
   const Cols<T> X = Xp.nxt();
   const unsigned long long want = st->sel_prefix >> 52;
   const int wid = threadIdx.x / SPAI_WAVE;
   const int lane = lane_id();
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
   ColumnWalk w(n, (int64_t)wid * gridDim.x + blockIdx.x, (int64_t)gridDim.x * (kSelThreads / 64));
-  for (int64_t j = w.begin; j < w.end; j += w.step) {
-    const int64_t b = X.beg[j];
-    const int len = X.len[j];
-    for (int base = 0; base < len; base += SPAI_WAVE) {
-      const int e = base + lane;
-      bool take = false;
-      unsigned long long key = 0;
-      if (e < len && !(excl_diag && X.idx[b + e] == (int)j)) {
-        key = mag_key((double)X.val[b + e]);
-        take = (key >> 52) == want;
-      }
-      const unsigned long long bal = __ballot(take);
-      if (bal) {
-        unsigned long long basepos = 0;
-        if (lane == 0) basepos = atomicAdd(&st->sel_count, (unsigned long long)__popcll(bal));
-        basepos = __shfl(basepos, 0, SPAI_WAVE);
-        if (take) selbuf[basepos + __popcll(bal & lanemask_lt())] = key;
+  // every wave walks the same number of rounds so the flush barriers line up
+  const int64_t my = w.begin < w.end ? (w.end - w.begin + w.step - 1) / w.step : 0;
+  __shared__ int64_t s_rounds[kSelThreads / 64];
+  if (lane == 0) s_rounds[wid] = my;
+  __syncthreads();
+  int64_t rounds = 0;
+  for (int i = 0; i < kSelThreads / 64; ++i) rounds = s_rounds[i] > rounds ? s_rounds[i] : rounds;
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t j = w.begin + r * w.step;
+    if (j < w.end) {
+      const int64_t b = X.beg[j];
+      const int len = X.len[j];
+      for (int base = 0; base < len; base += SPAI_WAVE) {
+        const int e = base + lane;
+        bool take = false;
+        unsigned long long key = 0;
+        if (e < len && !(excl_diag && X.idx[b + e] == (int)j)) {
+          key = mag_key((double)X.val[b + e]);
+          take = (key >> 52) == want;
+        }
+        const unsigned long long bal = __ballot(take);
+        if (bal) {
+          int pos0 = 0;
+          if (lane == 0) pos0 = atomicAdd(&s_cnt, __popcll(bal));
+          pos0 = __shfl(pos0, 0, SPAI_WAVE);
+          const int pos = pos0 + __popcll(bal & lanemask_lt());
+          if (take) {
+            if (pos < kStage) {
+              stage[pos] = key;
+            } else {                         // staging full: reserve a global slot directly
+              const unsigned long long g = atomicAdd(&st->sel_count, 1ull);
+              selbuf[g] = key;
+            }
+          }
+        }
       }
     }
+    // flush when the stage is at least half full (and at the end)
+    __syncthreads();
+    const int c = s_cnt < kStage ? s_cnt : kStage;
+    if (c >= kStage / 2 || r == rounds - 1) {
+      if (threadIdx.x == 0) s_base = c ? atomicAdd(&st->sel_count, (unsigned long long)c) : 0;
+      __syncthreads();
+      for (int i = threadIdx.x; i < c; i += kSelThreads) selbuf[s_base + i] = stage[i];
+      __syncthreads();
+      if (threadIdx.x == 0) s_cnt = 0;
+    }
+    __syncthreads();
   }
 }
 
@@ -1028,20 +1186,17 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist_buf(const unsigned lon
     if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
 }
 
-__global__ void k_sel_find_buf(const unsigned long long* hist, int shift, double eta,
-                               double* thr, DevState* st) {
+__global__ __launch_bounds__(1024) void k_sel_find_buf(const unsigned long long* hist, int shift,
+                                                       double eta, double* thr, DevState* st) {
   if (!st->any_active || !st->iter_active || st->sel_done) return;
-  if (threadIdx.x != 0) return;
-  long long acc = 0;
   const long long rank = st->sel_rank;
-  for (int i = 8191; i >= 0; --i) {
-    const long long c = (long long)hist[i];
-    if (acc + c >= rank) {
-      st->sel_prefix |= (unsigned long long)i << shift;
-      st->sel_rank = rank - acc;
-      break;
-    }
-    acc += c;
+  long long total, above;
+  int bin;
+  find_bin_desc(hist, 8192, rank, &total, &bin, &above);
+  if (threadIdx.x != 0) return;
+  if (bin >= 0) {
+    st->sel_prefix |= (unsigned long long)bin << shift;
+    st->sel_rank = rank - above;
   }
   if (shift == 0) {
     const double t = __longlong_as_double((long long)st->sel_prefix);
@@ -1072,14 +1227,14 @@ void launch_global_select(Pair<T> X, int exclude_diag, int64_t m, double eta, in
   hipLaunchKernelGGL(k_sel_reset, dim3(1), dim3(1024), 0, s, hist, 8192, st);
   hipLaunchKernelGGL(k_sel_hist_exp<T>, dim3(kSelGrid), dim3(kSelThreads), 0, s, X, exclude_diag,
                      hist, n, st);
-  hipLaunchKernelGGL(k_sel_find_exp, dim3(1), dim3(64), 0, s, hist, exclude_diag, m, thr, st);
+  hipLaunchKernelGGL(k_sel_find_exp, dim3(1), dim3(1024), 0, s, hist, exclude_diag, m, thr, st);
   hipLaunchKernelGGL(k_sel_collect<T>, dim3(kSelGrid), dim3(kSelThreads), 0, s, X, exclude_diag,
                      selbuf, n, st);
   for (int shift = 39; shift >= 0; shift -= 13) {
     hipLaunchKernelGGL(k_hist_clear, dim3(1), dim3(1024), 0, s, hist, 8192, st);
     hipLaunchKernelGGL(k_sel_hist_buf, dim3(256), dim3(kSelThreads), 0, s, selbuf, shift, hist,
                        st);
-    hipLaunchKernelGGL(k_sel_find_buf, dim3(1), dim3(64), 0, s, hist, shift, eta, thr, st);
+    hipLaunchKernelGGL(k_sel_find_buf, dim3(1), dim3(1024), 0, s, hist, shift, eta, thr, st);
   }
 }
 
@@ -1096,7 +1251,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
   const Cols<T> X = Xp.nxt();
   const int lane = lane_id();
   const double g = global ? *gthr : 0.0;
-  unsigned long long kept = 0;
+  unsigned long long kept = 0, seen = 0;
   ColumnWalk w(n, blockIdx.x, gridDim.x);
   for (int64_t j = w.begin; j < w.end; j += w.step) {
     const int64_t b = X.beg[j];
@@ -1135,10 +1290,11 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
     }
     if (lane == 0) X.len[j] = cnt;
     kept += (unsigned long long)cnt;
+    seen += (unsigned long long)len;
   }
-  if (lane == 0 && kept) {
-    unsigned long long* dst = (kind == 0) ? &st->nnz_m : (kind == 1 ? &st->nnz_p : nullptr);
-    if (dst) atomicAdd(dst, kept);
+  if (lane == 0 && blockIdx.x < kCntSlots) {
+    st->cnt[(3 + kind) * kCntSlots + blockIdx.x] += kept;
+    st->cnt[kind * kCntSlots + blockIdx.x] += seen;
   }
 }
 
@@ -1146,7 +1302,8 @@ template <typename T>
 void launch_compact(Pair<T> X, int kind, int colcap, int sym, int global, const double* tcol,
                     double eta, int64_t n, DevState* st, hipStream_t s) {
   const double* gthr = kind == 0 ? &st->thrM : &st->thrP;
-  hipLaunchKernelGGL(k_compact<T>, dim3(g_grid_cols), dim3(SPAI_WAVE), 0, s, X, kind, colcap, sym,
+  hipLaunchKernelGGL(k_compact<T>, dim3(resident_grid(k_compact<T>, 0)), dim3(SPAI_WAVE), 0, s, X,
+                     kind, colcap, sym,
                      global, tcol, gthr, eta, n, st);
 }
 

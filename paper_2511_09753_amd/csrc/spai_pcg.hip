@@ -24,14 +24,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kGrid = 2048;
 
-struct Mat {                  // CSR with float64 or float32 values
-  int64_t n;
-  const int64_t* rowptr;
-  const int32_t* col;
-  const double* val;
-  const float* val32;
-  __device__ __forceinline__ double v(int64_t q) const { return val32 ? (double)val32[q] : val[q]; }
-};
+using Mat = PcgMat;
 
 // Y[:, c0:c0+R) = A X[:, c0:c0+R) and per-block partials of sum_i W[i, r] Y[i, r].
 // Threads are (row, rhs) pairs: R = pow2 >= the chunk width, 256 / R rows per block step.
@@ -49,7 +42,8 @@ __global__ __launch_bounds__(kThreads) void k_spmm_dot(Mat A, const double* X, d
     const int64_t i = base + roff;
     if (i < A.n && on) {
       double y = 0.0;
-      for (int64_t q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q)
+      const int64_t q0 = A.row_begin(i), q1 = A.row_end(i);
+      for (int64_t q = q0; q < q1; ++q)
         y += A.v(q) * X[(int64_t)A.col[q] * nrhs + c0 + r];
       Y[i * nrhs + c0 + r] = y;
       if (W) acc += W[i * nrhs + c0 + r] * y;
@@ -97,12 +91,20 @@ __global__ __launch_bounds__(kThreads) void k_dot_rows(const double* Xa, const d
   }
 }
 
-__global__ void k_reduce_parts(const double* part, int nblocks, int nrhs, double* out) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
+// one workgroup per right-hand side: fixed strided partial sums, then a fixed tree
+__global__ __launch_bounds__(kThreads) void k_reduce_parts(const double* part, int nblocks,
+                                                           int nrhs, double* out) {
+  __shared__ double sh[kThreads];
+  const int r = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * nrhs + r];
-  out[r] = s;
+  for (int b = threadIdx.x; b < nblocks; b += kThreads) s += part[(int64_t)b * nrhs + r];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = sh[0];
 }
 
 struct RhsState {
@@ -232,8 +234,7 @@ struct Solver {
                          out ? part : nullptr);
     }
     if (out)
-      hipLaunchKernelGGL(k_reduce_parts, dim3((nrhs + 63) / 64), dim3(64), 0, s, part, kGrid, nrhs,
-                         out);
+      hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(kThreads), 0, s, part, kGrid, nrhs, out);
   }
 
   void dot(const double* Xa, const double* Xb, const double* Xc, double* out) {
@@ -243,7 +244,7 @@ struct Solver {
       hipLaunchKernelGGL(k_dot_rows, dim3(kGrid), dim3(kThreads), 0, s, Xa, Xb, Xc, n, nrhs, c0, cw, R,
                          part);
     }
-    hipLaunchKernelGGL(k_reduce_parts, dim3((nrhs + 63) / 64), dim3(64), 0, s, part, kGrid, nrhs, out);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(kThreads), 0, s, part, kGrid, nrhs, out);
   }
 
   void iteration(double rtol) {
@@ -266,11 +267,10 @@ int upload_csr(DevPool& pool, const HostCsr& h, bool f32, Mat& m, hipStream_t s)
   if ((rc = pool.alloc(&rp, h.n + 1)) || (rc = pool.alloc(&c, h.nnz))) return rc;
   HIPCHK(hipMemcpyAsync(rp, h.rowptr.data(), sizeof(int64_t) * (h.n + 1), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(c, h.col.data(), sizeof(int32_t) * h.nnz, hipMemcpyHostToDevice, s));
+  m = Mat{};
   m.n = h.n;
   m.rowptr = rp;
   m.col = c;
-  m.val = nullptr;
-  m.val32 = nullptr;
   if (f32) {
     std::vector<float> v(h.nnz);
     for (int64_t q = 0; q < h.nnz; ++q) v[q] = (float)h.val[q];
@@ -293,6 +293,72 @@ int upload_csr(DevPool& pool, const HostCsr& h, bool f32, Mat& m, hipStream_t s)
 
 using namespace spai;
 
+namespace spai {
+
+int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double* dX, double rtol,
+            int max_iter, int* iters, double* relres, hipStream_t s) {
+  int rc;
+  DevPool pool;
+  Solver S{};
+  S.A = A;
+  S.M = M;
+  S.n = A.n;
+  S.nrhs = nrhs;
+  S.s = s;
+  const int64_t tot = S.n * nrhs;
+  if ((rc = pool.alloc(&S.r, tot)) || (rc = pool.alloc(&S.z, tot)) || (rc = pool.alloc(&S.p, tot)) ||
+      (rc = pool.alloc(&S.q, tot)) || (rc = pool.alloc(&S.part, (int64_t)kGrid * nrhs)) ||
+      (rc = pool.alloc(&S.tmp, nrhs)) || (rc = pool.alloc(&S.S, nrhs)) || (rc = pool.alloc(&S.nactive, 1)))
+    return rc;
+  S.b = dB;
+  S.x = dX;
+  HIPCHK(hipMemsetAsync(S.nactive, 0, sizeof(int), s));
+  HIPCHK(hipMemsetAsync(S.S, 0, sizeof(RhsState) * nrhs, s));
+  const dim3 gs((nrhs + 63) / 64), bs(64);
+  // x_0 = 0, r = b, z = M r, p = z
+  hipLaunchKernelGGL(k_fill, dim3(kGrid), dim3(kThreads), 0, s, S.x, 0.0, tot);
+  hipLaunchKernelGGL(k_copy, dim3(kGrid), dim3(kThreads), 0, s, S.r, dB, tot);
+  S.dot(dB, dB, nullptr, S.tmp);
+  hipLaunchKernelGGL(k_init_rhs, gs, bs, 0, s, S.S, S.tmp, nrhs, S.nactive);
+  S.spmm(S.M, S.r, S.z, S.r, S.tmp);
+  hipLaunchKernelGGL(k_set_rz, gs, bs, 0, s, S.S, S.tmp, nrhs);
+  hipLaunchKernelGGL(k_copy, dim3(kGrid), dim3(kThreads), 0, s, S.p, S.z, tot);
+  HIPCHK(hipGetLastError());
+  // iterate in chunks, checking the running count between chunks
+  int it = 0;
+  const int chunk = 8;
+  while (it < max_iter) {
+    int nact = 0;
+    HIPCHK(hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (nact == 0) break;
+    const int k = std::min(chunk, max_iter - it);
+    for (int t = 0; t < k; ++t) S.iteration(rtol);
+    HIPCHK(hipGetLastError());
+    it += k;
+  }
+  // true residual ||b - A x|| / ||b||
+  S.spmm(S.A, S.x, S.q, nullptr, nullptr);
+  S.dot(dB, dB, S.q, S.tmp);     // sum (b - Ax)^2
+  std::vector<double> rr(nrhs);
+  HIPCHK(hipMemcpyAsync(rr.data(), S.tmp, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+  std::vector<RhsState> hs(nrhs);
+  HIPCHK(hipMemcpyAsync(hs.data(), S.S, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  bool indef = false, unconv = false;
+  for (int r = 0; r < nrhs; ++r) {
+    if (iters) iters[r] = hs[r].iters;
+    if (relres) relres[r] = hs[r].bnorm > 0.0 ? std::sqrt(rr[r]) / hs[r].bnorm : 0.0;
+    if (hs[r].status == 4) indef = true;
+    if (hs[r].status == 0) unconv = true;
+  }
+  if (indef) return PCG_INDEFINITE;
+  if (unconv) return SPAI_MAXITER;
+  return SPAI_OK;
+}
+
+}  // namespace spai
+
 extern "C" int pcg_solve(const spai_csr_t* A, const spai_csr_t* M, int nrhs, const double* B,
                          double* X, double rtol, int max_iter, int* iters, double* relres,
                          const spai_opts_t* opts) {
@@ -308,17 +374,10 @@ extern "C" int pcg_solve(const spai_csr_t* A, const spai_csr_t* M, int nrhs, con
     if (opts) o = *opts;
     hipStream_t s = (hipStream_t)o.stream;
     DevPool pool;
-    Solver S{};
-    S.n = hA.n;
-    S.nrhs = nrhs;
-    S.s = s;
-    if ((rc = upload_csr(pool, hA, false, S.A, s))) return rc;
-    if ((rc = upload_csr(pool, hM, o.precision == SPAI_PREC_MIXED, S.M, s))) return rc;
-    const int64_t tot = S.n * nrhs;
-    if ((rc = pool.alloc(&S.r, tot)) || (rc = pool.alloc(&S.z, tot)) || (rc = pool.alloc(&S.p, tot)) ||
-        (rc = pool.alloc(&S.q, tot)) || (rc = pool.alloc(&S.part, (int64_t)kGrid * nrhs)) ||
-        (rc = pool.alloc(&S.tmp, nrhs)) || (rc = pool.alloc(&S.S, nrhs)) || (rc = pool.alloc(&S.nactive, 1)))
-      return rc;
+    Mat dA, dM;
+    if ((rc = upload_csr(pool, hA, false, dA, s))) return rc;
+    if ((rc = upload_csr(pool, hM, o.precision == SPAI_PREC_MIXED, dM, s))) return rc;
+    const int64_t tot = hA.n * nrhs;
     const double* dB = B;
     double* dX = X;
     if (!A->on_device) {
@@ -328,52 +387,13 @@ extern "C" int pcg_solve(const spai_csr_t* A, const spai_csr_t* M, int nrhs, con
       dB = b2;
       dX = x2;
     }
-    S.b = dB;
-    S.x = dX;
-    HIPCHK(hipMemsetAsync(S.nactive, 0, sizeof(int), s));
-    HIPCHK(hipMemsetAsync(S.S, 0, sizeof(RhsState) * nrhs, s));
-    const dim3 gs((nrhs + 63) / 64), bs(64);
-    // x_0 = 0, r = b, z = M r, p = z
-    hipLaunchKernelGGL(k_fill, dim3(kGrid), dim3(kThreads), 0, s, S.x, 0.0, tot);
-    hipLaunchKernelGGL(k_copy, dim3(kGrid), dim3(kThreads), 0, s, S.r, dB, tot);
-    S.dot(dB, dB, nullptr, S.tmp);
-    hipLaunchKernelGGL(k_init_rhs, gs, bs, 0, s, S.S, S.tmp, nrhs, S.nactive);
-    S.spmm(S.M, S.r, S.z, S.r, S.tmp);
-    hipLaunchKernelGGL(k_set_rz, gs, bs, 0, s, S.S, S.tmp, nrhs);
-    hipLaunchKernelGGL(k_copy, dim3(kGrid), dim3(kThreads), 0, s, S.p, S.z, tot);
-    HIPCHK(hipGetLastError());
-    // iterate in chunks, checking the running count between chunks
-    int it = 0;
-    const int chunk = 8;
-    while (it < max_iter) {
-      int nact = 0;
-      HIPCHK(hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, s));
+    rc = pcg_run(dA, dM, nrhs, dB, dX, rtol, max_iter, iters, relres, s);
+    if (rc < 0) return rc;
+    if (!A->on_device) {
+      HIPCHK(hipMemcpyAsync(X, dX, sizeof(double) * tot, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      if (nact == 0) break;
-      const int k = std::min(chunk, max_iter - it);
-      for (int t = 0; t < k; ++t) S.iteration(rtol);
-      HIPCHK(hipGetLastError());
-      it += k;
     }
-    // true residual ||b - A x|| / ||b||
-    S.spmm(S.A, S.x, S.q, nullptr, nullptr);
-    S.dot(dB, dB, S.q, S.tmp);     // sum (b - Ax)^2
-    std::vector<double> rr(nrhs);
-    HIPCHK(hipMemcpyAsync(rr.data(), S.tmp, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-    std::vector<RhsState> hs(nrhs);
-    HIPCHK(hipMemcpyAsync(hs.data(), S.S, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, s));
-    if (!A->on_device) HIPCHK(hipMemcpyAsync(X, dX, sizeof(double) * tot, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    bool indef = false, unconv = false;
-    for (int r = 0; r < nrhs; ++r) {
-      if (iters) iters[r] = hs[r].iters;
-      if (relres) relres[r] = hs[r].bnorm > 0.0 ? std::sqrt(rr[r]) / hs[r].bnorm : 0.0;
-      if (hs[r].status == 4) indef = true;
-      if (hs[r].status == 0) unconv = true;
-    }
-    if (indef) return PCG_INDEFINITE;
-    if (unconv) return SPAI_MAXITER;
-    return SPAI_OK;
+    return rc;
   } catch (const std::bad_alloc&) {
     return fail(SPAI_ERR_NOMEM, "host allocation failed");
   } catch (...) {

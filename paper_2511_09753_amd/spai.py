@@ -46,14 +46,17 @@ class CapT(C.Structure):
 class OptsT(C.Structure):
     _fields_ = [("precision", C.c_int), ("symmetrize", C.c_int), ("drop_tol", C.c_double),
                 ("tie_eta", C.c_double), ("stream", C.c_void_p),
-                ("device_pool_limit", C.c_int64)]
+                ("device_pool_limit", C.c_int64), ("profile", C.c_int)]
 
 
 EXPORTS = [
     "spai_default_opts", "spai_create", "spai_iterate", "spai_get", "spai_stats",
     "spai_destroy", "pcg_solve", "spai_loss_fwd", "spai_loss_bwd", "spai_create_batched",
-    "spai_batched_resid", "spai_last_error", "spai_status_string",
+    "spai_batched_resid", "spai_last_error", "spai_status_string", "spai_reset", "spai_pcg",
+    "spai_profile",
 ]
+PHASES = ["dots", "update", "resid", "select", "compact", "bounds", "scalar", "pcg"]
+COUNTS = ["cand_m", "cand_p", "cand_pt", "kept_m", "kept_p", "kept_pt", "resid", "iters"]
 
 _lib = None
 
@@ -92,6 +95,9 @@ def load():
                                   C.POINTER(OptsT)]
     lib.spai_loss_bwd.argtypes = [C.POINTER(CsrT), C.POINTER(CsrT), C.c_double, P, P,
                                   C.POINTER(OptsT)]
+    lib.spai_reset.argtypes = [P]
+    lib.spai_pcg.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int, P, P, C.c_int]
+    lib.spai_profile.argtypes = [P, P, P, P]
     lib.spai_last_error.restype = C.c_char_p
     lib.spai_status_string.restype = C.c_char_p
     lib.spai_status_string.argtypes = [C.c_int]
@@ -170,6 +176,7 @@ class Options:
     tie_eta: float = 1e-9
     stream: object = None
     device_pool_limit: int = 0
+    profile: bool = False
 
     def c(self):
         o = OptsT()
@@ -180,6 +187,7 @@ class Options:
         o.tie_eta = self.tie_eta
         o.stream = _stream_ptr(self.stream)
         o.device_pool_limit = int(self.device_pool_limit)
+        o.profile = 1 if self.profile else 0
         return o
 
 
@@ -250,6 +258,47 @@ class SPAI:
                                  C.byref(s1), C.byref(s2), C.byref(fb)))
         return {"iters": it.value, "resid": res.value, "nnz_m": nm.value, "nnz_p": npp.value,
                 "step1": s1.value, "step2": s2.value, "mr_fallbacks": fb.value}
+
+    def reset(self):
+        """Restart from M_0 with the same A, method, cap and options."""
+        _check(load().spai_reset(self.h))
+
+    def pcg(self, B, rtol=1e-8, max_iter=10000):
+        """PCG with this handle's A and current M (both already on the device).
+
+        B: numpy (n x nrhs, host) or a torch CUDA tensor (device).  Returns
+        (X, iterations, true relative residuals, status).
+        """
+        torch_in = not isinstance(B, np.ndarray)
+        if torch_in:
+            torch = _torch()
+            Bt = B.to(dtype=torch.float64).contiguous()
+            if Bt.dim() == 1:
+                Bt = Bt[:, None]
+            X = torch.empty_like(Bt)
+            nrhs, bptr, xptr = Bt.shape[1], Bt.data_ptr(), X.data_ptr()
+        else:
+            Bn = np.ascontiguousarray(B, dtype=np.float64)
+            if Bn.ndim == 1:
+                Bn = Bn[:, None]
+            X = np.zeros_like(Bn)
+            nrhs, bptr, xptr = Bn.shape[1], Bn.ctypes.data, X.ctypes.data
+        iters = np.zeros(nrhs, dtype=np.int32)
+        relres = np.zeros(nrhs, dtype=np.float64)
+        rc = load().spai_pcg(self.h, int(nrhs), bptr, xptr, float(rtol), int(max_iter),
+                             iters.ctypes.data, relres.ctypes.data, 1 if torch_in else 0)
+        _check(rc, (SPAI_OK, SPAI_MAXITER, PCG_INDEFINITE))
+        return X, iters, relres, rc
+
+    def profile(self):
+        """Per-phase milliseconds / launches (opts.profile) and traffic counters."""
+        ms = np.zeros(len(PHASES), dtype=np.float64)
+        calls = np.zeros(len(PHASES), dtype=np.int64)
+        counts = np.zeros(len(COUNTS), dtype=np.int64)
+        _check(load().spai_profile(self.h, ms.ctypes.data, calls.ctypes.data, counts.ctypes.data))
+        return ({k: float(v) for k, v in zip(PHASES, ms)},
+                {k: int(v) for k, v in zip(PHASES, calls)},
+                {k: int(v) for k, v in zip(COUNTS, counts)})
 
     def batched_resid(self):
         out = np.zeros(self.nseg, dtype=np.float64)

@@ -225,3 +225,34 @@ def test_batched_per_matrix_parity():
         blk = Mg[off:off + n, off:off + n]
         assert pattern_diff(blk, ref.M) == (set(), set())
         off += n
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+@pytest.mark.parametrize("N", [16, 32])
+def test_handle_pcg_matches_csr_pcg(precision, N):
+    """spai_pcg (the handle's device-resident A and M) == pcg_solve on the exported M;
+    the whole pipeline (SPAI, then PCG) ends as the oracle's does: at 16^3 the SPAI is
+    SPD and beats Jacobi, at 32^3 it is indefinite and PCG reports it."""
+    S = _spai()
+    A = W.lognormal3d(N, W.seed_for(3))
+    n = A.shape[0]
+    h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=30,
+               options=S.Options(precision=precision))
+    h.iterate(30)
+    Mg = h.get()
+    B = W.rhs(n, 3, 5)
+    X1, it1, rel1, rc1 = h.pcg(B, rtol=1e-8)
+    h.close()
+    X2, it2, rel2, rc2 = S.pcg_solve(A, Mg, B, rtol=1e-8, options=S.Options(precision=precision))
+    print("handle pcg", it1, rc1, rel1, "csr pcg", it2, rc2, rel2)
+    assert rc1 == rc2
+    assert list(it1) == list(it2)
+    assert np.max(np.abs(X1 - X2)) <= 1e-12 * max(np.max(np.abs(X2)), 1e-300)
+    ref = O.lomr(A, oracle_rule(A, "global", 2.0, True), 30)
+    _, ito, sto = O.pcg_block(A, ref.M, B, rtol=1e-8)
+    if N == 16:
+        _, itj, _ = O.pcg_block(A, sp.diags(1.0 / A.diagonal()).tocsr(), B, rtol=1e-8)
+        assert rc1 == S.SPAI_OK and all(s == "converged" for s in sto)
+        assert max(abs(a - b) for a, b in zip(it1, ito)) <= 1 and max(it1) < min(itj)
+    else:
+        assert rc1 == S.PCG_INDEFINITE and all(s == "indefinite" for s in sto)
