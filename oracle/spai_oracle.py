@@ -50,7 +50,8 @@ import scipy.sparse as sp
 __all__ = [
     "frob", "fnorm", "initial_iterate", "residual", "DropRule", "cap_counts",
     "drop_main", "drop_direction", "mr", "cg", "lomr", "run", "pcg", "pcg_block",
-    "loss", "loss_grad", "OracleBreakdown",
+    "loss", "loss_grad", "OracleBreakdown", "column_residual", "row_residual",
+    "grad_m_entry", "grad_a_entry",
 ]
 
 UNIT_ROUNDOFF = 2.0 ** -53
@@ -480,3 +481,44 @@ def _on_pattern(G, P):
     rows = np.repeat(np.arange(P.shape[0]), np.diff(P.indptr))
     vals = np.asarray(G[rows, P.indices]).ravel()
     return sp.csr_matrix((vals, P.indices.copy(), P.indptr.copy()), shape=P.shape)
+
+
+# ----------------------------------------------------------------------------
+# single entries of the gradients, from one column / one row of R (for sampling
+# full-size results: perturbing m_kj changes only column j of R, perturbing a_ik only
+# row i)
+# ----------------------------------------------------------------------------
+
+def column_residual(A, M, j):
+    """r_j = e_j - A m_j as a dense float64 vector (column j of R = I - A M).
+
+    Pass A as CSR and M as CSC to avoid format conversions."""
+    A = A if sp.isspmatrix_csr(A) else sp.csr_matrix(A)
+    M = M if sp.isspmatrix_csc(M) else sp.csc_matrix(M)
+    r = -(A @ M[:, j]).toarray().ravel()
+    r[j] += 1.0
+    return r
+
+
+def row_residual(A, M, i):
+    """R(i, :) = e_i^T - A(i, :) M as a dense float64 vector (A, M as CSR)."""
+    A = A if sp.isspmatrix_csr(A) else sp.csr_matrix(A)
+    M = M if sp.isspmatrix_csr(M) else sp.csr_matrix(M)
+    row = -(A[i, :] @ M).toarray().ravel()
+    row[i] += 1.0
+    return row
+
+
+def grad_m_entry(A, M, k, j, A_csc=None):
+    """d f / d m_kj = -2 (A^T r_j)_k = -2 sum_u a_uk r_j(u) (A as CSR, M as CSC)."""
+    A_csc = A_csc if A_csc is not None else sp.csc_matrix(A)
+    r = column_residual(A, M, j)
+    col = A_csc[:, k]
+    return float(-2.0 * (col.T @ r)[0])
+
+
+def grad_a_entry(A, M, i, k):
+    """d f / d a_ik = -2 (R M^T)_ik = -2 sum_j R(i, j) m_kj (A, M as CSR)."""
+    M = M if sp.isspmatrix_csr(M) else sp.csr_matrix(M)
+    row = row_residual(A, M, i)
+    return float(-2.0 * (M[k, :] @ row)[0])

@@ -99,7 +99,7 @@ __device__ __forceinline__ void ks_insert(int* keys, int H, int key) {
 // probing terminates.
 __device__ __forceinline__ void ks_insert_bounded(int* keys, int H, int key, int* cnt, int limit,
                                                   int* over) {
-  if (*((volatile int*)cnt) >= limit) {
+  if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= limit) {
     *over = 1;
     return;
   }
@@ -138,9 +138,57 @@ __device__ inline void bitonic_sort_int(int* a, int S) {
   }
 }
 
+// Ascending bitonic sort of 64 * C keys held in registers: element c * 64 + lane is
+// v[c].  Fully unrolled so every register index is a compile-time constant.
+template <int C>
+__device__ __forceinline__ void wave_bitonic(int (&v)[C]) {
+  const int lane = lane_id();
+  constexpr int S = 64 * C;
+#pragma unroll
+  for (int k = 2; k <= S; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 64) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const int c2 = c ^ (j / 64);
+          if (c2 > c) {
+            const bool asc = (((c * 64 + lane) & k) == 0);
+            const int a = v[c], b = v[c2];
+            if ((a > b) == asc) { v[c] = b; v[c2] = a; }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const int i = c * 64 + lane;
+          const int o = __shfl_xor(v[c], j, SPAI_WAVE);
+          const bool asc = ((i & k) == 0);
+          const bool lower = ((i & j) == 0);
+          v[c] = (lower == asc) ? min(v[c], o) : max(v[c], o);
+        }
+      }
+    }
+  }
+}
+
+template <int C>
+__device__ __forceinline__ void sort_in_registers(int* keys, int cnt) {
+  int v[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int i = c * 64 + lane_id();
+    v[c] = i < cnt ? keys[i] : INT_MAX;
+  }
+  wave_bitonic<C>(v);
+#pragma unroll
+  for (int c = 0; c < C; ++c) keys[c * 64 + lane_id()] = v[c];
+}
+
 // Sort the keys of the set in place: keys[0..cnt) ascending, returns cnt.  The
 // compaction writes slot s to position <= s after the whole 64-slot chunk has been
-// read, so it can run in place; the tail up to next_pow2(cnt) is padded for the sort.
+// read, so it can run in place.  Up to 256 keys are sorted in registers with
+// shuffles; larger sets by the LDS bitonic network.
 __device__ inline int ks_sort_inplace(int* keys, int H) {
   int cnt = 0;
   for (int base = 0; base < H; base += SPAI_WAVE) {
@@ -152,10 +200,20 @@ __device__ inline int ks_sort_inplace(int* keys, int H) {
     cnt += __popcll(m);
     __syncthreads();
   }
-  int S = next_pow2(cnt > 0 ? cnt : 1);
-  for (int i = cnt + lane_id(); i < S; i += SPAI_WAVE) keys[i] = INT_MAX;
+  if (cnt <= 1) return cnt;
+  if (cnt <= 64 && H >= 64) {
+    sort_in_registers<1>(keys, cnt);
+  } else if (cnt <= 128 && H >= 128) {
+    sort_in_registers<2>(keys, cnt);
+  } else if (cnt <= 256 && H >= 256) {
+    sort_in_registers<4>(keys, cnt);
+  } else {
+    int S = next_pow2(cnt);
+    for (int i = cnt + lane_id(); i < S; i += SPAI_WAVE) keys[i] = INT_MAX;
+    __syncthreads();
+    bitonic_sort_int(keys, S);
+  }
   __syncthreads();
-  if (cnt > 1) bitonic_sort_int(keys, S);
   return cnt;
 }
 

@@ -35,19 +35,25 @@ __device__ __forceinline__ double aval(const Csr& A, int64_t q) {
 }
 
 // 8-byte aligned carve-up of the dynamic LDS of a per-column kernel
+// (offsets only, no integer round trip of the pointer, so the compiler still sees
+// LDS addresses and emits ds_* instructions rather than flat ones)
 struct Carve {
-  char* p;
-  __device__ explicit Carve(char* base) : p(base) {}
+  char* base;
+  unsigned off = 0;
+  __device__ explicit Carve(char* b) : base(b) {}
   template <typename U> __device__ U* take(int count) {
-    uintptr_t a = ((uintptr_t)p + 7) & ~(uintptr_t)7;
-    U* r = (U*)a;
-    p = (char*)(a + sizeof(U) * (size_t)count);
+    off = (off + 7u) & ~7u;
+    U* r = (U*)(base + off);
+    off += (unsigned)(sizeof(U) * (unsigned)count);
     return r;
   }
 };
 
-// Degree prefix of the rows rows[0..cnt): pre[e] = sum_{f<=e} deg(rows[f]); returns the total.
-__device__ inline int degree_prefix(const Csr& A, const int* rows, int cnt, int* pre) {
+// Degree prefix of the rows rows[0..cnt): pre[e] = sum_{f<=e} deg(rows[f]), and the
+// row starts rs[e] = rowptr[rows[e]] (kept so the products need no second lookup).
+// Returns the total.
+__device__ inline int degree_prefix(const Csr& A, const int* rows, int cnt, int* pre,
+                                    int64_t* rs) {
   const int lane = lane_id();
   int run = 0;
   for (int base = 0; base < cnt; base += SPAI_WAVE) {
@@ -55,7 +61,9 @@ __device__ inline int degree_prefix(const Csr& A, const int* rows, int cnt, int*
     int d = 0;
     if (e < cnt) {
       const int l = rows[e];
-      d = (int)(A.rowptr[l + 1] - A.rowptr[l]);
+      const int64_t q0 = A.rowptr[l];
+      d = (int)(A.rowptr[l + 1] - q0);
+      rs[e] = q0;
     }
     const int inc = wave_incl_scan(d);
     if (e < cnt) pre[e] = run + inc;
@@ -64,15 +72,93 @@ __device__ inline int degree_prefix(const Csr& A, const int* rows, int cnt, int*
   return run;
 }
 
-// Insert the column index of every nonzero of the rows rows[0..cnt) of A into the key set.
-__device__ inline void insert_products(const Csr& A, const int* rows, int cnt, const int* pre,
+// Insert the column index of every nonzero of the rows rows[0..cnt) of A into the key
+// set.  Eight products per lane are gathered before any insert so their loads overlap.
+__device__ inline void insert_products(const Csr& A, const int* pre, const int64_t* rs, int cnt,
                                        int total, int* keys, int H, int* kc, int limit,
                                        int* over) {
-  for (int p = lane_id(); p < total; p += SPAI_WAVE) {
-    const int e = upper_bound_int(pre, cnt, p);
-    const int before = e ? pre[e - 1] : 0;
-    const int64_t q = A.rowptr[rows[e]] + (p - before);
-    ks_insert_bounded(keys, H, A.col[q], kc, limit, over);
+  constexpr int U = 8;
+  for (int p0 = 0; p0 < total; p0 += SPAI_WAVE * U) {
+    int cols[U];
+#pragma unroll
+    for (int c = 0; c < U; ++c) {
+      const int p = p0 + c * SPAI_WAVE + lane_id();
+      cols[c] = -1;
+      if (p < total) {
+        const int e = upper_bound_int(pre, cnt, p);
+        const int before = e ? pre[e - 1] : 0;
+        cols[c] = A.col[rs[e] + (p - before)];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < U; ++c)
+      if (cols[c] >= 0) ks_insert_bounded(keys, H, cols[c], kc, limit, over);
+  }
+}
+
+// Pull over the rows of A selected by sorted keys: G keys per lane at a time, their row
+// bounds and first 8 entries loaded together before any is used, each row visited in
+// ascending column order: init(c) before key slot c, entry(c, col, a) per stored entry,
+// done(c, t) after key keys[t].
+template <int G, typename FI, typename FE, typename FD>
+__device__ __forceinline__ void pull_rows(const Csr& A, const int* keys, int nu, FI init, FE entry,
+                                          FD done) {
+  constexpr int U = 8;
+  const int lane = lane_id();
+  for (int t0 = 0; t0 < nu; t0 += SPAI_WAVE * G) {
+    int tt[G];
+    int64_t qa[G], qb[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      tt[c] = t0 + c * SPAI_WAVE + lane;
+      qa[c] = qb[c] = 0;
+      if (tt[c] < nu) {
+        const int u = keys[tt[c]];
+        qa[c] = A.rowptr[u];
+        qb[c] = A.rowptr[u + 1];
+      }
+    }
+    int cols[G][U];
+    double vals[G][U];
+#pragma unroll
+    for (int c = 0; c < G; ++c)
+#pragma unroll
+      for (int k = 0; k < U; ++k)
+        if (qa[c] + k < qb[c]) {
+          cols[c][k] = A.col[qa[c] + k];
+          vals[c][k] = aval(A, qa[c] + k);
+        }
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      if (tt[c] >= nu) continue;
+      init(c);
+#pragma unroll
+      for (int k = 0; k < U; ++k)
+        if (qa[c] + k < qb[c]) entry(c, cols[c][k], vals[c][k]);
+      for (int64_t q = qa[c] + U; q < qb[c]; ++q) entry(c, A.col[q], aval(A, q));
+      done(c, tt[c]);
+    }
+  }
+}
+
+// Row u of A in chunks of up to 8 entries, loaded together, visited in ascending order:
+// f(col, value) for every stored entry.
+template <typename F>
+__device__ __forceinline__ void for_row(const Csr& A, int64_t q0, int64_t q1, F f) {
+  constexpr int U = 8;
+  for (int64_t qb = q0; qb < q1; qb += U) {
+    int cols[U];
+    double vals[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      if (qb + k < q1) {
+        cols[k] = A.col[qb + k];
+        vals[k] = aval(A, qb + k);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (qb + k < q1) f(cols[k], vals[k]);
   }
 }
 
@@ -368,6 +454,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> 
   int* s_sorted = s_keys;
   int* s_kc = cv.take<int>(2);           // distinct-key count, overflow flag
   double* s_mv = cv.take<double>(L);
+  int64_t* s_rs = cv.take<int64_t>(L);   // row starts of the entries of m_j
   const int lane = lane_id();
   const Cols<T> M = Mp.now();
   const bool overflow = *total > R.cap;
@@ -389,7 +476,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> 
       s_mv[e] = (double)M.val[mb + e];
     }
     __syncthreads();
-    const int tot = degree_prefix(A, s_mi, lm, s_pre);
+    const int tot = degree_prefix(A, s_mi, lm, s_pre, s_rs);
     if (overflow) {
       if (lane == 0) atomicOr(&st->err, 2);
       __syncthreads();
@@ -399,7 +486,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> 
     if (lane == 0) { s_kc[0] = 0; s_kc[1] = 0; }
     __syncthreads();
     if (lane == 0) ks_insert_bounded(s_keys, H, (int)j, s_kc, H / 2, s_kc + 1);
-    insert_products(A, s_mi, lm, s_pre, tot, s_keys, H, s_kc, H / 2, s_kc + 1);
+    insert_products(A, s_pre, s_rs, lm, tot, s_keys, H, s_kc, H / 2, s_kc + 1);
     __syncthreads();
     if (s_kc[1]) {                 // more distinct rows than the tile holds
       defer_column(tier, big, st, j);
@@ -410,19 +497,21 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> 
     __syncthreads();
     const int64_t ob = off[j];
     double acc = 0.0;
-    for (int t = lane; t < nu; t += SPAI_WAVE) {
-      const int u = s_sorted[t];
-      double sum = 0.0;
-      for (int64_t q = A.rowptr[u]; q < A.rowptr[u + 1]; ++q) {
-        const int e = bsearch_idx(s_mi, lm, A.col[q]);
-        if (e >= 0) sum += aval(A, q) * s_mv[e];
-      }
-      const double r = ((u == (int)j) ? 1.0 : 0.0) - sum;
-      const T rt = (T)r;
-      R.idx[ob + t] = u;
-      R.val[ob + t] = rt;
-      acc += (double)rt * (double)rt;
-    }
+    double sum[2];
+    pull_rows<2>(
+        A, s_sorted, nu, [&](int c) { sum[c] = 0.0; },
+        [&](int c, int col, double a) {
+          const int e = bsearch_idx(s_mi, lm, col);
+          if (e >= 0) sum[c] += a * s_mv[e];
+        },
+        [&](int c, int t) {
+          const int u = s_sorted[t];
+          const double r = ((u == (int)j) ? 1.0 : 0.0) - sum[c];
+          const T rt = (T)r;
+          R.idx[ob + t] = u;
+          R.val[ob + t] = rt;
+          acc += (double)rt * (double)rt;
+        });
     acc = wave_sum(acc);
     if (lane == 0) {
       colnorm[j] = acc;
@@ -445,7 +534,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> 
 }
 
 static size_t resid_lds(Tile t) {
-  return (size_t)t.L * 4 * 2 + (size_t)t.H * 4 + 8 + (size_t)t.L * 8 + 64;
+  return (size_t)t.L * 4 * 2 + (size_t)t.H * 4 + 8 + (size_t)t.L * 16 + 64;
 }
 
 int g_grid_cols = 2048;   // fallback persistent grid of the per-column kernels
@@ -504,6 +593,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
   int* s_sorted = s_keys;
   int* s_kc = cv.take<int>(2);
   double* s_lv = cv.take<double>(L);
+  int64_t* s_rs = cv.take<int64_t>(L);
   const int lane = lane_id();
   const Cols<T> P = Pp.now();
 
@@ -529,11 +619,11 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
       s_lv[lr + e] = (double)P.val[pb + e];
     }
     __syncthreads();
-    const int tot = degree_prefix(A, s_li, lr + lp, s_pre);
+    const int tot = degree_prefix(A, s_li, lr + lp, s_pre, s_rs);
     ks_clear(s_keys, H);
     if (lane == 0) { s_kc[0] = 0; s_kc[1] = 0; }
     __syncthreads();
-    insert_products(A, s_li, lr + lp, s_pre, tot, s_keys, H, s_kc, H / 2, s_kc + 1);
+    insert_products(A, s_pre, s_rs, lr + lp, tot, s_keys, H, s_kc, H / 2, s_kc + 1);
     __syncthreads();
     if (s_kc[1]) {
       defer_column(tier, big, st, j);
@@ -547,37 +637,37 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
     const int* pi = s_li + lr;
     const double* pv = s_lv + lr;
     double d0 = 0, d1 = 0, d2 = 0, d3 = 0, d4 = 0, d5 = 0;
-    for (int t = lane; t < nu; t += SPAI_WAVE) {
-      const int u = s_sorted[t];
-      double ar = 0.0, ap = 0.0;
-      for (int64_t q = A.rowptr[u]; q < A.rowptr[u + 1]; ++q) {
-        const int l = A.col[q];
-        const double a = aval(A, q);
-        if (lr) {
-          const int e = bsearch_idx(ri, lr, l);
-          if (e >= 0) ar += a * rv[e];
-        }
-        if (lp) {
-          const int e = bsearch_idx(pi, lp, l);
-          if (e >= 0) ap += a * pv[e];
-        }
-      }
-      double ru = 0.0, pu = 0.0;
-      if (lr) {
-        const int e = bsearch_idx(ri, lr, u);
-        if (e >= 0) ru = rv[e];
-      }
-      if (lp) {
-        const int e = bsearch_idx(pi, lp, u);
-        if (e >= 0) pu = pv[e];
-      }
-      d0 += ru * ar;
-      d1 += ar * ar;
-      d2 += ar * ap;
-      d3 += ru * ap;
-      d4 += ap * ap;
-      d5 += pu * ap;
-    }
+    double ar[2], ap[2];
+    pull_rows<2>(
+        A, s_sorted, nu, [&](int c) { ar[c] = 0.0; ap[c] = 0.0; },
+        [&](int c, int l, double a) {
+          if (lr) {
+            const int e = bsearch_idx(ri, lr, l);
+            if (e >= 0) ar[c] += a * rv[e];
+          }
+          if (lp) {
+            const int e = bsearch_idx(pi, lp, l);
+            if (e >= 0) ap[c] += a * pv[e];
+          }
+        },
+        [&](int c, int t) {
+          const int u = s_sorted[t];
+          double ru = 0.0, pu = 0.0;
+          if (lr) {
+            const int e = bsearch_idx(ri, lr, u);
+            if (e >= 0) ru = rv[e];
+          }
+          if (lp) {
+            const int e = bsearch_idx(pi, lp, u);
+            if (e >= 0) pu = pv[e];
+          }
+          d0 += ru * ar[c];
+          d1 += ar[c] * ar[c];
+          d2 += ar[c] * ap[c];
+          d3 += ru * ap[c];
+          d4 += ap[c] * ap[c];
+          d5 += pu * ap[c];
+        });
     d0 = wave_sum(d0);
     d1 = wave_sum(d1);
     d2 = wave_sum(d2);
@@ -601,7 +691,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
 }
 
 static size_t dots_lds(Tile t) {
-  return (size_t)t.L * 4 * 2 + (size_t)t.H * 4 + 8 + (size_t)t.L * 8 + 64;
+  return (size_t)t.L * 4 * 2 + (size_t)t.H * 4 + 8 + (size_t)t.L * 16 + 64;
 }
 
 template <typename T>
@@ -726,7 +816,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
   // small tile: the neighbour columns m_l sit in LDS; large tile: they stay in global
   // memory and are searched in place (s_nbbeg / s_nboff hold their start and length)
   const bool nb_lds = tier == 0;
-  int64_t* s_nbbeg = nb_lds ? nullptr : cv.take<int64_t>(DG);
+  int64_t* s_nbbeg = cv.take<int64_t>(DG);
   const int lane = lane_id();
 
   const Cols<T> M = Mp.now();
@@ -806,6 +896,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
           len = M.len[l];
           s_nbcol[t] = l;
           s_nbval[t] = aval(A, qa + t);
+          s_nbbeg[t] = M.beg[l];
         }
         const int inc = wave_incl_scan(len);
         if (t < deg) s_nboff[t] = onb + run + inc - len;
@@ -813,15 +904,30 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
       }
       if (lane == 0) s_nboff[deg] = onb + run;
       __syncthreads();
-      for (int t = 0; t < deg; ++t) {
-        const int l = s_nbcol[t];
-        const int64_t b = M.beg[l];
-        const int len = M.len[l];
-        const int o = s_nboff[t];
-        for (int e = lane; e < len; e += SPAI_WAVE) {
-          s_li[o + e] = M.idx[b + e];
-          s_lv[o + e] = (double)M.val[b + e];
+      // one flattened gather over all neighbour entries, four per lane in flight
+      constexpr int U = 4;
+      for (int x0 = 0; x0 < run; x0 += SPAI_WAVE * U) {
+        int ix[U];
+        T vx[U];
+        int dst[U];
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+          const int pos = onb + x0 + c * SPAI_WAVE + lane;
+          dst[c] = -1;
+          if (pos < onb + run) {
+            const int t = upper_bound_int(s_nboff + 1, deg, pos);
+            const int64_t src = s_nbbeg[t] + (pos - s_nboff[t]);
+            ix[c] = M.idx[src];
+            vx[c] = M.val[src];
+            dst[c] = pos;
+          }
         }
+#pragma unroll
+        for (int c = 0; c < U; ++c)
+          if (dst[c] >= 0) {
+            s_li[dst[c]] = ix[c];
+            s_lv[dst[c]] = (double)vx[c];
+          }
       }
     } else if (deg) {
       for (int t = lane; t < deg; t += SPAI_WAVE) {
@@ -975,10 +1081,10 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
 
 static int update_deg(Tile t) { return t.L >= 2048 ? 256 : 64; }
 
-static size_t update_lds(Tile t, bool small) {
+static size_t update_lds(Tile t, bool) {
   const int DG = update_deg(t);
   return (size_t)t.L * 4 + (size_t)t.H * 4 + (size_t)DG * 4 * 2 + 4 + 8 + (size_t)t.L * 8 +
-         (size_t)DG * 8 + (small ? 0 : (size_t)DG * 8) + 96;
+         (size_t)DG * 8 * 2 + 96;
 }
 
 template <typename T>

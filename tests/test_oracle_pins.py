@@ -478,3 +478,33 @@ def test_workload_shapes():
     G = W.geometric_graph(1000, 9)
     assert abs(G - G.T).max() == 0
     assert 6.0 < G.nnz / 1000 - 1 < 10.0
+
+
+def test_gradient_entries_match_local_finite_differences():
+    """Single gradient entries against central differences of the one column / row of R
+    they touch (f = sum_j ||r_j||^2 = sum_i ||R(i,:)||^2)."""
+    A = sp.csr_matrix(W.grid9(6, 21))
+    M = sp.csr_matrix(W.loss_m_values(A, W.square_pattern(A), 22))
+    GA, GM = O.loss_grad(A, M)
+    h = 1e-6
+    rng = np.random.default_rng(3)
+    Mc = M.tocoo()
+    for e in rng.choice(M.nnz, 8, replace=False):
+        k, j = int(Mc.row[e]), int(Mc.col[e])
+        Mp, Mm = M.tolil(copy=True), M.tolil(copy=True)
+        Mp[k, j] += h
+        Mm[k, j] -= h
+        fd = (np.sum(O.column_residual(A, Mp, j) ** 2) - np.sum(O.column_residual(A, Mm, j) ** 2)) / (2 * h)
+        g = O.grad_m_entry(A, M, k, j)
+        assert g == pytest.approx(fd, rel=1e-7, abs=1e-9)
+        assert g == pytest.approx(GM[k, j], rel=1e-12, abs=1e-14)
+    Ac = A.tocoo()
+    for e in rng.choice(A.nnz, 8, replace=False):
+        i, k = int(Ac.row[e]), int(Ac.col[e])
+        Ap, Am = A.tolil(copy=True), A.tolil(copy=True)
+        Ap[i, k] += h
+        Am[i, k] -= h
+        fd = (np.sum(O.row_residual(Ap, M, i) ** 2) - np.sum(O.row_residual(Am, M, i) ** 2)) / (2 * h)
+        g = O.grad_a_entry(A, M, i, k)
+        assert g == pytest.approx(fd, rel=1e-7, abs=1e-9)
+        assert g == pytest.approx(GA[i, k], rel=1e-12, abs=1e-14)
