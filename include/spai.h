@@ -57,6 +57,13 @@ enum {
 
 enum { SPAI_MR = 0, SPAI_CG = 1, SPAI_LOMR = 2 };
 enum { SPAI_PREC_F64 = 0, SPAI_PREC_MIXED = 1 };
+
+/* Device layout of A inside a handle (results are bitwise the same in every layout):
+ *  SPAI_AFMT_AUTO: ELL when the largest row degree is at most 64, else CSR;
+ *  SPAI_AFMT_CSR:  CSR only;
+ *  SPAI_AFMT_ELL:  ELL (rows padded to a power-of-two width >= 8), SPAI_ERR_ARG when a
+ *                  row has more than 64 entries. */
+enum { SPAI_AFMT_AUTO = 0, SPAI_AFMT_CSR = 1, SPAI_AFMT_ELL = 2 };
 enum { SPAI_CAP_NONE = 0, SPAI_CAP_GLOBAL = 1, SPAI_CAP_COLUMN = 2 };
 
 typedef struct spai_handle spai_handle_t;
@@ -103,6 +110,7 @@ typedef struct {
                                returns SPAI_ERR_NOMEM                             */
   int profile;              /* 1: time every phase of an iteration with HIP events
                                on the handle's stream (see spai_profile), default 0 */
+  int a_format;             /* SPAI_AFMT_*, default SPAI_AFMT_AUTO                 */
 } spai_opts_t;
 
 /* Fill *opts with the defaults. */

@@ -332,6 +332,40 @@ struct Engine : EngineBase {
       HIPCHK(hipMemcpyAsync(d_v32, v32.data(), sizeof(float) * hA.nnz, hipMemcpyHostToDevice, s));
       A.val32 = d_v32;
     }
+    // ELL copy: row u in slots [u W, (u + 1) W), W = max(8, 2^ceil(log2 maxdeg))
+    const bool ell_ok = maxdeg <= 64;
+    if (opts.a_format == SPAI_AFMT_ELL && !ell_ok)
+      return fail(SPAI_ERR_ARG, "a_format ELL: a row of A has more than 64 entries");
+    if (opts.a_format != SPAI_AFMT_CSR && ell_ok) {
+      int sh = 3;
+      while ((int64_t(1) << sh) < maxdeg) ++sh;
+      const int64_t W = int64_t(1) << sh, tot = n * W;
+      std::vector<int32_t> ec((size_t)tot, -1);
+      std::vector<double> evv((size_t)tot, 0.0);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t q = hA.rowptr[i]; q < hA.rowptr[i + 1]; ++q) {
+          ec[(size_t)(i * W + q - hA.rowptr[i])] = hA.col[q];
+          evv[(size_t)(i * W + q - hA.rowptr[i])] = hA.val[q];
+        }
+      int32_t* d_ec;
+      double* d_ev;
+      if ((rc = dalloc(&d_ec, tot)) || (rc = dalloc(&d_ev, tot))) return rc;
+      HIPCHK(hipMemcpyAsync(d_ec, ec.data(), sizeof(int32_t) * tot, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(d_ev, evv.data(), sizeof(double) * tot, hipMemcpyHostToDevice, s));
+      if (opts.precision == SPAI_PREC_MIXED) {
+        std::vector<float> ev32((size_t)tot);
+        for (int64_t q = 0; q < tot; ++q) ev32[(size_t)q] = (float)evv[(size_t)q];
+        float* d_ev32;
+        if ((rc = dalloc(&d_ev32, tot))) return rc;
+        HIPCHK(hipMemcpyAsync(d_ev32, ev32.data(), sizeof(float) * tot, hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        A.eval32 = d_ev32;
+      }
+      HIPCHK(hipStreamSynchronize(s));
+      A.eshift = sh;
+      A.ecol = d_ec;
+      A.eval = d_ev;
+    }
     // ---- state
     if ((rc = dalloc(&st, 1)) || (rc = dalloc(&segst, nseg)) || (rc = dalloc(&seg_beg, nseg + 1)) ||
         (rc = dalloc(&cnt, (int64_t)kNCnt * kCntSlots)))
@@ -419,9 +453,15 @@ struct Engine : EngineBase {
     const Cols<T>& C = M.b[h.curM];
     PcgMat pa, pm;
     pa.n = n;
-    pa.rowptr = A.rowptr;
-    pa.col = A.col;
-    pa.val = A.val;
+    if (A.eshift >= 0) {
+      pa.eshift = A.eshift;
+      pa.col = A.ecol;
+      pa.val = A.eval;
+    } else {
+      pa.rowptr = A.rowptr;
+      pa.col = A.col;
+      pa.val = A.val;
+    }
     pm.n = n;
     pm.beg = C.beg;
     pm.len = C.len;
@@ -729,6 +769,7 @@ static void fill_defaults(spai_opts_t* o) {
   o->stream = nullptr;
   o->device_pool_limit = 0;
   o->profile = 0;
+  o->a_format = SPAI_AFMT_AUTO;
 }
 
 template <typename T>
@@ -764,6 +805,8 @@ static int check_common(int method, spai_cap_t cap, int max_iter, double tol,
   if (o.precision != SPAI_PREC_F64 && o.precision != SPAI_PREC_MIXED)
     return fail(SPAI_ERR_ARG, "unknown precision");
   if (!(o.drop_tol >= 0.0) || !(o.tie_eta >= 0.0)) return fail(SPAI_ERR_ARG, "bad drop_tol / tie_eta");
+  if (o.a_format != SPAI_AFMT_AUTO && o.a_format != SPAI_AFMT_CSR && o.a_format != SPAI_AFMT_ELL)
+    return fail(SPAI_ERR_ARG, "unknown a_format");
   return SPAI_OK;
 }
 

@@ -23,6 +23,13 @@ struct Csr {                 // A on the device (symmetric: row k == column k)
   const int32_t* col = nullptr;
   const double* val = nullptr;   // float64 values
   const float* val32 = nullptr;  // float32 copy (mixed precision), or null
+  // ELL copy, used when eshift >= 0: row u occupies slots [u << eshift, (u + 1) << eshift)
+  // (width a power of two >= 8), its entries first in ascending column order, then
+  // padding with column -1 and value 0.  Row u's address needs no row-pointer load.
+  int eshift = -1;
+  const int32_t* ecol = nullptr;
+  const double* eval = nullptr;   // float64 values, or null
+  const float* eval32 = nullptr;  // float32 values (mixed precision), or null
 };
 
 template <typename T>
@@ -90,6 +97,91 @@ __device__ __forceinline__ void ks_insert(int* keys, int H, int key) {
     int prev = atomicCAS(&keys[h], -1, key);
     if (prev == -1 || prev == key) return;
     h = (h + 1) & (unsigned)(H - 1);
+  }
+}
+
+// Insert up to U keys per lane (a negative key inserts nothing), every lane's CASes in
+// flight together, then linear probing for the few that collide.  Returns the number
+// of slots this lane claimed.  The caller keeps the table below full (see
+// ks_insert_rows), so every probe sequence ends at a free slot or at its own key.
+template <int U>
+__device__ __forceinline__ int ks_insert_batch(int* keys, int H, const int (&key)[U]) {
+  unsigned h[U];
+  bool pend[U];
+  int claimed = 0;
+#pragma unroll
+  for (int c = 0; c < U; ++c) {
+    pend[c] = key[c] >= 0;
+    h[c] = hash_key(key[c]) & (unsigned)(H - 1);
+  }
+  while (true) {
+    int prev[U];
+#pragma unroll
+    for (int c = 0; c < U; ++c) prev[c] = pend[c] ? atomicCAS(&keys[h[c]], -1, key[c]) : key[c];
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < U; ++c) {
+      if (!pend[c]) continue;
+      if (prev[c] == -1) {
+        ++claimed;
+        pend[c] = false;
+      } else if (prev[c] == key[c]) {
+        pend[c] = false;
+      } else {
+        h[c] = (h[c] + 1) & (unsigned)(H - 1);
+        any = true;
+      }
+    }
+    if (!any) break;
+  }
+  return claimed;
+}
+
+// ---- LDS position map: row index -> positions of that row in up to two lists ------
+// keys[slot] (-1 = empty) and pos[slot], two 16-bit list positions (0xFFFF = absent).
+// The caller sizes the map (a power of two) at least twice the number of keys, so
+// probing terminates.
+constexpr unsigned kNoPos = 0xFFFFu;
+
+__device__ __forceinline__ void lm_clear(int* keys, unsigned* pos, int hs) {
+  for (int i = lane_id(); i < hs; i += SPAI_WAVE) {
+    keys[i] = -1;
+    pos[i] = 0xFFFFFFFFu;
+  }
+}
+
+// record that row `key` sits at position e of list `half` (0 or 1)
+__device__ __forceinline__ void lm_put(int* keys, unsigned* pos, int hs, int key, int half, int e) {
+  unsigned h = hash_key(key) & (unsigned)(hs - 1);
+  while (true) {
+    const int prev = atomicCAS(&keys[h], -1, key);
+    if (prev == -1 || prev == key) break;
+    h = (h + 1) & (unsigned)(hs - 1);
+  }
+  atomicAnd(&pos[h], half ? (((unsigned)e << 16) | 0xFFFFu) : (0xFFFF0000u | (unsigned)e));
+}
+
+// position words of U rows (a negative row is absent); the U first probes (key and
+// position word of the home slot) are issued together
+template <int U>
+__device__ __forceinline__ void lm_find(const int* keys, const unsigned* pos, int hs,
+                                        const int (&key)[U], unsigned (&pw)[U]) {
+  unsigned h[U];
+  int k[U];
+#pragma unroll
+  for (int c = 0; c < U; ++c) {
+    h[c] = hash_key(key[c]) & (unsigned)(hs - 1);
+    k[c] = keys[h[c]];
+    pw[c] = pos[h[c]];
+  }
+#pragma unroll
+  for (int c = 0; c < U; ++c) {
+    while (k[c] != key[c] && k[c] != -1) {
+      h[c] = (h[c] + 1) & (unsigned)(hs - 1);
+      k[c] = keys[h[c]];
+      pw[c] = pos[h[c]];
+    }
+    if (k[c] != key[c] || key[c] < 0) pw[c] = 0xFFFFFFFFu;
   }
 }
 
@@ -243,6 +335,75 @@ __device__ __forceinline__ int bsearch_idx(const int* a, int n, int key) {
     if (a[mid] < key) lo = mid + 1; else hi = mid;
   }
   return (lo < n && a[lo] == key) ? lo : -1;
+}
+
+// U lower-bound searches in lock-step: lookup c looks for key[c] in the ascending list
+// a[base[c] .. base[c] + len[c]) and gets its index there in pos[c], or -1.  All U
+// lookups take the same power-of-two steps, so each step issues U independent LDS
+// reads instead of U dependent chains.
+template <int U>
+__device__ __forceinline__ void search_lockstep(const int* a, const int (&base)[U],
+                                                const int (&len)[U], const int (&key)[U],
+                                                int (&pos)[U]) {
+  int mx = 0;
+#pragma unroll
+  for (int c = 0; c < U; ++c) mx = max(mx, len[c]);
+  int lo[U];
+#pragma unroll
+  for (int c = 0; c < U; ++c) lo[c] = 0;
+  for (int step = mx ? (1 << (31 - __clz(mx))) : 0; step > 0; step >>= 1) {
+#pragma unroll
+    for (int c = 0; c < U; ++c) {
+      const int m = lo[c] + step;
+      if (m <= len[c] && a[base[c] + m - 1] < key[c]) lo[c] = m;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < U; ++c) pos[c] = (lo[c] < len[c] && a[base[c] + lo[c]] == key[c]) ? lo[c] : -1;
+}
+
+// the same with every lookup in one list a[0..n)
+template <int U>
+__device__ __forceinline__ void search_lockstep1(const int* a, int n, const int (&key)[U],
+                                                 int (&pos)[U]) {
+  int lo[U];
+#pragma unroll
+  for (int c = 0; c < U; ++c) lo[c] = 0;
+  for (int step = n ? (1 << (31 - __clz(n))) : 0; step > 0; step >>= 1) {
+#pragma unroll
+    for (int c = 0; c < U; ++c) {
+      const int m = lo[c] + step;
+      if (m <= n && a[m - 1] < key[c]) lo[c] = m;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < U; ++c) pos[c] = (lo[c] < n && a[lo[c]] == key[c]) ? lo[c] : -1;
+}
+
+// the same for two lists a[b0 .. b0 + n0) and a[b1 .. b1 + n1) searched for the same keys
+template <int U>
+__device__ __forceinline__ void search_lockstep2(const int* a, int b0, int n0, int b1, int n1,
+                                                 const int (&key)[U], int (&p0)[U],
+                                                 int (&p1)[U]) {
+  int l0[U], l1[U];
+#pragma unroll
+  for (int c = 0; c < U; ++c) l0[c] = l1[c] = 0;
+  const int mx = max(n0, n1);
+  for (int step = mx ? (1 << (31 - __clz(mx))) : 0; step > 0; step >>= 1) {
+#pragma unroll
+    for (int c = 0; c < U; ++c) {
+      const int m0 = l0[c] + step, m1 = l1[c] + step;
+      const bool g0 = m0 <= n0 && a[b0 + m0 - 1] < key[c];
+      const bool g1 = m1 <= n1 && a[b1 + m1 - 1] < key[c];
+      if (g0) l0[c] = m0;
+      if (g1) l1[c] = m1;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < U; ++c) {
+    p0[c] = (l0[c] < n0 && a[b0 + l0[c]] == key[c]) ? l0[c] : -1;
+    p1[c] = (l1[c] < n1 && a[b1 + l1[c]] == key[c]) ? l1[c] : -1;
+  }
 }
 
 // first position p with a[p] > v in ascending a[0..n)

@@ -52,19 +52,23 @@ struct DevPool {
   ~DevPool();
 };
 
-// matrix operand of the PCG kernels: CSR (rowptr) or padded columns (beg, len), with
-// float64 or float32 values
+// matrix operand of the PCG kernels: ELL (eshift >= 0: row i in [i << eshift,
+// (i + 1) << eshift), padding column -1), padded columns (beg, len) or CSR (rowptr),
+// with float64 or float32 values
 struct PcgMat {
   int64_t n = 0;
+  int eshift = -1;
   const int64_t* rowptr = nullptr;
   const int64_t* beg = nullptr;
   const int32_t* len = nullptr;
   const int32_t* col = nullptr;
   const double* val = nullptr;
   const float* val32 = nullptr;
-  __device__ __forceinline__ int64_t row_begin(int64_t i) const { return beg ? beg[i] : rowptr[i]; }
+  __device__ __forceinline__ int64_t row_begin(int64_t i) const {
+    return eshift >= 0 ? (i << eshift) : beg ? beg[i] : rowptr[i];
+  }
   __device__ __forceinline__ int64_t row_end(int64_t i) const {
-    return beg ? beg[i] + len[i] : rowptr[i + 1];
+    return eshift >= 0 ? ((i + 1) << eshift) : beg ? beg[i] + len[i] : rowptr[i + 1];
   }
   __device__ __forceinline__ double v(int64_t q) const { return val32 ? (double)val32[q] : val[q]; }
 };

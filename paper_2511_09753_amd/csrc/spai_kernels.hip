@@ -49,9 +49,8 @@ struct Carve {
   }
 };
 
-// Degree prefix of the rows rows[0..cnt): pre[e] = sum_{f<=e} deg(rows[f]), and the
-// row starts rs[e] = rowptr[rows[e]] (kept so the products need no second lookup).
-// Returns the total.
+// CSR only: degree prefix of the rows rows[0..cnt): pre[e] = sum_{f<=e} deg(rows[f]),
+// and the row starts rs[e] = rowptr[rows[e]].  Returns the total.
 __device__ inline int degree_prefix(const Csr& A, const int* rows, int cnt, int* pre,
                                     int64_t* rs) {
   const int lane = lane_id();
@@ -72,93 +71,127 @@ __device__ inline int degree_prefix(const Csr& A, const int* rows, int cnt, int*
   return run;
 }
 
-// Insert the column index of every nonzero of the rows rows[0..cnt) of A into the key
-// set.  Eight products per lane are gathered before any insert so their loads overlap.
-__device__ inline void insert_products(const Csr& A, const int* pre, const int64_t* rs, int cnt,
-                                       int total, int* keys, int H, int* kc, int limit,
-                                       int* over) {
-  constexpr int U = 8;
-  for (int p0 = 0; p0 < total; p0 += SPAI_WAVE * U) {
+// Insert into the key set the column index of every nonzero of the rows rows[0..cnt)
+// of A, four products per lane per batch, the loads of a batch in flight together.
+// In ELL the products are the cnt << eshift slots (padding skipped); in CSR they are
+// numbered through the degree prefix (pre, rs, total from degree_prefix).  `have` is
+// the number of distinct keys already in the set; after every batch the count (a wave
+// sum of the slots claimed) is compared with `limit`, and insertion stops once it is
+// exceeded.  With limit + 256 < H the table is never full, so probing terminates.
+// Returns the distinct count (> limit: the set outgrew the tile).
+__device__ inline int insert_products(const Csr& A, const int* rows, int cnt, const int* pre,
+                                      const int64_t* rs, int total, int* keys, int H, int have,
+                                      int limit) {
+  constexpr int U = 4;
+  const bool ell = A.eshift >= 0;
+  const int sh = A.eshift;
+  const int wm = ell ? (1 << sh) - 1 : 0;
+  const int tot = ell ? (cnt << sh) : total;
+  int count = have;
+  for (int p0 = 0; p0 < tot; p0 += SPAI_WAVE * U) {
     int cols[U];
 #pragma unroll
     for (int c = 0; c < U; ++c) {
       const int p = p0 + c * SPAI_WAVE + lane_id();
       cols[c] = -1;
-      if (p < total) {
-        const int e = upper_bound_int(pre, cnt, p);
-        const int before = e ? pre[e - 1] : 0;
-        cols[c] = A.col[rs[e] + (p - before)];
+      if (p < tot) {
+        if (ell) {
+          cols[c] = A.ecol[((int64_t)rows[p >> sh] << sh) + (p & wm)];
+        } else {
+          const int e = upper_bound_int(pre, cnt, p);
+          const int before = e ? pre[e - 1] : 0;
+          cols[c] = A.col[rs[e] + (p - before)];
+        }
       }
     }
+    count += wave_sum_int(ks_insert_batch<U>(keys, H, cols));
+    if (count > limit) break;
+  }
+  return count;
+}
+
+// Eight entries of A's row storage from slot q (q < qe; the row ends at qe), loaded
+// together: cols[k] = -1 where there is no entry.  ELL chunks are aligned 32-byte
+// pieces of the padded row.
+__device__ __forceinline__ void load_chunk(const Csr& A, int64_t q, int64_t qe, int (&cols)[8],
+                                           double (&vals)[8]) {
+  if (A.eshift >= 0) {
+    const int4 c0 = *(const int4*)(A.ecol + q);
+    const int4 c1 = *(const int4*)(A.ecol + q + 4);
+    cols[0] = c0.x; cols[1] = c0.y; cols[2] = c0.z; cols[3] = c0.w;
+    cols[4] = c1.x; cols[5] = c1.y; cols[6] = c1.z; cols[7] = c1.w;
+    if (A.eval32) {
+      const float4 v0 = *(const float4*)(A.eval32 + q);
+      const float4 v1 = *(const float4*)(A.eval32 + q + 4);
+      vals[0] = v0.x; vals[1] = v0.y; vals[2] = v0.z; vals[3] = v0.w;
+      vals[4] = v1.x; vals[5] = v1.y; vals[6] = v1.z; vals[7] = v1.w;
+    } else {
 #pragma unroll
-    for (int c = 0; c < U; ++c)
-      if (cols[c] >= 0) ks_insert_bounded(keys, H, cols[c], kc, limit, over);
+      for (int k = 0; k < 8; k += 2) {
+        const double2 v = *(const double2*)(A.eval + q + k);
+        vals[k] = v.x;
+        vals[k + 1] = v.y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      cols[k] = -1;
+      vals[k] = 0.0;
+      if (q + k < qe) {
+        cols[k] = A.col[q + k];
+        vals[k] = aval(A, q + k);
+      }
+    }
   }
 }
 
-// Pull over the rows of A selected by sorted keys: G keys per lane at a time, their row
-// bounds and first 8 entries loaded together before any is used, each row visited in
-// ascending column order: init(c) before key slot c, entry(c, col, a) per stored entry,
-// done(c, t) after key keys[t].
-template <int G, typename FI, typename FE, typename FD>
-__device__ __forceinline__ void pull_rows(const Csr& A, const int* keys, int nu, FI init, FE entry,
-                                          FD done) {
-  constexpr int U = 8;
+__device__ __forceinline__ void row_span(const Csr& A, int u, int64_t& q0, int64_t& q1) {
+  if (A.eshift >= 0) {
+    q0 = (int64_t)u << A.eshift;
+    q1 = q0 + ((int64_t)1 << A.eshift);
+  } else {
+    q0 = A.rowptr[u];
+    q1 = A.rowptr[u + 1];
+  }
+}
+
+// Pull over the rows of A selected by sorted keys[0..nu): G keys per lane at a time,
+// their first 8-entry chunks loaded together before any is used.  Row u is visited in
+// ascending column order, chunk by chunk: init(c) before key slot c, chunk(c, cols,
+// vals) per chunk (column -1: no entry), done(c, t) after key keys[t].
+template <int G, typename FI, typename FC, typename FD>
+__device__ __forceinline__ void pull_rows(const Csr& A, const int* keys, int nu, FI init,
+                                          FC chunk, FD done) {
   const int lane = lane_id();
   for (int t0 = 0; t0 < nu; t0 += SPAI_WAVE * G) {
     int tt[G];
     int64_t qa[G], qb[G];
+    int cols[G][8];
+    double vals[G][8];
 #pragma unroll
     for (int c = 0; c < G; ++c) {
       tt[c] = t0 + c * SPAI_WAVE + lane;
       qa[c] = qb[c] = 0;
-      if (tt[c] < nu) {
-        const int u = keys[tt[c]];
-        qa[c] = A.rowptr[u];
-        qb[c] = A.rowptr[u + 1];
-      }
+      if (tt[c] < nu) row_span(A, keys[tt[c]], qa[c], qb[c]);
     }
-    int cols[G][U];
-    double vals[G][U];
 #pragma unroll
-    for (int c = 0; c < G; ++c)
+    for (int c = 0; c < G; ++c) {
 #pragma unroll
-      for (int k = 0; k < U; ++k)
-        if (qa[c] + k < qb[c]) {
-          cols[c][k] = A.col[qa[c] + k];
-          vals[c][k] = aval(A, qa[c] + k);
-        }
+      for (int k = 0; k < 8; ++k) cols[c][k] = -1;
+      if (qa[c] < qb[c]) load_chunk(A, qa[c], qb[c], cols[c], vals[c]);
+    }
 #pragma unroll
     for (int c = 0; c < G; ++c) {
       if (tt[c] >= nu) continue;
       init(c);
-#pragma unroll
-      for (int k = 0; k < U; ++k)
-        if (qa[c] + k < qb[c]) entry(c, cols[c][k], vals[c][k]);
-      for (int64_t q = qa[c] + U; q < qb[c]; ++q) entry(c, A.col[q], aval(A, q));
+      chunk(c, cols[c], vals[c]);
+      for (int64_t q = qa[c] + 8; q < qb[c] && cols[c][7] >= 0; q += 8) {
+        load_chunk(A, q, qb[c], cols[c], vals[c]);
+        chunk(c, cols[c], vals[c]);
+      }
       done(c, tt[c]);
     }
-  }
-}
-
-// Row u of A in chunks of up to 8 entries, loaded together, visited in ascending order:
-// f(col, value) for every stored entry.
-template <typename F>
-__device__ __forceinline__ void for_row(const Csr& A, int64_t q0, int64_t q1, F f) {
-  constexpr int U = 8;
-  for (int64_t qb = q0; qb < q1; qb += U) {
-    int cols[U];
-    double vals[U];
-#pragma unroll
-    for (int k = 0; k < U; ++k) {
-      if (qb + k < q1) {
-        cols[k] = A.col[qb + k];
-        vals[k] = aval(A, qb + k);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < U; ++k)
-      if (qb + k < q1) f(cols[k], vals[k]);
   }
 }
 
@@ -447,48 +480,53 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> 
                                                      int tier, int L, int H) {
   if (!st->any_active) return;
   extern __shared__ char smem[];
+  const bool ell = A.eshift >= 0;
   Carve cv(smem);
   int* s_mi = cv.take<int>(L);
-  int* s_pre = cv.take<int>(L);
   int* s_keys = cv.take<int>(H);         // hash set, then the sorted keys
-  int* s_sorted = s_keys;
-  int* s_kc = cv.take<int>(2);           // distinct-key count, overflow flag
   double* s_mv = cv.take<double>(L);
-  int64_t* s_rs = cv.take<int64_t>(L);   // row starts of the entries of m_j
+  int* s_mk = cv.take<int>(2 * L);       // position map of m_j's rows
+  unsigned* s_mp = cv.take<unsigned>(2 * L);
+  int* s_pre = ell ? nullptr : cv.take<int>(L);           // CSR: degree prefix
+  int64_t* s_rs = ell ? nullptr : cv.take<int64_t>(L);    // CSR: row starts
   const int lane = lane_id();
   const Cols<T> M = Mp.now();
   const bool overflow = *total > R.cap;
+  const int limit = H / 2 - 1;
   unsigned long long outcnt = 0;
 
   auto body = [&](int64_t j) {
     const int64_t mb = M.beg[j];
     const int lm = M.len[j];
     if (lm > L) {
-      if (tier == 0) {
-        if (lane == 0) big.list[atomicAdd(big.count, 1)] = (int)j;
-      } else if (lane == 0) {
-        atomicOr(&st->err, 1);
-      }
+      defer_column(tier, big, st, j);
       return;
     }
-    for (int e = lane; e < lm; e += SPAI_WAVE) {
-      s_mi[e] = M.idx[mb + e];
-      s_mv[e] = (double)M.val[mb + e];
-    }
-    __syncthreads();
-    const int tot = degree_prefix(A, s_mi, lm, s_pre, s_rs);
     if (overflow) {
       if (lane == 0) atomicOr(&st->err, 2);
-      __syncthreads();
       return;
     }
+    const int hs = next_pow2(max(2 * lm, 64));
     ks_clear(s_keys, H);
-    if (lane == 0) { s_kc[0] = 0; s_kc[1] = 0; }
+    lm_clear(s_mk, s_mp, hs);
     __syncthreads();
-    if (lane == 0) ks_insert_bounded(s_keys, H, (int)j, s_kc, H / 2, s_kc + 1);
-    insert_products(A, s_pre, s_rs, lm, tot, s_keys, H, s_kc, H / 2, s_kc + 1);
+    for (int e = lane; e < lm; e += SPAI_WAVE) {
+      const int i = M.idx[mb + e];
+      s_mi[e] = i;
+      s_mv[e] = (double)M.val[mb + e];
+      lm_put(s_mk, s_mp, hs, i, 0, e);
+    }
     __syncthreads();
-    if (s_kc[1]) {                 // more distinct rows than the tile holds
+    int tot = 0;
+    if (!ell) {
+      tot = degree_prefix(A, s_mi, lm, s_pre, s_rs);
+      __syncthreads();
+    }
+    int kd[1] = {lane == 0 ? (int)j : -1};
+    int nk = wave_sum_int(ks_insert_batch<1>(s_keys, H, kd));
+    nk = insert_products(A, s_mi, lm, s_pre, s_rs, tot, s_keys, H, nk, limit);
+    __syncthreads();
+    if (nk > limit) {               // more distinct rows than the tile holds
       defer_column(tier, big, st, j);
       __syncthreads();
       return;
@@ -497,15 +535,20 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> 
     __syncthreads();
     const int64_t ob = off[j];
     double acc = 0.0;
-    double sum[2];
-    pull_rows<2>(
-        A, s_sorted, nu, [&](int c) { sum[c] = 0.0; },
-        [&](int c, int col, double a) {
-          const int e = bsearch_idx(s_mi, lm, col);
-          if (e >= 0) sum[c] += a * s_mv[e];
+    double sum[1];
+    pull_rows<1>(
+        A, s_keys, nu, [&](int c) { sum[c] = 0.0; },
+        [&](int c, const int (&cols)[8], const double (&vals)[8]) {
+          unsigned pw[8];
+          lm_find<8>(s_mk, s_mp, hs, cols, pw);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const unsigned e = pw[k] & kNoPos;
+            if (e != kNoPos) sum[c] += vals[k] * s_mv[e];
+          }
         },
         [&](int c, int t) {
-          const int u = s_sorted[t];
+          const int u = s_keys[t];
           const double r = ((u == (int)j) ? 1.0 : 0.0) - sum[c];
           const T rt = (T)r;
           R.idx[ob + t] = u;
@@ -533,8 +576,9 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> 
   if (lane == 0 && tier == 1 && outcnt) atomicAdd(&st->cnt[6 * kCntSlots + kCntSlots - 1], outcnt);
 }
 
-static size_t resid_lds(Tile t) {
-  return (size_t)t.L * 4 * 2 + (size_t)t.H * 4 + 8 + (size_t)t.L * 16 + 64;
+static size_t resid_lds(Tile t, bool ell) {
+  return (size_t)t.L * 4 + (size_t)t.H * 4 + (size_t)t.L * 8 + (size_t)t.L * 16 +
+         (ell ? 0 : (size_t)t.L * 12) + 64;
 }
 
 int g_grid_cols = 2048;   // fallback persistent grid of the per-column kernels
@@ -568,11 +612,12 @@ template <typename T>
 void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const int64_t* total,
                   double* colnorm, BigList big, DevState* st, Tile small, Tile large,
                   hipStream_t s) {
+  const bool ell = A.eshift >= 0;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
-  hipLaunchKernelGGL(k_resid<T>, dim3(resident_grid(k_resid<T>, resid_lds(small))), dim3(SPAI_WAVE),
-                     resid_lds(small), s, A, M, R,
-                     off, total, colnorm, big, st, 0, small.L, small.H);
-  hipLaunchKernelGGL(k_resid<T>, dim3(256), dim3(SPAI_WAVE), resid_lds(large), s, A, M, R, off,
+  hipLaunchKernelGGL(k_resid<T>, dim3(resident_grid(k_resid<T>, resid_lds(small, ell))),
+                     dim3(SPAI_WAVE), resid_lds(small, ell), s, A, M, R, off, total, colnorm, big,
+                     st, 0, small.L, small.H);
+  hipLaunchKernelGGL(k_resid<T>, dim3(256), dim3(SPAI_WAVE), resid_lds(large, ell), s, A, M, R, off,
                      total, colnorm, big, st, 1, large.L, large.H);
 }
 
@@ -586,46 +631,55 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
                                                     DevState* st, int tier, int L, int H) {
   if (!st->any_active || !st->iter_active) return;
   extern __shared__ char smem[];
+  const bool ell = A.eshift >= 0;
   Carve cv(smem);
-  int* s_li = cv.take<int>(L);
-  int* s_pre = cv.take<int>(L);
+  int* s_li = cv.take<int>(L);           // r_j rows, then p_j rows
   int* s_keys = cv.take<int>(H);
-  int* s_sorted = s_keys;
-  int* s_kc = cv.take<int>(2);
   double* s_lv = cv.take<double>(L);
-  int64_t* s_rs = cv.take<int64_t>(L);
+  int* s_mk = cv.take<int>(2 * L);       // position map: row -> (place in r_j, in p_j)
+  unsigned* s_mp = cv.take<unsigned>(2 * L);
+  int* s_pre = ell ? nullptr : cv.take<int>(L);
+  int64_t* s_rs = ell ? nullptr : cv.take<int64_t>(L);
   const int lane = lane_id();
   const Cols<T> P = Pp.now();
+  const int limit = H / 2 - 1;
 
   auto body = [&](int64_t j) {
     const int lr = useR ? R.len[j] : 0;
     const int lp = useP ? P.len[j] : 0;
     if (lr + lp > L) {
-      if (tier == 0) {
-        if (lane == 0) big.list[atomicAdd(big.count, 1)] = (int)j;
-      } else if (lane == 0) {
-        atomicOr(&st->err, 1);
-      }
+      defer_column(tier, big, st, j);
       return;
     }
     const int64_t rb = useR ? R.beg[j] : 0;
     const int64_t pb = useP ? P.beg[j] : 0;
-    for (int e = lane; e < lr; e += SPAI_WAVE) {
-      s_li[e] = R.idx[rb + e];
-      s_lv[e] = (double)R.val[rb + e];
-    }
-    for (int e = lane; e < lp; e += SPAI_WAVE) {
-      s_li[lr + e] = P.idx[pb + e];
-      s_lv[lr + e] = (double)P.val[pb + e];
-    }
-    __syncthreads();
-    const int tot = degree_prefix(A, s_li, lr + lp, s_pre, s_rs);
+    const int hs = next_pow2(max(2 * (lr + lp), 64));
     ks_clear(s_keys, H);
-    if (lane == 0) { s_kc[0] = 0; s_kc[1] = 0; }
+    lm_clear(s_mk, s_mp, hs);
     __syncthreads();
-    insert_products(A, s_pre, s_rs, lr + lp, tot, s_keys, H, s_kc, H / 2, s_kc + 1);
+    for (int e = lane; e < lr + lp; e += SPAI_WAVE) {   // both lists in one pass
+      int i;
+      double v;
+      if (e < lr) {
+        i = R.idx[rb + e];
+        v = (double)R.val[rb + e];
+      } else {
+        i = P.idx[pb + e - lr];
+        v = (double)P.val[pb + e - lr];
+      }
+      s_li[e] = i;
+      s_lv[e] = v;
+      lm_put(s_mk, s_mp, hs, i, e < lr ? 0 : 1, e < lr ? e : e - lr);
+    }
     __syncthreads();
-    if (s_kc[1]) {
+    int tot = 0;
+    if (!ell) {
+      tot = degree_prefix(A, s_li, lr + lp, s_pre, s_rs);
+      __syncthreads();
+    }
+    const int nk = insert_products(A, s_li, lr + lp, s_pre, s_rs, tot, s_keys, H, 0, limit);
+    __syncthreads();
+    if (nk > limit) {
       defer_column(tier, big, st, j);
       __syncthreads();
       return;
@@ -637,30 +691,26 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
     const int* pi = s_li + lr;
     const double* pv = s_lv + lr;
     double d0 = 0, d1 = 0, d2 = 0, d3 = 0, d4 = 0, d5 = 0;
-    double ar[2], ap[2];
-    pull_rows<2>(
-        A, s_sorted, nu, [&](int c) { ar[c] = 0.0; ap[c] = 0.0; },
-        [&](int c, int l, double a) {
-          if (lr) {
-            const int e = bsearch_idx(ri, lr, l);
-            if (e >= 0) ar[c] += a * rv[e];
-          }
-          if (lp) {
-            const int e = bsearch_idx(pi, lp, l);
-            if (e >= 0) ap[c] += a * pv[e];
+    double ar[1], ap[1];
+    pull_rows<1>(
+        A, s_keys, nu, [&](int c) { ar[c] = 0.0; ap[c] = 0.0; },
+        [&](int c, const int (&cols)[8], const double (&vals)[8]) {
+          unsigned pw[8];
+          lm_find<8>(s_mk, s_mp, hs, cols, pw);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const unsigned e0 = pw[k] & kNoPos, e1 = pw[k] >> 16;
+            if (e0 != kNoPos) ar[c] += vals[k] * rv[e0];
+            if (e1 != kNoPos) ap[c] += vals[k] * pv[e1];
           }
         },
         [&](int c, int t) {
-          const int u = s_sorted[t];
-          double ru = 0.0, pu = 0.0;
-          if (lr) {
-            const int e = bsearch_idx(ri, lr, u);
-            if (e >= 0) ru = rv[e];
-          }
-          if (lp) {
-            const int e = bsearch_idx(pi, lp, u);
-            if (e >= 0) pu = pv[e];
-          }
+          const int key[1] = {s_keys[t]};
+          unsigned pw[1];
+          lm_find<1>(s_mk, s_mp, hs, key, pw);
+          const unsigned e0 = pw[0] & kNoPos, e1 = pw[0] >> 16;
+          const double ru = e0 != kNoPos ? rv[e0] : 0.0;
+          const double pu = e1 != kNoPos ? pv[e1] : 0.0;
           d0 += ru * ar[c];
           d1 += ar[c] * ar[c];
           d2 += ar[c] * ap[c];
@@ -668,6 +718,8 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
           d4 += ap[c] * ap[c];
           d5 += pu * ap[c];
         });
+    (void)ri;
+    (void)pi;
     d0 = wave_sum(d0);
     d1 = wave_sum(d1);
     d2 = wave_sum(d2);
@@ -690,18 +742,20 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
   }
 }
 
-static size_t dots_lds(Tile t) {
-  return (size_t)t.L * 4 * 2 + (size_t)t.H * 4 + 8 + (size_t)t.L * 16 + 64;
+static size_t dots_lds(Tile t, bool ell) {
+  return (size_t)t.L * 4 + (size_t)t.H * 4 + (size_t)t.L * 8 + (size_t)t.L * 16 +
+         (ell ? 0 : (size_t)t.L * 12) + 64;
 }
 
 template <typename T>
 void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, double* colpart,
                  BigList big, DevState* st, Tile small, Tile large, hipStream_t s) {
+  const bool ell = A.eshift >= 0;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
-  hipLaunchKernelGGL(k_dots<T>, dim3(resident_grid(k_dots<T>, dots_lds(small))), dim3(SPAI_WAVE),
-                     dots_lds(small), s, A, R, P,
-                     useR, useP, colpart, big, st, 0, small.L, small.H);
-  hipLaunchKernelGGL(k_dots<T>, dim3(256), dim3(SPAI_WAVE), dots_lds(large), s, A, R, P, useR,
+  hipLaunchKernelGGL(k_dots<T>, dim3(resident_grid(k_dots<T>, dots_lds(small, ell))),
+                     dim3(SPAI_WAVE), dots_lds(small, ell), s, A, R, P, useR, useP, colpart, big,
+                     st, 0, small.L, small.H);
+  hipLaunchKernelGGL(k_dots<T>, dim3(256), dim3(SPAI_WAVE), dots_lds(large, ell), s, A, R, P, useR,
                      useP, colpart, big, st, 1, large.L, large.H);
 }
 
@@ -807,10 +861,8 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
   Carve cv(smem);
   int* s_li = cv.take<int>(L);
   int* s_keys = cv.take<int>(H);        // hash set, then the sorted keys
-  int* s_sorted = s_keys;
   int* s_nbcol = cv.take<int>(DG);
   int* s_nboff = cv.take<int>(DG + 1);
-  int* s_kc = cv.take<int>(2);
   double* s_lv = cv.take<double>(L);
   double* s_nbval = cv.take<double>(DG);
   // small tile: the neighbour columns m_l sit in LDS; large tile: they stay in global
@@ -832,22 +884,66 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
   const bool needPT = needP && mirror;
   const bool overflow = *total > Mo.cap || (md.doP && (*total > Po.cap || *total > PTo.cap));
 
+  const bool ell = A.eshift >= 0;
+  const int limit = H / 2 - 1;
+
   auto body = [&](int64_t j) {
     const SegState& g = seg.st[seg.segof(j)];
     const double a1 = g.coef[0], a2 = g.coef[1], c1 = g.coef[2], c2 = g.coef[3];
-    // ---- sizes and fit test
+    // ---- own lists: m_j | r_j | p_j | pT_j
     const int lm = md.doM ? M.len[j] : 0;
     const int lr = needR ? R.len[j] : 0;
     const int lp = needP ? P.len[j] : 0;
     const int lpt = needPT ? PT.len[j] : 0;
-    const int64_t qa = A.rowptr[j];
-    const int deg = needRT ? (int)(A.rowptr[j + 1] - qa) : 0;
-    int nbtot = 0;
-    for (int t = lane; t < deg; t += SPAI_WAVE) nbtot += M.len[A.col[qa + t]];
-    nbtot = wave_sum_int(nbtot);
-    const int lown = lm + lr + lp + lpt;
-    const int ltot = lown + (nb_lds ? nbtot : 0);
-    if (ltot > L || deg > DG) {
+    const int64_t mb = md.doM ? M.beg[j] : 0;
+    const int64_t rb = lr ? R.beg[j] : 0;
+    const int64_t pb = lp ? P.beg[j] : 0;
+    const int64_t ptb = lpt ? PT.beg[j] : 0;
+    const int om = 0, orr = lm, op = lm + lr, opt = lm + lr + lp, onb = lm + lr + lp + lpt;
+    // ---- neighbours l in N(j) (row j of A, for R^T): l, a_jl, where m_l sits, and the
+    // offsets s_nboff of their entries after the own lists
+    int64_t qa = 0;
+    int deg = 0;
+    if (needRT) {
+      if (ell) {
+        qa = (int64_t)j << A.eshift;
+        const int c = lane < (1 << A.eshift) ? A.ecol[qa + lane] : -1;
+        deg = __popcll(__ballot(c >= 0));
+      } else {
+        qa = A.rowptr[j];
+        deg = (int)(A.rowptr[j + 1] - qa);
+      }
+    }
+    if (deg > DG) {
+      defer_column(tier, big, st, j);
+      return;
+    }
+    int run = 0;
+    for (int base = 0; base < deg; base += SPAI_WAVE) {
+      const int t = base + lane;
+      int len = 0;
+      if (t < deg) {
+        int l;
+        double av;
+        if (ell) {
+          l = A.ecol[qa + t];
+          av = A.eval32 ? (double)A.eval32[qa + t] : A.eval[qa + t];
+        } else {
+          l = A.col[qa + t];
+          av = aval(A, qa + t);
+        }
+        len = M.len[l];
+        s_nbcol[t] = l;
+        s_nbval[t] = av;
+        s_nbbeg[t] = M.beg[l];
+      }
+      const int inc = wave_incl_scan(len);
+      if (t < deg) s_nboff[t] = onb + run + inc - len;
+      run += __shfl(inc, SPAI_WAVE - 1, SPAI_WAVE);
+    }
+    if (lane == 0) s_nboff[deg] = onb + run;
+    const int ltot = onb + (nb_lds ? run : 0);
+    if (ltot > L) {
       defer_column(tier, big, st, j);
       return;
     }
@@ -855,70 +951,38 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
       if (lane == 0) atomicOr(&st->err, 2);
       return;
     }
-    // ---- load the lists: m_j | r_j | p_j | pT_j | m_l for l in N(j)
-    const int om = 0, orr = lm, op = lm + lr, opt = lm + lr + lp, onb = lm + lr + lp + lpt;
+    ks_clear(s_keys, H);
+    __syncthreads();
+    // ---- every list entry held in LDS, in one flattened gather (four per lane in flight)
     {
-      const int64_t b = md.doM ? M.beg[j] : 0;
-      for (int e = lane; e < lm; e += SPAI_WAVE) {
-        s_li[om + e] = M.idx[b + e];
-        s_lv[om + e] = (double)M.val[b + e];
-      }
-    }
-    if (lr) {
-      const int64_t b = R.beg[j];
-      for (int e = lane; e < lr; e += SPAI_WAVE) {
-        s_li[orr + e] = R.idx[b + e];
-        s_lv[orr + e] = (double)R.val[b + e];
-      }
-    }
-    if (lp) {
-      const int64_t b = P.beg[j];
-      for (int e = lane; e < lp; e += SPAI_WAVE) {
-        s_li[op + e] = P.idx[b + e];
-        s_lv[op + e] = (double)P.val[b + e];
-      }
-    }
-    if (lpt) {
-      const int64_t b = PT.beg[j];
-      for (int e = lane; e < lpt; e += SPAI_WAVE) {
-        s_li[opt + e] = PT.idx[b + e];
-        s_lv[opt + e] = (double)PT.val[b + e];
-      }
-    }
-    if (deg && nb_lds) {
-      // neighbour offsets (prefix of their lengths), then their entries
-      int run = 0;
-      for (int base = 0; base < deg; base += SPAI_WAVE) {
-        const int t = base + lane;
-        int len = 0;
-        if (t < deg) {
-          const int l = A.col[qa + t];
-          len = M.len[l];
-          s_nbcol[t] = l;
-          s_nbval[t] = aval(A, qa + t);
-          s_nbbeg[t] = M.beg[l];
-        }
-        const int inc = wave_incl_scan(len);
-        if (t < deg) s_nboff[t] = onb + run + inc - len;
-        run += __shfl(inc, SPAI_WAVE - 1, SPAI_WAVE);
-      }
-      if (lane == 0) s_nboff[deg] = onb + run;
-      __syncthreads();
-      // one flattened gather over all neighbour entries, four per lane in flight
       constexpr int U = 4;
-      for (int x0 = 0; x0 < run; x0 += SPAI_WAVE * U) {
+      for (int x0 = 0; x0 < ltot; x0 += SPAI_WAVE * U) {
         int ix[U];
         T vx[U];
         int dst[U];
 #pragma unroll
         for (int c = 0; c < U; ++c) {
-          const int pos = onb + x0 + c * SPAI_WAVE + lane;
+          const int pos = x0 + c * SPAI_WAVE + lane;
           dst[c] = -1;
-          if (pos < onb + run) {
-            const int t = upper_bound_int(s_nboff + 1, deg, pos);
-            const int64_t src = s_nbbeg[t] + (pos - s_nboff[t]);
-            ix[c] = M.idx[src];
-            vx[c] = M.val[src];
+          if (pos < ltot) {
+            if (pos < orr) {
+              ix[c] = M.idx[mb + pos];
+              vx[c] = M.val[mb + pos];
+            } else if (pos < op) {
+              ix[c] = R.idx[rb + (pos - orr)];
+              vx[c] = R.val[rb + (pos - orr)];
+            } else if (pos < opt) {
+              ix[c] = P.idx[pb + (pos - op)];
+              vx[c] = P.val[pb + (pos - op)];
+            } else if (pos < onb) {
+              ix[c] = PT.idx[ptb + (pos - opt)];
+              vx[c] = PT.val[ptb + (pos - opt)];
+            } else {
+              const int t = upper_bound_int(s_nboff + 1, deg, pos);
+              const int64_t src = s_nbbeg[t] + (pos - s_nboff[t]);
+              ix[c] = M.idx[src];
+              vx[c] = M.val[src];
+            }
             dst[c] = pos;
           }
         }
@@ -929,32 +993,36 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
             s_lv[dst[c]] = (double)vx[c];
           }
       }
-    } else if (deg) {
-      for (int t = lane; t < deg; t += SPAI_WAVE) {
-        const int l = A.col[qa + t];
-        s_nbcol[t] = l;
-        s_nbval[t] = aval(A, qa + t);
-        s_nbbeg[t] = M.beg[l];
-        s_nboff[t] = M.len[l];
-      }
     }
     __syncthreads();
-    // ---- key union (at most H / 2 - 1 distinct keys)
-    ks_clear(s_keys, H);
-    if (lane == 0) { s_kc[0] = 0; s_kc[1] = 0; }
-    __syncthreads();
-    const int klim = H / 2 - 1;
-    if (lane == 0) ks_insert_bounded(s_keys, H, (int)j, s_kc, klim, s_kc + 1);
-    for (int e = lane; e < ltot; e += SPAI_WAVE) ks_insert_bounded(s_keys, H, s_li[e], s_kc, klim, s_kc + 1);
+    // ---- key union (at most limit distinct keys)
+    int kd[1] = {lane == 0 ? (int)j : -1};
+    int nkeys = wave_sum_int(ks_insert_batch<1>(s_keys, H, kd));
+    for (int x0 = 0; x0 < ltot && nkeys <= limit; x0 += SPAI_WAVE * 4) {
+      int kk[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int pos = x0 + c * SPAI_WAVE + lane;
+        kk[c] = pos < ltot ? s_li[pos] : -1;
+      }
+      nkeys += wave_sum_int(ks_insert_batch<4>(s_keys, H, kk));
+    }
     if (!nb_lds)
-      for (int t = 0; t < deg; ++t) {
-        const int64_t b = s_nbbeg[t];
-        const int len = s_nboff[t];
-        for (int e = lane; e < len; e += SPAI_WAVE)
-          ks_insert_bounded(s_keys, H, M.idx[b + e], s_kc, klim, s_kc + 1);
+      for (int t = 0; t < deg && nkeys <= limit; ++t) {
+        const int64_t b0 = s_nbbeg[t];
+        const int len = s_nboff[t + 1] - s_nboff[t];
+        for (int x0 = 0; x0 < len && nkeys <= limit; x0 += SPAI_WAVE * 4) {
+          int kk[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int e = x0 + c * SPAI_WAVE + lane;
+            kk[c] = e < len ? M.idx[b0 + e] : -1;
+          }
+          nkeys += wave_sum_int(ks_insert_batch<4>(s_keys, H, kk));
+        }
       }
     __syncthreads();
-    if (s_kc[1]) {
+    if (nkeys > limit) {
       defer_column(tier, big, st, j);
       __syncthreads();
       return;
@@ -967,28 +1035,44 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
     for (int base = 0; base < nk; base += SPAI_WAVE) {
       const int t = base + lane;
       const bool valid = t < nk;
-      const int k = valid ? s_sorted[t] : 0;
+      const int k = valid ? s_keys[t] : -1;
       double mv = 0.0, rv = 0.0, rtv = 0.0, pv = 0.0, ptv = 0.0;
-      if (valid) {
-        if (lm) { const int e = bsearch_idx(s_li + om, lm, k); if (e >= 0) mv = s_lv[om + e]; }
-        if (lr) { const int e = bsearch_idx(s_li + orr, lr, k); if (e >= 0) rv = s_lv[orr + e]; }
-        if (lp) { const int e = bsearch_idx(s_li + op, lp, k); if (e >= 0) pv = s_lv[op + e]; }
-        if (lpt) { const int e = bsearch_idx(s_li + opt, lpt, k); if (e >= 0) ptv = s_lv[opt + e]; }
-        if (needRT) {
-          double sum = 0.0;
-          for (int t2 = 0; t2 < deg; ++t2) {
-            if (nb_lds) {
-              const int o = s_nboff[t2];
-              const int e = bsearch_idx(s_li + o, s_nboff[t2 + 1] - o, k);
-              if (e >= 0) sum += s_nbval[t2] * s_lv[o + e];
-            } else {
-              const int64_t b = s_nbbeg[t2];
-              const int e = bsearch_idx(M.idx + b, s_nboff[t2], k);
-              if (e >= 0) sum += s_nbval[t2] * (double)M.val[b + e];
+      {
+        const int ob4[4] = {om, orr, op, opt}, ln4[4] = {lm, lr, lp, lpt}, k4[4] = {k, k, k, k};
+        int p4[4];
+        search_lockstep<4>(s_li, ob4, ln4, k4, p4);
+        if (p4[0] >= 0) mv = s_lv[om + p4[0]];
+        if (p4[1] >= 0) rv = s_lv[orr + p4[1]];
+        if (p4[2] >= 0) pv = s_lv[op + p4[2]];
+        if (p4[3] >= 0) ptv = s_lv[opt + p4[3]];
+      }
+      if (needRT) {
+        double sum = 0.0;
+        for (int t0 = 0; t0 < deg; t0 += 8) {
+          int b8[8], n8[8], k8[8], p8[8];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const int t2 = t0 + c;
+            b8[c] = t2 < deg ? s_nboff[t2] : 0;
+            n8[c] = t2 < deg ? s_nboff[t2 + 1] - b8[c] : 0;
+            k8[c] = k;
+          }
+          if (nb_lds) {
+            search_lockstep<8>(s_li, b8, n8, k8, p8);
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+              if (p8[c] >= 0) sum += s_nbval[t0 + c] * s_lv[b8[c] + p8[c]];
+          } else {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+              if (t0 + c >= deg) continue;
+              const int64_t b0 = s_nbbeg[t0 + c];
+              const int e = bsearch_idx(M.idx + b0, n8[c], k);
+              if (e >= 0) sum += s_nbval[t0 + c] * (double)M.val[b0 + e];
             }
           }
-          rtv = (double)(T)(((k == (int)j) ? 1.0 : 0.0) - sum);
         }
+        rtv = (double)(T)(((k == (int)j) ? 1.0 : 0.0) - sum);
       }
       // M candidate
       bool keepM = false, offM = false;

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -26,51 +27,179 @@ constexpr int kGrid = 2048;
 
 using Mat = PcgMat;
 
-// Y[:, c0:c0+R) = A X[:, c0:c0+R) and per-block partials of sum_i W[i, r] Y[i, r].
-// Threads are (row, rhs) pairs: R = pow2 >= the chunk width, 256 / R rows per block step.
-__global__ __launch_bounds__(kThreads) void k_spmm_dot(Mat A, const double* X, double* Y,
-                                                       const double* W, int nrhs, int c0, int cw,
-                                                       int R, double* part) {
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// a wave-uniform 64-bit value moved to scalar registers
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return ((int64_t)hi << 32) | (int64_t)(unsigned)lo;
+}
+
+enum { kLayEll = 0, kLayPad = 1, kLayCsr = 2 };
+
+template <int LAY>
+__device__ __forceinline__ int64_t row_lo(const Mat& A, int64_t i) {
+  if (LAY == kLayEll) return i << A.eshift;
+  if (LAY == kLayPad) return A.beg[i];
+  return A.rowptr[i];
+}
+template <int LAY>
+__device__ __forceinline__ int64_t row_hi(const Mat& A, int64_t i) {
+  if (LAY == kLayEll) return (i + 1) << A.eshift;
+  if (LAY == kLayPad) return A.beg[i] + A.len[i];
+  return A.rowptr[i + 1];
+}
+template <typename VT>
+__device__ __forceinline__ VT entry_val(const Mat& A, int64_t q) {
+  if constexpr (sizeof(VT) == 4) return A.val32[q];
+  else return A.val[q];
+}
+__device__ __forceinline__ float readlane_val(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane_val(double v, int l) { return readlane_f64(v, l); }
+
+// G gathers of one row, all issued before any is used: entry e0 + k of the row (held
+// one per lane in cc) selects row col of X, whose 64-value piece starting at column c0
+// is one 512-byte line; lane k's value sits at byte offset loff.  Entries past cnt
+// repeat the last one, so every load is in bounds and there is no branch between them.
+template <int G>
+__device__ __forceinline__ void gather_row(const double* X, int nrhs, int c0, unsigned loff,
+                                           int cc, int e0, int cnt, double (&xs)[G]) {
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    const int e = min(e0 + k, cnt - 1);
+    const int col = __builtin_amdgcn_readlane(cc, e);
+    const char* xrow = (const char*)(X + ((int64_t)col * nrhs + c0));   // uniform base
+    xs[k] = *(const double*)(xrow + loff);
+  }
+}
+
+// y += v_e x_e over the entries e0 .. min(e0 + G, cnt) in order (v_e widened to float64)
+template <int G, typename VT>
+__device__ __forceinline__ void accumulate_row(double& y, VT cv, int e0, int cnt,
+                                               const double (&xs)[G]) {
+#pragma unroll
+  for (int k = 0; k < G; ++k)
+    if (e0 + k < cnt) y += (double)readlane_val(cv, e0 + k) * xs[k];
+}
+
+// Y[:, c0:c0+64) = K X[:, c0:c0+64) and per-block partials of sum_i W[i, r] Y[i, r].
+// One wave per row, lane r owning right-hand side c0 + r, so every gather is one
+// 512-byte line of X.  The row's entries are loaded by the lanes together (one per
+// lane) and broadcast with readlane, so the row's gathers (up to 16 in flight) wait on
+// a single entry load; the next row's entries and the descriptor of the row after it
+// are loaded while the current row's gathers are in flight.  Row i's sum runs over its
+// entries in stored (ascending column) order.  The rows are split into eight
+// contiguous ranges, one per XCD (workgroups are dealt round-robin over the XCDs), so
+// the rows that gather the same row of X run on one XCD close together in time.
+template <typename VT, int LAY>
+__global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, double* Y,
+                                                        const double* W, int nrhs, int c0,
+                                                        double* part) {
   __shared__ double sh[kThreads];
-  const int t = threadIdx.x;
-  const int r = t % R;
-  const int rows_per = kThreads / R;
-  const int roff = t / R;
+  constexpr int WPB = kThreads / 64;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t xcd = blockIdx.x & 7, kb = blockIdx.x >> 3, nb = gridDim.x >> 3;
+  const int64_t per = (A.n + 7) / 8;
+  const int64_t r0 = xcd * per;
+  const int64_t r1 = r0 + per < A.n ? r0 + per : A.n;
+  const int64_t stride = nb * WPB;
+  const bool on = c0 + lane < nrhs;
+  const int64_t cofs = c0 + lane;
+  const unsigned loff = on ? (unsigned)lane * 8u : 0u;   // idle lanes re-read column c0
   double acc = 0.0;
-  const bool on = r < cw;
-  for (int64_t base = (int64_t)blockIdx.x * rows_per; base < A.n; base += (int64_t)gridDim.x * rows_per) {
-    const int64_t i = base + roff;
-    if (i < A.n && on) {
-      double y = 0.0;
-      const int64_t q0 = A.row_begin(i), q1 = A.row_end(i);
-      constexpr int U = 8;
-      for (int64_t qb = q0; qb < q1; qb += U) {      // 8 gathers in flight, summed in order
-        int cols[U];
-        double vals[U], xs[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k)
-          if (qb + k < q1) {
-            cols[k] = A.col[qb + k];
-            vals[k] = A.v(qb + k);
-          }
-#pragma unroll
-        for (int k = 0; k < U; ++k)
-          if (qb + k < q1) xs[k] = X[(int64_t)cols[k] * nrhs + c0 + r];
-#pragma unroll
-        for (int k = 0; k < U; ++k)
-          if (qb + k < q1) y += vals[k] * xs[k];
-      }
-      Y[i * nrhs + c0 + r] = y;
-      if (W) acc += W[i * nrhs + c0 + r] * y;
+  int64_t i = r0 + kb * WPB + wv;
+  // row i: descriptor (a, b) and its first 64 entries (ec, ev), one per lane;
+  // row i + stride: descriptor (na, nbe)
+  int64_t a = 0, b = 0, na = 0, nbe = 0;
+  int ec = -1;
+  VT ev = 0;
+  if (i < r1) {
+    a = row_lo<LAY>(A, i);
+    b = row_hi<LAY>(A, i);
+    if (a + lane < b) {
+      ec = A.col[a + lane];
+      ev = entry_val<VT>(A, a + lane);
     }
   }
+  if (i + stride < r1) {
+    na = row_lo<LAY>(A, i + stride);
+    nbe = row_hi<LAY>(A, i + stride);
+  }
+  for (; i < r1; i += stride) {
+    const int64_t in = i + stride;
+    const int cnt = __popcll(__ballot(ec >= 0));   // ELL padding (column -1) sits last
+    int nc = -1;
+    VT nv = 0;
+    int64_t ma = 0, mb = 0;
+    auto prefetch = [&]() {
+      if (in < r1 && na + lane < nbe) {
+        nc = A.col[na + lane];
+        nv = entry_val<VT>(A, na + lane);
+      }
+      if (in + stride < r1) {
+        ma = row_lo<LAY>(A, in + stride);
+        mb = row_hi<LAY>(A, in + stride);
+      }
+    };
+    double y = 0.0;
+    if (cnt == 0) {
+      prefetch();
+    } else if (cnt <= 8) {
+      double xs[8];
+      gather_row<8>(X, nrhs, c0, loff, ec, 0, cnt, xs);
+      prefetch();
+      accumulate_row<8>(y, ev, 0, cnt, xs);
+    } else {
+      double xs[16];
+      gather_row<16>(X, nrhs, c0, loff, ec, 0, cnt, xs);
+      prefetch();
+      accumulate_row<16>(y, ev, 0, cnt, xs);
+      for (int e0 = 16; e0 < cnt; e0 += 16) {
+        gather_row<16>(X, nrhs, c0, loff, ec, e0, cnt, xs);
+        accumulate_row<16>(y, ev, e0, cnt, xs);
+      }
+      for (int64_t q = a + 64; q < b; q += 64) {   // rows longer than 64 entries
+        int cc = -1;
+        VT cv = 0;
+        if (q + lane < b) {
+          cc = A.col[q + lane];
+          cv = entry_val<VT>(A, q + lane);
+        }
+        const int cn = __popcll(__ballot(cc >= 0));
+        if (cn == 0) break;
+        for (int e0 = 0; e0 < cn; e0 += 16) {
+          gather_row<16>(X, nrhs, c0, loff, cc, e0, cn, xs);
+          accumulate_row<16>(y, cv, e0, cn, xs);
+        }
+      }
+    }
+    if (on) {
+      Y[i * nrhs + cofs] = y;
+      if (W) acc += W[i * nrhs + cofs] * y;
+    }
+    ec = nc;
+    ev = nv;
+    a = na;
+    b = nbe;
+    na = ma;
+    nbe = mb;
+  }
   if (!part) return;
-  sh[t] = acc;
+  sh[threadIdx.x] = acc;
   __syncthreads();
-  if (t < cw) {
-    double s = 0.0;
-    for (int k = t; k < kThreads; k += R) s += sh[k];
-    part[(int64_t)blockIdx.x * nrhs + c0 + t] = s;
+  if (threadIdx.x < 64 && c0 + (int)threadIdx.x < nrhs) {
+    double sum = 0.0;
+    for (int w = 0; w < WPB; ++w) sum += sh[w * 64 + threadIdx.x];
+    part[(int64_t)blockIdx.x * nrhs + c0 + threadIdx.x] = sum;
   }
 }
 
@@ -166,12 +295,10 @@ __global__ void k_alpha(RhsState* S, const double* pq, int nrhs, int* nactive) {
   g.iters += 1;
 }
 
-// x += alpha p, r -= alpha q (inactive right-hand sides have alpha = 0)
-// x += alpha p, r -= alpha q (inactive right-hand sides have alpha = 0), fused with the
-// per-block partials of ||r||^2 for every right-hand side
-__global__ __launch_bounds__(kThreads) void k_axpy(double* x, double* rv, const double* p,
-                                                   const double* q, const RhsState* S, int64_t n,
-                                                   int nrhs, int R, double* part) {
+// r -= alpha q (inactive right-hand sides have alpha = 0), fused with the per-block
+// partials of ||r||^2 for every right-hand side; x is updated later, in k_pupd
+__global__ __launch_bounds__(kThreads) void k_axpy(double* rv, const double* q, const RhsState* S,
+                                                   int64_t n, int nrhs, int R, double* part) {
   __shared__ double sh[kThreads];
   const int t = threadIdx.x;
   const int r = t % R;
@@ -186,7 +313,6 @@ __global__ __launch_bounds__(kThreads) void k_axpy(double* x, double* rv, const 
         const int64_t o = i * nrhs + r;
         double rr = rv[o];
         if (a != 0.0) {
-          x[o] = x[o] + a * p[o];
           rr = rr - a * q[o];
           rv[o] = rr;
         }
@@ -226,44 +352,49 @@ __global__ void k_beta(RhsState* S, const double* rz_new, int nrhs) {
   g.rz = rz_new[r];
 }
 
-// p = z + beta p for running right-hand sides
-__global__ __launch_bounds__(kThreads) void k_pupd(double* p, const double* z, const RhsState* S,
-                                                   int64_t n, int nrhs, int R) {
+// x += alpha p with this iteration's alpha (zero for right-hand sides that had already
+// stopped), then p = z + beta p for the running ones: p is read once for both
+__global__ __launch_bounds__(kThreads) void k_pupd(double* p, double* x, const double* z,
+                                                   const RhsState* S, int64_t n, int nrhs, int R) {
   const int t = threadIdx.x;
   const int r = t % R;
   const int rows_per = kThreads / R;
   const int roff = t / R;
-  if (r >= nrhs || !S[r].active) return;
+  if (r >= nrhs) return;
+  const double a = S[r].alpha;
+  const bool act = S[r].active != 0;
+  if (a == 0.0 && !act) return;
   const double b = S[r].beta;
   for (int64_t base = (int64_t)blockIdx.x * rows_per; base < n; base += (int64_t)gridDim.x * rows_per) {
     const int64_t i = base + roff;
     if (i < n) {
       const int64_t o = i * nrhs + r;
-      p[o] = z[o] + b * p[o];
+      const double po = p[o];
+      if (a != 0.0) x[o] = x[o] + a * po;
+      if (act) p[o] = z[o] + b * po;
     }
   }
 }
 
 // the same updates for more than 64 right-hand sides (flat indexing)
-__global__ __launch_bounds__(kThreads) void k_axpy_wide(double* x, double* rv, const double* p,
-                                                        const double* q, const RhsState* S,
-                                                        int64_t n, int nrhs) {
+__global__ __launch_bounds__(kThreads) void k_axpy_wide(double* rv, const double* q,
+                                                        const RhsState* S, int64_t n, int nrhs) {
   const int64_t tot = n * nrhs;
   for (int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x; o < tot; o += (int64_t)gridDim.x * kThreads) {
     const double a = S[o % nrhs].alpha;
-    if (a != 0.0) {
-      x[o] = x[o] + a * p[o];
-      rv[o] = rv[o] - a * q[o];
-    }
+    if (a != 0.0) rv[o] = rv[o] - a * q[o];
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_pupd_wide(double* p, const double* z,
+__global__ __launch_bounds__(kThreads) void k_pupd_wide(double* p, double* x, const double* z,
                                                         const RhsState* S, int64_t n, int nrhs) {
   const int64_t tot = n * nrhs;
   for (int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x; o < tot; o += (int64_t)gridDim.x * kThreads) {
     const int r = (int)(o % nrhs);
-    if (S[r].active) p[o] = z[o] + S[r].beta * p[o];
+    const double a = S[r].alpha;
+    const double po = p[o];
+    if (a != 0.0) x[o] = x[o] + a * po;
+    if (S[r].active) p[o] = z[o] + S[r].beta * po;
   }
 }
 
@@ -294,15 +425,47 @@ struct Solver {
   }
 
   // Y = Mat X with optional per-RHS dot (W, Y)
+  int spmm_grid = kGrid;   // workgroups of the last product (blocks of its partials)
+
+  // the product kernel walks its rows in a persistent grid: as many workgroups as fit
+  // on the chip at once (a multiple of the 8 XCDs), at most kGrid
+  template <typename VT, int LAY>
+  static int resident_spmm_grid() {
+    static int grid = 0;
+    if (grid) return grid;
+    int dev = 0, cus = 0, per = 0;
+    int g = kGrid;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_spmm_wave<VT, LAY>, kThreads, 0) ==
+            hipSuccess &&
+        per > 0 && cus > 0)
+      g = std::min(kGrid, std::max(8, per * cus / 8 * 8));
+    else
+      (void)hipGetLastError();
+    grid = g;
+    return g;
+  }
+
+  template <typename VT, int LAY>
+  void spmm_as(const Mat& K, const double* X, double* Y, const double* W, double* pt) {
+    spmm_grid = resident_spmm_grid<VT, LAY>();
+    for (int c0 = 0; c0 < nrhs; c0 += 64)
+      hipLaunchKernelGGL((k_spmm_wave<VT, LAY>), dim3(spmm_grid), dim3(kThreads), 0, s, K, X, Y,
+                         W, nrhs, c0, pt);
+  }
+  template <typename VT>
+  void spmm_v(const Mat& K, const double* X, double* Y, const double* W, double* pt) {
+    if (K.eshift >= 0) spmm_as<VT, kLayEll>(K, X, Y, W, pt);
+    else if (K.beg) spmm_as<VT, kLayPad>(K, X, Y, W, pt);
+    else spmm_as<VT, kLayCsr>(K, X, Y, W, pt);
+  }
   void spmm(const Mat& K, const double* X, double* Y, const double* W, double* out) {
-    for (int c0 = 0; c0 < nrhs; c0 += 64) {
-      const int cw = std::min(64, nrhs - c0);
-      const int R = pow2(cw);
-      hipLaunchKernelGGL(k_spmm_dot, dim3(kGrid), dim3(kThreads), 0, s, K, X, Y, W, nrhs, c0, cw, R,
-                         out ? part : nullptr);
-    }
+    if (K.val32) spmm_v<float>(K, X, Y, W, out ? part : nullptr);
+    else spmm_v<double>(K, X, Y, W, out ? part : nullptr);
     if (out)
-      hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(kThreads), 0, s, part, kGrid, nrhs, out);
+      hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(kThreads), 0, s, part, spmm_grid, nrhs,
+                         out);
   }
 
   void dot(const double* Xa, const double* Xb, const double* Xc, double* out) {
@@ -319,21 +482,21 @@ struct Solver {
     const dim3 gs((nrhs + 63) / 64), bs(64);
     spmm(A, p, q, p, tmp);                                       // q = A p, (p, q)
     hipLaunchKernelGGL(k_alpha, gs, bs, 0, s, S, tmp, nrhs, nactive);
-    if (nrhs <= 64) {                                            // x, r update fused with ||r||^2
-      hipLaunchKernelGGL(k_axpy, dim3(kGrid), dim3(kThreads), 0, s, x, r, p, q, S, n, nrhs,
-                         pow2(nrhs), part);
+    if (nrhs <= 64) {                                            // r update fused with ||r||^2
+      hipLaunchKernelGGL(k_axpy, dim3(kGrid), dim3(kThreads), 0, s, r, q, S, n, nrhs, pow2(nrhs),
+                         part);
       hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(kThreads), 0, s, part, kGrid, nrhs, tmp);
     } else {
-      hipLaunchKernelGGL(k_axpy_wide, dim3(kGrid), dim3(kThreads), 0, s, x, r, p, q, S, n, nrhs);
+      hipLaunchKernelGGL(k_axpy_wide, dim3(kGrid), dim3(kThreads), 0, s, r, q, S, n, nrhs);
       dot(r, r, nullptr, tmp);
     }
     hipLaunchKernelGGL(k_conv, gs, bs, 0, s, S, tmp, rtol, nrhs, nactive);
     spmm(M, r, z, r, tmp);                                       // z = M r, (r, z)
     hipLaunchKernelGGL(k_beta, gs, bs, 0, s, S, tmp, nrhs);
-    if (nrhs <= 64)
-      hipLaunchKernelGGL(k_pupd, dim3(kGrid), dim3(kThreads), 0, s, p, z, S, n, nrhs, pow2(nrhs));
+    if (nrhs <= 64)                                              // x += alpha p, p = z + beta p
+      hipLaunchKernelGGL(k_pupd, dim3(kGrid), dim3(kThreads), 0, s, p, x, z, S, n, nrhs, pow2(nrhs));
     else
-      hipLaunchKernelGGL(k_pupd_wide, dim3(kGrid), dim3(kThreads), 0, s, p, z, S, n, nrhs);
+      hipLaunchKernelGGL(k_pupd_wide, dim3(kGrid), dim3(kThreads), 0, s, p, x, z, S, n, nrhs);
   }
 };
 

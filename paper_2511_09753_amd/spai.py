@@ -46,7 +46,7 @@ class CapT(C.Structure):
 class OptsT(C.Structure):
     _fields_ = [("precision", C.c_int), ("symmetrize", C.c_int), ("drop_tol", C.c_double),
                 ("tie_eta", C.c_double), ("stream", C.c_void_p),
-                ("device_pool_limit", C.c_int64), ("profile", C.c_int)]
+                ("device_pool_limit", C.c_int64), ("profile", C.c_int), ("a_format", C.c_int)]
 
 
 EXPORTS = [
@@ -55,6 +55,7 @@ EXPORTS = [
     "spai_batched_resid", "spai_last_error", "spai_status_string", "spai_reset", "spai_pcg",
     "spai_profile",
 ]
+A_FORMATS = {"auto": 0, "csr": 1, "ell": 2}
 PHASES = ["dots", "update", "resid", "select", "compact", "bounds", "scalar", "pcg"]
 COUNTS = ["cand_m", "cand_p", "cand_pt", "kept_m", "kept_p", "kept_pt", "resid", "iters"]
 
@@ -177,6 +178,7 @@ class Options:
     stream: object = None
     device_pool_limit: int = 0
     profile: bool = False
+    a_format: str = "auto"      # layout of A on the device: "auto", "csr" or "ell"
 
     def c(self):
         o = OptsT()
@@ -188,6 +190,7 @@ class Options:
         o.stream = _stream_ptr(self.stream)
         o.device_pool_limit = int(self.device_pool_limit)
         o.profile = 1 if self.profile else 0
+        o.a_format = A_FORMATS[self.a_format]
         return o
 
 

@@ -135,11 +135,14 @@ def test_aniso256_full_against_stored_oracle(method):
         assert st["nnz_p"] == gold["nnz_p"][-1]
 
 
-def test_pcg_multi_rhs_aniso():
+@pytest.mark.parametrize("nrhs", [4, 16, 32, 48, 80])
+def test_pcg_multi_rhs_aniso(nrhs):
+    """Every width path of the block PCG: generic (4), 16- and 32-wide chunks (16, 32,
+    48) and more than 64 right-hand sides (80)."""
     S = _spai()
     A = W.aniso2d(64, 1.0, 0.01)
     ref = O.lomr(A, oracle_rule(A, "column", 3.0, True), 10)
-    B = W.rhs(A.shape[0], 4, W.seed_for(2, 1))
+    B = W.rhs(A.shape[0], nrhs, W.seed_for(2, 1))
     X, it, relres, rc = S.pcg_solve(A, ref.M, B, rtol=1e-8)
     Xo, ito, sto = O.pcg_block(A, ref.M, B, rtol=1e-8)
     assert rc == S.SPAI_OK
@@ -256,3 +259,58 @@ def test_handle_pcg_matches_csr_pcg(precision, N):
         assert max(abs(a - b) for a, b in zip(it1, ito)) <= 1 and max(it1) < min(itj)
     else:
         assert rc1 == S.PCG_INDEFINITE and all(s == "indefinite" for s in sto)
+
+
+def _arrow(n, seed):
+    """SPD arrow matrix: a 5-point-like band plus a dense first row and column, so one
+    row has n entries (above the ELL width limit of 64)."""
+    rng = np.random.default_rng(seed)
+    T = sp.diags([np.full(n - 1, -1.0), np.full(n, 4.0), np.full(n - 1, -1.0)], [-1, 0, 1],
+                 format="lil")
+    w = rng.uniform(0.1, 0.2, n) / np.sqrt(n)
+    T[0, 1:] = w[1:]
+    T[1:, 0] = w[1:, None]
+    T[0, 0] = 4.0 + 1.0
+    return sp.csr_matrix(T)
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+@pytest.mark.parametrize("method,mode,value", [("mr", "global", 2.0), ("cg", "column", 3.0),
+                                               ("lomr", "global", 2.0), ("lomr", "column", 3.0)])
+@pytest.mark.parametrize("name", ["lognormal10", "geo900"])
+def test_a_layouts_bitwise_equal(name, method, mode, value, precision):
+    """A held as CSR or as padded ELL rows: every sum runs in the same order, so the
+    iterates, the residual history and a PCG solve agree bit for bit."""
+    S = _spai()
+    A = W.lognormal3d(10, 7) if name == "lognormal10" else W.geometric_graph(900, 11)
+    B = W.rhs(A.shape[0], 3, 9)
+    outs = []
+    for fmt in ("csr", "ell"):
+        h = S.SPAI(A, method, mode, value, True, max_iter=10,
+                   options=S.Options(precision=precision, a_format=fmt))
+        _, hist, _ = h.iterate(10)
+        M = h.get()
+        st = h.stats()
+        X, it, _, rc = h.pcg(B, rtol=1e-8, max_iter=300) if method != "mr" else (None, None, None, 0)
+        h.close()
+        outs.append((hist, M, st, X, it, rc))
+    (h0, M0, s0, X0, i0, c0), (h1, M1, s1, X1, i1, c1) = outs
+    assert np.array_equal(h0, h1)
+    assert (M0 != M1).nnz == 0 and M0.nnz == M1.nnz
+    assert s0["nnz_m"] == s1["nnz_m"] and s0["nnz_p"] == s1["nnz_p"]
+    if X0 is not None:
+        assert c0 == c1 and list(i0) == list(i1)
+        assert np.array_equal(X0, X1)
+
+
+def test_heavy_row_uses_csr_and_matches_oracle():
+    """A row with more than 64 entries: the automatic layout falls back to CSR (and an
+    explicit ELL request is refused); the result still matches the oracle."""
+    S = _spai()
+    A = _arrow(200, 4)
+    with pytest.raises(S.SpaiError):
+        S.SPAI(A, "lomr", "global", 2.0, True, max_iter=5, options=S.Options(a_format="ell"))
+    r0, hist, Mg, st, rc = _run_gpu(S, A, "lomr", "global", 2.0, True, 8)
+    ref = O.lomr(A, oracle_rule(A, "global", 2.0, True), 8)
+    assert rel_err(hist, ref.resid[1:]) <= TOL_F64
+    assert pattern_diff(Mg, ref.M) == (set(), set())
