@@ -474,7 +474,9 @@ void launch_bound_resid(const Csr& A, Pair<T> M, int64_t* ub, int64_t n, const D
 }
 
 template <typename T>
-__global__ __launch_bounds__(SPAI_WAVE) void k_resid(Csr A, Pair<T> Mp, Cols<T> R,
+// five waves per SIMD: measured faster than the compiler's own choice (four) for this
+// kernel, with no spills
+__global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5))) void k_resid(Csr A, Pair<T> Mp, Cols<T> R,
                                                      const int64_t* off, const int64_t* total,
                                                      double* colnorm, BigList big, DevState* st,
                                                      int tier, int L, int H) {
@@ -1192,37 +1194,103 @@ void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, Up
 // ============================================================================
 
 constexpr int kSelThreads = 256;
-constexpr int kSelGrid = 1024;
 
 __device__ __forceinline__ unsigned long long mag_key(double v) {
   return (unsigned long long)__double_as_longlong(fabs(v));
 }
 
+// ---- grouped walk over the entries of 64 consecutive columns ----------------------
+// A one-wave workgroup takes columns j0 .. j0+63 at once: lane c holds column j0 + c's
+// start cb and length cl (loaded together) and ex, the exclusive prefix of the
+// lengths, so the T entries of the group form one flat range.  Entry x belongs to the
+// column c with ex[c] <= x < ex[c] + cl[c], found by a six-step shuffle search, and
+// kGU entries per lane are loaded per batch, all in flight together.  This replaces
+// two dependent loads per column (descriptor, then entries) by about one per group.
+constexpr int kGU = 4;
+
+struct Group64 {
+  int64_t j0, cb;
+  int cl, ex, T;
+};
+
+template <typename T>
+__device__ __forceinline__ Group64 group_load(const Cols<T>& X, int64_t j0, int64_t n) {
+  Group64 g;
+  g.j0 = j0;
+  const int64_t j = j0 + lane_id();
+  g.cb = 0;
+  g.cl = 0;
+  if (j < n) {
+    g.cb = X.beg[j];
+    g.cl = X.len[j];
+  }
+  const int inc = wave_incl_scan(g.cl);
+  g.ex = inc - g.cl;
+  g.T = __shfl(inc, SPAI_WAVE - 1, SPAI_WAVE);
+  return g;
+}
+
+// group column of flat entry x (< T): the last c with ex[c] <= x.  The shuffles read
+// other lanes' registers, so every lane of the wave must execute this (and group_src)
+// together, outside any lane-dependent branch.
+__device__ __forceinline__ int group_col(const Group64& g, int x) {
+  int c = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1)
+    if (__shfl(g.ex, c + step, SPAI_WAVE) <= x) c += step;
+  return c;
+}
+
+__device__ __forceinline__ int64_t group_src(const Group64& g, int c, int x) {
+  return __shfl(g.cb, c, SPAI_WAVE) + (int64_t)(x - __shfl(g.ex, c, SPAI_WAVE));
+}
+
 // exponent histogram (bits 62..52) of the candidates; counts diagonal entries apart
 template <typename T>
-__global__ __launch_bounds__(kSelThreads) void k_sel_hist_exp(Pair<T> Xp, int excl_diag,
-                                                              unsigned long long* hist, int64_t n,
-                                                              DevState* st) {
+__global__ __launch_bounds__(SPAI_WAVE) void k_sel_hist_exp(Pair<T> Xp, int excl_diag,
+                                                            unsigned long long* hist, int64_t n,
+                                                            DevState* st) {
   if (!st->any_active || !st->iter_active) return;
   __shared__ unsigned int h[2048];
-  for (int i = threadIdx.x; i < 2048; i += kSelThreads) h[i] = 0;
+  const int lane = lane_id();
+  for (int i = lane; i < 2048; i += SPAI_WAVE) h[i] = 0;
   __syncthreads();
   const Cols<T> X = Xp.nxt();
-  const int wid = threadIdx.x / SPAI_WAVE;
-  const int lane = lane_id();
-  ColumnWalk w(n, (int64_t)wid * gridDim.x + blockIdx.x, (int64_t)gridDim.x * (kSelThreads / 64));
   long long diag = 0;
-  for (int64_t j = w.begin; j < w.end; j += w.step) {
-    const int64_t b = X.beg[j];
-    const int len = X.len[j];
-    for (int e = lane; e < len; e += SPAI_WAVE) {
-      if (excl_diag && X.idx[b + e] == (int)j) { ++diag; continue; }
-      const unsigned long long key = mag_key((double)X.val[b + e]);
-      atomicAdd(&h[(int)(key >> 52)], 1u);
+  const int64_t ng = (n + 63) / 64;
+  for (int64_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
+    const Group64 g = group_load(X, gi * 64, n);
+    for (int x0 = 0; x0 < g.T; x0 += SPAI_WAVE * kGU) {
+      int col[kGU], idx[kGU];
+      T val[kGU];
+#pragma unroll
+      for (int u = 0; u < kGU; ++u) {
+        const int x = x0 + u * SPAI_WAVE + lane;
+        const int xc = min(x, g.T - 1);            // all lanes shuffle together
+        const int c = group_col(g, xc);
+        const int64_t src = group_src(g, c, xc);
+        col[u] = -1;
+        idx[u] = -1;
+        val[u] = (T)0;
+        if (x < g.T) {
+          col[u] = c;
+          if (excl_diag) idx[u] = X.idx[src];
+          val[u] = X.val[src];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kGU; ++u) {
+        if (col[u] < 0) continue;
+        if (excl_diag && idx[u] == (int)(g.j0 + col[u])) {
+          ++diag;
+          continue;
+        }
+        atomicAdd(&h[(int)(mag_key((double)val[u]) >> 52)], 1u);
+      }
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 2048; i += kSelThreads)
+  for (int i = lane; i < 2048; i += SPAI_WAVE)
     if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
   diag = wave_sum_ll(diag);
   if (lane == 0 && diag) atomicAdd((unsigned long long*)&st->sel_diag, (unsigned long long)diag);
@@ -1285,73 +1353,67 @@ __global__ __launch_bounds__(1024) void k_sel_find_exp(const unsigned long long*
   st->sel_done = 0;
 }
 
-// gather the keys inside the selected exponent bin: each workgroup stages its keys
-// in LDS and reserves global space with one atomic per flush
-constexpr int kStage = 2048;
+// keys whose exponent bin is the selected one, staged in LDS (one stage per one-wave
+// workgroup) and flushed to the global buffer with one atomic reservation per flush
+constexpr int kStage = 1024;
 template <typename T>
-__global__ __launch_bounds__(kSelThreads) void k_sel_collect(Pair<T> Xp, int excl_diag,
-                                                             unsigned long long* selbuf,
-                                                             int64_t n, DevState* st) {
+__global__ __launch_bounds__(SPAI_WAVE) void k_sel_collect(Pair<T> Xp, int excl_diag,
+                                                           unsigned long long* selbuf,
+                                                           int64_t n, DevState* st) {
   if (!st->any_active || !st->iter_active || st->sel_done) return;
   __shared__ unsigned long long stage[kStage];
-  __shared__ int s_cnt;
-  __shared__ unsigned long long s_base;
   const Cols<T> X = Xp.nxt();
   const unsigned long long want = st->sel_prefix >> 52;
-  const int wid = threadIdx.x / SPAI_WAVE;
   const int lane = lane_id();
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
-  ColumnWalk w(n, (int64_t)wid * gridDim.x + blockIdx.x, (int64_t)gridDim.x * (kSelThreads / 64));
-  // every wave walks the same number of rounds so the flush barriers line up
-  const int64_t my = w.begin < w.end ? (w.end - w.begin + w.step - 1) / w.step : 0;
-  __shared__ int64_t s_rounds[kSelThreads / 64];
-  if (lane == 0) s_rounds[wid] = my;
-  __syncthreads();
-  int64_t rounds = 0;
-  for (int i = 0; i < kSelThreads / 64; ++i) rounds = s_rounds[i] > rounds ? s_rounds[i] : rounds;
-  for (int64_t r = 0; r < rounds; ++r) {
-    const int64_t j = w.begin + r * w.step;
-    if (j < w.end) {
-      const int64_t b = X.beg[j];
-      const int len = X.len[j];
-      for (int base = 0; base < len; base += SPAI_WAVE) {
-        const int e = base + lane;
+  int cnt = 0;                                    // staged keys (wave-uniform)
+  auto flush = [&]() {
+    __syncthreads();
+    unsigned long long base = 0;
+    if (lane == 0 && cnt) base = atomicAdd(&st->sel_count, (unsigned long long)cnt);
+    base = __shfl(base, 0, SPAI_WAVE);
+    for (int i = lane; i < cnt; i += SPAI_WAVE) selbuf[base + i] = stage[i];
+    __syncthreads();
+    cnt = 0;
+  };
+  const int64_t ng = (n + 63) / 64;
+  for (int64_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
+    const Group64 g = group_load(X, gi * 64, n);
+    for (int x0 = 0; x0 < g.T; x0 += SPAI_WAVE * kGU) {
+      if (cnt > kStage - SPAI_WAVE * kGU) flush();
+      int idx[kGU];
+      T val[kGU];
+      bool ok[kGU];
+      int col[kGU];
+#pragma unroll
+      for (int u = 0; u < kGU; ++u) {
+        const int x = x0 + u * SPAI_WAVE + lane;
+        const int xc = min(x, g.T - 1);            // all lanes shuffle together
+        const int c = group_col(g, xc);
+        const int64_t src = group_src(g, c, xc);
+        ok[u] = x < g.T;
+        idx[u] = -1;
+        val[u] = (T)0;
+        col[u] = c;
+        if (ok[u]) {
+          if (excl_diag) idx[u] = X.idx[src];
+          val[u] = X.val[src];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kGU; ++u) {
         bool take = false;
         unsigned long long key = 0;
-        if (e < len && !(excl_diag && X.idx[b + e] == (int)j)) {
-          key = mag_key((double)X.val[b + e]);
+        if (ok[u] && !(excl_diag && idx[u] == (int)(g.j0 + col[u]))) {
+          key = mag_key((double)val[u]);
           take = (key >> 52) == want;
         }
         const unsigned long long bal = __ballot(take);
-        if (bal) {
-          int pos0 = 0;
-          if (lane == 0) pos0 = atomicAdd(&s_cnt, __popcll(bal));
-          pos0 = __shfl(pos0, 0, SPAI_WAVE);
-          const int pos = pos0 + __popcll(bal & lanemask_lt());
-          if (take) {
-            if (pos < kStage) {
-              stage[pos] = key;
-            } else {                         // staging full: reserve a global slot directly
-              const unsigned long long g = atomicAdd(&st->sel_count, 1ull);
-              selbuf[g] = key;
-            }
-          }
-        }
+        if (take) stage[cnt + __popcll(bal & lanemask_lt())] = key;
+        cnt += __popcll(bal);
       }
     }
-    // flush when the stage is at least half full (and at the end)
-    __syncthreads();
-    const int c = s_cnt < kStage ? s_cnt : kStage;
-    if (c >= kStage / 2 || r == rounds - 1) {
-      if (threadIdx.x == 0) s_base = c ? atomicAdd(&st->sel_count, (unsigned long long)c) : 0;
-      __syncthreads();
-      for (int i = threadIdx.x; i < c; i += kSelThreads) selbuf[s_base + i] = stage[i];
-      __syncthreads();
-      if (threadIdx.x == 0) s_cnt = 0;
-    }
-    __syncthreads();
   }
+  flush();
 }
 
 // histogram of 13 key bits at `shift` among the collected keys matching the prefix above
@@ -1415,11 +1477,12 @@ void launch_global_select(Pair<T> X, int exclude_diag, int64_t m, double eta, in
                           DevState* st, hipStream_t s) {
   double* thr = which == 0 ? &st->thrM : &st->thrP;
   hipLaunchKernelGGL(k_sel_reset, dim3(1), dim3(1024), 0, s, hist, 8192, st);
-  hipLaunchKernelGGL(k_sel_hist_exp<T>, dim3(kSelGrid), dim3(kSelThreads), 0, s, X, exclude_diag,
-                     hist, n, st);
+  const int ng = (int)std::min<int64_t>((n + 63) / 64, 1 << 30);
+  hipLaunchKernelGGL(k_sel_hist_exp<T>, dim3(std::min(ng, resident_grid(k_sel_hist_exp<T>, 0))),
+                     dim3(SPAI_WAVE), 0, s, X, exclude_diag, hist, n, st);
   hipLaunchKernelGGL(k_sel_find_exp, dim3(1), dim3(1024), 0, s, hist, exclude_diag, m, thr, st);
-  hipLaunchKernelGGL(k_sel_collect<T>, dim3(kSelGrid), dim3(kSelThreads), 0, s, X, exclude_diag,
-                     selbuf, n, st);
+  hipLaunchKernelGGL(k_sel_collect<T>, dim3(std::min(ng, resident_grid(k_sel_collect<T>, 0))),
+                     dim3(SPAI_WAVE), 0, s, X, exclude_diag, selbuf, n, st);
   for (int shift = 39; shift >= 0; shift -= 13) {
     hipLaunchKernelGGL(k_hist_clear, dim3(1), dim3(1024), 0, s, hist, 8192, st);
     hipLaunchKernelGGL(k_sel_hist_buf, dim3(256), dim3(kSelThreads), 0, s, selbuf, shift, hist,
@@ -1432,56 +1495,108 @@ void launch_global_select(Pair<T> X, int exclude_diag, int64_t m, double eta, in
 // keep rule + in-place compaction
 // ============================================================================
 
+// Keep rule and in-place compaction, 64 columns per one-wave workgroup (grouped walk).
+// Each round of 64 consecutive entries takes a ballot of the kept ones; a kept
+// entry's place in its column is the column's running count (s_run, LDS) plus the
+// kept entries before it in the same column segment of the round.  It moves only
+// toward the column start, and a batch's entries are all loaded before any is written.
 template <typename T>
 __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int colcap, int sym,
                                                        int global, const double* tcol,
                                                        const double* gthr, double eta, int64_t n,
                                                        DevState* st) {
   if (!st->any_active || !st->iter_active) return;
+  __shared__ int s_run[SPAI_WAVE];
   const Cols<T> X = Xp.nxt();
   const int lane = lane_id();
-  const double g = global ? *gthr : 0.0;
+  const double gt = global ? *gthr : 0.0;
+  const bool need_tk = colcap && ((kind == 0 && sym) || kind == 2);
   unsigned long long kept = 0, seen = 0;
-  ColumnWalk w(n, blockIdx.x, gridDim.x);
-  for (int64_t j = w.begin; j < w.end; j += w.step) {
-    const int64_t b = X.beg[j];
-    const int len = X.len[j];
-    const double tj = colcap ? tcol[j] : 0.0;
-    int cnt = 0;
-    for (int base = 0; base < len; base += SPAI_WAVE) {
-      const int e = base + lane;
-      bool keep = false;
-      int k = 0;
-      T v = (T)0;
-      if (e < len) {
-        k = X.idx[b + e];
-        v = X.val[b + e];
-        const double a = fabs((double)v);
-        if (kind == 0 && k == (int)j) {
-          keep = true;
-        } else if (global) {
-          keep = a > g;
-        } else if (colcap) {
-          double t = tj;
-          if (kind == 0 && sym) t = fmax(t, tcol[k]);
-          if (kind == 2) t = tcol[k];
-          keep = a > t * (1.0 + eta);
-        } else {
-          keep = true;
+  const int64_t ng = (n + 63) / 64;
+  for (int64_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
+    const Group64 g = group_load(X, gi * 64, n);
+    const int64_t jl = g.j0 + lane;
+    const double tl = (colcap && jl < n) ? tcol[jl] : 0.0;   // this lane's column threshold
+    s_run[lane] = 0;
+    __syncthreads();
+    for (int x0 = 0; x0 < g.T; x0 += SPAI_WAVE * kGU) {
+      int col[kGU], idx[kGU];
+      T val[kGU];
+      double tk[kGU];
+#pragma unroll
+      for (int u = 0; u < kGU; ++u) {
+        const int x = x0 + u * SPAI_WAVE + lane;
+        const int xc = min(x, g.T - 1);            // all lanes shuffle together
+        const int c = group_col(g, xc);
+        const int64_t src = group_src(g, c, xc);
+        col[u] = c;
+        idx[u] = -1;
+        val[u] = (T)0;
+        tk[u] = 0.0;
+        if (x < g.T) {
+          idx[u] = X.idx[src];
+          val[u] = X.val[src];
         }
       }
-      const unsigned long long bal = __ballot(keep);
-      if (keep) {
-        const int64_t pos = b + cnt + __popcll(bal & lanemask_lt());
-        X.idx[pos] = k;
-        X.val[pos] = v;
+      if (need_tk) {
+#pragma unroll
+        for (int u = 0; u < kGU; ++u)
+          if (idx[u] >= 0) tk[u] = tcol[idx[u]];
       }
-      cnt += __popcll(bal);
+#pragma unroll
+      for (int u = 0; u < kGU; ++u) {
+        const int rb = x0 + u * SPAI_WAVE;           // flat index of lane 0's entry
+        const int x = rb + lane;
+        const bool ok = x < g.T;
+        const int c = col[u];
+        const int j = (int)(g.j0 + c);
+        // every shuffle below runs on all lanes
+        const double tcj = __shfl(tl, c, SPAI_WAVE);
+        const int64_t cbc = __shfl(g.cb, c, SPAI_WAVE);
+        const int exc = __shfl(g.ex, c, SPAI_WAVE);
+        bool keep = false;
+        if (ok) {
+          const int k = idx[u];
+          const double a = fabs((double)val[u]);
+          if (kind == 0 && k == j) {
+            keep = true;
+          } else if (global) {
+            keep = a > gt;
+          } else if (colcap) {
+            double t = tcj;
+            if (kind == 0 && sym) t = fmax(t, tk[u]);
+            if (kind == 2) t = tk[u];
+            keep = a > t * (1.0 + eta);
+          } else {
+            keep = true;
+          }
+        }
+        const unsigned long long bal = __ballot(keep);
+        const int seg0 = max(0, exc - rb);          // first lane of my column in this round
+        const unsigned long long below = lanemask_lt() & ~((seg0 >= 64) ? ~0ull : ((1ull << seg0) - 1ull));
+        const int before = __popcll(bal & below);
+        const int base = s_run[c];
+        if (keep) {
+          const int64_t pos = cbc + base + before;
+          X.idx[pos] = idx[u];
+          X.val[pos] = val[u];
+        }
+        const int cn = __shfl_down(c, 1, SPAI_WAVE);
+        const bool last = ok && (lane == SPAI_WAVE - 1 || x + 1 >= g.T || cn != c);
+        __syncthreads();
+        if (last) s_run[c] = base + before + (keep ? 1 : 0);
+        __syncthreads();
+      }
     }
-    if (lane == 0) X.len[j] = cnt;
-    kept += (unsigned long long)cnt;
-    seen += (unsigned long long)len;
+    if (jl < n) {
+      X.len[jl] = s_run[lane];
+      kept += (unsigned long long)s_run[lane];
+      seen += (unsigned long long)g.cl;
+    }
+    __syncthreads();
   }
+  kept = (unsigned long long)wave_sum_ll((long long)kept);
+  seen = (unsigned long long)wave_sum_ll((long long)seen);
   if (lane == 0 && blockIdx.x < kCntSlots) {
     st->cnt[(3 + kind) * kCntSlots + blockIdx.x] += kept;
     st->cnt[kind * kCntSlots + blockIdx.x] += seen;
@@ -1492,9 +1607,9 @@ template <typename T>
 void launch_compact(Pair<T> X, int kind, int colcap, int sym, int global, const double* tcol,
                     double eta, int64_t n, DevState* st, hipStream_t s) {
   const double* gthr = kind == 0 ? &st->thrM : &st->thrP;
-  hipLaunchKernelGGL(k_compact<T>, dim3(resident_grid(k_compact<T>, 0)), dim3(SPAI_WAVE), 0, s, X,
-                     kind, colcap, sym,
-                     global, tcol, gthr, eta, n, st);
+  const int ng = (int)std::min<int64_t>((n + 63) / 64, 1 << 30);
+  hipLaunchKernelGGL(k_compact<T>, dim3(std::min(ng, resident_grid(k_compact<T>, 0))),
+                     dim3(SPAI_WAVE), 0, s, X, kind, colcap, sym, global, tcol, gthr, eta, n, st);
 }
 
 // ============================================================================

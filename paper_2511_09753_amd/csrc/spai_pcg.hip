@@ -150,6 +150,9 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
         mb = row_hi<LAY>(A, in + stride);
       }
     };
+    // this row's W value, loaded up front (the store of Y below may alias it, so the
+    // compiler could not move the load ahead of the store by itself)
+    const double wv_i = (W && on) ? W[i * nrhs + cofs] : 0.0;
     double y = 0.0;
     if (cnt == 0) {
       prefetch();
@@ -184,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
     }
     if (on) {
       Y[i * nrhs + cofs] = y;
-      if (W) acc += W[i * nrhs + cofs] * y;
+      acc += wv_i * y;
     }
     ec = nc;
     ev = nv;
@@ -297,8 +300,10 @@ __global__ void k_alpha(RhsState* S, const double* pq, int nrhs, int* nactive) {
 
 // r -= alpha q (inactive right-hand sides have alpha = 0), fused with the per-block
 // partials of ||r||^2 for every right-hand side; x is updated later, in k_pupd
-__global__ __launch_bounds__(kThreads) void k_axpy(double* rv, const double* q, const RhsState* S,
-                                                   int64_t n, int nrhs, int R, double* part) {
+__global__ __launch_bounds__(kThreads) void k_axpy(double* __restrict__ rv,
+                                                   const double* __restrict__ q,
+                                                   const RhsState* __restrict__ S, int64_t n,
+                                                   int nrhs, int R, double* __restrict__ part) {
   __shared__ double sh[kThreads];
   const int t = threadIdx.x;
   const int r = t % R;
@@ -354,8 +359,10 @@ __global__ void k_beta(RhsState* S, const double* rz_new, int nrhs) {
 
 // x += alpha p with this iteration's alpha (zero for right-hand sides that had already
 // stopped), then p = z + beta p for the running ones: p is read once for both
-__global__ __launch_bounds__(kThreads) void k_pupd(double* p, double* x, const double* z,
-                                                   const RhsState* S, int64_t n, int nrhs, int R) {
+__global__ __launch_bounds__(kThreads) void k_pupd(double* __restrict__ p, double* __restrict__ x,
+                                                   const double* __restrict__ z,
+                                                   const RhsState* __restrict__ S, int64_t n,
+                                                   int nrhs, int R) {
   const int t = threadIdx.x;
   const int r = t % R;
   const int rows_per = kThreads / R;
