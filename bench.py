@@ -52,6 +52,51 @@ def algorithmic_bytes(c, n, nnzA, s_val, s_aval, iters):
     }
 
 
+def lomr_alg_bytes(c, n, nnzA, s_val, s_aval, iters):
+    """Whole-iteration algorithmic bytes of LOMR (each operand of the iteration read once,
+    each output written once): 2E(A) + 3E(R) + 3E(P) + 3E(M), E(X) = nnz(X)(s + 4) + 8(n + 1)."""
+    def E(nnz, s):
+        return nnz * (s + 4) + 8 * (n + 1)
+    it = max(iters, 1)
+    return (2 * E(nnzA, s_aval) + 3 * E(c["resid"] / it, s_val) + 3 * E(c["kept_p"] / it, s_val)
+            + 3 * E(c["kept_m"] / it, s_val))
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, or None when that summary is missing or was taken on other kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_lognormal96.md")
+    src = os.path.join(ROOT, "paper_2511_09753_amd", "csrc", "spai_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    want = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != want:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def calib_copy(nbytes):
+    """A plain device-to-device copy of nbytes (the reference the HBM counters are
+    scaled by): reads nbytes, writes nbytes."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": nbytes, "launches": 3}), flush=True)
+
+
 def cpu_baseline(A, budget_s=20.0):
     """The oracle (as it stands) on a bounded sample of the workload: LOMR iterations
     from M_0 on the same matrix until ~budget_s seconds have been spent."""
@@ -82,7 +127,12 @@ def main():
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pcg", action="store_true", help="(diagnostics only) skip the PCG leg")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
+    if args.calib_copy:
+        calib_copy(args.calib_copy)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU column sharding is a design note, not built", file=sys.stderr)
@@ -143,6 +193,8 @@ def main():
     launches_per_iter = ph_calls[dom] / max(iters_timed, 1)
     dom_bytes = alg[dom] / max(launches_per_iter, 1e-9)
     achieved = dom_bytes / (dom_launch_ms * 1e-3) / 1e9
+    it_bytes = lomr_alg_bytes(cnt, n, nnzA, 4, 4, iters_timed)
+    it_gbs = it_bytes / (spai_ms / max(iters_timed, 1) * 1e-3) / 1e9
     r_mixed = float(hist[-1])
     stats = h.stats()
     log(f"mixed: ||I-AM||_F after {done} its = {r_mixed:.6e}, nnz(M)={stats['nnz_m']}, "
@@ -217,9 +269,11 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"k_{dom}"),
             "alg_bytes_per_launch": dom_bytes, "avg_launch_ms": dom_launch_ms,
         },
+        "iteration_alg_bytes": it_bytes,
+        "iteration_alg_gbs": it_gbs,
         "cpu_baseline": cpu,
         "spai_ms_per_iter": spai_ms / max(iters_timed, 1),
         "pcg_ms_per_step": ph_ms["pcg"] / args.steps,
