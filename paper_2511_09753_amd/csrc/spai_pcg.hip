@@ -81,16 +81,25 @@ __device__ __forceinline__ void gather_row(const double* X, int nrhs, int c0, un
   }
 }
 
-// y += v_e x_e over the entries e0 .. min(e0 + G, cnt) in order (v_e widened to float64)
+// y += v_e x_e over the entries e0 .. min(e0 + G, cnt) in order (v_e widened to float64);
+// the gathered value of the entry in column `diag` (the row's own index) is kept in xd
 template <int G, typename VT>
-__device__ __forceinline__ void accumulate_row(double& y, VT cv, int e0, int cnt,
-                                               const double (&xs)[G]) {
+__device__ __forceinline__ void accumulate_row(double& y, VT cv, int cc, int e0, int cnt,
+                                               const double (&xs)[G], int diag, double& xd,
+                                               bool& found) {
 #pragma unroll
   for (int k = 0; k < G; ++k)
-    if (e0 + k < cnt) y += (double)readlane_val(cv, e0 + k) * xs[k];
+    if (e0 + k < cnt) {
+      y += (double)readlane_val(cv, e0 + k) * xs[k];
+      if (__builtin_amdgcn_readlane(cc, e0 + k) == diag) {
+        xd = xs[k];
+        found = true;
+      }
+    }
 }
 
-// Y[:, c0:c0+64) = K X[:, c0:c0+64) and per-block partials of sum_i W[i, r] Y[i, r].
+// Y[:, c0:c0+64) = K X[:, c0:c0+64) and, when dot is set, per-block partials of
+// sum_i X[i, r] Y[i, r] (X[i, :] taken from the row's own diagonal gather).
 // One wave per row, lane r owning right-hand side c0 + r, so every gather is one
 // 512-byte line of X.  The row's entries are loaded by the lanes together (one per
 // lane) and broadcast with readlane, so the row's gathers (up to 16 in flight) wait on
@@ -101,7 +110,7 @@ __device__ __forceinline__ void accumulate_row(double& y, VT cv, int e0, int cnt
 // the rows that gather the same row of X run on one XCD close together in time.
 template <typename VT, int LAY>
 __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, double* Y,
-                                                        const double* W, int nrhs, int c0,
+                                                        int dot, int nrhs, int c0,
                                                         double* part) {
   __shared__ double sh[kThreads];
   constexpr int WPB = kThreads / 64;
@@ -150,9 +159,10 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
         mb = row_hi<LAY>(A, in + stride);
       }
     };
-    // this row's W value, loaded up front (the store of Y below may alias it, so the
-    // compiler could not move the load ahead of the store by itself)
-    const double wv_i = (W && on) ? W[i * nrhs + cofs] : 0.0;
+    // X[i, :] for the dot: the row's own (diagonal) gather
+    const int diag = dot ? (int)i : -1;
+    double xd = 0.0;
+    bool found = false;
     double y = 0.0;
     if (cnt == 0) {
       prefetch();
@@ -160,15 +170,15 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
       double xs[8];
       gather_row<8>(X, nrhs, c0, loff, ec, 0, cnt, xs);
       prefetch();
-      accumulate_row<8>(y, ev, 0, cnt, xs);
+      accumulate_row<8>(y, ev, ec, 0, cnt, xs, diag, xd, found);
     } else {
       double xs[16];
       gather_row<16>(X, nrhs, c0, loff, ec, 0, cnt, xs);
       prefetch();
-      accumulate_row<16>(y, ev, 0, cnt, xs);
+      accumulate_row<16>(y, ev, ec, 0, cnt, xs, diag, xd, found);
       for (int e0 = 16; e0 < cnt; e0 += 16) {
         gather_row<16>(X, nrhs, c0, loff, ec, e0, cnt, xs);
-        accumulate_row<16>(y, ev, e0, cnt, xs);
+        accumulate_row<16>(y, ev, ec, e0, cnt, xs, diag, xd, found);
       }
       for (int64_t q = a + 64; q < b; q += 64) {   // rows longer than 64 entries
         int cc = -1;
@@ -181,13 +191,17 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
         if (cn == 0) break;
         for (int e0 = 0; e0 < cn; e0 += 16) {
           gather_row<16>(X, nrhs, c0, loff, cc, e0, cn, xs);
-          accumulate_row<16>(y, cv, e0, cn, xs);
+          accumulate_row<16>(y, cv, cc, e0, cn, xs, diag, xd, found);
         }
       }
     }
     if (on) {
       Y[i * nrhs + cofs] = y;
-      acc += wv_i * y;
+      if (dot) {
+        // a row without a diagonal entry loads X[i, :] after all
+        const double wv = found ? xd : X[i * nrhs + cofs];
+        acc += wv * y;
+      }
     }
     ec = nc;
     ev = nv;
@@ -431,7 +445,6 @@ struct Solver {
     return R;
   }
 
-  // Y = Mat X with optional per-RHS dot (W, Y)
   int spmm_grid = kGrid;   // workgroups of the last product (blocks of its partials)
 
   // the product kernel walks its rows in a persistent grid: as many workgroups as fit
@@ -455,21 +468,22 @@ struct Solver {
   }
 
   template <typename VT, int LAY>
-  void spmm_as(const Mat& K, const double* X, double* Y, const double* W, double* pt) {
+  void spmm_as(const Mat& K, const double* X, double* Y, double* pt) {
     spmm_grid = resident_spmm_grid<VT, LAY>();
     for (int c0 = 0; c0 < nrhs; c0 += 64)
       hipLaunchKernelGGL((k_spmm_wave<VT, LAY>), dim3(spmm_grid), dim3(kThreads), 0, s, K, X, Y,
-                         W, nrhs, c0, pt);
+                         pt ? 1 : 0, nrhs, c0, pt);
   }
   template <typename VT>
-  void spmm_v(const Mat& K, const double* X, double* Y, const double* W, double* pt) {
-    if (K.eshift >= 0) spmm_as<VT, kLayEll>(K, X, Y, W, pt);
-    else if (K.beg) spmm_as<VT, kLayPad>(K, X, Y, W, pt);
-    else spmm_as<VT, kLayCsr>(K, X, Y, W, pt);
+  void spmm_v(const Mat& K, const double* X, double* Y, double* pt) {
+    if (K.eshift >= 0) spmm_as<VT, kLayEll>(K, X, Y, pt);
+    else if (K.beg) spmm_as<VT, kLayPad>(K, X, Y, pt);
+    else spmm_as<VT, kLayCsr>(K, X, Y, pt);
   }
-  void spmm(const Mat& K, const double* X, double* Y, const double* W, double* out) {
-    if (K.val32) spmm_v<float>(K, X, Y, W, out ? part : nullptr);
-    else spmm_v<double>(K, X, Y, W, out ? part : nullptr);
+  // Y = Mat X, and with out set the per-RHS dots (X, Y) reduced into out
+  void spmm(const Mat& K, const double* X, double* Y, double* out) {
+    if (K.val32) spmm_v<float>(K, X, Y, out ? part : nullptr);
+    else spmm_v<double>(K, X, Y, out ? part : nullptr);
     if (out)
       hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(kThreads), 0, s, part, spmm_grid, nrhs,
                          out);
@@ -487,7 +501,7 @@ struct Solver {
 
   void iteration(double rtol) {
     const dim3 gs((nrhs + 63) / 64), bs(64);
-    spmm(A, p, q, p, tmp);                                       // q = A p, (p, q)
+    spmm(A, p, q, tmp);                                       // q = A p, (p, q)
     hipLaunchKernelGGL(k_alpha, gs, bs, 0, s, S, tmp, nrhs, nactive);
     if (nrhs <= 64) {                                            // r update fused with ||r||^2
       hipLaunchKernelGGL(k_axpy, dim3(kGrid), dim3(kThreads), 0, s, r, q, S, n, nrhs, pow2(nrhs),
@@ -498,7 +512,7 @@ struct Solver {
       dot(r, r, nullptr, tmp);
     }
     hipLaunchKernelGGL(k_conv, gs, bs, 0, s, S, tmp, rtol, nrhs, nactive);
-    spmm(M, r, z, r, tmp);                                       // z = M r, (r, z)
+    spmm(M, r, z, tmp);                                       // z = M r, (r, z)
     hipLaunchKernelGGL(k_beta, gs, bs, 0, s, S, tmp, nrhs);
     if (nrhs <= 64)                                              // x += alpha p, p = z + beta p
       hipLaunchKernelGGL(k_pupd, dim3(kGrid), dim3(kThreads), 0, s, p, x, z, S, n, nrhs, pow2(nrhs));
@@ -567,7 +581,7 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
   hipLaunchKernelGGL(k_copy, dim3(kGrid), dim3(kThreads), 0, s, S.r, dB, tot);
   S.dot(dB, dB, nullptr, S.tmp);
   hipLaunchKernelGGL(k_init_rhs, gs, bs, 0, s, S.S, S.tmp, nrhs, S.nactive);
-  S.spmm(S.M, S.r, S.z, S.r, S.tmp);
+  S.spmm(S.M, S.r, S.z, S.tmp);
   hipLaunchKernelGGL(k_set_rz, gs, bs, 0, s, S.S, S.tmp, nrhs);
   hipLaunchKernelGGL(k_copy, dim3(kGrid), dim3(kThreads), 0, s, S.p, S.z, tot);
   HIPCHK(hipGetLastError());
@@ -585,7 +599,7 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
     it += k;
   }
   // true residual ||b - A x|| / ||b||
-  S.spmm(S.A, S.x, S.q, nullptr, nullptr);
+  S.spmm(S.A, S.x, S.q, nullptr);
   S.dot(dB, dB, S.q, S.tmp);     // sum (b - Ax)^2
   std::vector<double> rr(nrhs);
   HIPCHK(hipMemcpyAsync(rr.data(), S.tmp, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
