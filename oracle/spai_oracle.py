@@ -38,6 +38,10 @@ GPU library's options):
   2x2 Gram determinant) take the MR step (gamma = 0).
 * Stop when ||I - A M_i||_F / sqrt(n) <= tol (the "backward error" of
   Section 7.2; Tables 5-6 are consistent with this scaling).
+* Pi-weighted variants (Section 5): the MR step of Algorithm 5 has numerator
+  (Z, A Z), the one the Pi^{-1}-weighted product gives and Algorithm 8 uses at
+  i = 0 (the printed (Z, Pi A Z) is read as a typo); their drop rules are the
+  ones above with Z in R's place.
 """
 from __future__ import annotations
 
@@ -51,7 +55,7 @@ __all__ = [
     "frob", "fnorm", "initial_iterate", "residual", "DropRule", "cap_counts",
     "drop_main", "drop_direction", "mr", "cg", "lomr", "run", "pcg", "pcg_block",
     "loss", "loss_grad", "OracleBreakdown", "column_residual", "row_residual",
-    "grad_m_entry", "grad_a_entry",
+    "grad_m_entry", "grad_a_entry", "jacobi", "mr_spd", "cg_spd", "lomr_spd", "run_spd",
 ]
 
 UNIT_ROUNDOFF = 2.0 ** -53
@@ -390,8 +394,178 @@ def lomr(A, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = Tr
     return out
 
 
+# ----------------------------------------------------------------------------
+# Pi-weighted variants (Section 5, Algorithms 5, 7 and 8)
+# ----------------------------------------------------------------------------
+
+def jacobi(A) -> sp.csr_matrix:
+    """Pi = D_A^{-1}, the preconditioner of Section 5 and of the experiments of Section 7."""
+    return sp.diags(1.0 / sp.csr_matrix(A).diagonal()).tocsr()
+
+
+def mr_spd(A, Pi, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = True,
+           M0=None) -> Result:
+    """MR with Pi-weighted inner products (Algorithm 5).
+
+    Z_i = Pi R_i; alpha_i = (Z_i, A Z_i)_F / (A Z_i, Pi A Z_i)_F;
+    M_{i+1} = D_M(M_i + alpha_i Z_i).  Section 5 weights the Frobenius product by Pi^{-1}
+    so that Pi A is self-adjoint; in that product the MR step for Pi A with residual Z
+    has numerator (Z, A Z) (it minimises (R_{i+1}, Pi R_{i+1})), and Algorithm 8 takes
+    the same numerator at i = 0, so the printed (Z_i, Pi A Z_i) is read as (Z_i, A Z_i).
+    Z, like MR's R, is not dropped.
+    """
+    A = sp.csr_matrix(A)
+    Pi = sp.csr_matrix(Pi)
+    n = A.shape[0]
+    c, Minit = initial_iterate(A)
+    M = Minit if M0 is None else _csc(M0)
+    R = residual(A, M)
+    out = Result(M, None, c=c)
+    out.resid.append(fnorm(R))
+    out.nnz_m.append(M.nnz)
+    if _converged(out.resid[-1], n, tol):
+        out.status = "converged"
+        return out
+    for i in range(max_iter):
+        Z = _csc(Pi @ R)
+        AZ = _csc(A @ Z)
+        az_paz = frob(AZ, _csc(Pi @ AZ))
+        if az_paz == 0.0:
+            out.status = "converged"
+            break
+        z_az = frob(Z, AZ)
+        alpha = z_az / az_paz
+        M = drop_main(M + alpha * Z, rule)
+        R = residual(A, M) if explicit else _csc(R - alpha * AZ)
+        out.scalars.append({"alpha": alpha, "z_az": z_az, "az_paz": az_paz})
+        out.resid.append(fnorm(R))
+        out.nnz_m.append(M.nnz)
+        out.iters = i + 1
+        if _converged(out.resid[-1], n, tol):
+            out.status = "converged"
+            break
+    out.M = M
+    return out
+
+
+def cg_spd(A, Pi, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = True,
+           M0=None) -> Result:
+    """Matrix CG preconditioned by Pi (Algorithm 7).
+
+    Z_0 = Pi R_0, P_0 = D_P(Z_0); alpha_i = (R_i, Z_i)_F / (P_i, A P_i)_F;
+    M_{i+1} = D_M(M_i + alpha_i P_i); Z_{i+1} = Pi R_{i+1};
+    beta_{i+1} = (R_{i+1}, Z_{i+1})_F / (R_i, Z_i)_F; P_{i+1} = D_P(Z_{i+1} + beta_{i+1} P_i).
+    """
+    A = sp.csr_matrix(A)
+    Pi = sp.csr_matrix(Pi)
+    n = A.shape[0]
+    c, Minit = initial_iterate(A)
+    M = Minit if M0 is None else _csc(M0)
+    R = residual(A, M)
+    Z = _csc(Pi @ R)
+    P = drop_direction(Z, rule)
+    rz = frob(R, Z)
+    out = Result(M, P, c=c)
+    out.resid.append(fnorm(R))
+    out.nnz_m.append(M.nnz)
+    out.nnz_p.append(P.nnz)
+    if _converged(out.resid[-1], n, tol):
+        out.status = "converged"
+        return out
+    for i in range(max_iter):
+        if rz == 0.0:
+            out.status = "converged"
+            break
+        AP = _csc(A @ P)
+        p_ap = frob(P, AP)
+        if not p_ap > 0.0:
+            out.status = "breakdown"
+            break
+        alpha = rz / p_ap
+        M = drop_main(M + alpha * P, rule)
+        R = residual(A, M) if explicit else _csc(R - alpha * AP)
+        Z = _csc(Pi @ R)
+        rz_new = frob(R, Z)
+        beta = rz_new / rz
+        P = drop_direction(Z + beta * P, rule)
+        out.scalars.append({"alpha": alpha, "beta": beta, "p_ap": p_ap, "rz": rz})
+        rz = rz_new
+        out.resid.append(fnorm(R))
+        out.nnz_m.append(M.nnz)
+        out.nnz_p.append(P.nnz)
+        out.iters = i + 1
+        if _converged(out.resid[-1], n, tol):
+            out.status = "converged"
+            break
+    out.M, out.P = M, P
+    return out
+
+
+def lomr_spd(A, Pi, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = True,
+             M0=None) -> Result:
+    """Locally optimal MR with Pi-weighted inner products (Algorithm 8).
+
+    Z_i = Pi R_i; (delta_i, gamma_i) from the five products (Z, AZ), (AZ, Pi AZ),
+    (AZ, Pi AP), (Z, AP), (AP, Pi AP) in the roles Theorem 4.2 gives (R, AR), (AR, AR),
+    (AR, AP), (R, AP), (AP, AP); M_{i+1} = D_M(M_i + delta_i Z_i + gamma_i P_{i-1}),
+    P_i = D_P(delta_i Z_i + gamma_i P_{i-1}), P_{-1} = 0, the MR step at i = 0.
+    """
+    A = sp.csr_matrix(A)
+    Pi = sp.csr_matrix(Pi)
+    n = A.shape[0]
+    c, Minit = initial_iterate(A)
+    M = Minit if M0 is None else _csc(M0)
+    R = residual(A, M)
+    P = _csc(sp.csc_matrix((n, n)))
+    out = Result(M, P, c=c)
+    out.resid.append(fnorm(R))
+    out.nnz_m.append(M.nnz)
+    out.nnz_p.append(0)
+    if _converged(out.resid[-1], n, tol):
+        out.status = "converged"
+        return out
+    for i in range(max_iter):
+        Z = _csc(Pi @ R)
+        AZ = _csc(A @ Z)
+        AP = _csc(A @ P)
+        PAZ = _csc(Pi @ AZ)
+        PAP = _csc(Pi @ AP)
+        az_paz = frob(AZ, PAZ)
+        if az_paz == 0.0:
+            out.status = "converged"
+            break
+        z_az = frob(Z, AZ)
+        az_pap = frob(AZ, PAP)
+        z_ap = frob(Z, AP)
+        ap_pap = frob(AP, PAP)
+        delta, gamma, fell_back = lomr_coefficients(z_az, az_paz, az_pap, z_ap, ap_pap, i == 0)
+        M = drop_main(M + delta * Z + gamma * P, rule)
+        Rnew = residual(A, M) if explicit else _csc(R - delta * AZ - gamma * AP)
+        P = drop_direction(delta * Z + gamma * P, rule)
+        R = Rnew
+        out.scalars.append({"delta": delta, "gamma": gamma, "z_az": z_az, "az_paz": az_paz,
+                            "az_pap": az_pap, "z_ap": z_ap, "ap_pap": ap_pap,
+                            "mr_fallback": fell_back})
+        out.resid.append(fnorm(R))
+        out.nnz_m.append(M.nnz)
+        out.nnz_p.append(P.nnz)
+        out.iters = i + 1
+        if _converged(out.resid[-1], n, tol):
+            out.status = "converged"
+            break
+    out.M, out.P = M, P
+    return out
+
+
 def run(method: str, A, rule: DropRule, max_iter: int, tol: float = 0.0, **kw) -> Result:
     return {"mr": mr, "cg": cg, "lomr": lomr}[method](A, rule, max_iter, tol, **kw)
+
+
+def run_spd(method: str, A, Pi, rule: DropRule, max_iter: int, tol: float = 0.0,
+            **kw) -> Result:
+    """The Pi-weighted variant of `method` (Algorithms 5, 7, 8)."""
+    return {"mr": mr_spd, "cg": cg_spd, "lomr": lomr_spd}[method](A, Pi, rule, max_iter, tol,
+                                                                   **kw)
 
 
 # ----------------------------------------------------------------------------

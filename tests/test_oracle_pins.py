@@ -508,3 +508,106 @@ def test_gradient_entries_match_local_finite_differences():
         g = O.grad_a_entry(A, M, i, k)
         assert g == pytest.approx(fd, rel=1e-7, abs=1e-9)
         assert g == pytest.approx(GA[i, k], rel=1e-12, abs=1e-14)
+
+
+# ----------------------------------------------------------------------------
+# Pi-weighted variants (Section 5; Algorithms 5, 7, 8), Pi = D_A^{-1}
+# ----------------------------------------------------------------------------
+
+def _pi_weighted(A, Pi, M):
+    """(R, Pi R)_F with R = I - A M, dense."""
+    Ad, Pd = _dense(A), _dense(Pi)
+    R = np.eye(Ad.shape[0]) - Ad @ _dense(M)
+    return float(np.sum(R * (Pd @ R)))
+
+
+def test_pi_weighted_variants_reduce_to_plain_ones_for_scalar_pi():
+    """With Pi = I/4 (the Laplacian's constant diagonal, a power of two) every Pi-weighted
+    quantity is an exact rescaling, so the weighted methods retrace the plain ones."""
+    A = W.laplace2d(7)
+    Pi = O.jacobi(A)
+    assert np.all(Pi.diagonal() == 0.25)
+    rule = O.DropRule(mode="global", m=O.cap_counts(A, "global", 2.0, True))
+    for method in ("mr", "cg", "lomr"):
+        a = O.run_spd(method, A, Pi, rule, 8)
+        b = O.run(method, A, rule, 8)
+        assert a.resid == b.resid
+        assert (a.M != b.M).nnz == 0
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_mr_spd_step_minimises_pi_weighted_residual(seed):
+    """alpha_i minimises (R_{i+1}, Pi R_{i+1})_F along Z_i (found by a scalar minimiser on
+    the dense objective); the printed numerator (Z, Pi A Z) would not."""
+    from scipy.optimize import minimize_scalar
+    A = W.lognormal3d(3, seed)
+    Pi = O.jacobi(A)
+    res = O.mr_spd(A, Pi, O.DropRule.no_drop(), 4)
+    c, M = O.initial_iterate(A)
+    for s in res.scalars:
+        R = O.residual(A, M)
+        Z = sp.csc_matrix(Pi @ R)
+        opt = minimize_scalar(lambda a: _pi_weighted(A, Pi, M + a * Z), bracket=(0.0, 1.0),
+                              tol=1e-14)
+        assert s["alpha"] == pytest.approx(opt.x, rel=1e-6)
+        AZ = A @ Z
+        printed = O.frob(Z, Pi @ AZ) / O.frob(AZ, Pi @ AZ)
+        assert abs(printed - opt.x) > 1e-3 * abs(opt.x)
+        M = sp.csc_matrix(M + s["alpha"] * Z)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_lomr_spd_step_is_pi_weighted_two_dim_least_squares(seed):
+    """(delta_i, gamma_i) minimise (R_{i+1}, Pi R_{i+1})_F over M_i + span{Z_i, P_{i-1}}:
+    dense least squares on Pi^(1/2)-scaled columns."""
+    A = W.lognormal3d(3, 10 + seed)
+    Pi = O.jacobi(A)
+    h = np.sqrt(Pi.diagonal())[:, None]
+    Ad = _dense(A)
+    res = O.lomr_spd(A, Pi, O.DropRule.no_drop(), 5)
+    c, M = O.initial_iterate(A)
+    P = sp.csc_matrix(A.shape)
+    for i, s in enumerate(res.scalars):
+        R = O.residual(A, M)
+        Z = sp.csc_matrix(Pi @ R)
+        dirs = [Z] if i == 0 else [Z, P]
+        cols = np.stack([(h * (Ad @ _dense(D))).ravel() for D in dirs], axis=1)
+        coef, *_ = np.linalg.lstsq(cols, (h * _dense(R)).ravel(), rcond=None)
+        assert s["delta"] == pytest.approx(coef[0], rel=1e-8)
+        if i:
+            assert s["gamma"] == pytest.approx(coef[1], rel=1e-7, abs=1e-12)
+        dM = s["delta"] * Z + (s["gamma"] * P if i else 0.0 * Z)
+        M = sp.csc_matrix(M + dM)
+        P = sp.csc_matrix(dM)
+
+
+def test_cg_spd_orthogonality_and_finite_termination():
+    """Matrix CG preconditioned by Pi: (R_i, Pi R_j)_F = 0 and (P_i, A P_j)_F = 0 for i != j;
+    with A = S L S (L the 4 x 4 Dirichlet Laplacian, S a positive diagonal) Pi A is similar
+    to L / 4, which has 9 distinct eigenvalues, so it ends at step 9, while the plain
+    method on the same A does not."""
+    rng = np.random.default_rng(5)
+    L = W.laplace2d(4)
+    S = sp.diags(rng.uniform(0.5, 2.0, L.shape[0]))
+    A = sp.csr_matrix(S @ L @ S)
+    Pi = O.jacobi(A)
+    rule = O.DropRule.no_drop()
+    res = O.cg_spd(A, Pi, rule, 9)
+    assert res.resid[8] > 1e-6 * res.resid[0]
+    assert res.resid[9] < 1e-10 * res.resid[0]
+    assert O.cg(A, rule, 9).resid[9] > 1e-6 * res.resid[0]
+    Rs, Ps = [], []
+    c, M = O.initial_iterate(A)
+    R = O.residual(A, M)
+    P = sp.csc_matrix(Pi @ R)
+    for i in range(6):
+        Rs.append(R)
+        Ps.append(P)
+        r = O.cg_spd(A, Pi, rule, i + 1)
+        R = O.residual(A, r.M)
+        P = r.P
+    scale = O.frob(Rs[0], Pi @ Rs[0])
+    for i in range(1, 6):
+        for j in range(i):
+            assert abs(O.frob(Rs[i], Pi @ Rs[j])) <= 1e-10 * scale
+            assert abs(O.frob(Ps[i], A @ Ps[j])) <= 1e-9 * scale
