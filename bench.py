@@ -127,6 +127,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pcg", action="store_true", help="(diagnostics only) skip the PCG leg")
+    ap.add_argument("--no-jacobi", action="store_true", help="skip the Pi-weighted LOMR leg")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
@@ -151,9 +152,9 @@ def main():
     log(f"workload: 3D lognormal 7-point {N}^3, n={n}, nnz={nnzA}")
     B = torch.from_numpy(W.rhs(n, args.nrhs, W.seed_for(3, 1))).cuda()
 
-    def make(prec, profile):
+    def make(prec, profile, jacobi=False):
         return S.SPAI(A, "lomr", "global", 2.0, True, max_iter=max(args.iters, 60),
-                      options=S.Options(precision=prec, profile=profile))
+                      options=S.Options(precision=prec, profile=profile, jacobi=jacobi))
 
     def step(h, its):
         h.reset()
@@ -243,6 +244,22 @@ def main():
     else:
         h.close()
 
+    # ---------------- Pi-weighted LOMR (Algorithm 8, Pi = D_A^{-1}), same workload and cap
+    jac = None
+    if not args.no_jacobi:
+        hj = make("mixed", True, jacobi=True)
+        hj.reset()
+        hj.iterate(args.iters)                       # warm-up
+        j0, _, k0 = hj.profile()
+        hj.reset()
+        _, histj, _ = hj.iterate(args.iters)
+        j1, _, k1 = hj.profile()
+        jms = sum(j1[k] - j0[k] for k in j1 if k != "pcg") / max(k1["iters"] - k0["iters"], 1)
+        hj.close()
+        jac = {"method": "LOMR_SPD (Pi = D_A^-1), mixed", "spai_ms_per_iter": jms,
+               "resid_fro": float(histj[-1]), "iters": args.iters}
+        log("jacobi-weighted LOMR:", json.dumps(jac))
+
     cpu = None if args.no_cpu else cpu_baseline(A)
     if cpu:
         log("cpu baseline:", json.dumps(cpu))
@@ -283,6 +300,7 @@ def main():
         "resid_fro": r_mixed,
         "pcg_iters_max": int(pcg[0].max()) if pcg else None,
         "mixed_vs_f64": f64,
+        "jacobi_lomr": jac,
     }
     print(json.dumps(out), flush=True)
 

@@ -111,6 +111,10 @@ typedef struct {
   int profile;              /* 1: time every phase of an iteration with HIP events
                                on the handle's stream (see spai_profile), default 0 */
   int a_format;             /* SPAI_AFMT_*, default SPAI_AFMT_AUTO                 */
+  int jacobi;               /* 1: the Pi-weighted variants of Section 5 with
+                               Pi = D_A^{-1} (MR: Algorithm 5, CG: Algorithm 7,
+                               LOMR: Algorithm 8); the direction lists hold
+                               Z = Pi R; default 0                                 */
 } spai_opts_t;
 
 /* Fill *opts with the defaults. */

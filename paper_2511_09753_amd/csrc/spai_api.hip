@@ -166,6 +166,7 @@ struct Engine : EngineBase {
   Cols<T> R;
   int64_t *ub = nullptr, *off = nullptr, *total = nullptr, *scantmp = nullptr;
   double *colpart = nullptr, *colnorm = nullptr, *red = nullptr, *red_rr = nullptr;
+  double *colrz = nullptr, *red_rz = nullptr;   // (R, Z)_F per column / matrix (weighted)
   double *blockpart = nullptr, *cvec = nullptr, *hist = nullptr;
   int32_t* kcol = nullptr;
   double *tM = nullptr, *tP = nullptr;
@@ -405,6 +406,7 @@ struct Engine : EngineBase {
         (rc = dalloc(&red, (int64_t)nseg * kND)) || (rc = dalloc(&red_rr, nseg)) ||
         (rc = dalloc(&blockpart, 1024 * kND)) || (rc = dalloc(&cvec, nseg)))
       return rc;
+    if (opts.jacobi && ((rc = dalloc(&colrz, n)) || (rc = dalloc(&red_rz, nseg)))) return rc;
     hist_cap = std::max(max_iter, 1);
     if ((rc = dalloc(&hist, (int64_t)nseg * hist_cap))) return rc;
     if (colcap) {
@@ -525,6 +527,7 @@ struct Engine : EngineBase {
     md.sym = opts.symmetrize ? 1 : 0;
     md.colcap = colcap ? 1 : 0;
     md.u = opts.drop_tol;
+    md.weighted = opts.jacobi ? 1 : 0;
     return md;
   }
 
@@ -534,17 +537,20 @@ struct Engine : EngineBase {
     launch_scan(ub, off, total, n, scantmp, s);
     te();
     tb(SPAI_PH_RESID);
-    launch_resid<T>(A, M, R, off, total, colnorm, big[0], st, tRs, tRl, s);
+    launch_resid<T>(A, M, R, off, total, colnorm, opts.jacobi, colrz, big[0], st, tRs, tRl, s);
     te();
     tb(SPAI_PH_SCALAR);
     launch_reduce(colnorm, 1, n, seg, nseg > 1 ? seg_beg : nullptr, red_rr, blockpart, s);
-    launch_scal_post(method, seg, red_rr, tol, hist, hist_cap, setup, st, s);
+    if (opts.jacobi)
+      launch_reduce(colrz, 1, n, seg, nseg > 1 ? seg_beg : nullptr, red_rz, blockpart, s);
+    launch_scal_post(method, seg, red_rr, opts.jacobi ? red_rz : nullptr, tol, hist, hist_cap,
+                     setup, st, s);
     te();
   }
 
   void dots_step(int useR, int useP) {
     tb(SPAI_PH_DOTS);
-    launch_dots<T>(A, R, P, useR, useP, colpart, big[1], st, tDs, tDl, s);
+    launch_dots<T>(A, R, P, useR, useP, opts.jacobi, colpart, big[1], st, tDs, tDl, s);
     te();
     tb(SPAI_PH_SCALAR);
     launch_reduce(colpart, kND, n, seg, nseg > 1 ? seg_beg : nullptr, red, blockpart, s);
@@ -770,6 +776,7 @@ static void fill_defaults(spai_opts_t* o) {
   o->device_pool_limit = 0;
   o->profile = 0;
   o->a_format = SPAI_AFMT_AUTO;
+  o->jacobi = 0;
 }
 
 template <typename T>
@@ -805,6 +812,7 @@ static int check_common(int method, spai_cap_t cap, int max_iter, double tol,
   if (o.precision != SPAI_PREC_F64 && o.precision != SPAI_PREC_MIXED)
     return fail(SPAI_ERR_ARG, "unknown precision");
   if (!(o.drop_tol >= 0.0) || !(o.tie_eta >= 0.0)) return fail(SPAI_ERR_ARG, "bad drop_tol / tie_eta");
+  if (o.jacobi != 0 && o.jacobi != 1) return fail(SPAI_ERR_ARG, "jacobi must be 0 or 1");
   if (o.a_format != SPAI_AFMT_AUTO && o.a_format != SPAI_AFMT_CSR && o.a_format != SPAI_AFMT_ELL)
     return fail(SPAI_ERR_ARG, "unknown a_format");
   return SPAI_OK;

@@ -19,6 +19,7 @@ constexpr int kNCnt = 7;
 struct SegState {
   double dots[kND];   // reduced dots of the current iteration
   double rr;          // ||R_i||_F^2 of the current iterate
+  double rz;          // (R_i, Z_i)_F with Z = Pi R (Pi-weighted CG), else ||R_i||_F^2
   double coef[4];     // a1, a2 (M + a1 X1 + a2 X2), c1, c2 (P = c1 R + c2 P)
   double step1, step2;// last step sizes (MR alpha | CG alpha, beta | LOMR delta, gamma)
   double inv_sqrt_n;  // 1 / sqrt(rows of this matrix)
@@ -82,6 +83,8 @@ struct UpdMode {
   int sym;       // symmetrize M
   int colcap;    // per-column caps: compute per-column thresholds
   double u;      // small-entry threshold on off-diagonal M (0 = off)
+  int weighted;  // Pi = D_A^{-1}: the R list holds Z = Pi R, and R^T is scaled to Z^T
+  int pad;
 };
 
 // ---------------- launchers (all enqueue on `s`) -----------------------------
@@ -108,12 +111,13 @@ void launch_bound_resid(const Csr& A, Pair<T> M, int64_t* ub, int64_t n, const D
                         hipStream_t s);
 template <typename T>
 void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const int64_t* total,
-                  double* colnorm, BigList big, DevState* st, Tile small, Tile large,
-                  hipStream_t s);
+                  double* colnorm, int weighted, double* colrz, BigList big, DevState* st,
+                  Tile small, Tile large, hipStream_t s);
 
 template <typename T>
-void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, double* colpart,
-                 BigList big, DevState* st, Tile small, Tile large, hipStream_t s);
+void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, int weighted,
+                 double* colpart, BigList big, DevState* st, Tile small, Tile large,
+                 hipStream_t s);
 
 template <typename T>
 void launch_bound_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, UpdMode md,
@@ -138,8 +142,9 @@ void launch_compact(Pair<T> X, int kind, int colcap, int sym, int global, const 
 
 void launch_scal_step(int method, const Seg& seg, const double* red, DevState* st,
                       hipStream_t s);
-void launch_scal_post(int method, const Seg& seg, const double* red, double tol, double* hist,
-                      int hist_cap, int setup, DevState* st, hipStream_t s);
+void launch_scal_post(int method, const Seg& seg, const double* red, const double* red_rz,
+                      double tol, double* hist, int hist_cap, int setup, DevState* st,
+                      hipStream_t s);
 extern int g_grid_cols;   // persistent grid of the per-column kernels (multiple of 8)
 void launch_flip(int which, DevState* st, hipStream_t s);   // 0: curM, 1: curP
 

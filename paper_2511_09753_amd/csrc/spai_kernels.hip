@@ -158,8 +158,8 @@ __device__ __forceinline__ void row_span(const Csr& A, int u, int64_t& q0, int64
 
 // Pull over the rows of A selected by sorted keys[0..nu): G keys per lane at a time,
 // their first 8-entry chunks loaded together before any is used.  Row u is visited in
-// ascending column order, chunk by chunk: init(c) before key slot c, chunk(c, cols,
-// vals) per chunk (column -1: no entry), done(c, t) after key keys[t].
+// ascending column order, chunk by chunk: init(c, t) before key keys[t] (slot c),
+// chunk(c, cols, vals) per chunk (column -1: no entry), done(c, t) after it.
 template <int G, typename FI, typename FC, typename FD>
 __device__ __forceinline__ void pull_rows(const Csr& A, const int* keys, int nu, FI init,
                                           FC chunk, FD done) {
@@ -184,7 +184,7 @@ __device__ __forceinline__ void pull_rows(const Csr& A, const int* keys, int nu,
 #pragma unroll
     for (int c = 0; c < G; ++c) {
       if (tt[c] >= nu) continue;
-      init(c);
+      init(c, tt[c]);
       chunk(c, cols[c], vals[c]);
       for (int64_t q = qa[c] + 8; q < qb[c] && cols[c][7] >= 0; q += 8) {
         load_chunk(A, q, qb[c], cols[c], vals[c]);
@@ -478,8 +478,9 @@ template <typename T>
 // kernel, with no spills
 __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5))) void k_resid(Csr A, Pair<T> Mp, Cols<T> R,
                                                      const int64_t* off, const int64_t* total,
-                                                     double* colnorm, BigList big, DevState* st,
-                                                     int tier, int L, int H) {
+                                                     double* colnorm, int weighted, double* colrz,
+                                                     BigList big, DevState* st, int tier, int L,
+                                                     int H) {
   if (!st->any_active) return;
   extern __shared__ char smem[];
   const bool ell = A.eshift >= 0;
@@ -536,10 +537,17 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
     const int nu = ks_sort_inplace(s_keys, H);
     __syncthreads();
     const int64_t ob = off[j];
-    double acc = 0.0;
+    double acc = 0.0, acc_rz = 0.0;
     double sum[1];
+    double diag[1];             // a_uu of the pulled row (the Pi weight is 1 / a_uu)
+    int key[1];
     pull_rows<1>(
-        A, s_keys, nu, [&](int c) { sum[c] = 0.0; },
+        A, s_keys, nu,
+        [&](int c, int t) {
+          sum[c] = 0.0;
+          diag[c] = 0.0;
+          key[c] = s_keys[t];
+        },
         [&](int c, const int (&cols)[8], const double (&vals)[8]) {
           unsigned pw[8];
           lm_find<8>(s_mk, s_mp, hs, cols, pw);
@@ -547,19 +555,28 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
           for (int k = 0; k < 8; ++k) {
             const unsigned e = pw[k] & kNoPos;
             if (e != kNoPos) sum[c] += vals[k] * s_mv[e];
+            if (cols[k] == key[c]) diag[c] = vals[k];
           }
         },
         [&](int c, int t) {
-          const int u = s_keys[t];
+          const int u = key[c];
           const double r = ((u == (int)j) ? 1.0 : 0.0) - sum[c];
           const T rt = (T)r;
+          T out = rt;
+          if (weighted) {                   // Z = Pi R, Pi = D_A^{-1}
+            const double pi = 1.0 / diag[c];
+            out = (T)(pi * r);
+            acc_rz += (double)rt * (double)out;
+          }
           R.idx[ob + t] = u;
-          R.val[ob + t] = rt;
+          R.val[ob + t] = out;
           acc += (double)rt * (double)rt;
         });
     acc = wave_sum(acc);
+    if (weighted) acc_rz = wave_sum(acc_rz);
     if (lane == 0) {
       colnorm[j] = acc;
+      if (weighted) colrz[j] = acc_rz;
       R.beg[j] = ob;
       R.len[j] = nu;
     }
@@ -612,15 +629,15 @@ static int resident_grid(K kernel, size_t lds) {
 
 template <typename T>
 void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const int64_t* total,
-                  double* colnorm, BigList big, DevState* st, Tile small, Tile large,
-                  hipStream_t s) {
+                  double* colnorm, int weighted, double* colrz, BigList big, DevState* st,
+                  Tile small, Tile large, hipStream_t s) {
   const bool ell = A.eshift >= 0;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
   hipLaunchKernelGGL(k_resid<T>, dim3(resident_grid(k_resid<T>, resid_lds(small, ell))),
-                     dim3(SPAI_WAVE), resid_lds(small, ell), s, A, M, R, off, total, colnorm, big,
-                     st, 0, small.L, small.H);
+                     dim3(SPAI_WAVE), resid_lds(small, ell), s, A, M, R, off, total, colnorm,
+                     weighted, colrz, big, st, 0, small.L, small.H);
   hipLaunchKernelGGL(k_resid<T>, dim3(256), dim3(SPAI_WAVE), resid_lds(large, ell), s, A, M, R, off,
-                     total, colnorm, big, st, 1, large.L, large.H);
+                     total, colnorm, weighted, colrz, big, st, 1, large.L, large.H);
 }
 
 // ============================================================================
@@ -629,8 +646,9 @@ void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const 
 
 template <typename T>
 __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp, int useR,
-                                                    int useP, double* colpart, BigList big,
-                                                    DevState* st, int tier, int L, int H) {
+                                                    int useP, int weighted, double* colpart,
+                                                    BigList big, DevState* st, int tier, int L,
+                                                    int H) {
   if (!st->any_active || !st->iter_active) return;
   extern __shared__ char smem[];
   const bool ell = A.eshift >= 0;
@@ -693,9 +711,16 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
     const int* pi = s_li + lr;
     const double* pv = s_lv + lr;
     double d0 = 0, d1 = 0, d2 = 0, d3 = 0, d4 = 0, d5 = 0;
-    double ar[1], ap[1];
+    double ar[1], ap[1], diag[1];
+    int key[1];
     pull_rows<1>(
-        A, s_keys, nu, [&](int c) { ar[c] = 0.0; ap[c] = 0.0; },
+        A, s_keys, nu,
+        [&](int c, int t) {
+          ar[c] = 0.0;
+          ap[c] = 0.0;
+          diag[c] = 0.0;
+          key[c] = s_keys[t];
+        },
         [&](int c, const int (&cols)[8], const double (&vals)[8]) {
           unsigned pw[8];
           lm_find<8>(s_mk, s_mp, hs, cols, pw);
@@ -704,21 +729,29 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
             const unsigned e0 = pw[k] & kNoPos, e1 = pw[k] >> 16;
             if (e0 != kNoPos) ar[c] += vals[k] * rv[e0];
             if (e1 != kNoPos) ap[c] += vals[k] * pv[e1];
+            if (cols[k] == key[c]) diag[c] = vals[k];
           }
         },
         [&](int c, int t) {
-          const int key[1] = {s_keys[t]};
+          const int kk[1] = {key[c]};
           unsigned pw[1];
-          lm_find<1>(s_mk, s_mp, hs, key, pw);
+          lm_find<1>(s_mk, s_mp, hs, kk, pw);
           const unsigned e0 = pw[0] & kNoPos, e1 = pw[0] >> 16;
           const double ru = e0 != kNoPos ? rv[e0] : 0.0;
           const double pu = e1 != kNoPos ? pv[e1] : 0.0;
           d0 += ru * ar[c];
-          d1 += ar[c] * ar[c];
-          d2 += ar[c] * ap[c];
           d3 += ru * ap[c];
-          d4 += ap[c] * ap[c];
           d5 += pu * ap[c];
+          if (weighted) {            // (AZ, Pi AZ), (AZ, Pi AP), (AP, Pi AP), Pi = D_A^{-1}
+            const double pi = 1.0 / diag[c];
+            d1 += ar[c] * (pi * ar[c]);
+            d2 += ar[c] * (pi * ap[c]);
+            d4 += ap[c] * (pi * ap[c]);
+          } else {
+            d1 += ar[c] * ar[c];
+            d2 += ar[c] * ap[c];
+            d4 += ap[c] * ap[c];
+          }
         });
     (void)ri;
     (void)pi;
@@ -750,15 +783,16 @@ static size_t dots_lds(Tile t, bool ell) {
 }
 
 template <typename T>
-void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, double* colpart,
-                 BigList big, DevState* st, Tile small, Tile large, hipStream_t s) {
+void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, int weighted,
+                 double* colpart, BigList big, DevState* st, Tile small, Tile large,
+                 hipStream_t s) {
   const bool ell = A.eshift >= 0;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
   hipLaunchKernelGGL(k_dots<T>, dim3(resident_grid(k_dots<T>, dots_lds(small, ell))),
-                     dim3(SPAI_WAVE), dots_lds(small, ell), s, A, R, P, useR, useP, colpart, big,
-                     st, 0, small.L, small.H);
+                     dim3(SPAI_WAVE), dots_lds(small, ell), s, A, R, P, useR, useP, weighted,
+                     colpart, big, st, 0, small.L, small.H);
   hipLaunchKernelGGL(k_dots<T>, dim3(256), dim3(SPAI_WAVE), dots_lds(large, ell), s, A, R, P, useR,
-                     useP, colpart, big, st, 1, large.L, large.H);
+                     useP, weighted, colpart, big, st, 1, large.L, large.H);
 }
 
 // ============================================================================
@@ -921,12 +955,13 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
       return;
     }
     int run = 0;
+    double ajj = 0.0;                 // a_jj (Pi-weighted variants: Pi_jj = 1 / a_jj)
     for (int base = 0; base < deg; base += SPAI_WAVE) {
       const int t = base + lane;
       int len = 0;
+      int l = -1;
+      double av = 0.0;
       if (t < deg) {
-        int l;
-        double av;
         if (ell) {
           l = A.ecol[qa + t];
           av = A.eval32 ? (double)A.eval32[qa + t] : A.eval[qa + t];
@@ -939,6 +974,8 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
         s_nbval[t] = av;
         s_nbbeg[t] = M.beg[l];
       }
+      const unsigned long long dj = __ballot(l == (int)j);
+      if (dj) ajj = __shfl(av, __ffsll((long long)dj) - 1, SPAI_WAVE);
       const int inc = wave_incl_scan(len);
       if (t < deg) s_nboff[t] = onb + run + inc - len;
       run += __shfl(inc, SPAI_WAVE - 1, SPAI_WAVE);
@@ -1074,7 +1111,8 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
             }
           }
         }
-        rtv = (double)(T)(((k == (int)j) ? 1.0 : 0.0) - sum);
+        const double rj = ((k == (int)j) ? 1.0 : 0.0) - sum;
+        rtv = md.weighted ? (double)(T)((1.0 / ajj) * rj) : (double)(T)rj;   // Z^T = Pi R^T
       }
       // M candidate
       bool keepM = false, offM = false;
@@ -1635,14 +1673,15 @@ __global__ void k_scal_step(int method, Seg seg, const double* red, DevState* st
         g.step2 = 0.0;
       }
     } else if (method == kCG) {
-      if (!(g.rr > 0.0)) {
+      // rz = (R, Z)_F (Algorithm 7; = ||R||_F^2 unweighted, Algorithm 3)
+      if (!(g.rz > 0.0)) {
         g.stop = 1;
         g.status = 1;
       } else if (!(d[5] > 0.0)) {       // (P, A P) <= 0: A is not SPD, or P = 0
         g.stop = 1;
         g.status = 3;
       } else {
-        const double alpha = g.rr / d[5];
+        const double alpha = g.rz / d[5];
         g.coef[0] = alpha; g.coef[1] = 0.0;
         g.step1 = alpha;
       }
@@ -1703,16 +1742,18 @@ void launch_scal_step(int method, const Seg& seg, const double* red, DevState* s
 }
 
 // after R_{i+1}: record ||R||, test the stopping rule, CG's beta
-__global__ void k_scal_post(int method, Seg seg, const double* red, double tol, double* hist,
-                            int hist_cap, int setup, DevState* st) {
+__global__ void k_scal_post(int method, Seg seg, const double* red, const double* red_rz,
+                            double tol, double* hist, int hist_cap, int setup, DevState* st) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= seg.nseg) return;
   if (!st->iter_active) return;
   SegState& g = seg.st[s];
   const double rr_new = red[s];
+  const double rz_new = red_rz ? red_rz[s] : rr_new;
   const double rn = sqrt(rr_new);
   if (setup) {                          // R_0: no iteration counted
     g.rr = rr_new;
+    g.rz = rz_new;
     g.last_resid = rn;
     g.coef[0] = 0.0; g.coef[1] = 0.0; g.coef[2] = 1.0; g.coef[3] = 0.0;   // CG: P_0 = R_0
     if (tol > 0.0 && rn * g.inv_sqrt_n <= tol) { g.stop = 1; g.status = 1; }
@@ -1723,22 +1764,24 @@ __global__ void k_scal_post(int method, Seg seg, const double* red, double tol, 
   if (hist && g.iters < hist_cap) hist[(int64_t)s * hist_cap + g.iters] = rn;
   g.iters += 1;
   if (method == kCG) {
-    const double beta = g.rr > 0.0 ? rr_new / g.rr : 0.0;
+    const double beta = g.rz > 0.0 ? rz_new / g.rz : 0.0;
     g.coef[2] = 1.0;
     g.coef[3] = beta;
     g.step2 = beta;
   }
   g.rr = rr_new;
+  g.rz = rz_new;
   if (tol > 0.0 && rn * g.inv_sqrt_n <= tol) {
     g.stop = 1;
     g.status = 1;
   }
 }
 
-void launch_scal_post(int method, const Seg& seg, const double* red, double tol, double* hist,
-                      int hist_cap, int setup, DevState* st, hipStream_t s) {
+void launch_scal_post(int method, const Seg& seg, const double* red, const double* red_rz,
+                      double tol, double* hist, int hist_cap, int setup, DevState* st,
+                      hipStream_t s) {
   hipLaunchKernelGGL(k_scal_post, dim3((seg.nseg + 255) / 256), dim3(256), 0, s, method, seg, red,
-                     tol, hist, hist_cap, setup, st);
+                     red_rz, tol, hist, hist_cap, setup, st);
 }
 
 __global__ void k_flip(int which, DevState* st) {
@@ -1757,8 +1800,9 @@ void launch_flip(int which, DevState* st, hipStream_t s) {
   template void launch_bound_resid<T>(const Csr&, Pair<T>, int64_t*, int64_t, const DevState*,    \
                                       hipStream_t);                                               \
   template void launch_resid<T>(const Csr&, Pair<T>, Cols<T>, const int64_t*, const int64_t*,    \
-                                double*, BigList, DevState*, Tile, Tile, hipStream_t);            \
-  template void launch_dots<T>(const Csr&, Cols<T>, Pair<T>, int, int, double*, BigList,          \
+                                double*, int, double*, BigList, DevState*, Tile, Tile,            \
+                                hipStream_t);                                                     \
+  template void launch_dots<T>(const Csr&, Cols<T>, Pair<T>, int, int, int, double*, BigList,     \
                                DevState*, Tile, Tile, hipStream_t);                               \
   template void launch_bound_update<T>(const Csr&, Pair<T>, Cols<T>, Pair<T>, Pair<T>, UpdMode,   \
                                        int64_t*, int64_t, const DevState*, hipStream_t);          \

@@ -46,7 +46,8 @@ class CapT(C.Structure):
 class OptsT(C.Structure):
     _fields_ = [("precision", C.c_int), ("symmetrize", C.c_int), ("drop_tol", C.c_double),
                 ("tie_eta", C.c_double), ("stream", C.c_void_p),
-                ("device_pool_limit", C.c_int64), ("profile", C.c_int), ("a_format", C.c_int)]
+                ("device_pool_limit", C.c_int64), ("profile", C.c_int), ("a_format", C.c_int),
+                ("jacobi", C.c_int)]
 
 
 EXPORTS = [
@@ -179,6 +180,7 @@ class Options:
     device_pool_limit: int = 0
     profile: bool = False
     a_format: str = "auto"      # layout of A on the device: "auto", "csr" or "ell"
+    jacobi: bool = False        # Pi = D_A^{-1}-weighted variants (Algorithms 5, 7, 8)
 
     def c(self):
         o = OptsT()
@@ -191,6 +193,7 @@ class Options:
         o.device_pool_limit = int(self.device_pool_limit)
         o.profile = 1 if self.profile else 0
         o.a_format = A_FORMATS[self.a_format]
+        o.jacobi = 1 if self.jacobi else 0
         return o
 
 

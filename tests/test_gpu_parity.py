@@ -26,9 +26,9 @@ def _spai():
 
 
 def _run_gpu(S, A, method, mode, value, relative, iters, precision="f64", tol=0.0,
-             symmetrize=True):
+             symmetrize=True, jacobi=False):
     h = S.SPAI(A, method, mode, value, relative, max_iter=iters, tol=tol,
-               options=S.Options(precision=precision, symmetrize=symmetrize))
+               options=S.Options(precision=precision, symmetrize=symmetrize, jacobi=jacobi))
     r0 = h.stats()["resid"]
     done, hist, rc = h.iterate(iters)
     M = h.get()
@@ -314,3 +314,44 @@ def test_heavy_row_uses_csr_and_matches_oracle():
     ref = O.lomr(A, oracle_rule(A, "global", 2.0, True), 8)
     assert rel_err(hist, ref.resid[1:]) <= TOL_F64
     assert pattern_diff(Mg, ref.M) == (set(), set())
+
+
+# ----------------------------------------------------------------------------
+# Pi-weighted variants, Pi = D_A^{-1} (Section 5: Algorithms 5, 7, 8)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
+@pytest.mark.parametrize("mode,value,relative", [("global", 2.0, True), ("column", 3.0, True)])
+@pytest.mark.parametrize("name,make", SMALL)
+def test_small_parity_jacobi_f64(name, make, method, mode, value, relative):
+    S = _spai()
+    A = make()
+    iters = 12
+    r0, hist, Mg, st, rc = _run_gpu(S, A, method, mode, value, relative, iters, jacobi=True)
+    ref = O.run_spd(method, A, O.jacobi(A), oracle_rule(A, mode, value, relative), iters)
+    print(name, method, mode, "gpu", hist[-3:], "oracle", ref.resid[-3:])
+    assert r0 == pytest.approx(ref.resid[0], rel=1e-14)
+    assert len(hist) == ref.iters
+    assert rel_err(hist, ref.resid[1:]) <= TOL_F64
+    only_g, only_o = pattern_diff(Mg, ref.M)
+    assert not only_g and not only_o, (len(only_g), len(only_o))
+    assert value_err(Mg, ref.M) <= 1e-9
+    assert st["nnz_m"] == ref.M.nnz
+    if method != "mr":
+        assert st["nnz_p"] == ref.P.nnz
+    assert abs(Mg - Mg.T).nnz == 0
+
+
+@pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
+def test_jacobi_mixed_against_f64_oracle(method):
+    """Mixed precision against the FP64 oracle on a variable-coefficient problem (where
+    D_A^{-1} is not a multiple of I, so the weighting changes every step)."""
+    S = _spai()
+    A = W.lognormal3d(12, 3000)
+    iters = 12
+    r0, hist, Mg, st, rc = _run_gpu(S, A, method, "global", 2.0, True, iters, precision="mixed",
+                                    jacobi=True)
+    ref = O.run_spd(method, A, O.jacobi(A), oracle_rule(A, "global", 2.0, True), iters)
+    assert rel_err(hist, ref.resid[1:]) <= TOL_MIXED
+    _, hist_plain, _, _, _ = _run_gpu(S, A, method, "global", 2.0, True, iters, precision="mixed")
+    assert rel_err(hist_plain, hist) > 1e-3      # a different trajectory from the plain method
