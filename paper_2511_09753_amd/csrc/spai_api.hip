@@ -180,6 +180,7 @@ struct Engine : EngineBase {
   Seg seg;
   Tile tRs{128, 512}, tRl{1024, 4096}, tDs{256, 512}, tDl{1024, 4096}, tUs{384, 512},
       tUl{2048, 4096};
+  Tile tRh{0, 0}, tDh{0, 0}, tUh{0, 0};   // huge tiles (device-memory scratch), sized from n
   int hist_cap = 0;
   int iters_host = 0;
   hipGraph_t graph = nullptr;
@@ -414,7 +415,31 @@ struct Engine : EngineBase {
       HIPCHK(hipMemcpyAsync(kcol, kc.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
     }
     for (int b = 0; b < 3; ++b)
-      if ((rc = dalloc(&big[b].list, n)) || (rc = dalloc(&big[b].count, 1))) return rc;
+      if ((rc = dalloc(&big[b].list, n)) || (rc = dalloc(&big[b].count, 1)) ||
+          (rc = dalloc(&big[b].list2, n)) || (rc = dalloc(&big[b].count2, 1)))
+        return rc;
+    // huge tiles: a column's lists and key set can reach n entries (the residual's and the
+    // dots' lists are held under 32768 so map positions fit in 16 bits)
+    {
+      auto p2 = [](int64_t x) { int64_t p = 1; while (p < x) p <<= 1; return p; };
+      const bool ell = A.eshift >= 0;
+      const int64_t Lr = std::max<int64_t>(2048, std::min<int64_t>(32768, p2(n)));
+      const int64_t Ld = std::max<int64_t>(2048, std::min<int64_t>(32768, p2(2 * n)));
+      const int64_t Lu = std::max<int64_t>(4096, std::min<int64_t>(131072, p2(4 * n)));
+      const int64_t Hk = std::max<int64_t>(8192, std::min<int64_t>(131072, 2 * p2(n + 1)));
+      tRh = Tile{(int)Lr, (int)Hk};
+      tDh = Tile{(int)Ld, (int)Hk};
+      tUh = Tile{(int)Lu, (int)Hk, (int)std::max<int64_t>(256, p2(maxdeg))};
+      int64_t stride = (int64_t)std::max({resid_tile_bytes(tRh, ell), dots_tile_bytes(tDh, ell),
+                                          update_tile_bytes(tUh)});
+      stride = (stride + 255) / 256 * 256;
+      char* scr;
+      if ((rc = dalloc(&scr, stride * kHugeGrid))) return rc;
+      for (int b = 0; b < 3; ++b) {
+        big[b].scratch = scr;
+        big[b].scratch_stride = stride;
+      }
+    }
     if (global) {
       if ((rc = dalloc(&selhist, 8192)) || (rc = dalloc(&selbuf, capU))) return rc;
     }
@@ -537,7 +562,8 @@ struct Engine : EngineBase {
     launch_scan(ub, off, total, n, scantmp, s);
     te();
     tb(SPAI_PH_RESID);
-    launch_resid<T>(A, M, R, off, total, colnorm, opts.jacobi, colrz, big[0], st, tRs, tRl, s);
+    launch_resid<T>(A, M, R, off, total, colnorm, opts.jacobi, colrz, big[0], st, tRs, tRl, tRh,
+                    s);
     te();
     tb(SPAI_PH_SCALAR);
     launch_reduce(colnorm, 1, n, seg, nseg > 1 ? seg_beg : nullptr, red_rr, blockpart, s);
@@ -550,7 +576,7 @@ struct Engine : EngineBase {
 
   void dots_step(int useR, int useP) {
     tb(SPAI_PH_DOTS);
-    launch_dots<T>(A, R, P, useR, useP, opts.jacobi, colpart, big[1], st, tDs, tDl, s);
+    launch_dots<T>(A, R, P, useR, useP, opts.jacobi, colpart, big[1], st, tDs, tDl, tDh, s);
     te();
     tb(SPAI_PH_SCALAR);
     launch_reduce(colpart, kND, n, seg, nseg > 1 ? seg_beg : nullptr, red, blockpart, s);
@@ -564,7 +590,8 @@ struct Engine : EngineBase {
     launch_scan(ub, off, total, n, scantmp, s);
     te();
     tb(SPAI_PH_UPDATE);
-    launch_update<T>(A, M, R, P, PT, md, off, total, kcol, tM, tP, big[2], seg, st, tUs, tUl, s);
+    launch_update<T>(A, M, R, P, PT, md, off, total, kcol, tM, tP, big[2], seg, st, tUs, tUl, tUh,
+                     s);
     te();
     if (global) {
       tb(SPAI_PH_SELECT);

@@ -68,12 +68,20 @@ struct Pair {                      // ping-pong pair of column buffers
   __device__ __forceinline__ Cols<T> nxt() const { return b[*cur ^ 1]; }
 };
 
+// Columns too big for a tile are deferred to the next tier: small LDS tile -> large LDS
+// tile -> huge tile, whose working set lives in device memory (`scratch`, one slice of
+// `scratch_stride` bytes per workgroup); beyond that SPAI_ERR_CAPACITY.
 struct BigList {
   int* list = nullptr;             // columns left to the large-tile pass
   int* count = nullptr;
+  int* list2 = nullptr;            // columns left to the huge-tile pass
+  int* count2 = nullptr;
+  char* scratch = nullptr;
+  int64_t scratch_stride = 0;
 };
 
-struct Tile { int L, H; };         // per-column LDS tile: list entries and hash slots
+struct Tile { int L, H, DG = 0; }; // per-column tile: list entries, hash slots, neighbours (0: default)
+constexpr int kHugeGrid = 64;      // workgroups of the huge-tile pass
 
 struct UpdMode {
   int doM;       // form the (symmetrized, small-dropped) M candidates
@@ -112,11 +120,11 @@ void launch_bound_resid(const Csr& A, Pair<T> M, int64_t* ub, int64_t n, const D
 template <typename T>
 void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const int64_t* total,
                   double* colnorm, int weighted, double* colrz, BigList big, DevState* st,
-                  Tile small, Tile large, hipStream_t s);
+                  Tile small, Tile large, Tile huge, hipStream_t s);
 
 template <typename T>
 void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, int weighted,
-                 double* colpart, BigList big, DevState* st, Tile small, Tile large,
+                 double* colpart, BigList big, DevState* st, Tile small, Tile large, Tile huge,
                  hipStream_t s);
 
 template <typename T>
@@ -126,7 +134,11 @@ template <typename T>
 void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, UpdMode md,
                    const int64_t* off, const int64_t* total, const int32_t* kcol, double* tM,
                    double* tP, BigList big, const Seg& seg, DevState* st, Tile small,
-                   Tile large, hipStream_t s);
+                   Tile large, Tile huge, hipStream_t s);
+// bytes of one workgroup's working set for a tile (the huge tier's scratch slice)
+size_t resid_tile_bytes(Tile t, bool ell);
+size_t dots_tile_bytes(Tile t, bool ell);
+size_t update_tile_bytes(Tile t);
 
 // global cap: exact (b+1)-th largest magnitude among the candidates in X.nxt()
 template <typename T>

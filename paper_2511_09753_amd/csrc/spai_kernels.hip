@@ -195,12 +195,31 @@ __device__ __forceinline__ void pull_rows(const Csr& A, const int* keys, int nu,
   }
 }
 
-// a column that does not fit its tile: hand it to the large tile, or flag it there
+// a column that does not fit its tile: hand it to the next tier, or flag it after the last
 __device__ inline void defer_column(int tier, BigList big, DevState* st, int64_t j) {
   if (lane_id() == 0) {
     if (tier == 0) big.list[atomicAdd(big.count, 1)] = (int)j;
+    else if (tier == 1) big.list2[atomicAdd(big.count2, 1)] = (int)j;
     else atomicOr(&st->err, 1);
   }
+}
+
+// Barrier of a per-column kernel.  In the huge tier the working set is device memory
+// and its hash tables are updated with atomics, which are performed in L2: the fence
+// (device scope, so the acquire side invalidates L1) keeps later plain loads from
+// reading stale L1 lines.
+template <bool GS>
+__device__ __forceinline__ void tile_sync() {
+  if constexpr (GS) __threadfence();
+  __syncthreads();
+}
+
+// working-set base of a per-column kernel: dynamic LDS, or (GS, the huge tier) this
+// workgroup's slice of the device-memory scratch
+template <bool GS>
+__device__ __forceinline__ char* tile_base(char* smem, const BigList& big) {
+  if constexpr (GS) return big.scratch + (int64_t)blockIdx.x * big.scratch_stride;
+  else return smem;
 }
 
 // ============================================================================
@@ -473,9 +492,9 @@ void launch_bound_resid(const Csr& A, Pair<T> M, int64_t* ub, int64_t n, const D
                      ub, n, st);
 }
 
-template <typename T>
 // five waves per SIMD: measured faster than the compiler's own choice (four) for this
 // kernel, with no spills
+template <typename T, bool GS>
 __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5))) void k_resid(Csr A, Pair<T> Mp, Cols<T> R,
                                                      const int64_t* off, const int64_t* total,
                                                      double* colnorm, int weighted, double* colrz,
@@ -484,7 +503,7 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
   if (!st->any_active) return;
   extern __shared__ char smem[];
   const bool ell = A.eshift >= 0;
-  Carve cv(smem);
+  Carve cv(tile_base<GS>(smem, big));
   int* s_mi = cv.take<int>(L);
   int* s_keys = cv.take<int>(H);         // hash set, then the sorted keys
   double* s_mv = cv.take<double>(L);
@@ -512,30 +531,30 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
     const int hs = next_pow2(max(2 * lm, 64));
     ks_clear(s_keys, H);
     lm_clear(s_mk, s_mp, hs);
-    __syncthreads();
+    tile_sync<GS>();
     for (int e = lane; e < lm; e += SPAI_WAVE) {
       const int i = M.idx[mb + e];
       s_mi[e] = i;
       s_mv[e] = (double)M.val[mb + e];
       lm_put(s_mk, s_mp, hs, i, 0, e);
     }
-    __syncthreads();
+    tile_sync<GS>();
     int tot = 0;
     if (!ell) {
       tot = degree_prefix(A, s_mi, lm, s_pre, s_rs);
-      __syncthreads();
+      tile_sync<GS>();
     }
     int kd[1] = {lane == 0 ? (int)j : -1};
     int nk = wave_sum_int(ks_insert_batch<1>(s_keys, H, kd));
     nk = insert_products(A, s_mi, lm, s_pre, s_rs, tot, s_keys, H, nk, limit);
-    __syncthreads();
+    tile_sync<GS>();
     if (nk > limit) {               // more distinct rows than the tile holds
       defer_column(tier, big, st, j);
-      __syncthreads();
+      tile_sync<GS>();
       return;
     }
     const int nu = ks_sort_inplace(s_keys, H);
-    __syncthreads();
+    tile_sync<GS>();
     const int64_t ob = off[j];
     double acc = 0.0, acc_rz = 0.0;
     double sum[1];
@@ -581,18 +600,21 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
       R.len[j] = nu;
     }
     outcnt += (unsigned long long)nu;
-    __syncthreads();
+    tile_sync<GS>();
   };
 
   if (tier == 0) {
     ColumnWalk w(A.n, blockIdx.x, gridDim.x);
     for (int64_t j = w.begin; j < w.end; j += w.step) body(j);
-  } else {
+  } else if (tier == 1) {
     const int cnt = *big.count;
     for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list[t]);
+  } else {
+    const int cnt = *big.count2;
+    for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list2[t]);
   }
   if (lane == 0 && tier == 0 && blockIdx.x < kCntSlots) st->cnt[6 * kCntSlots + blockIdx.x] += outcnt;
-  if (lane == 0 && tier == 1 && outcnt) atomicAdd(&st->cnt[6 * kCntSlots + kCntSlots - 1], outcnt);
+  if (lane == 0 && tier >= 1 && outcnt) atomicAdd(&st->cnt[6 * kCntSlots + kCntSlots - 1], outcnt);
 }
 
 static size_t resid_lds(Tile t, bool ell) {
@@ -630,21 +652,26 @@ static int resident_grid(K kernel, size_t lds) {
 template <typename T>
 void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const int64_t* total,
                   double* colnorm, int weighted, double* colrz, BigList big, DevState* st,
-                  Tile small, Tile large, hipStream_t s) {
+                  Tile small, Tile large, Tile huge, hipStream_t s) {
   const bool ell = A.eshift >= 0;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
-  hipLaunchKernelGGL(k_resid<T>, dim3(resident_grid(k_resid<T>, resid_lds(small, ell))),
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
+  hipLaunchKernelGGL((k_resid<T, false>), dim3(resident_grid(k_resid<T, false>, resid_lds(small, ell))),
                      dim3(SPAI_WAVE), resid_lds(small, ell), s, A, M, R, off, total, colnorm,
                      weighted, colrz, big, st, 0, small.L, small.H);
-  hipLaunchKernelGGL(k_resid<T>, dim3(256), dim3(SPAI_WAVE), resid_lds(large, ell), s, A, M, R, off,
-                     total, colnorm, weighted, colrz, big, st, 1, large.L, large.H);
+  hipLaunchKernelGGL((k_resid<T, false>), dim3(256), dim3(SPAI_WAVE), resid_lds(large, ell), s, A, M,
+                     R, off, total, colnorm, weighted, colrz, big, st, 1, large.L, large.H);
+  hipLaunchKernelGGL((k_resid<T, true>), dim3(kHugeGrid), dim3(SPAI_WAVE), 0, s, A, M, R, off, total,
+                     colnorm, weighted, colrz, big, st, 2, huge.L, huge.H);
 }
+
+size_t resid_tile_bytes(Tile t, bool ell) { return resid_lds(t, ell); }
 
 // ============================================================================
 // SpGEMM fused with Frobenius dots: A r_j and A p_j in LDS, never stored
 // ============================================================================
 
-template <typename T>
+template <typename T, bool GS>
 __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp, int useR,
                                                     int useP, int weighted, double* colpart,
                                                     BigList big, DevState* st, int tier, int L,
@@ -652,7 +679,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
   if (!st->any_active || !st->iter_active) return;
   extern __shared__ char smem[];
   const bool ell = A.eshift >= 0;
-  Carve cv(smem);
+  Carve cv(tile_base<GS>(smem, big));
   int* s_li = cv.take<int>(L);           // r_j rows, then p_j rows
   int* s_keys = cv.take<int>(H);
   double* s_lv = cv.take<double>(L);
@@ -676,7 +703,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
     const int hs = next_pow2(max(2 * (lr + lp), 64));
     ks_clear(s_keys, H);
     lm_clear(s_mk, s_mp, hs);
-    __syncthreads();
+    tile_sync<GS>();
     for (int e = lane; e < lr + lp; e += SPAI_WAVE) {   // both lists in one pass
       int i;
       double v;
@@ -691,21 +718,21 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
       s_lv[e] = v;
       lm_put(s_mk, s_mp, hs, i, e < lr ? 0 : 1, e < lr ? e : e - lr);
     }
-    __syncthreads();
+    tile_sync<GS>();
     int tot = 0;
     if (!ell) {
       tot = degree_prefix(A, s_li, lr + lp, s_pre, s_rs);
-      __syncthreads();
+      tile_sync<GS>();
     }
     const int nk = insert_products(A, s_li, lr + lp, s_pre, s_rs, tot, s_keys, H, 0, limit);
-    __syncthreads();
+    tile_sync<GS>();
     if (nk > limit) {
       defer_column(tier, big, st, j);
-      __syncthreads();
+      tile_sync<GS>();
       return;
     }
     const int nu = ks_sort_inplace(s_keys, H);
-    __syncthreads();
+    tile_sync<GS>();
     const int* ri = s_li;
     const double* rv = s_lv;
     const int* pi = s_li + lr;
@@ -765,15 +792,18 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
       double* o = colpart + j * kND;
       o[0] = d0; o[1] = d1; o[2] = d2; o[3] = d3; o[4] = d4; o[5] = d5;
     }
-    __syncthreads();
+    tile_sync<GS>();
   };
 
   if (tier == 0) {
     ColumnWalk w(A.n, blockIdx.x, gridDim.x);
     for (int64_t j = w.begin; j < w.end; j += w.step) body(j);
-  } else {
+  } else if (tier == 1) {
     const int cnt = *big.count;
     for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list[t]);
+  } else {
+    const int cnt = *big.count2;
+    for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list2[t]);
   }
 }
 
@@ -784,16 +814,21 @@ static size_t dots_lds(Tile t, bool ell) {
 
 template <typename T>
 void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, int weighted,
-                 double* colpart, BigList big, DevState* st, Tile small, Tile large,
+                 double* colpart, BigList big, DevState* st, Tile small, Tile large, Tile huge,
                  hipStream_t s) {
   const bool ell = A.eshift >= 0;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
-  hipLaunchKernelGGL(k_dots<T>, dim3(resident_grid(k_dots<T>, dots_lds(small, ell))),
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
+  hipLaunchKernelGGL((k_dots<T, false>), dim3(resident_grid(k_dots<T, false>, dots_lds(small, ell))),
                      dim3(SPAI_WAVE), dots_lds(small, ell), s, A, R, P, useR, useP, weighted,
                      colpart, big, st, 0, small.L, small.H);
-  hipLaunchKernelGGL(k_dots<T>, dim3(256), dim3(SPAI_WAVE), dots_lds(large, ell), s, A, R, P, useR,
-                     useP, weighted, colpart, big, st, 1, large.L, large.H);
+  hipLaunchKernelGGL((k_dots<T, false>), dim3(256), dim3(SPAI_WAVE), dots_lds(large, ell), s, A, R, P,
+                     useR, useP, weighted, colpart, big, st, 1, large.L, large.H);
+  hipLaunchKernelGGL((k_dots<T, true>), dim3(kHugeGrid), dim3(SPAI_WAVE), 0, s, A, R, P, useR, useP,
+                     weighted, colpart, big, st, 2, huge.L, huge.H);
 }
+
+size_t dots_tile_bytes(Tile t, bool ell) { return dots_lds(t, ell); }
 
 // ============================================================================
 // merge (SpGEAM) + symmetrize + small-entry drop + per-column thresholds
@@ -885,7 +920,7 @@ __device__ inline double kth_largest_cols(const int32_t* idx, const T* val, int 
   return t;
 }
 
-template <typename T>
+template <typename T, bool GS>
 __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp,
                                                       Pair<T> PTp, UpdMode md, const int64_t* off,
                                                       const int64_t* total, const int32_t* kcol,
@@ -894,7 +929,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
                                                       int H, int DG) {
   if (!st->any_active || !st->iter_active) return;
   extern __shared__ char smem[];
-  Carve cv(smem);
+  Carve cv(tile_base<GS>(smem, big));
   int* s_li = cv.take<int>(L);
   int* s_keys = cv.take<int>(H);        // hash set, then the sorted keys
   int* s_nbcol = cv.take<int>(DG);
@@ -991,7 +1026,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
       return;
     }
     ks_clear(s_keys, H);
-    __syncthreads();
+    tile_sync<GS>();
     // ---- every list entry held in LDS, in one flattened gather (four per lane in flight)
     {
       constexpr int U = 4;
@@ -1033,7 +1068,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
           }
       }
     }
-    __syncthreads();
+    tile_sync<GS>();
     // ---- key union (at most limit distinct keys)
     int kd[1] = {lane == 0 ? (int)j : -1};
     int nkeys = wave_sum_int(ks_insert_batch<1>(s_keys, H, kd));
@@ -1060,14 +1095,14 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
           nkeys += wave_sum_int(ks_insert_batch<4>(s_keys, H, kk));
         }
       }
-    __syncthreads();
+    tile_sync<GS>();
     if (nkeys > limit) {
       defer_column(tier, big, st, j);
-      __syncthreads();
+      tile_sync<GS>();
       return;
     }
     const int nk = ks_sort_inplace(s_keys, H);
-    __syncthreads();
+    tile_sync<GS>();
     // ---- values, candidates
     const int64_t ob = off[j];
     int cntM = 0, cntMo = 0, cntP = 0, cntPT = 0;
@@ -1169,7 +1204,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
       cntP += __popcll(bp);
       cntPT += __popcll(bpt);
     }
-    __syncthreads();
+    tile_sync<GS>();
     if (lane == 0) {
       if (md.doM) { Mo.beg[j] = ob; Mo.len[j] = cntM; }
       if (md.doP) {
@@ -1181,7 +1216,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
       // thresholds from the candidates this wave has just written (L1/L2 resident)
       const int k = kcol[j];
       __threadfence_block();
-      __syncthreads();
+      tile_sync<GS>();
       if (md.doM) {
         const double t = kth_largest_cols(Mo.idx + ob, Mo.val + ob, cntM, (int)j, k - 1);
         if (lane == 0) tM[j] = t;
@@ -1191,19 +1226,22 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
         if (lane == 0) tP[j] = t;
       }
     }
-    __syncthreads();
+    tile_sync<GS>();
   };
 
   if (tier == 0) {
     ColumnWalk w(A.n, blockIdx.x, gridDim.x);
     for (int64_t j = w.begin; j < w.end; j += w.step) body(j);
-  } else {
+  } else if (tier == 1) {
     const int cnt = *big.count;
     for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list[t]);
+  } else {
+    const int cnt = *big.count2;
+    for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list2[t]);
   }
 }
 
-static int update_deg(Tile t) { return t.L >= 2048 ? 256 : 64; }
+static int update_deg(Tile t) { return t.DG ? t.DG : (t.L >= 2048 ? 256 : 64); }
 
 static size_t update_lds(Tile t, bool) {
   const int DG = update_deg(t);
@@ -1211,19 +1249,25 @@ static size_t update_lds(Tile t, bool) {
          (size_t)DG * 8 * 2 + 96;
 }
 
+size_t update_tile_bytes(Tile t) { return update_lds(t, false); }
+
 template <typename T>
 void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, UpdMode md,
                    const int64_t* off, const int64_t* total, const int32_t* kcol, double* tM,
                    double* tP, BigList big, const Seg& seg, DevState* st, Tile small, Tile large,
-                   hipStream_t s) {
+                   Tile huge, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
-  hipLaunchKernelGGL(k_update<T>, dim3(resident_grid(k_update<T>, update_lds(small, true))),
-                     dim3(SPAI_WAVE), update_lds(small, true), s, A, M,
-                     R, P, PT, md, off, total, kcol, tM, tP, big, seg, st, 0, small.L, small.H,
-                     update_deg(small));
-  hipLaunchKernelGGL(k_update<T>, dim3(256), dim3(SPAI_WAVE), update_lds(large, false), s, A, M, R, P,
-                     PT, md, off, total, kcol, tM, tP, big, seg, st, 1, large.L, large.H,
-                     update_deg(large));
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
+  hipLaunchKernelGGL((k_update<T, false>),
+                     dim3(resident_grid(k_update<T, false>, update_lds(small, true))),
+                     dim3(SPAI_WAVE), update_lds(small, true), s, A, M, R, P, PT, md, off, total,
+                     kcol, tM, tP, big, seg, st, 0, small.L, small.H, update_deg(small));
+  hipLaunchKernelGGL((k_update<T, false>), dim3(256), dim3(SPAI_WAVE), update_lds(large, false), s,
+                     A, M, R, P, PT, md, off, total, kcol, tM, tP, big, seg, st, 1, large.L,
+                     large.H, update_deg(large));
+  hipLaunchKernelGGL((k_update<T, true>), dim3(kHugeGrid), dim3(SPAI_WAVE), 0, s, A, M, R, P, PT,
+                     md, off, total, kcol, tM, tP, big, seg, st, 2, huge.L, huge.H,
+                     update_deg(huge));
 }
 
 // ============================================================================
@@ -1800,15 +1844,15 @@ void launch_flip(int which, DevState* st, hipStream_t s) {
   template void launch_bound_resid<T>(const Csr&, Pair<T>, int64_t*, int64_t, const DevState*,    \
                                       hipStream_t);                                               \
   template void launch_resid<T>(const Csr&, Pair<T>, Cols<T>, const int64_t*, const int64_t*,    \
-                                double*, int, double*, BigList, DevState*, Tile, Tile,            \
+                                double*, int, double*, BigList, DevState*, Tile, Tile, Tile,      \
                                 hipStream_t);                                                     \
   template void launch_dots<T>(const Csr&, Cols<T>, Pair<T>, int, int, int, double*, BigList,     \
-                               DevState*, Tile, Tile, hipStream_t);                               \
+                               DevState*, Tile, Tile, Tile, hipStream_t);                         \
   template void launch_bound_update<T>(const Csr&, Pair<T>, Cols<T>, Pair<T>, Pair<T>, UpdMode,   \
                                        int64_t*, int64_t, const DevState*, hipStream_t);          \
   template void launch_update<T>(const Csr&, Pair<T>, Cols<T>, Pair<T>, Pair<T>, UpdMode,         \
                                  const int64_t*, const int64_t*, const int32_t*, double*,         \
-                                 double*, BigList, const Seg&, DevState*, Tile, Tile,             \
+                                 double*, BigList, const Seg&, DevState*, Tile, Tile, Tile,       \
                                  hipStream_t);                                                    \
   template void launch_global_select<T>(Pair<T>, int, int64_t, double, int, unsigned long long*,  \
                                         unsigned long long*, int64_t, DevState*, hipStream_t);    \

@@ -355,3 +355,24 @@ def test_jacobi_mixed_against_f64_oracle(method):
     assert rel_err(hist, ref.resid[1:]) <= TOL_MIXED
     _, hist_plain, _, _, _ = _run_gpu(S, A, method, "global", 2.0, True, iters, precision="mixed")
     assert rel_err(hist_plain, hist) > 1e-3      # a different trajectory from the plain method
+
+
+@pytest.mark.parametrize("name,method", [("tri100eigs4k", "mr"), ("tri100eigs4k", "cg"),
+                                         ("tri100eigs4k", "lomr"), ("4bw100eigs20k", "lomr"),
+                                         ("4bw100eigs20k2", "lomr"), ("rand20k", "lomr"),
+                                         ("rand20k2", "cg")])
+def test_paper_recipe_parity_jacobi(name, method):
+    """The paper's recipe matrices under the protocol of Experiment 05 (Pi = D_A^{-1},
+    3% density cap): FP64 GPU against the oracle for 6 iterations."""
+    S = _spai()
+    k = W.PAPER_RECIPES.index(name)
+    A = W.paper_recipe(name, W.seed_for(6, k))
+    n = A.shape[0]
+    m = int(round(0.03 * n * n))
+    r0, hist, Mg, st, rc = _run_gpu(S, A, method, "global", m, False, 6, jacobi=True)
+    ref = O.run_spd(method, A, O.jacobi(A), O.DropRule(mode="global", m=m), 6)
+    assert len(hist) == ref.iters
+    assert rel_err(hist, ref.resid[1:]) <= TOL_F64
+    assert st["nnz_m"] == ref.M.nnz
+    only_g, only_o = pattern_diff(Mg, ref.M)
+    assert not only_g and not only_o
