@@ -52,7 +52,10 @@ enum {
   SPAI_ERR_NONFINITE = -4,
   SPAI_ERR_NOMEM = -5,      /* device allocation failed or exceeds the pool cap */
   SPAI_ERR_HIP = -6,        /* a HIP runtime call failed                        */
-  SPAI_ERR_CAPACITY = -7    /* a column exceeded the largest per-column tile    */
+  SPAI_ERR_CAPACITY = -7    /* a column exceeded the largest per-column tile:
+                               the device-memory tile, sized at create time from n
+                               (lists up to 32768 entries, key sets up to 65535
+                               rows; the update's own lists up to 131072 entries) */
 };
 
 enum { SPAI_MR = 0, SPAI_CG = 1, SPAI_LOMR = 2 };

@@ -101,6 +101,39 @@ int check_symmetric_pattern(const HostCsr& h) {
   return SPAI_OK;
 }
 
+// Processing order with locality: breadth-first balls of about `ball` rows grown in A's
+// graph, each seeded at the smallest row not yet taken and limited to untaken rows,
+// concatenated.  Rows processed at the same time then share most of the rows they
+// gather, so an XCD's working set stays within its L2.
+const int kBallRows = 2048;
+
+void locality_order(const HostCsr& h, int ball, std::vector<int32_t>& order) {
+  const int64_t n = h.n;
+  order.clear();
+  order.reserve((size_t)n);
+  std::vector<char> taken((size_t)n, 0);
+  std::vector<int32_t> queue;
+  int64_t seed = 0;
+  while ((int64_t)order.size() < n) {
+    while (taken[(size_t)seed]) ++seed;
+    queue.clear();
+    queue.push_back((int32_t)seed);
+    taken[(size_t)seed] = 1;
+    size_t head = 0;
+    while (head < queue.size() && (int)queue.size() < ball) {
+      const int32_t u = queue[head++];
+      for (int64_t q = h.rowptr[u]; q < h.rowptr[u + 1] && (int)queue.size() < ball; ++q) {
+        const int32_t v = h.col[q];
+        if (!taken[(size_t)v]) {
+          taken[(size_t)v] = 1;
+          queue.push_back(v);
+        }
+      }
+    }
+    order.insert(order.end(), queue.begin(), queue.end());
+  }
+}
+
 int DevPool::alloc_bytes(void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 8;
@@ -181,6 +214,7 @@ struct Engine : EngineBase {
   Tile tRs{128, 512}, tRl{1024, 4096}, tDs{256, 512}, tDl{1024, 4096}, tUs{384, 512},
       tUl{2048, 4096};
   Tile tRh{0, 0}, tDh{0, 0}, tUh{0, 0};   // huge tiles (device-memory scratch), sized from n
+  int32_t* d_order = nullptr;             // locality order of the rows (breadth-first balls)
   int hist_cap = 0;
   int iters_host = 0;
   hipGraph_t graph = nullptr;
@@ -368,6 +402,14 @@ struct Engine : EngineBase {
       A.ecol = d_ec;
       A.eval = d_ev;
     }
+    // ---- locality order of the rows (for the PCG products)
+    {
+      std::vector<int32_t> ord;
+      locality_order(hA, kBallRows, ord);
+      if ((rc = dalloc(&d_order, n))) return rc;
+      HIPCHK(hipMemcpyAsync(d_order, ord.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
     // ---- state
     if ((rc = dalloc(&st, 1)) || (rc = dalloc(&segst, nseg)) || (rc = dalloc(&seg_beg, nseg + 1)) ||
         (rc = dalloc(&cnt, (int64_t)kNCnt * kCntSlots)))
@@ -507,7 +549,7 @@ struct Engine : EngineBase {
       dX = x2;
     }
     tb(SPAI_PH_PCG);
-    rc = pcg_run(pa, pm, nrhs, dB, dX, rtol, max_iter, iters, relres, s);
+    rc = pcg_run(pa, pm, nrhs, dB, dX, rtol, max_iter, iters, relres, d_order, s);
     te();
     if (rc < 0) return rc;
     if (!on_device) {

@@ -38,6 +38,9 @@ int check_spd_symmetric(const HostCsr& h);
 int check_symmetric_pattern(const HostCsr& h);
 // position of entry (i, j) or -1
 int64_t find_entry(const HostCsr& h, int64_t i, int32_t j);
+// permutation of the rows in breadth-first balls of about `ball` rows (locality order)
+void locality_order(const HostCsr& h, int ball, std::vector<int32_t>& order);
+extern const int kBallRows;   // ball size of the locality order (rows)
 
 // owner of a handle's or a call's device allocations
 struct DevPool {
@@ -73,8 +76,9 @@ struct PcgMat {
   __device__ __forceinline__ double v(int64_t q) const { return val32 ? (double)val32[q] : val[q]; }
 };
 
-// preconditioned CG on device-resident operands (B, X on the device)
+// preconditioned CG on device-resident operands (B, X on the device); `order` (device,
+// n rows, or null for the natural order) is the order in which the products visit rows
 int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double* dX, double rtol,
-            int max_iter, int* iters, double* relres, hipStream_t s);
+            int max_iter, int* iters, double* relres, const int32_t* order, hipStream_t s);
 
 }  // namespace spai

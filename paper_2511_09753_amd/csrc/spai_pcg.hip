@@ -111,7 +111,7 @@ __device__ __forceinline__ void accumulate_row(double& y, VT cv, int cc, int e0,
 template <typename VT, int LAY>
 __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, double* Y,
                                                         int dot, int nrhs, int c0,
-                                                        double* part) {
+                                                        const int32_t* order, double* part) {
   __shared__ double sh[kThreads];
   constexpr int WPB = kThreads / 64;
   const int lane = threadIdx.x & 63;
@@ -124,14 +124,16 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
   const bool on = c0 + lane < nrhs;
   const int64_t cofs = c0 + lane;
   const unsigned loff = on ? (unsigned)lane * 8u : 0u;   // idle lanes re-read column c0
+  auto rowof = [&](int64_t k) -> int64_t { return order ? (int64_t)order[k] : k; };
   double acc = 0.0;
-  int64_t i = r0 + kb * WPB + wv;
-  // row i: descriptor (a, b) and its first 64 entries (ec, ev), one per lane;
-  // row i + stride: descriptor (na, nbe)
-  int64_t a = 0, b = 0, na = 0, nbe = 0;
+  int64_t k = r0 + kb * WPB + wv;
+  // position k: row i, its descriptor (a, b) and first 64 entries (ec, ev), one per lane;
+  // position k + stride: row ni and descriptor (na, nbe); position k + 2 stride: row mi
+  int64_t i = 0, ni = 0, mi = 0, a = 0, b = 0, na = 0, nbe = 0;
   int ec = -1;
   VT ev = 0;
-  if (i < r1) {
+  if (k < r1) {
+    i = rowof(k);
     a = row_lo<LAY>(A, i);
     b = row_hi<LAY>(A, i);
     if (a + lane < b) {
@@ -139,25 +141,28 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
       ev = entry_val<VT>(A, a + lane);
     }
   }
-  if (i + stride < r1) {
-    na = row_lo<LAY>(A, i + stride);
-    nbe = row_hi<LAY>(A, i + stride);
+  if (k + stride < r1) {
+    ni = rowof(k + stride);
+    na = row_lo<LAY>(A, ni);
+    nbe = row_hi<LAY>(A, ni);
   }
-  for (; i < r1; i += stride) {
-    const int64_t in = i + stride;
+  if (k + 2 * stride < r1) mi = rowof(k + 2 * stride);
+  for (; k < r1; k += stride) {
+    const int64_t kn = k + stride;
     const int cnt = __popcll(__ballot(ec >= 0));   // ELL padding (column -1) sits last
     int nc = -1;
     VT nv = 0;
-    int64_t ma = 0, mb = 0;
+    int64_t ma = 0, mb = 0, li = 0;
     auto prefetch = [&]() {
-      if (in < r1 && na + lane < nbe) {
+      if (kn < r1 && na + lane < nbe) {
         nc = A.col[na + lane];
         nv = entry_val<VT>(A, na + lane);
       }
-      if (in + stride < r1) {
-        ma = row_lo<LAY>(A, in + stride);
-        mb = row_hi<LAY>(A, in + stride);
+      if (kn + stride < r1) {
+        ma = row_lo<LAY>(A, mi);
+        mb = row_hi<LAY>(A, mi);
       }
+      if (kn + 2 * stride < r1) li = rowof(kn + 2 * stride);
     };
     // X[i, :] for the dot: the row's own (diagonal) gather
     const int diag = dot ? (int)i : -1;
@@ -209,6 +214,9 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
     b = nbe;
     na = ma;
     nbe = mb;
+    i = ni;
+    ni = mi;
+    mi = li;
   }
   if (!part) return;
   sh[threadIdx.x] = acc;
@@ -438,6 +446,7 @@ struct Solver {
   const double* b;
   RhsState* S;
   int* nactive;
+  const int32_t* order = nullptr;   // row visiting order of the products (null: natural)
 
   static int pow2(int w) {
     int R = 1;
@@ -472,7 +481,7 @@ struct Solver {
     spmm_grid = resident_spmm_grid<VT, LAY>();
     for (int c0 = 0; c0 < nrhs; c0 += 64)
       hipLaunchKernelGGL((k_spmm_wave<VT, LAY>), dim3(spmm_grid), dim3(kThreads), 0, s, K, X, Y,
-                         pt ? 1 : 0, nrhs, c0, pt);
+                         pt ? 1 : 0, nrhs, c0, order, pt);
   }
   template <typename VT>
   void spmm_v(const Mat& K, const double* X, double* Y, double* pt) {
@@ -557,7 +566,7 @@ using namespace spai;
 namespace spai {
 
 int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double* dX, double rtol,
-            int max_iter, int* iters, double* relres, hipStream_t s) {
+            int max_iter, int* iters, double* relres, const int32_t* order, hipStream_t s) {
   int rc;
   DevPool pool;
   Solver S{};
@@ -566,6 +575,7 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
   S.n = A.n;
   S.nrhs = nrhs;
   S.s = s;
+  S.order = order;
   const int64_t tot = S.n * nrhs;
   if ((rc = pool.alloc(&S.r, tot)) || (rc = pool.alloc(&S.z, tot)) || (rc = pool.alloc(&S.p, tot)) ||
       (rc = pool.alloc(&S.q, tot)) || (rc = pool.alloc(&S.part, (int64_t)kGrid * nrhs)) ||
@@ -648,7 +658,13 @@ extern "C" int pcg_solve(const spai_csr_t* A, const spai_csr_t* M, int nrhs, con
       dB = b2;
       dX = x2;
     }
-    rc = pcg_run(dA, dM, nrhs, dB, dX, rtol, max_iter, iters, relres, s);
+    std::vector<int32_t> ord;
+    locality_order(hA, kBallRows, ord);
+    int32_t* d_order;
+    if ((rc = pool.alloc(&d_order, hA.n))) return rc;
+    HIPCHK(hipMemcpyAsync(d_order, ord.data(), sizeof(int32_t) * hA.n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    rc = pcg_run(dA, dM, nrhs, dB, dX, rtol, max_iter, iters, relres, d_order, s);
     if (rc < 0) return rc;
     if (!A->on_device) {
       HIPCHK(hipMemcpyAsync(X, dX, sizeof(double) * tot, hipMemcpyDeviceToHost, s));
