@@ -58,3 +58,27 @@ def test_host_side_errors(S):
     _expect(S, -1, lambda: S.SPAI(D, "mr", "global", 3, False))        # cap below diagonal count
     _expect(S, -1, lambda: S.SPAI(D, "mr", "column", 0.2, False))      # column cap below one
     _expect(S, -1, lambda: S.SPAI(D, "lomr", "global", 0.0, False))
+
+
+def test_degenerate_shapes_and_options(S):
+    E = sp.csr_matrix((0, 0))
+    _expect(S, -1, lambda: S.SPAI(E, "mr"))                            # empty matrix
+    D = sp.identity(4, format="csr") * 2.0
+    _expect(S, -1, lambda: S.SPAI(D, "mr", options=S.Options(drop_tol=-1.0)))
+    _expect(S, -1, lambda: S.SPAI(D, "mr", max_iter=-1))
+    _expect(S, -1, lambda: S.SPAI(None, "mr", "global", 2.0, True, batch=[D, D]))
+
+
+def test_c_level_option_checks(S):
+    """Option fields the Python wrapper always normalizes, set out of range directly."""
+    import ctypes as C
+    lib = S.load()
+    D = sp.identity(4, format="csr") * 2.0
+    a = S._Csr(D)
+    for field, bad in (("jacobi", 2), ("a_format", 7), ("precision", 9)):
+        o = S.Options().c()
+        setattr(o, field, bad)
+        h = C.c_void_p()
+        rc = lib.spai_create(C.byref(a.c), S.METHODS["mr"], S.cap("none", 0.0, False), 10, 0.0,
+                             C.byref(o), C.byref(h))
+        assert rc == -1, field

@@ -376,3 +376,145 @@ def test_paper_recipe_parity_jacobi(name, method):
     assert st["nnz_m"] == ref.M.nnz
     only_g, only_o = pattern_diff(Mg, ref.M)
     assert not only_g and not only_o
+
+
+# ----------------------------------------------------------------------------
+# degenerate inputs and edge cases
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
+@pytest.mark.parametrize("a", [4.0, 7.0, 0.3, 1e-3])
+def test_one_by_one(a, method):
+    """n = 1: M_0 = tr(A)/tr(A^2) = 1/a up to rounding, so R_0 is zero or a rounding
+    residue; the GPU stops with the oracle when R_0 is exactly zero, and otherwise ends at
+    the rounding level too.  PCG on the 1 x 1 system then solves it in one step."""
+    S = _spai()
+    A = sp.csr_matrix(np.array([[a]]))
+    ref = O.run(method, A, oracle_rule(A, "none", 0, False), 3)
+    h = S.SPAI(A, method, max_iter=3)
+    assert h.stats()["resid"] == pytest.approx(ref.resid[0], abs=1e-16)
+    done, hist, rc = h.iterate(3)
+    Mg = h.get()
+    if ref.resid[0] == 0.0:
+        assert done == ref.iters == 0 and rc == S.SPAI_CONVERGED
+    assert all(x <= 4e-16 for x in hist)
+    assert Mg.shape == (1, 1) and Mg.nnz == 1
+    assert abs(Mg[0, 0] * a - 1.0) <= 4e-16
+    B = np.array([[2.0, -1.0, 0.5]])
+    X, it, relres, prc = h.pcg(B, rtol=1e-8)
+    h.close()
+    xo, ito, sto = O.pcg_block(A, ref.M, B, rtol=1e-8)
+    assert prc == S.SPAI_OK and list(it) == list(ito)
+    assert np.max(np.abs(X - B / a)) <= 1e-15 * np.max(np.abs(B / a))
+
+
+def test_iterate_zero_and_reset():
+    """iterate(0) runs nothing and leaves M_0 = c I; reset restarts bit for bit."""
+    S = _spai()
+    A = W.lognormal3d(6, 21)
+    c, M0 = O.initial_iterate(A)
+    h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=6)
+    done, hist, rc = h.iterate(0)
+    assert done == 0 and len(hist) == 0 and rc == S.SPAI_OK
+    M = h.get()
+    assert M.nnz == A.shape[0] and sp.triu(M, 1).nnz == 0
+    assert value_err(M, M0) <= 1e-14
+    _, h1, _ = h.iterate(6)
+    M1 = h.get()
+    h.reset()
+    assert (h.get() != M).nnz == 0
+    _, h2, _ = h.iterate(6)
+    assert np.array_equal(h1, h2) and (h.get() != M1).nnz == 0
+    with pytest.raises(S.SpaiError):
+        h.iterate(1)                                   # beyond max_iter
+    h.close()
+
+
+@pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
+def test_diagonal_matrix(method):
+    """A diagonal A: the iterates stay diagonal and follow the oracle; with Pi = D_A^{-1}
+    = A^{-1} every weighted method reaches M = A^{-1} in its first (MR-type) step."""
+    S = _spai()
+    d = np.random.default_rng(3).uniform(1.0, 100.0, 300)
+    A = sp.diags(d).tocsr()
+    r0, hist, Mg, st, rc = _run_gpu(S, A, method, "none", 0, False, 10)
+    ref = O.run(method, A, oracle_rule(A, "none", 0, False), 10)
+    assert rel_err(hist, ref.resid[1:]) <= TOL_F64
+    assert Mg.nnz == 300 and sp.triu(Mg, 1).nnz == 0
+    assert value_err(Mg, ref.M) <= 1e-12
+    r0, hist, Mg, st, rc = _run_gpu(S, A, method, "none", 0, False, 1, jacobi=True)
+    ref = O.run_spd(method, A, O.jacobi(A), oracle_rule(A, "none", 0, False), 1)
+    assert r0 == pytest.approx(ref.resid[0], rel=1e-14)
+    assert ref.resid[1] <= 1e-14 and hist[0] <= 1e-14
+    assert np.max(np.abs(Mg.diagonal() * d - 1.0)) <= 1e-15
+
+
+@pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
+@pytest.mark.parametrize("name", ["laplace8", "lognormal6"])
+def test_column_cap_one(name, method):
+    """k_j = 1: only the largest entry of each column survives.  On the 8 x 8 Laplacian
+    the off-diagonal entries of R_0 outweigh its diagonal, the tied neighbours cancel in
+    the symmetrized direction and P_0 = 0, so matrix CG stops at once with a breakdown, as
+    the oracle does; M stays diagonal."""
+    S = _spai()
+    A = W.laplace2d(8) if name == "laplace8" else W.lognormal3d(6, 5)
+    r0, hist, Mg, st, rc = _run_gpu(S, A, method, "column", 1, False, 8)
+    ref = O.run(method, A, oracle_rule(A, "column", 1, False), 8)
+    assert len(hist) == ref.iters
+    assert (rc == S.SPAI_BREAKDOWN) == (ref.status == "breakdown")
+    if ref.iters:
+        assert rel_err(hist, ref.resid[1:]) <= TOL_F64
+    assert pattern_diff(Mg, ref.M) == (set(), set())
+    assert value_err(Mg, ref.M) <= 1e-9
+    assert sp.triu(Mg, 1).nnz == 0
+
+
+def test_cg_breakdown_on_indefinite_matrix():
+    """A symmetric matrix with a positive diagonal but one negative eigenvalue (the 10 x 10
+    Laplacian shifted by -0.2 I): without dropping, (P_i, A P_i) turns negative at the same
+    iteration on the GPU as in the oracle, which both report as a breakdown; MR and LOMR
+    keep going and follow the oracle."""
+    S = _spai()
+    A = sp.csr_matrix(W.laplace2d(10) - 0.2 * sp.identity(100))
+    ref = O.cg(A, O.DropRule(mode="none", u=0.0), 30)
+    assert ref.status == "breakdown" and ref.iters == 9
+    h = S.SPAI(A, "cg", "none", 0, False, max_iter=30, options=S.Options(drop_tol=0.0))
+    done, hist, rc = h.iterate(30)
+    Mg = h.get()
+    h.close()
+    assert rc == S.SPAI_BREAKDOWN and done == 9
+    assert rel_err(hist, ref.resid[1:]) <= 1e-9
+    assert value_err(Mg, ref.M) <= 1e-8
+    for method in ("mr", "lomr"):
+        h = S.SPAI(A, method, "none", 0, False, max_iter=12, options=S.Options(drop_tol=0.0))
+        done, hist, rc = h.iterate(12)
+        h.close()
+        refm = O.run(method, A, O.DropRule(mode="none", u=0.0), 12)
+        assert rc == S.SPAI_OK and done == 12
+        assert rel_err(hist, refm.resid[1:]) <= 1e-9
+
+
+@pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
+def test_batched_jacobi_parity(method):
+    """The batched handle with Pi = D_A^{-1}: each matrix of the batch follows its own
+    oracle run (per-matrix scalars and per-matrix (R, Z)_F)."""
+    S = _spai()
+    mats = W.batch_geometric(5, 909, 300, 1200)
+    iters = 8
+    h = S.SPAI(None, method, "column", 4.0, False, max_iter=iters, batch=mats,
+               options=S.Options(jacobi=True))
+    done, hist, rc = h.iterate(iters)
+    res = h.batched_resid()
+    Mg = h.get()
+    h.close()
+    off = 0
+    for b, A in enumerate(mats):
+        ref = O.run_spd(method, A, O.jacobi(A), oracle_rule(A, "column", 4.0, False), iters)
+        assert ref.iters == iters
+        assert res[b] == pytest.approx(ref.resid[-1], rel=TOL_F64)
+        n = A.shape[0]
+        blk = Mg[off:off + n, off:off + n]
+        assert pattern_diff(blk, ref.M) == (set(), set())
+        assert value_err(blk, ref.M) <= 1e-9
+        off += n
+    assert Mg[:mats[0].shape[0], mats[0].shape[0]:].nnz == 0
