@@ -56,6 +56,7 @@ __all__ = [
     "drop_main", "drop_direction", "mr", "cg", "lomr", "run", "pcg", "pcg_block",
     "loss", "loss_grad", "OracleBreakdown", "column_residual", "row_residual",
     "grad_m_entry", "grad_a_entry", "jacobi", "mr_spd", "cg_spd", "lomr_spd", "run_spd",
+    "extreme_eigenvalues", "lanczos",
 ]
 
 UNIT_ROUNDOFF = 2.0 ** -53
@@ -621,6 +622,61 @@ def pcg_block(A, M, B, rtol: float = 1e-8, max_iter: int = 10000):
         iters.append(it)
         status.append(st)
     return X, np.array(iters), status
+
+
+# ----------------------------------------------------------------------------
+# spectrum of a symmetric iterate (the lambda_min / lambda_max of Tables 4-6; whether a
+# SPAI is positive definite, Section 7.1)
+# ----------------------------------------------------------------------------
+
+LANCZOS_INVARIANT = 1e-12
+
+
+def extreme_eigenvalues(S) -> tuple[float, float]:
+    """(lambda_min, lambda_max) of a symmetric matrix: the definition, through a dense
+    symmetric eigensolver (small matrices only)."""
+    w = np.linalg.eigvalsh(sp.csr_matrix(S).toarray())
+    return float(w[0]), float(w[-1])
+
+
+def lanczos(S, steps: int, v0):
+    """The Lanczos process with full reorthogonalisation, written from its textbook
+    definition (Golub and Van Loan, Matrix Computations, Section 10.1): v_0 = v0/||v0||;
+    per step w = S v_j, Gram-Schmidt against all previous v twice, alpha_j = v_j^T S v_j
+    (the sum of the two projections on v_j), beta_j = ||w||, v_{j+1} = w / beta_j; stop
+    early when beta_j <= 1e-12 max_{i<=j}(|alpha_i| + beta_i).  At most min(steps, n)
+    steps.  Returns (theta_min, theta_max, res_min, res_max, steps taken): the extreme
+    eigenvalues of T_k = tridiag(beta, alpha, beta) and beta_k |y_k| for their unit
+    eigenvectors y (the distance to the nearest eigenvalue of S is at most res)."""
+    S = sp.csr_matrix(S)
+    n = S.shape[0]
+    K = min(int(steps), n)
+    v0 = np.asarray(v0, dtype=np.float64)
+    V = np.zeros((n, K + 1))
+    V[:, 0] = v0 / np.linalg.norm(v0)
+    alpha, beta = [], []
+    scale = 0.0
+    for j in range(K):
+        w = S @ V[:, j]
+        Vj = V[:, :j + 1]
+        h1 = Vj.T @ w
+        w = w - Vj @ h1
+        h2 = Vj.T @ w
+        w = w - Vj @ h2
+        a = float(h1[j] + h2[j])
+        b = float(np.linalg.norm(w))
+        alpha.append(a)
+        beta.append(b)
+        scale = max(scale, abs(a) + b)
+        if b <= LANCZOS_INVARIANT * scale:
+            break
+        if j + 1 < K:
+            V[:, j + 1] = w / b
+    k = len(alpha)
+    T = np.diag(alpha) + np.diag(beta[:k - 1], 1) + np.diag(beta[:k - 1], -1)
+    theta, Y = np.linalg.eigh(T)
+    res = beta[k - 1] * np.abs(Y[k - 1, :])
+    return float(theta[0]), float(theta[-1]), float(res[0]), float(res[-1]), k
 
 
 # ----------------------------------------------------------------------------

@@ -259,6 +259,14 @@ def test_implicit_and_explicit_residuals_agree_without_dropping():
         e = O.run(meth, A, O.DropRule.no_drop(), 8, explicit=True)
         i = O.run(meth, A, O.DropRule.no_drop(), 8, explicit=False)
         assert np.allclose(e.resid, i.resid, rtol=1e-9, atol=1e-12)
+    # the Pi-weighted forms, on a variable-coefficient A (Pi not a multiple of I)
+    A = W.lognormal3d(4, 12)
+    Pi = O.jacobi(A)
+    for meth in ("mr", "cg", "lomr"):
+        e = O.run_spd(meth, A, Pi, O.DropRule.no_drop(), 8, explicit=True)
+        i = O.run_spd(meth, A, Pi, O.DropRule.no_drop(), 8, explicit=False)
+        assert np.allclose(e.resid, i.resid, rtol=1e-9, atol=1e-12)
+        assert abs(e.M - i.M).max() <= 1e-9 * abs(e.M).max()
 
 
 def test_special_cases():
@@ -638,3 +646,48 @@ def test_paper_recipe_matrices_match_table_3_structure():
             assert 0.5 < lmin < 1.0 and lmax > 1e9
         else:
             assert lmax / lmin > 1e8
+
+
+# ----------------------------------------------------------------------------
+# spectrum of a symmetric matrix (the lambda_min / lambda_max columns of Tables 4-6)
+# ----------------------------------------------------------------------------
+
+def test_extreme_eigenvalues_closed_forms():
+    """1-D Laplacian tridiag(-1, 2, -1): lambda_k = 2 - 2 cos(k pi / (n + 1)); 5-point
+    2-D Laplacian on an N x N grid: 4 - 2 cos(j pi/(N+1)) - 2 cos(k pi/(N+1))."""
+    n = 37
+    T = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1])
+    lo, hi = O.extreme_eigenvalues(T)
+    assert lo == pytest.approx(2 - 2 * np.cos(np.pi / (n + 1)), rel=1e-12)
+    assert hi == pytest.approx(2 - 2 * np.cos(n * np.pi / (n + 1)), rel=1e-12)
+    N = 12
+    lo, hi = O.extreme_eigenvalues(W.laplace2d(N))
+    c1, cN = np.cos(np.pi / (N + 1)), np.cos(N * np.pi / (N + 1))
+    assert lo == pytest.approx(4 - 4 * c1, rel=1e-12)
+    assert hi == pytest.approx(4 - 4 * cN, rel=1e-12)
+
+
+def test_lanczos_pins():
+    rng = np.random.default_rng(5)
+    # (a) n steps on a small symmetric matrix: the Ritz values are the eigenvalues
+    B = rng.standard_normal((40, 40))
+    S = sp.csr_matrix(B + B.T)
+    lo, hi = O.extreme_eigenvalues(S)
+    t0, t1, r0, r1, k = O.lanczos(S, 40, rng.standard_normal(40))
+    assert t0 == pytest.approx(lo, abs=1e-10 * abs(hi)) and t1 == pytest.approx(hi, rel=1e-10)
+    # (b) an invariant subspace: a diagonal matrix with 3 distinct values and a start
+    # vector touching all of them ends after 3 steps with exactly those extremes
+    D = sp.diags(np.repeat([1.0, 4.0, 9.0], 10))
+    t0, t1, r0, r1, k = O.lanczos(D, 20, np.ones(30))
+    assert k == 3 and t0 == pytest.approx(1.0, rel=1e-12) and t1 == pytest.approx(9.0, rel=1e-12)
+    assert r0 <= 1e-10 and r1 <= 1e-10
+    # (c) few steps on the 2-D Laplacian: Ritz values lie inside the spectrum, each within
+    # its residual bound of an eigenvalue, and the outer ones near the closed forms
+    A = W.laplace2d(30)
+    w = np.linalg.eigvalsh(A.toarray())
+    t0, t1, r0, r1, k = O.lanczos(A, 60, rng.standard_normal(A.shape[0]))
+    assert k == 60
+    assert w[0] - 1e-12 <= t0 <= t1 <= w[-1] + 1e-12
+    assert np.min(np.abs(w - t0)) <= r0 * (1 + 1e-9) + 1e-12
+    assert np.min(np.abs(w - t1)) <= r1 * (1 + 1e-9) + 1e-12
+    assert t1 == pytest.approx(w[-1], rel=1e-3)
