@@ -118,6 +118,14 @@ typedef struct {
                                Pi = D_A^{-1} (MR: Algorithm 5, CG: Algorithm 7,
                                LOMR: Algorithm 8); the direction lists hold
                                Z = Pi R; default 0                                 */
+  int explicit_residual;    /* 1 (default): R_{i+1} = I - A M_{i+1} after every
+                               update (Section 6.2).  0: the update formulas of
+                               Algorithms 1, 3, 4 (and 5, 7, 8), R_{i+1} = R_i -
+                               alpha A R_i (MR), R_i - alpha A P_i (CG),
+                               R_i - A P_i (LOMR); valid only without dropping, so
+                               it requires SPAI_CAP_NONE, drop_tol = 0 and
+                               symmetrize = 0 (else SPAI_ERR_ARG); not for batched
+                               handles                                             */
 } spai_opts_t;
 
 /* Fill *opts with the defaults. */
@@ -201,6 +209,31 @@ int spai_reset(spai_handle_t* h);
  */
 int spai_pcg(spai_handle_t* h, int nrhs, const double* B, double* X, double rtol,
              int max_iter, int* iters, double* relres, int on_device);
+
+/*
+ * spai_spectrum — extreme eigenvalues of the handle's current iterate M (the
+ *   lambda_min / lambda_max the paper reports for its SPAIs, Tables 4-6; M is
+ *   positive definite iff lambda_min > 0, Section 7.1), estimated by `steps` steps
+ *   (1..2048; clamped to n) of the Lanczos process with full reorthogonalisation
+ *   from the start vector v0 (n float64, device when on_device = 1, else host; not
+ *   all zero; the caller draws it, e.g. at random).  The process stops early when
+ *   an invariant subspace is found (the Ritz values are then eigenvalues).
+ * out (host, 4 doubles): theta_min, theta_max (extreme Ritz values; lambda_min <=
+ *   theta_min, theta_max <= lambda_max), and res_min, res_max: each Ritz value is
+ *   within res of an eigenvalue of M.  *steps_done (may be NULL): steps taken.
+ *   Requires symmetrize = 1.  Allocates n (steps + 1) doubles for the basis for the
+ *   duration of the call.  Synchronises the stream.
+ */
+int spai_spectrum(spai_handle_t* h, int steps, const double* v0, int on_device, double* out,
+                  int* steps_done);
+
+/*
+ * spai_csr_spectrum — the same for an exactly symmetric CSR matrix S (for instance
+ *   A, or an exported M); v0 is on the device when S->on_device.  Returns
+ *   SPAI_ERR_NOT_SYMMETRIC for a matrix that is not exactly symmetric.
+ */
+int spai_csr_spectrum(const spai_csr_t* S, int steps, const double* v0, double* out,
+                      int* steps_done, const spai_opts_t* opts);
 
 /* Phases timed when opts.profile = 1, and traffic counters (cumulative since create). */
 enum {

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libspai.so")
-SOURCES = ["spai_kernels.hip", "spai_api.hip", "spai_pcg.hip", "spai_loss.hip"]
+SOURCES = ["spai_kernels.hip", "spai_api.hip", "spai_pcg.hip", "spai_loss.hip", "spai_spectrum.hip"]
 ARCH = os.environ.get("SPAI_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

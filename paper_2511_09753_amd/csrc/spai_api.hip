@@ -173,6 +173,8 @@ struct EngineBase {
   virtual int pcg(int nrhs, const double* B, double* X, double rtol, int max_iter, int* iters,
                   double* relres, int on_device) = 0;
   virtual int profile(double* ms, int64_t* calls, int64_t* counts) = 0;
+  virtual int spectrum(int steps, const double* v0, int on_device, double* out,
+                       int* steps_done) = 0;
 };
 
 template <typename T>
@@ -197,6 +199,10 @@ struct Engine : EngineBase {
   Csr A;
   Pair<T> M, P, PT;
   Cols<T> R;
+  // implicit residual (opts.explicit_residual = 0): the next residual is formed in Rn
+  // (and Zn, Pi-weighted) and copied over R; Pi-weighted, R holds Z and Rraw holds R
+  Cols<T> Rn{}, Zn{}, Rraw{};
+  bool implicit = false;
   int64_t *ub = nullptr, *off = nullptr, *total = nullptr, *scantmp = nullptr;
   double *colpart = nullptr, *colnorm = nullptr, *red = nullptr, *red_rr = nullptr;
   double *colrz = nullptr, *red_rz = nullptr;   // (R, Z)_F per column / matrix (weighted)
@@ -341,7 +347,8 @@ struct Engine : EngineBase {
     const double nnzP_max = method == SPAI_MR ? 0.0 : nnzM_max;
     // offsets come from per-column bounds that count duplicate products, so the pools
     // hold the sum of the bounds (not the number of distinct entries)
-    const double capR_d = (double)n + nnzM_max * (double)maxdeg;
+    // (the implicit update's bound also counts supp(R_i): up to n^2 more)
+    const double capR_d = (double)n + nnzM_max * (double)maxdeg + (opts.explicit_residual ? 0.0 : n2);
     const double capU_d = (double)n + nnzM_max + capR_d + 2.0 * nnzP_max + nnzM_max * (double)maxdeg;
     if (capU_d > 4.0e9) return fail(SPAI_ERR_NOMEM, "worst-case pattern too large (set a cap)");
     const int64_t capR = (int64_t)capR_d, capU = (int64_t)capU_d;
@@ -439,6 +446,11 @@ struct Engine : EngineBase {
       if ((rc = alloc_cols(PT.b[b], capP))) return rc;
     }
     if ((rc = alloc_cols(R, capR))) return rc;
+    implicit = !opts.explicit_residual;
+    if (implicit) {
+      if ((rc = alloc_cols(Rn, capR))) return rc;
+      if (opts.jacobi && ((rc = alloc_cols(Zn, capR)) || (rc = alloc_cols(Rraw, capR)))) return rc;
+    }
     M.cur = &st->curM;
     P.cur = &st->curP;
     PT.cur = &st->curP;
@@ -560,6 +572,35 @@ struct Engine : EngineBase {
     return rc;
   }
 
+  int spectrum(int steps, const double* v0, int on_device, double* out,
+               int* steps_done) override {
+    if (!opts.symmetrize) return fail(SPAI_ERR_ARG, "spai_spectrum needs a symmetrized iterate");
+    if (!v0 || !out) return fail(SPAI_ERR_ARG, "spai_spectrum: null argument");
+    HIPCHK(hipStreamSynchronize(s));
+    DevState h;
+    HIPCHK(hipMemcpy(&h, st, sizeof(DevState), hipMemcpyDeviceToHost));
+    const Cols<T>& C = M.b[h.curM];
+    PcgMat pm;
+    pm.n = n;
+    pm.beg = C.beg;
+    pm.len = C.len;
+    pm.col = C.idx;
+    if (sizeof(T) == 4) pm.val32 = (const float*)C.val; else pm.val = (const double*)C.val;
+    DevPool tmp;
+    int rc;
+    const double* dv0 = v0;
+    if (!on_device) {
+      double* d;
+      if ((rc = tmp.alloc(&d, n))) return rc;
+      HIPCHK(hipMemcpyAsync(d, v0, sizeof(double) * n, hipMemcpyHostToDevice, s));
+      dv0 = d;
+    }
+    const int64_t rest = opts.device_pool_limit > 0
+                             ? std::max<int64_t>(1, opts.device_pool_limit - (int64_t)pool.used)
+                             : 0;
+    return lanczos_run(pm, steps, dv0, out, steps_done, rest, s);
+  }
+
   int profile(double* ms, int64_t* calls, int64_t* counts) override {
     HIPCHK(hipStreamSynchronize(s));
     collect();
@@ -604,6 +645,8 @@ struct Engine : EngineBase {
     launch_scan(ub, off, total, n, scantmp, s);
     te();
     tb(SPAI_PH_RESID);
+    if (implicit && opts.jacobi)         // R_0 itself, for the implicit updates
+      launch_resid<T>(A, M, Rraw, off, total, colnorm, 0, colrz, big[0], st, tRs, tRl, tRh, s);
     launch_resid<T>(A, M, R, off, total, colnorm, opts.jacobi, colrz, big[0], st, tRs, tRl, tRh,
                     s);
     te();
@@ -613,6 +656,32 @@ struct Engine : EngineBase {
       launch_reduce(colrz, 1, n, seg, nseg > 1 ? seg_beg : nullptr, red_rz, blockpart, s);
     launch_scal_post(method, seg, red_rr, opts.jacobi ? red_rz : nullptr, tol, hist, hist_cap,
                      setup, st, s);
+    te();
+  }
+
+  // R_{i+1} = R_i - c A X without dropping; X = the direction list R (xsrc 0) or P.now()
+  void implicit_step(int xsrc, int cidx) {
+    Cols<T> Rin = opts.jacobi ? Rraw : R;
+    tb(SPAI_PH_BOUNDS);
+    launch_bound_impl<T>(A, Rin, R, P, xsrc, ub, n, st, s);
+    launch_scan(ub, off, total, n, scantmp, s);
+    te();
+    tb(SPAI_PH_RESID);
+    launch_resid_impl<T>(A, Rin, R, P, xsrc, cidx, seg, off, total, Rn, Zn, opts.jacobi, colnorm,
+                         colrz, big[0], st, tDs, tDl, tDh, s);
+    if (opts.jacobi) {
+      launch_copy_cols<T>(Rn, Rraw, n, total, st, s);
+      launch_copy_cols<T>(Zn, R, n, total, st, s);
+    } else {
+      launch_copy_cols<T>(Rn, R, n, total, st, s);
+    }
+    te();
+    tb(SPAI_PH_SCALAR);
+    launch_reduce(colnorm, 1, n, seg, nseg > 1 ? seg_beg : nullptr, red_rr, blockpart, s);
+    if (opts.jacobi)
+      launch_reduce(colrz, 1, n, seg, nseg > 1 ? seg_beg : nullptr, red_rz, blockpart, s);
+    launch_scal_post(method, seg, red_rr, opts.jacobi ? red_rz : nullptr, tol, hist, hist_cap, 0,
+                     st, s);
     te();
   }
 
@@ -661,16 +730,19 @@ struct Engine : EngineBase {
     if (method == SPAI_MR) {
       dots_step(1, 0);
       update_step(mode(1, 1, 0, 0));
-      resid_step(0);
+      if (implicit) implicit_step(0, 0);     // R - alpha A R
+      else resid_step(0);
     } else if (method == SPAI_CG) {
       dots_step(0, 1);
       update_step(mode(1, 2, 0, 0));
-      resid_step(0);
+      if (implicit) implicit_step(1, 0);     // R - alpha A P
+      else resid_step(0);
       p_update_step();
     } else {
       dots_step(1, 1);
       update_step(mode(1, 1, 2, 1));
-      resid_step(0);
+      if (implicit) implicit_step(1, -1);    // R - A P_i, P_i = delta R + gamma P_{i-1}
+      else resid_step(0);
     }
   }
 
@@ -846,6 +918,7 @@ static void fill_defaults(spai_opts_t* o) {
   o->profile = 0;
   o->a_format = SPAI_AFMT_AUTO;
   o->jacobi = 0;
+  o->explicit_residual = 1;
 }
 
 template <typename T>
@@ -882,6 +955,12 @@ static int check_common(int method, spai_cap_t cap, int max_iter, double tol,
     return fail(SPAI_ERR_ARG, "unknown precision");
   if (!(o.drop_tol >= 0.0) || !(o.tie_eta >= 0.0)) return fail(SPAI_ERR_ARG, "bad drop_tol / tie_eta");
   if (o.jacobi != 0 && o.jacobi != 1) return fail(SPAI_ERR_ARG, "jacobi must be 0 or 1");
+  if (o.explicit_residual != 0 && o.explicit_residual != 1)
+    return fail(SPAI_ERR_ARG, "explicit_residual must be 0 or 1");
+  if (!o.explicit_residual &&
+      (cap.mode != SPAI_CAP_NONE || o.drop_tol != 0.0 || o.symmetrize))
+    return fail(SPAI_ERR_ARG,
+                "the implicit residual needs no dropping: no cap, drop_tol 0, symmetrize 0");
   if (o.a_format != SPAI_AFMT_AUTO && o.a_format != SPAI_AFMT_CSR && o.a_format != SPAI_AFMT_ELL)
     return fail(SPAI_ERR_ARG, "unknown a_format");
   return SPAI_OK;
@@ -924,6 +1003,7 @@ int spai_create_batched(const spai_csr_t* As, int nb, int method, spai_cap_t cap
     int rc = check_common(method, cap, max_iter, tol, opts, o);
     if (rc) return rc;
     if (cap.mode == SPAI_CAP_GLOBAL) return fail(SPAI_ERR_ARG, "batched handles take column caps only");
+    if (!o.explicit_residual) return fail(SPAI_ERR_ARG, "batched handles use the explicit residual");
     // block-diagonal assembly
     HostCsr big;
     big.n = 0;
@@ -1013,6 +1093,18 @@ int spai_pcg(spai_handle_t* h, int nrhs, const double* B, double* X, double rtol
   if (!h) return fail(SPAI_ERR_ARG, "null handle");
   try {
     return h->eng->pcg(nrhs, B, X, rtol, max_iter, iters, relres, on_device);
+  } catch (const std::bad_alloc&) {
+    return fail(SPAI_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_spectrum(spai_handle_t* h, int steps, const double* v0, int on_device, double* out,
+                  int* steps_done) {
+  if (!h) return fail(SPAI_ERR_ARG, "null handle");
+  try {
+    return h->eng->spectrum(steps, v0, on_device, out, steps_done);
   } catch (const std::bad_alloc&) {
     return fail(SPAI_ERR_NOMEM, "host allocation failed");
   } catch (...) {

@@ -81,4 +81,10 @@ struct PcgMat {
 int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double* dX, double rtol,
             int max_iter, int* iters, double* relres, const int32_t* order, hipStream_t s);
 
+// extreme Ritz values of S (symmetric) after up to `steps` Lanczos steps with full
+// reorthogonalisation from the device vector dv0: out = {theta_min, theta_max, res_min,
+// res_max}; pool_limit bounds the call's device memory (0: none)
+int lanczos_run(const PcgMat& S, int steps, const double* dv0, double* out, int* steps_done,
+                int64_t pool_limit, hipStream_t s);
+
 }  // namespace spai

@@ -127,6 +127,20 @@ void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, int wei
                  double* colpart, BigList big, DevState* st, Tile small, Tile large, Tile huge,
                  hipStream_t s);
 
+// implicit residual R_{i+1} = R_i - c A X (no dropping): X is Xr (xsrc 0) or P.now()
+// (xsrc 1), c the segment's coef[cidx] (cidx -1: c = 1); Zout gets Pi R_{i+1} (weighted)
+template <typename T>
+void launch_bound_impl(const Csr& A, Cols<T> Rin, Cols<T> Xr, Pair<T> P, int xsrc, int64_t* ub,
+                       int64_t n, const DevState* st, hipStream_t s);
+template <typename T>
+void launch_resid_impl(const Csr& A, Cols<T> Rin, Cols<T> Xr, Pair<T> P, int xsrc, int cidx,
+                       const Seg& seg, const int64_t* off, const int64_t* total, Cols<T> Rout,
+                       Cols<T> Zout, int weighted, double* colnorm, double* colrz, BigList big,
+                       DevState* st, Tile small, Tile large, Tile huge, hipStream_t s);
+template <typename T>
+void launch_copy_cols(Cols<T> src, Cols<T> dst, int64_t n, const int64_t* total,
+                      const DevState* st, hipStream_t s);
+
 template <typename T>
 void launch_bound_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, UpdMode md,
                          int64_t* ub, int64_t n, const DevState* st, hipStream_t s);

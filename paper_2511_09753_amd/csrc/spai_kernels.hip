@@ -831,6 +831,241 @@ void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, int wei
 size_t dots_tile_bytes(Tile t, bool ell) { return dots_lds(t, ell); }
 
 // ============================================================================
+// implicit residual update R_{i+1} = R_i - c A X_i (Algorithms 1, 3, 4 as printed,
+// Section 6.2: valid only while nothing is dropped)
+// ============================================================================
+//
+// X is R_i itself (MR, c = alpha), P_i (CG, c = alpha) or the new direction P_i =
+// delta R_i + gamma P_{i-1} (LOMR, c = 1).  In the Pi-weighted forms the direction
+// lists hold Z = Pi R, so R_i comes from its own buffer and Z_{i+1} is written beside
+// R_{i+1}.  Output column j: supp(r_j) united with the rows reached from supp(x_j)
+// through A, values r_uj - c sum_l a_ul x_lj (l ascending), written at off[j].
+
+struct ImplSrc {
+  int xsrc;      // 0: X is the direction-list buffer given as Xr, 1: X is P.now()
+  int cidx;      // coefficient index into the segment's coef[], -1: c = 1
+};
+
+template <typename T>
+__global__ void k_bound_impl(Csr A, Cols<T> Rin, Cols<T> Xr, Pair<T> Pp, ImplSrc src, int64_t* ub,
+                             int64_t n, const DevState* st) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  if (!st->any_active || !st->iter_active) return;
+  const Cols<T> X = src.xsrc ? Pp.now() : Xr;
+  const int64_t b = X.beg[j];
+  const int lx = X.len[j];
+  int64_t s = Rin.len[j];
+  for (int e = 0; e < lx; ++e) {
+    const int l = X.idx[b + e];
+    s += A.rowptr[l + 1] - A.rowptr[l];
+  }
+  ub[j] = s;
+}
+
+template <typename T>
+void launch_bound_impl(const Csr& A, Cols<T> Rin, Cols<T> Xr, Pair<T> P, int xsrc, int64_t* ub,
+                       int64_t n, const DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_bound_impl<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, Rin,
+                     Xr, P, ImplSrc{xsrc, 0}, ub, n, st);
+}
+
+template <typename T, bool GS>
+__global__ __launch_bounds__(SPAI_WAVE) void k_resid_impl(Csr A, Cols<T> Rin, Cols<T> Xr,
+                                                          Pair<T> Pp, ImplSrc src, Seg seg,
+                                                          const int64_t* off,
+                                                          const int64_t* total, Cols<T> Rout,
+                                                          Cols<T> Zout, int weighted,
+                                                          double* colnorm, double* colrz,
+                                                          BigList big, DevState* st, int tier,
+                                                          int L, int H) {
+  if (!st->any_active || !st->iter_active) return;
+  extern __shared__ char smem[];
+  const bool ell = A.eshift >= 0;
+  Carve cv(tile_base<GS>(smem, big));
+  int* s_li = cv.take<int>(L);           // r_j rows, then x_j rows
+  int* s_keys = cv.take<int>(H);
+  double* s_lv = cv.take<double>(L);
+  int* s_mk = cv.take<int>(2 * L);       // position map: row -> (place in r_j, in x_j)
+  unsigned* s_mp = cv.take<unsigned>(2 * L);
+  int* s_pre = ell ? nullptr : cv.take<int>(L);
+  int64_t* s_rs = ell ? nullptr : cv.take<int64_t>(L);
+  const int lane = lane_id();
+  const Cols<T> X = src.xsrc ? Pp.now() : Xr;
+  const bool overflow = *total > Rout.cap;
+  const int limit = H / 2 - 1;
+
+  auto body = [&](int64_t j) {
+    const int lr = Rin.len[j];
+    const int lx = X.len[j];
+    if (lr + lx > L) {
+      defer_column(tier, big, st, j);
+      return;
+    }
+    if (overflow) {
+      if (lane == 0) atomicOr(&st->err, 2);
+      return;
+    }
+    const SegState& g = seg.st[seg.segof(j)];
+    // a stopped matrix of a batch keeps its residual
+    const double c = g.stop ? 0.0 : (src.cidx < 0 ? 1.0 : g.coef[src.cidx]);
+    const int64_t rb = Rin.beg[j];
+    const int64_t xb = X.beg[j];
+    const int hs = next_pow2(max(2 * (lr + lx), 64));
+    ks_clear(s_keys, H);
+    lm_clear(s_mk, s_mp, hs);
+    tile_sync<GS>();
+    for (int e = lane; e < lr + lx; e += SPAI_WAVE) {
+      int i;
+      double v;
+      if (e < lr) {
+        i = Rin.idx[rb + e];
+        v = (double)Rin.val[rb + e];
+      } else {
+        i = X.idx[xb + e - lr];
+        v = (double)X.val[xb + e - lr];
+      }
+      s_li[e] = i;
+      s_lv[e] = v;
+      lm_put(s_mk, s_mp, hs, i, e < lr ? 0 : 1, e < lr ? e : e - lr);
+    }
+    tile_sync<GS>();
+    int nk = 0;
+    for (int b0 = 0; b0 < lr; b0 += SPAI_WAVE) {           // supp(r_j)
+      const int kd[1] = {b0 + lane < lr ? s_li[b0 + lane] : -1};
+      nk += wave_sum_int(ks_insert_batch<1>(s_keys, H, kd));
+    }
+    int tot = 0;
+    if (!ell) {
+      tot = degree_prefix(A, s_li + lr, lx, s_pre, s_rs);
+      tile_sync<GS>();
+    }
+    if (nk <= limit)
+      nk = insert_products(A, s_li + lr, lx, s_pre, s_rs, tot, s_keys, H, nk, limit);
+    tile_sync<GS>();
+    if (nk > limit) {
+      defer_column(tier, big, st, j);
+      tile_sync<GS>();
+      return;
+    }
+    const int nu = ks_sort_inplace(s_keys, H);
+    tile_sync<GS>();
+    const double* rv = s_lv;
+    const double* xv = s_lv + lr;
+    const int64_t ob = off[j];
+    double acc = 0.0, acc_rz = 0.0;
+    double ax[1], diag[1];
+    int key[1];
+    pull_rows<1>(
+        A, s_keys, nu,
+        [&](int cc, int t) {
+          ax[cc] = 0.0;
+          diag[cc] = 0.0;
+          key[cc] = s_keys[t];
+        },
+        [&](int cc, const int (&cols)[8], const double (&vals)[8]) {
+          unsigned pw[8];
+          lm_find<8>(s_mk, s_mp, hs, cols, pw);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const unsigned e1 = pw[k] >> 16;
+            if (e1 != kNoPos) ax[cc] += vals[k] * xv[e1];
+            if (cols[k] == key[cc]) diag[cc] = vals[k];
+          }
+        },
+        [&](int cc, int t) {
+          const int kk[1] = {key[cc]};
+          unsigned pw[1];
+          lm_find<1>(s_mk, s_mp, hs, kk, pw);
+          const unsigned e0 = pw[0] & kNoPos;
+          const double ru = e0 != kNoPos ? rv[e0] : 0.0;
+          const double r = ru - c * ax[cc];
+          const T rt = (T)r;
+          Rout.idx[ob + t] = key[cc];
+          Rout.val[ob + t] = rt;
+          acc += (double)rt * (double)rt;
+          if (weighted) {                   // Z = Pi R, Pi = D_A^{-1}
+            const T zt = (T)((1.0 / diag[cc]) * r);
+            Zout.idx[ob + t] = key[cc];
+            Zout.val[ob + t] = zt;
+            acc_rz += (double)rt * (double)zt;
+          }
+        });
+    acc = wave_sum(acc);
+    if (weighted) acc_rz = wave_sum(acc_rz);
+    if (lane == 0) {
+      colnorm[j] = acc;
+      Rout.beg[j] = ob;
+      Rout.len[j] = nu;
+      if (weighted) {
+        colrz[j] = acc_rz;
+        Zout.beg[j] = ob;
+        Zout.len[j] = nu;
+      }
+    }
+    tile_sync<GS>();
+  };
+
+  if (tier == 0) {
+    ColumnWalk w(A.n, blockIdx.x, gridDim.x);
+    for (int64_t j = w.begin; j < w.end; j += w.step) body(j);
+  } else if (tier == 1) {
+    const int cnt = *big.count;
+    for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list[t]);
+  } else {
+    const int cnt = *big.count2;
+    for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list2[t]);
+  }
+}
+
+template <typename T>
+void launch_resid_impl(const Csr& A, Cols<T> Rin, Cols<T> Xr, Pair<T> P, int xsrc, int cidx,
+                       const Seg& seg, const int64_t* off, const int64_t* total, Cols<T> Rout,
+                       Cols<T> Zout, int weighted, double* colnorm, double* colrz, BigList big,
+                       DevState* st, Tile small, Tile large, Tile huge, hipStream_t s) {
+  const bool ell = A.eshift >= 0;
+  const ImplSrc src{xsrc, cidx};
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
+  hipLaunchKernelGGL((k_resid_impl<T, false>),
+                     dim3(resident_grid(k_resid_impl<T, false>, dots_lds(small, ell))),
+                     dim3(SPAI_WAVE), dots_lds(small, ell), s, A, Rin, Xr, P, src, seg, off, total,
+                     Rout, Zout, weighted, colnorm, colrz, big, st, 0, small.L, small.H);
+  hipLaunchKernelGGL((k_resid_impl<T, false>), dim3(256), dim3(SPAI_WAVE), dots_lds(large, ell), s,
+                     A, Rin, Xr, P, src, seg, off, total, Rout, Zout, weighted, colnorm, colrz, big,
+                     st, 1, large.L, large.H);
+  hipLaunchKernelGGL((k_resid_impl<T, true>), dim3(kHugeGrid), dim3(SPAI_WAVE), 0, s, A, Rin, Xr,
+                     P, src, seg, off, total, Rout, Zout, weighted, colnorm, colrz, big, st, 2,
+                     huge.L, huge.H);
+}
+
+// dst := src for column lists laid out at the same offsets (entries [0, *total))
+template <typename T>
+__global__ void k_copy_cols(Cols<T> src, Cols<T> dst, int64_t n, const int64_t* total,
+                            const DevState* st) {
+  if (!st->any_active || !st->iter_active) return;
+  // an overflowing total was flagged by the producer, which then wrote nothing
+  const int64_t tot = min(*total, min(src.cap, dst.cap));
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot || q < n; q += stride) {
+    if (q < n) {
+      dst.beg[q] = src.beg[q];
+      dst.len[q] = src.len[q];
+    }
+    if (q < tot) {
+      dst.idx[q] = src.idx[q];
+      dst.val[q] = src.val[q];
+    }
+  }
+}
+
+template <typename T>
+void launch_copy_cols(Cols<T> src, Cols<T> dst, int64_t n, const int64_t* total,
+                      const DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_cols<T>, dim3(2048), dim3(256), 0, s, src, dst, n, total, st);
+}
+
+// ============================================================================
 // merge (SpGEAM) + symmetrize + small-entry drop + per-column thresholds
 // ============================================================================
 //
@@ -1848,6 +2083,14 @@ void launch_flip(int which, DevState* st, hipStream_t s) {
                                 hipStream_t);                                                     \
   template void launch_dots<T>(const Csr&, Cols<T>, Pair<T>, int, int, int, double*, BigList,     \
                                DevState*, Tile, Tile, Tile, hipStream_t);                         \
+  template void launch_bound_impl<T>(const Csr&, Cols<T>, Cols<T>, Pair<T>, int, int64_t*,       \
+                                     int64_t, const DevState*, hipStream_t);                      \
+  template void launch_resid_impl<T>(const Csr&, Cols<T>, Cols<T>, Pair<T>, int, int, const Seg&, \
+                                     const int64_t*, const int64_t*, Cols<T>, Cols<T>, int,       \
+                                     double*, double*, BigList, DevState*, Tile, Tile, Tile,      \
+                                     hipStream_t);                                                \
+  template void launch_copy_cols<T>(Cols<T>, Cols<T>, int64_t, const int64_t*, const DevState*,   \
+                                    hipStream_t);                                                 \
   template void launch_bound_update<T>(const Csr&, Pair<T>, Cols<T>, Pair<T>, Pair<T>, UpdMode,   \
                                        int64_t*, int64_t, const DevState*, hipStream_t);          \
   template void launch_update<T>(const Csr&, Pair<T>, Cols<T>, Pair<T>, Pair<T>, UpdMode,         \

@@ -47,14 +47,14 @@ class OptsT(C.Structure):
     _fields_ = [("precision", C.c_int), ("symmetrize", C.c_int), ("drop_tol", C.c_double),
                 ("tie_eta", C.c_double), ("stream", C.c_void_p),
                 ("device_pool_limit", C.c_int64), ("profile", C.c_int), ("a_format", C.c_int),
-                ("jacobi", C.c_int)]
+                ("jacobi", C.c_int), ("explicit_residual", C.c_int)]
 
 
 EXPORTS = [
     "spai_default_opts", "spai_create", "spai_iterate", "spai_get", "spai_stats",
     "spai_destroy", "pcg_solve", "spai_loss_fwd", "spai_loss_bwd", "spai_create_batched",
     "spai_batched_resid", "spai_last_error", "spai_status_string", "spai_reset", "spai_pcg",
-    "spai_profile",
+    "spai_profile", "spai_spectrum", "spai_csr_spectrum",
 ]
 A_FORMATS = {"auto": 0, "csr": 1, "ell": 2}
 PHASES = ["dots", "update", "resid", "select", "compact", "bounds", "scalar", "pcg"]
@@ -100,6 +100,9 @@ def load():
     lib.spai_reset.argtypes = [P]
     lib.spai_pcg.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int, P, P, C.c_int]
     lib.spai_profile.argtypes = [P, P, P, P]
+    lib.spai_spectrum.argtypes = [P, C.c_int, P, C.c_int, P, C.POINTER(C.c_int)]
+    lib.spai_csr_spectrum.argtypes = [C.POINTER(CsrT), C.c_int, P, P, C.POINTER(C.c_int),
+                                      C.POINTER(OptsT)]
     lib.spai_last_error.restype = C.c_char_p
     lib.spai_status_string.restype = C.c_char_p
     lib.spai_status_string.argtypes = [C.c_int]
@@ -181,6 +184,7 @@ class Options:
     profile: bool = False
     a_format: str = "auto"      # layout of A on the device: "auto", "csr" or "ell"
     jacobi: bool = False        # Pi = D_A^{-1}-weighted variants (Algorithms 5, 7, 8)
+    explicit_residual: bool = True   # False: the update formulas, no dropping (Section 6.2)
 
     def c(self):
         o = OptsT()
@@ -194,6 +198,7 @@ class Options:
         o.profile = 1 if self.profile else 0
         o.a_format = A_FORMATS[self.a_format]
         o.jacobi = 1 if self.jacobi else 0
+        o.explicit_residual = 1 if self.explicit_residual else 0
         return o
 
 
@@ -306,6 +311,22 @@ class SPAI:
                 {k: int(v) for k, v in zip(PHASES, calls)},
                 {k: int(v) for k, v in zip(COUNTS, counts)})
 
+    def spectrum(self, v0, steps=100):
+        """Extreme Ritz values of the current M after up to `steps` Lanczos steps from v0
+        (numpy on the host or a torch CUDA tensor): (theta_min, theta_max, res_min,
+        res_max, steps taken); each theta is within its res of an eigenvalue of M."""
+        out = np.zeros(4, dtype=np.float64)
+        done = C.c_int(0)
+        if isinstance(v0, np.ndarray):
+            v = np.ascontiguousarray(v0, dtype=np.float64)
+            ptr, dev = v.ctypes.data, 0
+        else:
+            v = v0.to(dtype=_torch().float64).contiguous()
+            ptr, dev = v.data_ptr(), 1
+        _check(load().spai_spectrum(self.h, int(steps), ptr, dev, out.ctypes.data,
+                                    C.byref(done)))
+        return float(out[0]), float(out[1]), float(out[2]), float(out[3]), done.value
+
     def batched_resid(self):
         out = np.zeros(self.nseg, dtype=np.float64)
         _check(load().spai_batched_resid(self.h, out.ctypes.data))
@@ -354,6 +375,24 @@ def pcg_solve(A, M, B, rtol=1e-8, max_iter=10000, options: Options | None = None
                        int(max_iter), iters.ctypes.data, relres.ctypes.data, C.byref(opts))
     _check(rc, (SPAI_OK, SPAI_MAXITER, PCG_INDEFINITE))
     return X, iters, relres, rc
+
+
+def spectrum(S, v0, steps=100, options: Options | None = None):
+    """Extreme Ritz values of an exactly symmetric CSR matrix S (scipy on the host with a
+    numpy v0, or torch CSR on the device with a device v0); returns as SPAI.spectrum."""
+    opts = (options or Options()).c()
+    s = _Csr(S)
+    out = np.zeros(4, dtype=np.float64)
+    done = C.c_int(0)
+    if s.device:
+        v = v0.to(dtype=_torch().float64).contiguous()
+        ptr = v.data_ptr()
+    else:
+        v = np.ascontiguousarray(v0, dtype=np.float64)
+        ptr = v.ctypes.data
+    _check(load().spai_csr_spectrum(C.byref(s.c), int(steps), ptr, out.ctypes.data,
+                                    C.byref(done), C.byref(opts)))
+    return float(out[0]), float(out[1]), float(out[2]), float(out[3]), done.value
 
 
 def loss_fwd(A, M, options: Options | None = None) -> float:

@@ -67,6 +67,12 @@ def test_degenerate_shapes_and_options(S):
     _expect(S, -1, lambda: S.SPAI(D, "mr", options=S.Options(drop_tol=-1.0)))
     _expect(S, -1, lambda: S.SPAI(D, "mr", max_iter=-1))
     _expect(S, -1, lambda: S.SPAI(None, "mr", "global", 2.0, True, batch=[D, D]))
+    # the implicit residual update only without dropping
+    impl = dict(symmetrize=False, drop_tol=0.0, explicit_residual=False)
+    _expect(S, -1, lambda: S.SPAI(D, "mr", "global", 8, False, options=S.Options(**impl)))
+    _expect(S, -1, lambda: S.SPAI(D, "mr", options=S.Options(**{**impl, "symmetrize": True})))
+    _expect(S, -1, lambda: S.SPAI(D, "mr", options=S.Options(**{**impl, "drop_tol": 1e-16})))
+    _expect(S, -1, lambda: S.SPAI(None, "mr", batch=[D, D], options=S.Options(**impl)))
 
 
 def test_c_level_option_checks(S):
@@ -75,10 +81,16 @@ def test_c_level_option_checks(S):
     lib = S.load()
     D = sp.identity(4, format="csr") * 2.0
     a = S._Csr(D)
-    for field, bad in (("jacobi", 2), ("a_format", 7), ("precision", 9)):
+    for field, bad in (("jacobi", 2), ("a_format", 7), ("precision", 9),
+                       ("explicit_residual", 3)):
         o = S.Options().c()
         setattr(o, field, bad)
         h = C.c_void_p()
         rc = lib.spai_create(C.byref(a.c), S.METHODS["mr"], S.cap("none", 0.0, False), 10, 0.0,
                              C.byref(o), C.byref(h))
         assert rc == -1, field
+
+
+def test_spectrum_rejects_unsymmetric_matrix_on_host(S):
+    A = sp.csr_matrix(np.array([[2.0, 1.0], [0.5, 2.0]]))
+    _expect(S, -2, lambda: S.spectrum(A, np.ones(2), steps=2))

@@ -153,3 +153,21 @@ def test_loss_autograd_function():
     assert float(L) == pytest.approx(O.loss(A, M), rel=1e-12)
     assert np.max(np.abs(a.grad.cpu().numpy() - oA.data)) <= 1e-10 * np.max(np.abs(oA.data))
     assert np.max(np.abs(m.grad.cpu().numpy() - oM.data)) <= 1e-10 * np.max(np.abs(oM.data))
+
+
+def test_lognormal96_spectrum_of_a_against_oracle_lanczos():
+    """Lanczos on the full-size A (n = 884,736): the same 40 steps as the oracle from the
+    same start vector; the Ritz values agree and bracket what the Gershgorin discs allow."""
+    S = _spai()
+    A = W.workload("lognormal96").A
+    n = A.shape[0]
+    v0 = np.random.default_rng(96).standard_normal(n)
+    g = S.spectrum(A, v0, steps=40)
+    o = O.lanczos(A, 40, v0)
+    scale = max(abs(o[0]), abs(o[1]))
+    print("gpu", g, "oracle", o)
+    assert g[4] == o[4] == 40
+    assert abs(g[0] - o[0]) <= 1e-9 * scale and abs(g[1] - o[1]) <= 1e-9 * scale
+    d = A.diagonal()
+    radius = np.asarray(abs(A).sum(axis=1)).ravel() - np.abs(d)
+    assert np.min(d - radius) - 1e-9 * scale <= g[0] <= g[1] <= np.max(d + radius) + 1e-9 * scale

@@ -518,3 +518,134 @@ def test_batched_jacobi_parity(method):
         assert value_err(blk, ref.M) <= 1e-9
         off += n
     assert Mg[:mats[0].shape[0], mats[0].shape[0]:].nnz == 0
+
+
+# ----------------------------------------------------------------------------
+# implicit residual update without dropping (the printed Algorithms 1, 3, 4, 5, 7, 8)
+# ----------------------------------------------------------------------------
+
+IMPLICIT = dict(symmetrize=False, drop_tol=0.0, explicit_residual=False)
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+@pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
+@pytest.mark.parametrize("name,make,iters", [("laplace8", lambda: W.laplace2d(8), 14),
+                                             ("lognormal5", lambda: W.lognormal3d(5, 9), 10),
+                                             ("geo400", lambda: W.geometric_graph(400, 3), 6)])
+def test_implicit_residual_parity(name, make, iters, method, jacobi):
+    """R_{i+1} = R_i - alpha A P_i on the GPU against the oracle's implicit runs; the
+    iterates fill in (no dropping) until some columns leave the small tile."""
+    S = _spai()
+    A = make()
+    h = S.SPAI(A, method, "none", 0, False, max_iter=iters,
+               options=S.Options(jacobi=jacobi, **IMPLICIT))
+    r0 = h.stats()["resid"]
+    done, hist, rc = h.iterate(iters)
+    Mg = h.get()
+    h.close()
+    rule = O.DropRule.no_drop()
+    if jacobi:
+        ref = O.run_spd(method, A, O.jacobi(A), rule, iters, explicit=False)
+    else:
+        ref = O.run(method, A, rule, iters, explicit=False)
+    assert r0 == pytest.approx(ref.resid[0], rel=1e-14)
+    assert done == ref.iters == iters
+    assert rel_err(hist, ref.resid[1:]) <= 1e-9
+    assert pattern_diff(Mg, ref.M) == (set(), set())
+    assert value_err(Mg, ref.M) <= 1e-9
+    # no symmetrization: M is not symmetric once A's diagonal varies
+    # the explicit residual of the same handle type agrees up to the drift of the updates
+    h = S.SPAI(A, method, "none", 0, False, max_iter=iters,
+               options=S.Options(jacobi=jacobi, symmetrize=False, drop_tol=0.0))
+    _, hist_e, _ = h.iterate(iters)
+    h.close()
+    assert rel_err(hist_e, hist) <= 1e-7
+
+
+def test_implicit_residual_mixed_precision():
+    """FP32 storage under the implicit update: the residual recurrence in FP32 values,
+    sums in FP64, against the FP64 oracle."""
+    S = _spai()
+    A = W.lognormal3d(6, 4)
+    h = S.SPAI(A, "lomr", "none", 0, False, max_iter=8,
+               options=S.Options(precision="mixed", jacobi=True, **IMPLICIT))
+    _, hist, _ = h.iterate(8)
+    h.close()
+    ref = O.run_spd("lomr", A, O.jacobi(A), O.DropRule.no_drop(), 8, explicit=False)
+    assert rel_err(hist, ref.resid[1:]) <= TOL_MIXED
+
+
+# ----------------------------------------------------------------------------
+# spectrum of M: Lanczos with full reorthogonalisation
+# ----------------------------------------------------------------------------
+
+def test_spectrum_exact_with_n_steps():
+    """n steps (or an invariant subspace) on the 12 x 12 Laplacian: the extreme Ritz
+    values are the closed-form extreme eigenvalues."""
+    S = _spai()
+    A = W.laplace2d(12)
+    n = A.shape[0]
+    v0 = np.random.default_rng(1).standard_normal(n)
+    t0, t1, r0, r1, k = S.spectrum(A, v0, steps=400)
+    lo, hi = O.extreme_eigenvalues(A)
+    assert k <= n
+    assert t0 == pytest.approx(lo, rel=1e-10) and t1 == pytest.approx(hi, rel=1e-10)
+    o = O.lanczos(A, 400, v0)
+    assert o[4] == k
+
+
+@pytest.mark.parametrize("steps", [1, 2, 25, 80])
+@pytest.mark.parametrize("name", ["lognormal10", "geo900"])
+def test_spectrum_matches_oracle_lanczos(name, steps):
+    """The same Lanczos steps as the oracle from the same start vector: the Ritz values
+    agree, lie inside the spectrum and within their residual bounds of eigenvalues."""
+    S = _spai()
+    A = W.lognormal3d(10, 3) if name == "lognormal10" else W.geometric_graph(900, 2)
+    n = A.shape[0]
+    v0 = np.random.default_rng(steps).standard_normal(n)
+    g = S.spectrum(A, v0, steps=steps)
+    o = O.lanczos(A, steps, v0)
+    scale = max(abs(o[0]), abs(o[1]))
+    assert g[4] == o[4] == steps
+    assert abs(g[0] - o[0]) <= 1e-9 * scale and abs(g[1] - o[1]) <= 1e-9 * scale
+    assert abs(g[2] - o[2]) <= 1e-7 * scale and abs(g[3] - o[3]) <= 1e-7 * scale
+    w = np.linalg.eigvalsh(A.toarray())
+    assert w[0] - 1e-9 * scale <= g[0] <= g[1] <= w[-1] + 1e-9 * scale
+    assert np.min(np.abs(w - g[0])) <= g[2] + 1e-9 * scale
+    assert np.min(np.abs(w - g[1])) <= g[3] + 1e-9 * scale
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_handle_spectrum_of_the_iterate(precision):
+    """spai_spectrum on the handle's device-resident M equals spai_csr_spectrum on the
+    exported M bit for bit, and matches the oracle's M's extreme eigenvalues."""
+    S = _spai()
+    A = W.lognormal3d(8, 17)
+    n = A.shape[0]
+    h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=10,
+               options=S.Options(precision=precision))
+    h.iterate(10)
+    Mg = h.get()
+    v0 = np.random.default_rng(3).standard_normal(n)
+    g = h.spectrum(v0, steps=n)
+    h.close()
+    c = S.spectrum(Mg, v0, steps=n)
+    assert g == c
+    ref = O.lomr(A, oracle_rule(A, "global", 2.0, True), 10)
+    lo, hi = O.extreme_eigenvalues(ref.M)
+    tol = 1e-7 if precision == "f64" else 1e-4
+    assert g[0] == pytest.approx(lo, rel=tol, abs=tol * abs(hi))
+    assert g[1] == pytest.approx(hi, rel=tol)
+
+
+def test_spectrum_argument_errors():
+    S = _spai()
+    A = W.laplace2d(6)
+    with pytest.raises(S.SpaiError):
+        S.spectrum(A, np.zeros(A.shape[0]), steps=5)            # zero start vector
+    with pytest.raises(S.SpaiError):
+        S.spectrum(A, np.ones(A.shape[0]), steps=0)
+    h = S.SPAI(A, "mr", "none", 0, False, max_iter=2, options=S.Options(**IMPLICIT))
+    with pytest.raises(S.SpaiError):
+        h.spectrum(np.ones(A.shape[0]), steps=5)                # M not symmetrized
+    h.close()
