@@ -38,6 +38,13 @@ GPU library's options):
   2x2 Gram determinant) take the MR step (gamma = 0).
 * Stop when ||I - A M_i||_F / sqrt(n) <= tol (the "backward error" of
   Section 7.2; Tables 5-6 are consistent with this scaling).
+* Heuristic drop score (Appendix A, optional, global cap only): the entries of
+  the symmetrized, small-dropped M~ are ranked by the effect of dropping them on
+  ||I - A M~||_F^2, s_kl = m_kl^2 ||A e_k||^2 + 2 m_kl (A R~)_kl with R~ = I - A M~
+  (the derivation's square kept; the printed rule lacks it), and since M stays
+  symmetric they are dropped in symmetric pairs ranked by s_kl + s_lk, which is
+  exactly the effect of dropping that pair alone.  Ties as above with the band
+  sigma > t + eta |t| (scores may be negative).
 * Pi-weighted variants (Section 5): the MR step of Algorithm 5 has numerator
   (Z, A Z), the one the Pi^{-1}-weighted product gives and Algorithm 8 uses at
   i = 0 (the printed (Z, Pi A Z) is read as a typo); their drop rules are the
@@ -56,7 +63,7 @@ __all__ = [
     "drop_main", "drop_direction", "mr", "cg", "lomr", "run", "pcg", "pcg_block",
     "loss", "loss_grad", "OracleBreakdown", "column_residual", "row_residual",
     "grad_m_entry", "grad_a_entry", "jacobi", "mr_spd", "cg_spd", "lomr_spd", "run_spd",
-    "extreme_eigenvalues", "lanczos",
+    "extreme_eigenvalues", "lanczos", "heuristic_scores", "pair_scores",
 ]
 
 UNIT_ROUNDOFF = 2.0 ** -53
@@ -117,7 +124,9 @@ class DropRule:
     ``k`` the per-column caps (array of length n), as produced by
     :func:`cap_counts`.  ``u`` is the small-entry threshold of Appendix A
     step 2 (0 disables it), ``eta`` the tie band, ``symmetrize`` Appendix A
-    step 1.
+    step 1.  ``score`` (global cap only): rank the entries of M by the heuristic
+    of Appendix A (:func:`heuristic_scores`, :func:`pair_scores`) instead of by
+    magnitude; the drop of P stays hard thresholding.
     """
     mode: str = "none"
     m: int = 0
@@ -125,6 +134,7 @@ class DropRule:
     u: float = UNIT_ROUNDOFF
     eta: float = 1e-9
     symmetrize: bool = True
+    score: bool = False
 
     @staticmethod
     def no_drop() -> "DropRule":
@@ -176,8 +186,36 @@ def _from_entries(rows, cols, vals, shape):
     return _csc(sp.csc_matrix((vals, (rows, cols)), shape=shape))
 
 
-def drop_main(X, rule: DropRule) -> sp.csc_matrix:
-    """D_M: the drop rule on the main iterate (Appendix A steps 1-3 + Section 6.1)."""
+def heuristic_scores(A, X) -> sp.csc_matrix:
+    """The effect on ||R||_F^2 of dropping each stored entry of X alone (Appendix A):
+    s_kl = m_kl^2 ||A e_k||_2^2 + 2 m_kl (A R)_kl with R = I - A X, on X's pattern.
+    The square on m_kl is the one the derivation carries (the printed selection rule
+    omits it).  Dropping one entry per column changes ||R||_F^2 by exactly the sum of
+    these; entries of one column also couple through (A e_k)^T (A e_r)."""
+    A = sp.csr_matrix(A)
+    X = _csc(X)
+    R = residual(A, X)
+    AR = sp.csr_matrix(A @ R)
+    colnorm2 = np.asarray(A.multiply(A).sum(axis=0)).ravel()      # ||A e_k||_2^2
+    rows, cols, vals = _entries(X)
+    ar = np.asarray(AR[rows, cols]).ravel()
+    return _csc(sp.csc_matrix((vals * vals * colnorm2[rows] + 2.0 * vals * ar, (rows, cols)),
+                              shape=X.shape))
+
+
+def pair_scores(A, X) -> sp.csc_matrix:
+    """For a symmetric X: sigma_kl = s_kl + s_lk, the effect on ||R||_F^2 of dropping the
+    symmetric pair {(k, l), (l, k)} alone (its two entries lie in different columns, so
+    they do not couple); on the diagonal, s_kk itself."""
+    Sc = heuristic_scores(A, X)
+    P = _csc(Sc + Sc.T)
+    P.setdiag(Sc.diagonal())
+    return _csc(P)
+
+
+def drop_main(X, rule: DropRule, A=None) -> sp.csc_matrix:
+    """D_M: the drop rule on the main iterate (Appendix A steps 1-3 + Section 6.1).
+    With rule.score the cap of step 3 ranks by the pair scores of Appendix A (A needed)."""
     X = _csc(X)
     n = X.shape[0]
     if rule.symmetrize:                                  # step 1: M := (M + M^T) / 2
@@ -193,10 +231,21 @@ def drop_main(X, rule: DropRule) -> sp.csc_matrix:
             b = rule.m - ndiag
             if b < 0:
                 raise ValueError("cap below the number of diagonal entries")
-            mags = np.abs(vals[keep & ~diag])
-            if len(mags) > b:
-                t = np.sort(mags)[::-1][b]
-                keep &= diag | (np.abs(vals) > t * (1.0 + rule.eta))
+            if rule.score:
+                if not rule.symmetrize:
+                    raise ValueError("the score drops symmetric pairs: symmetrize first")
+                Xk = _from_entries(rows[keep], cols[keep], vals[keep], X.shape)
+                Sg = pair_scores(A, Xk)
+                sig = np.asarray(Sg[rows, cols]).ravel()
+                cand = sig[keep & ~diag]
+                if len(cand) > b:
+                    t = np.sort(cand)[::-1][b]
+                    keep &= diag | (sig > t + rule.eta * abs(t))
+            else:
+                mags = np.abs(vals[keep & ~diag])
+                if len(mags) > b:
+                    t = np.sort(mags)[::-1][b]
+                    keep &= diag | (np.abs(vals) > t * (1.0 + rule.eta))
     elif rule.mode == "column":
         k = np.asarray(rule.k, dtype=np.int64)
         if np.any(k < 1):
@@ -271,7 +320,7 @@ def mr(A, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = True
             break
         r_ar = frob(R, AR)
         alpha = r_ar / ar_ar
-        M = drop_main(M + alpha * R, rule)
+        M = drop_main(M + alpha * R, rule, A)
         R = residual(A, M) if explicit else _csc(R - alpha * AR)
         out.scalars.append({"alpha": alpha, "r_ar": r_ar, "ar_ar": ar_ar})
         out.resid.append(fnorm(R))
@@ -315,7 +364,7 @@ def cg(A, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = True
             out.status = "breakdown"
             break
         alpha = rr / p_ap
-        M = drop_main(M + alpha * P, rule)
+        M = drop_main(M + alpha * P, rule, A)
         R = residual(A, M) if explicit else _csc(R - alpha * AP)
         rr_new = frob(R, R)
         beta = rr_new / rr
@@ -377,7 +426,7 @@ def lomr(A, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = Tr
         r_ap = frob(R, AP)
         ap_ap = frob(AP, AP)
         delta, gamma, fell_back = lomr_coefficients(r_ar, ar_ar, ar_ap, r_ap, ap_ap, i == 0)
-        M = drop_main(M + delta * R + gamma * P, rule)
+        M = drop_main(M + delta * R + gamma * P, rule, A)
         Rnew = residual(A, M) if explicit else _csc(R - delta * AR - gamma * AP)
         P = drop_direction(delta * R + gamma * P, rule)
         R = Rnew
@@ -436,7 +485,7 @@ def mr_spd(A, Pi, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: boo
             break
         z_az = frob(Z, AZ)
         alpha = z_az / az_paz
-        M = drop_main(M + alpha * Z, rule)
+        M = drop_main(M + alpha * Z, rule, A)
         R = residual(A, M) if explicit else _csc(R - alpha * AZ)
         out.scalars.append({"alpha": alpha, "z_az": z_az, "az_paz": az_paz})
         out.resid.append(fnorm(R))
@@ -483,7 +532,7 @@ def cg_spd(A, Pi, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: boo
             out.status = "breakdown"
             break
         alpha = rz / p_ap
-        M = drop_main(M + alpha * P, rule)
+        M = drop_main(M + alpha * P, rule, A)
         R = residual(A, M) if explicit else _csc(R - alpha * AP)
         Z = _csc(Pi @ R)
         rz_new = frob(R, Z)
@@ -540,7 +589,7 @@ def lomr_spd(A, Pi, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: b
         z_ap = frob(Z, AP)
         ap_pap = frob(AP, PAP)
         delta, gamma, fell_back = lomr_coefficients(z_az, az_paz, az_pap, z_ap, ap_pap, i == 0)
-        M = drop_main(M + delta * Z + gamma * P, rule)
+        M = drop_main(M + delta * Z + gamma * P, rule, A)
         Rnew = residual(A, M) if explicit else _csc(R - delta * AZ - gamma * AP)
         P = drop_direction(delta * Z + gamma * P, rule)
         R = Rnew

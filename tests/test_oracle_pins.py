@@ -691,3 +691,87 @@ def test_lanczos_pins():
     assert np.min(np.abs(w - t0)) <= r0 * (1 + 1e-9) + 1e-12
     assert np.min(np.abs(w - t1)) <= r1 * (1 + 1e-9) + 1e-12
     assert t1 == pytest.approx(w[-1], rel=1e-3)
+
+
+# ----------------------------------------------------------------------------
+# heuristic drop score of Appendix A
+# ----------------------------------------------------------------------------
+
+def _sym_iterate(A, seed, density=0.15):
+    """A symmetric M with a full diagonal and random off-diagonal entries."""
+    n = A.shape[0]
+    rng = np.random.default_rng(seed)
+    B = sp.random(n, n, density=density, random_state=rng, format="csc")
+    B.data = rng.standard_normal(B.nnz) * 0.05
+    return sp.csc_matrix(B + B.T + sp.diags(rng.uniform(0.1, 0.3, n)))
+
+
+def _fro2(A, M):
+    return O.fnorm(O.residual(A, M)) ** 2
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_heuristic_score_is_the_exact_effect_of_one_drop(seed):
+    """Dropping one entry changes ||R||_F^2 by exactly s_kl; dropping a symmetric pair by
+    exactly s_kl + s_lk; two entries of one column couple through 2 m m' (Ae_k)^T(Ae_r)."""
+    A = W.lognormal3d(3, 40 + seed)
+    M = _sym_iterate(A, seed)
+    base = _fro2(A, M)
+    Sc = O.heuristic_scores(A, M)
+    Sg = O.pair_scores(A, M)
+    rows, cols, vals = O._entries(M)
+    Acsc = sp.csc_matrix(A)
+    rng = np.random.default_rng(seed)
+    for q in rng.choice(len(vals), 12, replace=False):
+        k, l, m = rows[q], cols[q], vals[q]
+        E = sp.csc_matrix(([m], ([k], [l])), shape=M.shape)
+        d1 = _fro2(A, M - E) - base
+        assert d1 == pytest.approx(Sc[k, l], rel=1e-9, abs=1e-12 * base)
+        if k != l:
+            E2 = E + E.T
+            d2 = _fro2(A, M - E2) - base
+            assert d2 == pytest.approx(Sg[k, l], rel=1e-9, abs=1e-12 * base)
+            assert Sg[k, l] == Sg[l, k]
+    # coupling inside a column: eq. with the (A e_k)^T (A e_r) term
+    col = M[:, 5].tocoo()
+    k, r = col.row[0], col.row[1]
+    mk, mr = M[k, 5], M[r, 5]
+    E = sp.csc_matrix(([mk, mr], ([k, r], [5, 5])), shape=M.shape)
+    d = _fro2(A, M - E) - base
+    cpl = 2.0 * mk * mr * float((Acsc[:, k].T @ Acsc[:, r]).toarray()[0, 0])
+    assert d == pytest.approx(Sc[k, 5] + Sc[r, 5] + cpl, rel=1e-9, abs=1e-12 * base)
+
+
+def test_score_drop_keeps_the_best_pairs_brute_force():
+    """The score cap keeps the diagonal and the b/2 symmetric pairs of largest pair
+    score: the set an exhaustive search over the pairs to keep finds when it maximises
+    the summed pair scores (= minimises the summed effects of the dropped pairs)."""
+    import itertools
+    A = W.lognormal3d(2, 8)
+    n = A.shape[0]
+    M = _sym_iterate(A, 11, density=0.3)
+    rows, cols, vals = O._entries(M)
+    pairs = sorted({(min(a, b), max(a, b)) for a, b in zip(rows, cols) if a != b})
+    Sg = O.pair_scores(A, M)
+    assert len(pairs) >= 8 and len({Sg[a, b] for a, b in pairs}) == len(pairs)   # no ties
+    differs = []
+    for keep_pairs in (1, 3, len(pairs) // 2):
+        m = n + 2 * keep_pairs
+        got = O.drop_main(M, O.DropRule(mode="global", m=m, u=0.0, score=True), A).tocoo()
+        best = max(itertools.combinations(pairs, keep_pairs),
+                   key=lambda ks: sum(Sg[a, b] for a, b in ks))
+        want = {(a, b) for a, b in best} | {(b, a) for a, b in best} | {(i, i) for i in range(n)}
+        assert set(zip(got.row.tolist(), got.col.tolist())) == want
+        mag = O.drop_main(M, O.DropRule(mode="global", m=m, u=0.0), A).tocoo()
+        assert len(mag.row) == len(got.row)
+        differs.append(set(zip(mag.row.tolist(), mag.col.tolist())) != want)
+    assert any(differs)                   # the score is not the magnitude rule in disguise
+
+
+def test_score_drop_run_stays_symmetric_and_capped():
+    A = W.lognormal3d(5, 3)
+    rule = O.DropRule(mode="global", m=O.cap_counts(A, "global", 2.0, True), score=True)
+    for meth in ("mr", "cg", "lomr"):
+        r = O.run(meth, A, rule, 6)
+        assert r.M.nnz <= rule.m and abs(r.M - r.M.T).max() == 0.0
+        assert r.resid[-1] < r.resid[0]
