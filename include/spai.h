@@ -126,6 +126,16 @@ typedef struct {
                                it requires SPAI_CAP_NONE, drop_tol = 0 and
                                symmetrize = 0 (else SPAI_ERR_ARG); not for batched
                                handles                                             */
+  int drop_score;           /* 1: the global cap of M ranks its candidates by the
+                               heuristic of Appendix A instead of by magnitude: with
+                               M~ the symmetrized, small-dropped candidates and
+                               R~ = I - A M~, s_kl = m_kl^2 ||A e_k||^2 +
+                               2 m_kl (A R~)_kl is the change of ||R~||_F^2 from
+                               dropping m_kl alone; off-diagonal entries are kept or
+                               dropped in symmetric pairs ranked by s_kl + s_lk
+                               (keep score > t + tie_eta |t|, t the (b+1)-th largest).
+                               P keeps hard thresholding.  Requires SPAI_CAP_GLOBAL
+                               and symmetrize = 1; default 0                      */
 } spai_opts_t;
 
 /* Fill *opts with the defaults. */

@@ -220,6 +220,8 @@ struct Engine : EngineBase {
   Tile tRs{128, 512}, tRl{1024, 4096}, tDs{256, 512}, tDl{1024, 4096}, tUs{384, 512},
       tUl{2048, 4096};
   Tile tRh{0, 0}, tDh{0, 0}, tUh{0, 0};   // huge tiles (device-memory scratch), sized from n
+  Tile tSs{128, 1024}, tSl{1024, 8192}, tSh{0, 0};   // heuristic-score tiles
+  double *score = nullptr, *sigma = nullptr;          // per-candidate scores and pair sums
   int32_t* d_order = nullptr;             // locality order of the rows (breadth-first balls)
   int hist_cap = 0;
   int iters_host = 0;
@@ -484,8 +486,10 @@ struct Engine : EngineBase {
       tRh = Tile{(int)Lr, (int)Hk};
       tDh = Tile{(int)Ld, (int)Hk};
       tUh = Tile{(int)Lu, (int)Hk, (int)std::max<int64_t>(256, p2(maxdeg))};
+      tSh = Tile{(int)Lr, (int)Hk};
       int64_t stride = (int64_t)std::max({resid_tile_bytes(tRh, ell), dots_tile_bytes(tDh, ell),
                                           update_tile_bytes(tUh)});
+      if (opts.drop_score) stride = std::max<int64_t>(stride, (int64_t)score_tile_bytes(tSh, ell));
       stride = (stride + 255) / 256 * 256;
       char* scr;
       if ((rc = dalloc(&scr, stride * kHugeGrid))) return rc;
@@ -496,6 +500,7 @@ struct Engine : EngineBase {
     }
     if (global) {
       if ((rc = dalloc(&selhist, 8192)) || (rc = dalloc(&selbuf, capU))) return rc;
+      if (opts.drop_score && ((rc = dalloc(&score, capU)) || (rc = dalloc(&sigma, capU)))) return rc;
     }
     prof = opts.profile != 0 && !batched_graph;
     return init_iterate();
@@ -704,15 +709,18 @@ struct Engine : EngineBase {
     launch_update<T>(A, M, R, P, PT, md, off, total, kcol, tM, tP, big[2], seg, st, tUs, tUl, tUh,
                      s);
     te();
+    const double* keyM = (global && md.doM && score) ? sigma : nullptr;
     if (global) {
       tb(SPAI_PH_SELECT);
-      if (md.doM) launch_global_select<T>(M, 1, m_global, opts.tie_eta, 0, selhist, selbuf, n, st, s);
+      if (keyM) launch_score<T>(A, M, score, sigma, big[2], st, tSs, tSl, tSh, n, s);
+      if (md.doM)
+        launch_global_select<T>(M, 1, m_global, opts.tie_eta, 0, selhist, selbuf, n, st, s, keyM);
       if (md.doP) launch_global_select<T>(P, 0, m_global, opts.tie_eta, 1, selhist, selbuf, n, st, s);
       te();
     }
     tb(SPAI_PH_COMPACT);
     if (md.doM) {
-      launch_compact<T>(M, 0, colcap, md.sym, global, tM, opts.tie_eta, n, st, s);
+      launch_compact<T>(M, 0, colcap, md.sym, global, tM, opts.tie_eta, n, st, s, keyM);
       launch_flip(0, st, s);
     }
     if (md.doP) {
@@ -751,6 +759,7 @@ struct Engine : EngineBase {
     HIPCHK(hipMemcpy(&h, st, sizeof(DevState), hipMemcpyDeviceToHost));
     if (h.err & 1) return fail(SPAI_ERR_CAPACITY, "a column exceeded the largest per-column tile");
     if (h.err & 2) return fail(SPAI_ERR_NOMEM, "an iterate exceeded its device pool");
+    if (h.err & 4) return fail(SPAI_ERR_HIP, "internal: candidate pattern not symmetric");
     return SPAI_OK;
   }
 
@@ -919,6 +928,7 @@ static void fill_defaults(spai_opts_t* o) {
   o->a_format = SPAI_AFMT_AUTO;
   o->jacobi = 0;
   o->explicit_residual = 1;
+  o->drop_score = 0;
 }
 
 template <typename T>
@@ -963,6 +973,9 @@ static int check_common(int method, spai_cap_t cap, int max_iter, double tol,
                 "the implicit residual needs no dropping: no cap, drop_tol 0, symmetrize 0");
   if (o.a_format != SPAI_AFMT_AUTO && o.a_format != SPAI_AFMT_CSR && o.a_format != SPAI_AFMT_ELL)
     return fail(SPAI_ERR_ARG, "unknown a_format");
+  if (o.drop_score != 0 && o.drop_score != 1) return fail(SPAI_ERR_ARG, "drop_score must be 0 or 1");
+  if (o.drop_score && (cap.mode != SPAI_CAP_GLOBAL || !o.symmetrize))
+    return fail(SPAI_ERR_ARG, "the heuristic drop score needs a global cap and symmetrize = 1");
   return SPAI_OK;
 }
 

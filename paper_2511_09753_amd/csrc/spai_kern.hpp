@@ -154,17 +154,27 @@ size_t resid_tile_bytes(Tile t, bool ell);
 size_t dots_tile_bytes(Tile t, bool ell);
 size_t update_tile_bytes(Tile t);
 
-// global cap: exact (b+1)-th largest magnitude among the candidates in X.nxt()
+// global cap: exact (b+1)-th largest magnitude among the candidates in X.nxt() (score
+// non-null: the (b+1)-th largest of the signed scores stored beside the candidates)
 template <typename T>
 void launch_global_select(Pair<T> X, int exclude_diag, int64_t m, double eta, int which,
                           unsigned long long* hist, unsigned long long* selbuf, int64_t n,
-                          DevState* st, hipStream_t s);
+                          DevState* st, hipStream_t s, const double* score = nullptr);
+
+// Appendix A heuristic scores of the M candidates in M.nxt(): sc per entry, sig the pair
+// sums (the selection key); tiles as for the residual, sized by score_tile_bytes
+template <typename T>
+void launch_score(const Csr& A, Pair<T> M, double* sc, double* sig, BigList big, DevState* st,
+                  Tile small, Tile large, Tile huge, int64_t n, hipStream_t s);
+size_t score_tile_bytes(Tile t, bool ell);
 
 // keep rule + in-place compaction of the candidates in X.nxt();
-// kind 0: M (diagonal kept), 1: P (column threshold tcol[j]), 2: P^T (tcol[row])
+// kind 0: M (diagonal kept), 1: P (column threshold tcol[j]), 2: P^T (tcol[row]);
+// score non-null (global cap): keep score > threshold instead of |x| > threshold
 template <typename T>
 void launch_compact(Pair<T> X, int kind, int colcap, int sym, int global, const double* tcol,
-                    double eta, int64_t n, DevState* st, hipStream_t s);
+                    double eta, int64_t n, DevState* st, hipStream_t s,
+                    const double* score = nullptr);
 
 void launch_scal_step(int method, const Seg& seg, const double* red, DevState* st,
                       hipStream_t s);

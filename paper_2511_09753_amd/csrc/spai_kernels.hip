@@ -1516,6 +1516,17 @@ __device__ __forceinline__ unsigned long long mag_key(double v) {
   return (unsigned long long)__double_as_longlong(fabs(v));
 }
 
+// signed doubles (the heuristic drop scores) as keys that order like the values: the
+// sign bit flipped for v >= 0, every bit flipped for v < 0
+__device__ __forceinline__ unsigned long long ord_key(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+
+__device__ __forceinline__ double ord_value(unsigned long long k) {
+  return __longlong_as_double((long long)((k >> 63) ? (k & ~(1ull << 63)) : ~k));
+}
+
 // ---- grouped walk over the entries of 64 consecutive columns ----------------------
 // A one-wave workgroup takes columns j0 .. j0+63 at once: lane c holds column j0 + c's
 // start cb and length cl (loaded together) and ex, the exclusive prefix of the
@@ -1562,15 +1573,19 @@ __device__ __forceinline__ int64_t group_src(const Group64& g, int c, int x) {
   return __shfl(g.cb, c, SPAI_WAVE) + (int64_t)(x - __shfl(g.ex, c, SPAI_WAVE));
 }
 
-// exponent histogram (bits 62..52) of the candidates; counts diagonal entries apart
-template <typename T>
-__global__ __launch_bounds__(SPAI_WAVE) void k_sel_hist_exp(Pair<T> Xp, int excl_diag,
+// histogram of the top key bits (63..52; for magnitudes bit 63 is 0) of the candidates,
+// counting diagonal entries apart.  SC: the keys are the signed scores sc[] stored beside
+// the candidates instead of their magnitudes.
+template <typename T, bool SC>
+__global__ __launch_bounds__(SPAI_WAVE) void k_sel_hist_exp(Pair<T> Xp, const double* sc,
+                                                            int excl_diag,
                                                             unsigned long long* hist, int64_t n,
                                                             DevState* st) {
   if (!st->any_active || !st->iter_active) return;
-  __shared__ unsigned int h[2048];
+  constexpr int NB = SC ? 4096 : 2048;
+  __shared__ unsigned int h[NB];
   const int lane = lane_id();
-  for (int i = lane; i < 2048; i += SPAI_WAVE) h[i] = 0;
+  for (int i = lane; i < NB; i += SPAI_WAVE) h[i] = 0;
   __syncthreads();
   const Cols<T> X = Xp.nxt();
   long long diag = 0;
@@ -1580,19 +1595,21 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_sel_hist_exp(Pair<T> Xp, int excl
     for (int x0 = 0; x0 < g.T; x0 += SPAI_WAVE * kGU) {
       int col[kGU], idx[kGU];
       T val[kGU];
+      double sv[kGU];
 #pragma unroll
       for (int u = 0; u < kGU; ++u) {
         const int x = x0 + u * SPAI_WAVE + lane;
         const int xc = min(x, g.T - 1);            // all lanes shuffle together
         const int c = group_col(g, xc);
         const int64_t src = group_src(g, c, xc);
+        sv[u] = 0.0;
         col[u] = -1;
         idx[u] = -1;
         val[u] = (T)0;
         if (x < g.T) {
           col[u] = c;
           if (excl_diag) idx[u] = X.idx[src];
-          val[u] = X.val[src];
+          if constexpr (SC) sv[u] = sc[src]; else val[u] = X.val[src];
         }
       }
 #pragma unroll
@@ -1602,12 +1619,13 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_sel_hist_exp(Pair<T> Xp, int excl
           ++diag;
           continue;
         }
-        atomicAdd(&h[(int)(mag_key((double)val[u]) >> 52)], 1u);
+        const unsigned long long key = SC ? ord_key(sv[u]) : mag_key((double)val[u]);
+        atomicAdd(&h[(int)(key >> 52)], 1u);
       }
     }
   }
   __syncthreads();
-  for (int i = lane; i < 2048; i += SPAI_WAVE)
+  for (int i = lane; i < NB; i += SPAI_WAVE)
     if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
   diag = wave_sum_ll(diag);
   if (lane == 0 && diag) atomicAdd((unsigned long long*)&st->sel_diag, (unsigned long long)diag);
@@ -1646,13 +1664,13 @@ __device__ inline void find_bin_desc(const unsigned long long* hist, int nbins, 
 
 // find the exponent bin of the (b+1)-th largest; b = m - (diagonal count if excluded)
 __global__ __launch_bounds__(1024) void k_sel_find_exp(const unsigned long long* hist,
-                                                       int excl_diag, int64_t m, double* thr,
-                                                       DevState* st) {
+                                                       int excl_diag, int64_t m, int signed_keys,
+                                                       double* thr, DevState* st) {
   if (!st->any_active || !st->iter_active) return;
   const long long b = m - (excl_diag ? st->sel_diag : 0);
   long long total, above;
   int bin;
-  find_bin_desc(hist, 2048, b + 1, &total, &bin, &above);
+  find_bin_desc(hist, signed_keys ? 4096 : 2048, b + 1, &total, &bin, &above);
   if (threadIdx.x != 0) return;
   st->sel_count = 0;
   if (b < 0) {                      // cap below the diagonal count: keep only the diagonal
@@ -1662,7 +1680,7 @@ __global__ __launch_bounds__(1024) void k_sel_find_exp(const unsigned long long*
   }
   if (total <= b) {                  // |supp| within the cap: nothing to drop
     st->sel_done = 1;
-    *thr = 0.0;
+    *thr = signed_keys ? -INFINITY : 0.0;
     return;
   }
   st->sel_prefix = (unsigned long long)bin << 52;
@@ -1673,8 +1691,9 @@ __global__ __launch_bounds__(1024) void k_sel_find_exp(const unsigned long long*
 // keys whose exponent bin is the selected one, staged in LDS (one stage per one-wave
 // workgroup) and flushed to the global buffer with one atomic reservation per flush
 constexpr int kStage = 1024;
-template <typename T>
-__global__ __launch_bounds__(SPAI_WAVE) void k_sel_collect(Pair<T> Xp, int excl_diag,
+template <typename T, bool SC>
+__global__ __launch_bounds__(SPAI_WAVE) void k_sel_collect(Pair<T> Xp, const double* sc,
+                                                           int excl_diag,
                                                            unsigned long long* selbuf,
                                                            int64_t n, DevState* st) {
   if (!st->any_active || !st->iter_active || st->sel_done) return;
@@ -1699,6 +1718,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_sel_collect(Pair<T> Xp, int excl_
       if (cnt > kStage - SPAI_WAVE * kGU) flush();
       int idx[kGU];
       T val[kGU];
+      double sv[kGU];
       bool ok[kGU];
       int col[kGU];
 #pragma unroll
@@ -1710,10 +1730,11 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_sel_collect(Pair<T> Xp, int excl_
         ok[u] = x < g.T;
         idx[u] = -1;
         val[u] = (T)0;
+        sv[u] = 0.0;
         col[u] = c;
         if (ok[u]) {
           if (excl_diag) idx[u] = X.idx[src];
-          val[u] = X.val[src];
+          if constexpr (SC) sv[u] = sc[src]; else val[u] = X.val[src];
         }
       }
 #pragma unroll
@@ -1721,7 +1742,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_sel_collect(Pair<T> Xp, int excl_
         bool take = false;
         unsigned long long key = 0;
         if (ok[u] && !(excl_diag && idx[u] == (int)(g.j0 + col[u]))) {
-          key = mag_key((double)val[u]);
+          key = SC ? ord_key(sv[u]) : mag_key((double)val[u]);
           take = (key >> 52) == want;
         }
         const unsigned long long bal = __ballot(take);
@@ -1756,7 +1777,8 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist_buf(const unsigned lon
 }
 
 __global__ __launch_bounds__(1024) void k_sel_find_buf(const unsigned long long* hist, int shift,
-                                                       double eta, double* thr, DevState* st) {
+                                                       double eta, int signed_keys, double* thr,
+                                                       DevState* st) {
   if (!st->any_active || !st->iter_active || st->sel_done) return;
   const long long rank = st->sel_rank;
   long long total, above;
@@ -1768,8 +1790,13 @@ __global__ __launch_bounds__(1024) void k_sel_find_buf(const unsigned long long*
     st->sel_rank = rank - above;
   }
   if (shift == 0) {
-    const double t = __longlong_as_double((long long)st->sel_prefix);
-    *thr = t * (1.0 + eta);
+    if (signed_keys) {                 // keep score > t + eta |t|
+      const double t = ord_value(st->sel_prefix);
+      *thr = t + eta * fabs(t);
+    } else {                           // keep |x| > t (1 + eta)
+      const double t = __longlong_as_double((long long)st->sel_prefix);
+      *thr = t * (1.0 + eta);
+    }
     st->sel_done = 1;
   }
 }
@@ -1791,21 +1818,214 @@ __global__ void k_hist_clear(unsigned long long* hist, int nbins, const DevState
 template <typename T>
 void launch_global_select(Pair<T> X, int exclude_diag, int64_t m, double eta, int which,
                           unsigned long long* hist, unsigned long long* selbuf, int64_t n,
-                          DevState* st, hipStream_t s) {
+                          DevState* st, hipStream_t s, const double* score) {
   double* thr = which == 0 ? &st->thrM : &st->thrP;
+  const int sk = score ? 1 : 0;
   hipLaunchKernelGGL(k_sel_reset, dim3(1), dim3(1024), 0, s, hist, 8192, st);
   const int ng = (int)std::min<int64_t>((n + 63) / 64, 1 << 30);
-  hipLaunchKernelGGL(k_sel_hist_exp<T>, dim3(std::min(ng, resident_grid(k_sel_hist_exp<T>, 0))),
-                     dim3(SPAI_WAVE), 0, s, X, exclude_diag, hist, n, st);
-  hipLaunchKernelGGL(k_sel_find_exp, dim3(1), dim3(1024), 0, s, hist, exclude_diag, m, thr, st);
-  hipLaunchKernelGGL(k_sel_collect<T>, dim3(std::min(ng, resident_grid(k_sel_collect<T>, 0))),
-                     dim3(SPAI_WAVE), 0, s, X, exclude_diag, selbuf, n, st);
+  if (score)
+    hipLaunchKernelGGL((k_sel_hist_exp<T, true>),
+                       dim3(std::min(ng, resident_grid(k_sel_hist_exp<T, true>, 0))),
+                       dim3(SPAI_WAVE), 0, s, X, score, exclude_diag, hist, n, st);
+  else
+    hipLaunchKernelGGL((k_sel_hist_exp<T, false>),
+                       dim3(std::min(ng, resident_grid(k_sel_hist_exp<T, false>, 0))),
+                       dim3(SPAI_WAVE), 0, s, X, score, exclude_diag, hist, n, st);
+  hipLaunchKernelGGL(k_sel_find_exp, dim3(1), dim3(1024), 0, s, hist, exclude_diag, m, sk, thr,
+                     st);
+  if (score)
+    hipLaunchKernelGGL((k_sel_collect<T, true>),
+                       dim3(std::min(ng, resident_grid(k_sel_collect<T, true>, 0))),
+                       dim3(SPAI_WAVE), 0, s, X, score, exclude_diag, selbuf, n, st);
+  else
+    hipLaunchKernelGGL((k_sel_collect<T, false>),
+                       dim3(std::min(ng, resident_grid(k_sel_collect<T, false>, 0))),
+                       dim3(SPAI_WAVE), 0, s, X, score, exclude_diag, selbuf, n, st);
   for (int shift = 39; shift >= 0; shift -= 13) {
     hipLaunchKernelGGL(k_hist_clear, dim3(1), dim3(1024), 0, s, hist, 8192, st);
     hipLaunchKernelGGL(k_sel_hist_buf, dim3(256), dim3(kSelThreads), 0, s, selbuf, shift, hist,
                        st);
-    hipLaunchKernelGGL(k_sel_find_buf, dim3(1), dim3(1024), 0, s, hist, shift, eta, thr, st);
+    hipLaunchKernelGGL(k_sel_find_buf, dim3(1), dim3(1024), 0, s, hist, shift, eta, sk, thr, st);
   }
+}
+
+// ============================================================================
+// heuristic drop score of Appendix A (global cap, optional)
+// ============================================================================
+//
+// For the candidates M~ (symmetrized, small entries dropped) in M.nxt(): per entry
+//   s_kl = m_kl^2 ||A e_k||^2 + 2 m_kl (A R~)_kl,   R~ = I - A M~,
+// the change of ||R~||_F^2 from dropping that entry alone, and per symmetric pair
+//   sigma_kl = s_kl + s_lk
+// (the change from dropping the pair; its entries lie in different columns and do not
+// couple).  Column l: r~_l = e_l - A m~_l is formed in LDS (keys sorted, values beside
+// them), then each candidate row k pulls row k of A against it, which also gives
+// ||A e_k||^2 = sum_t a_kt^2 (A symmetric).
+
+template <typename T, bool GS>
+__global__ __launch_bounds__(SPAI_WAVE) void k_score(Csr A, Pair<T> Mp, double* sc, BigList big,
+                                                     DevState* st, int tier, int L, int H) {
+  if (!st->any_active || !st->iter_active) return;
+  extern __shared__ char smem[];
+  const bool ell = A.eshift >= 0;
+  Carve cv(tile_base<GS>(smem, big));
+  int* s_mi = cv.take<int>(L);
+  int* s_keys = cv.take<int>(H);         // hash set, then the sorted rows of r~_l
+  double* s_mv = cv.take<double>(L);
+  int* s_mk = cv.take<int>(2 * L);       // position map of m~_l's rows
+  unsigned* s_mp = cv.take<unsigned>(2 * L);
+  double* s_rv = cv.take<double>(H / 2); // r~_l values beside the sorted keys
+  int* s_pre = ell ? nullptr : cv.take<int>(L);
+  int64_t* s_rs = ell ? nullptr : cv.take<int64_t>(L);
+  const int lane = lane_id();
+  const Cols<T> Mc = Mp.nxt();
+  const int limit = H / 2 - 1;
+
+  auto body = [&](int64_t j) {
+    const int64_t mb = Mc.beg[j];
+    const int lm = Mc.len[j];
+    if (lm > L) {
+      defer_column(tier, big, st, j);
+      return;
+    }
+    const int hs = next_pow2(max(2 * lm, 64));
+    ks_clear(s_keys, H);
+    lm_clear(s_mk, s_mp, hs);
+    tile_sync<GS>();
+    for (int e = lane; e < lm; e += SPAI_WAVE) {
+      const int i = Mc.idx[mb + e];
+      s_mi[e] = i;
+      s_mv[e] = (double)Mc.val[mb + e];
+      lm_put(s_mk, s_mp, hs, i, 0, e);
+    }
+    tile_sync<GS>();
+    int tot = 0;
+    if (!ell) {
+      tot = degree_prefix(A, s_mi, lm, s_pre, s_rs);
+      tile_sync<GS>();
+    }
+    int kd[1] = {lane == 0 ? (int)j : -1};
+    int nk = wave_sum_int(ks_insert_batch<1>(s_keys, H, kd));
+    nk = insert_products(A, s_mi, lm, s_pre, s_rs, tot, s_keys, H, nk, limit);
+    tile_sync<GS>();
+    if (nk > limit) {
+      defer_column(tier, big, st, j);
+      tile_sync<GS>();
+      return;
+    }
+    const int nu = ks_sort_inplace(s_keys, H);
+    tile_sync<GS>();
+    double sum[1];
+    int key[1];
+    pull_rows<1>(
+        A, s_keys, nu,
+        [&](int c, int t) {
+          sum[c] = 0.0;
+          key[c] = s_keys[t];
+        },
+        [&](int c, const int (&cols)[8], const double (&vals)[8]) {
+          unsigned pw[8];
+          lm_find<8>(s_mk, s_mp, hs, cols, pw);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const unsigned e = pw[k] & kNoPos;
+            if (e != kNoPos) sum[c] += vals[k] * s_mv[e];
+          }
+        },
+        [&](int c, int t) { s_rv[t] = ((key[c] == (int)j) ? 1.0 : 0.0) - sum[c]; });
+    tile_sync<GS>();
+    // per candidate row k: (A r~_l)_k and ||A e_k||^2 from row k of A
+    for (int e = lane; e < lm; e += SPAI_WAVE) {
+      const int k = s_mi[e];
+      const double m = s_mv[e];
+      int64_t q0, q1;
+      row_span(A, k, q0, q1);
+      double ar = 0.0, n2 = 0.0;
+      for (int64_t q = q0; q < q1; q += 8) {
+        int cols[8];
+        double vals[8];
+        load_chunk(A, q, q1, cols, vals);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          if (cols[c] < 0) continue;
+          n2 += vals[c] * vals[c];
+          const int pos = bsearch_idx(s_keys, nu, cols[c]);
+          if (pos >= 0) ar += vals[c] * s_rv[pos];
+        }
+        if (cols[7] < 0) break;
+      }
+      sc[mb + e] = (m * m) * n2 + (2.0 * m) * ar;
+    }
+    tile_sync<GS>();
+  };
+
+  if (tier == 0) {
+    ColumnWalk w(A.n, blockIdx.x, gridDim.x);
+    for (int64_t j = w.begin; j < w.end; j += w.step) body(j);
+  } else if (tier == 1) {
+    const int cnt = *big.count;
+    for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list[t]);
+  } else {
+    const int cnt = *big.count2;
+    for (int t = blockIdx.x; t < cnt; t += gridDim.x) body(big.list2[t]);
+  }
+}
+
+static size_t score_lds(Tile t, bool ell) {
+  return (size_t)t.L * 4 + (size_t)t.H * 4 + (size_t)t.L * 8 + (size_t)t.L * 16 +
+         (size_t)(t.H / 2) * 8 + (ell ? 0 : (size_t)t.L * 12) + 128;
+}
+
+size_t score_tile_bytes(Tile t, bool ell) { return score_lds(t, ell); }
+
+// sigma at entry (k, l) of the candidates: s_kl + s_lk, the partner found by binary
+// search in column k (the candidates are exactly symmetric); the diagonal keeps s_kk
+template <typename T>
+__global__ __launch_bounds__(SPAI_WAVE) void k_score_pair(Pair<T> Mp, const double* sc,
+                                                          double* sig, int64_t n,
+                                                          DevState* st) {
+  if (!st->any_active || !st->iter_active) return;
+  const Cols<T> X = Mp.nxt();
+  const int lane = lane_id();
+  const int64_t ng = (n + 63) / 64;
+  for (int64_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
+    const Group64 g = group_load(X, gi * 64, n);
+    for (int x0 = 0; x0 < g.T; x0 += SPAI_WAVE) {
+      const int x = x0 + lane;
+      const int xc = min(x, g.T - 1);              // all lanes shuffle together
+      const int c = group_col(g, xc);
+      const int64_t src = group_src(g, c, xc);
+      if (x >= g.T) continue;
+      const int l = (int)(g.j0 + c);
+      const int k = X.idx[src];
+      double v = sc[src];
+      if (k != l) {
+        const int64_t kb = X.beg[k];
+        const int p = bsearch_idx(X.idx + kb, X.len[k], l);
+        if (p >= 0) v = v + sc[kb + p];
+        else atomicOr(&st->err, 4);              // not symmetric: cannot happen
+      }
+      sig[src] = v;
+    }
+  }
+}
+
+template <typename T>
+void launch_score(const Csr& A, Pair<T> M, double* sc, double* sig, BigList big, DevState* st,
+                  Tile small, Tile large, Tile huge, int64_t n, hipStream_t s) {
+  const bool ell = A.eshift >= 0;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
+  hipLaunchKernelGGL((k_score<T, false>), dim3(resident_grid(k_score<T, false>, score_lds(small, ell))),
+                     dim3(SPAI_WAVE), score_lds(small, ell), s, A, M, sc, big, st, 0, small.L,
+                     small.H);
+  hipLaunchKernelGGL((k_score<T, false>), dim3(256), dim3(SPAI_WAVE), score_lds(large, ell), s, A,
+                     M, sc, big, st, 1, large.L, large.H);
+  hipLaunchKernelGGL((k_score<T, true>), dim3(kHugeGrid), dim3(SPAI_WAVE), 0, s, A, M, sc, big, st,
+                     2, huge.L, huge.H);
+  const int ng = (int)std::min<int64_t>((n + 63) / 64, 1 << 30);
+  hipLaunchKernelGGL(k_score_pair<T>, dim3(std::min(ng, resident_grid(k_score_pair<T>, 0))),
+                     dim3(SPAI_WAVE), 0, s, M, sc, sig, n, st);
 }
 
 // ============================================================================
@@ -1821,7 +2041,7 @@ template <typename T>
 __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int colcap, int sym,
                                                        int global, const double* tcol,
                                                        const double* gthr, double eta, int64_t n,
-                                                       DevState* st) {
+                                                       DevState* st, const double* score) {
   if (!st->any_active || !st->iter_active) return;
   __shared__ int s_run[SPAI_WAVE];
   const Cols<T> X = Xp.nxt();
@@ -1839,7 +2059,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
     for (int x0 = 0; x0 < g.T; x0 += SPAI_WAVE * kGU) {
       int col[kGU], idx[kGU];
       T val[kGU];
-      double tk[kGU];
+      double tk[kGU], sv[kGU];
 #pragma unroll
       for (int u = 0; u < kGU; ++u) {
         const int x = x0 + u * SPAI_WAVE + lane;
@@ -1850,9 +2070,11 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
         idx[u] = -1;
         val[u] = (T)0;
         tk[u] = 0.0;
+        sv[u] = 0.0;
         if (x < g.T) {
           idx[u] = X.idx[src];
           val[u] = X.val[src];
+          if (score) sv[u] = score[src];
         }
       }
       if (need_tk) {
@@ -1878,7 +2100,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
           if (kind == 0 && k == j) {
             keep = true;
           } else if (global) {
-            keep = a > gt;
+            keep = (score ? sv[u] : a) > gt;
           } else if (colcap) {
             double t = tcj;
             if (kind == 0 && sym) t = fmax(t, tk[u]);
@@ -1922,11 +2144,12 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
 
 template <typename T>
 void launch_compact(Pair<T> X, int kind, int colcap, int sym, int global, const double* tcol,
-                    double eta, int64_t n, DevState* st, hipStream_t s) {
+                    double eta, int64_t n, DevState* st, hipStream_t s, const double* score) {
   const double* gthr = kind == 0 ? &st->thrM : &st->thrP;
   const int ng = (int)std::min<int64_t>((n + 63) / 64, 1 << 30);
   hipLaunchKernelGGL(k_compact<T>, dim3(std::min(ng, resident_grid(k_compact<T>, 0))),
-                     dim3(SPAI_WAVE), 0, s, X, kind, colcap, sym, global, tcol, gthr, eta, n, st);
+                     dim3(SPAI_WAVE), 0, s, X, kind, colcap, sym, global, tcol, gthr, eta, n, st,
+                     score);
 }
 
 // ============================================================================
@@ -2098,9 +2321,12 @@ void launch_flip(int which, DevState* st, hipStream_t s) {
                                  double*, BigList, const Seg&, DevState*, Tile, Tile, Tile,       \
                                  hipStream_t);                                                    \
   template void launch_global_select<T>(Pair<T>, int, int64_t, double, int, unsigned long long*,  \
-                                        unsigned long long*, int64_t, DevState*, hipStream_t);    \
+                                        unsigned long long*, int64_t, DevState*, hipStream_t,     \
+                                        const double*);                                           \
   template void launch_compact<T>(Pair<T>, int, int, int, int, const double*, double, int64_t,    \
-                                  DevState*, hipStream_t);
+                                  DevState*, hipStream_t, const double*);                         \
+  template void launch_score<T>(const Csr&, Pair<T>, double*, double*, BigList, DevState*, Tile,  \
+                                Tile, Tile, int64_t, hipStream_t);
 
 SPAI_INST(double)
 SPAI_INST(float)

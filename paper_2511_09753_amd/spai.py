@@ -47,7 +47,7 @@ class OptsT(C.Structure):
     _fields_ = [("precision", C.c_int), ("symmetrize", C.c_int), ("drop_tol", C.c_double),
                 ("tie_eta", C.c_double), ("stream", C.c_void_p),
                 ("device_pool_limit", C.c_int64), ("profile", C.c_int), ("a_format", C.c_int),
-                ("jacobi", C.c_int), ("explicit_residual", C.c_int)]
+                ("jacobi", C.c_int), ("explicit_residual", C.c_int), ("drop_score", C.c_int)]
 
 
 EXPORTS = [
@@ -185,6 +185,7 @@ class Options:
     a_format: str = "auto"      # layout of A on the device: "auto", "csr" or "ell"
     jacobi: bool = False        # Pi = D_A^{-1}-weighted variants (Algorithms 5, 7, 8)
     explicit_residual: bool = True   # False: the update formulas, no dropping (Section 6.2)
+    drop_score: bool = False    # global cap of M by the heuristic score of Appendix A
 
     def c(self):
         o = OptsT()
@@ -199,6 +200,7 @@ class Options:
         o.a_format = A_FORMATS[self.a_format]
         o.jacobi = 1 if self.jacobi else 0
         o.explicit_residual = 1 if self.explicit_residual else 0
+        o.drop_score = 1 if self.drop_score else 0
         return o
 
 

@@ -94,3 +94,11 @@ def test_c_level_option_checks(S):
 def test_spectrum_rejects_unsymmetric_matrix_on_host(S):
     A = sp.csr_matrix(np.array([[2.0, 1.0], [0.5, 2.0]]))
     _expect(S, -2, lambda: S.spectrum(A, np.ones(2), steps=2))
+
+
+def test_score_drop_needs_global_cap_and_symmetrize(S):
+    D = sp.identity(4, format="csr") * 2.0
+    _expect(S, -1, lambda: S.SPAI(D, "mr", "column", 2, False, options=S.Options(drop_score=True)))
+    _expect(S, -1, lambda: S.SPAI(D, "mr", "none", 0, False, options=S.Options(drop_score=True)))
+    _expect(S, -1, lambda: S.SPAI(D, "mr", "global", 8, False,
+                                  options=S.Options(drop_score=True, symmetrize=False)))

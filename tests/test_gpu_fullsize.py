@@ -171,3 +171,23 @@ def test_lognormal96_spectrum_of_a_against_oracle_lanczos():
     d = A.diagonal()
     radius = np.asarray(abs(A).sum(axis=1)).ravel() - np.abs(d)
     assert np.min(d - radius) - 1e-9 * scale <= g[0] <= g[1] <= np.max(d + radius) + 1e-9 * scale
+
+
+def test_lognormal96_score_drop_properties():
+    """The Appendix A score rule at full size (n = 884,736), 3 LOMR iterations: the cap
+    holds, M is exactly symmetric, and the reported ||I - A M||_F is the residual of the
+    exported M evaluated by the oracle."""
+    S = _spai()
+    wl = W.workload("lognormal96")
+    A = wl.A
+    m = O.cap_counts(A, "global", 2.0, True)
+    h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=3, options=S.Options(drop_score=True))
+    done, hist, _ = h.iterate(3)
+    M = h.get()
+    st = h.stats()
+    h.close()
+    assert done == 3 and st["nnz_m"] == M.nnz <= m
+    assert abs(M - M.T).nnz == 0
+    r = O.fnorm(O.residual(A, M))
+    assert hist[-1] == pytest.approx(r, rel=1e-10)
+    assert hist[-1] < hist[0]

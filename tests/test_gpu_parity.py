@@ -649,3 +649,52 @@ def test_spectrum_argument_errors():
     with pytest.raises(S.SpaiError):
         h.spectrum(np.ones(A.shape[0]), steps=5)                # M not symmetrized
     h.close()
+
+
+# ----------------------------------------------------------------------------
+# heuristic drop score of Appendix A under the global cap
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("jacobi", [False, True])
+@pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
+@pytest.mark.parametrize("name,make", SMALL)
+def test_score_drop_parity_f64(name, make, method, jacobi):
+    S = _spai()
+    A = make()
+    iters = 10
+    m = O.cap_counts(A, "global", 2.0, True)
+    h = S.SPAI(A, method, "global", 2.0, True, max_iter=iters,
+               options=S.Options(drop_score=True, jacobi=jacobi))
+    done, hist, rc = h.iterate(iters)
+    Mg = h.get()
+    st = h.stats()
+    h.close()
+    rule = O.DropRule(mode="global", m=m, score=True)
+    ref = (O.run_spd(method, A, O.jacobi(A), rule, iters) if jacobi
+           else O.run(method, A, rule, iters))
+    assert len(hist) == ref.iters
+    assert rel_err(hist, ref.resid[1:]) <= TOL_F64
+    only_g, only_o = pattern_diff(Mg, ref.M)
+    assert not only_g and not only_o, (len(only_g), len(only_o))
+    assert value_err(Mg, ref.M) <= 1e-9
+    assert st["nnz_m"] == ref.M.nnz <= m
+    assert abs(Mg - Mg.T).nnz == 0
+
+
+def test_score_drop_mixed_and_differs_from_magnitude():
+    """FP32 storage with the score rule against the FP64 oracle; and the score rule takes
+    another trajectory than hard thresholding."""
+    S = _spai()
+    A = W.lognormal3d(12, 3000)
+    iters = 10
+    m = O.cap_counts(A, "global", 2.0, True)
+    ref = O.lomr(A, O.DropRule(mode="global", m=m, score=True), iters)
+    h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=iters,
+               options=S.Options(precision="mixed", drop_score=True))
+    _, hist, _ = h.iterate(iters)
+    h.close()
+    assert rel_err(hist, ref.resid[1:]) <= TOL_MIXED
+    h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=iters)
+    _, hist_mag, _ = h.iterate(iters)
+    h.close()
+    assert rel_err(hist_mag, hist) > 1e-4
