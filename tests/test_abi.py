@@ -102,3 +102,43 @@ def test_score_drop_needs_global_cap_and_symmetrize(S):
     _expect(S, -1, lambda: S.SPAI(D, "mr", "none", 0, False, options=S.Options(drop_score=True)))
     _expect(S, -1, lambda: S.SPAI(D, "mr", "global", 8, False,
                                   options=S.Options(drop_score=True, symmetrize=False)))
+
+
+def test_oracle_and_product_path_are_separate():
+    """The oracle imports nothing from the package and the package nothing from the
+    oracle; bench.py uses the oracle only in its cpu_baseline leg."""
+    import ast
+    import glob
+
+    def imports(path):
+        tree = ast.parse(open(path).read())
+        out = []
+        for node in ast.walk(tree):
+            if isinstance(node, ast.Import):
+                out += [a.name for a in node.names]
+            elif isinstance(node, ast.ImportFrom) and node.module:
+                out.append(node.module)
+        return out
+
+    for f in glob.glob(os.path.join(ROOT, "oracle", "*.py")):
+        assert not any(m.startswith("paper_2511_09753_amd") for m in imports(f)), f
+    for f in glob.glob(os.path.join(ROOT, "paper_2511_09753_amd", "**", "*.py"), recursive=True):
+        assert not any(m.split(".")[0] == "oracle" for m in imports(f)), f
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    users = {fn.name for fn in ast.walk(tree) if isinstance(fn, ast.FunctionDef)
+             for node in ast.walk(fn)
+             if isinstance(node, ast.ImportFrom) and node.module and node.module.startswith("oracle")}
+    assert users == {"cpu_baseline"}
+    top = [n for n in tree.body if isinstance(n, (ast.Import, ast.ImportFrom))]
+    assert not any(isinstance(n, ast.ImportFrom) and n.module and n.module.startswith("oracle")
+                   for n in top)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    from paper_2511_09753_amd import spai as S
+    monkeypatch.setattr(S, "_lib", None)
+    monkeypatch.setattr(S, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libspai.so"))
+    with pytest.raises(RuntimeError):
+        S.load()
+    with pytest.raises(RuntimeError):
+        S.SPAI(sp.identity(3, format="csr") * 2.0, "mr")
