@@ -8,7 +8,9 @@ iterate values, float64 sums, global cap 2 nnz(A)), then PCG with the resulting 
 memory before the timed region.  Prints one JSON line (rank 0).
 
 Extra legs (not timed as steps): the float64 path on the same workload and the
-mixed-vs-float64 time to equal ||I - A M||_F, and the CPU oracle on a bounded sample.
+mixed-vs-float64 time to equal ||I - A M||_F, the Pi-weighted LOMR, the Appendix A
+heuristic drop score under the same cap, Lanczos extremes of the final M, and the CPU
+oracle on a bounded sample.
 """
 import argparse
 import json
@@ -103,8 +105,8 @@ def exp05():
     (Pi = D_A^{-1}) with a 3% density cap, snapshots after 5, 20 and 100 iterations unless
     ||I - AM||_F / sqrt(n) <= 1e-6 comes first; per snapshot lambda_min(M), lambda_max(M)
     as the extreme Ritz values of up to 300 Lanczos steps on the GPU (each with its
-    residual bound; a negative theta_min proves M indefinite), ||I - AM||_F, iterations, nnz(M)/n^2, and vector PCG iterations with M (one RHS, to
-    1e-8) beside Jacobi's.  The realisations differ from the authors', so the comparison
+    residual bound; a negative theta_min proves M indefinite), ||I - AM||_F, iterations,
+    nnz(M)/n^2, and vector PCG iterations with M (one RHS, to 1e-8) beside Jacobi's.  The realisations differ from the authors', so the comparison
     with the tables is qualitative."""
     import numpy as np
     import scipy.sparse as sp
@@ -190,6 +192,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pcg", action="store_true", help="(diagnostics only) skip the PCG leg")
     ap.add_argument("--no-jacobi", action="store_true", help="skip the Pi-weighted LOMR leg")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the heuristic-score and spectrum legs")
     ap.add_argument("--exp05", action="store_true",
                     help="run the Experiment 05/06 protocol on the paper's recipe matrices and exit")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
@@ -219,9 +223,10 @@ def main():
     log(f"workload: 3D lognormal 7-point {N}^3, n={n}, nnz={nnzA}")
     B = torch.from_numpy(W.rhs(n, args.nrhs, W.seed_for(3, 1))).cuda()
 
-    def make(prec, profile, jacobi=False):
+    def make(prec, profile, jacobi=False, score=False):
         return S.SPAI(A, "lomr", "global", 2.0, True, max_iter=max(args.iters, 60),
-                      options=S.Options(precision=prec, profile=profile, jacobi=jacobi))
+                      options=S.Options(precision=prec, profile=profile, jacobi=jacobi,
+                                        drop_score=score))
 
     def step(h, its):
         h.reset()
@@ -270,6 +275,18 @@ def main():
     if pcg:
         log(f"PCG 64 RHS: iterations min/max {pcg[0].min()}/{pcg[0].max()}, "
             f"max true rel res {pcg[1].max():.2e}, status {pcg[2]}")
+
+    # ---------------- spectrum of the final M: Lanczos on the device (Tables 4-6 columns)
+    spec = None
+    if not args.no_extras:
+        v0 = torch.from_numpy(np.random.default_rng(W.seed_for(3, 2)).standard_normal(n)).cuda()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lo, hi, rlo, rhi, ks = h.spectrum(v0, steps=100)
+        torch.cuda.synchronize()
+        spec = {"lanczos_steps": ks, "theta_min": lo, "theta_max": hi, "res_min": rlo,
+                "res_max": rhi, "seconds": time.perf_counter() - t}
+        log("spectrum of M:", json.dumps(spec))
 
     # ---------------- float64 path and time to equal residual
     f64 = None
@@ -327,6 +344,25 @@ def main():
                "resid_fro": float(histj[-1]), "iters": args.iters}
         log("jacobi-weighted LOMR:", json.dumps(jac))
 
+    # ---------------- Appendix A heuristic drop score under the same cap (LOMR, mixed)
+    score = None
+    if not args.no_extras:
+        hs = make("mixed", True, score=True)
+        hs.reset()
+        hs.iterate(args.iters)                       # warm-up
+        s0, _, q0 = hs.profile()
+        hs.reset()
+        _, hists, _ = hs.iterate(args.iters)
+        s1, _, q1 = hs.profile()
+        its = max(q1["iters"] - q0["iters"], 1)
+        score = {"method": "LOMR, Appendix A score in the global cap, mixed",
+                 "spai_ms_per_iter": sum(s1[k] - s0[k] for k in s1 if k != "pcg") / its,
+                 "select_ms_per_iter": (s1["select"] - s0["select"]) / its,
+                 "resid_fro": float(hists[-1]), "resid_fro_magnitude_rule": r_mixed,
+                 "iters": args.iters}
+        hs.close()
+        log("score drop:", json.dumps(score))
+
     cpu = None if args.no_cpu else cpu_baseline(A)
     if cpu:
         log("cpu baseline:", json.dumps(cpu))
@@ -368,6 +404,8 @@ def main():
         "pcg_iters_max": int(pcg[0].max()) if pcg else None,
         "mixed_vs_f64": f64,
         "jacobi_lomr": jac,
+        "score_lomr": score,
+        "spectrum_of_m": spec,
     }
     print(json.dumps(out), flush=True)
 
