@@ -64,12 +64,20 @@ def lomr_alg_bytes(c, n, nnzA, s_val, s_aval, iters):
             + 3 * E(c["kept_m"] / it, s_val))
 
 
+# kernel of each timed phase, and the source file its code lives in
+PHASE_KERNEL = {"dots": "k_dots", "update": "k_update", "resid": "k_resid", "compact": "k_compact",
+                "pcg_mx": "k_spmm_wave_mx", "pcg_ax": "k_spmm_wave_ax"}
+KERNEL_SOURCE = {"k_dots": "spai_kernels.hip", "k_update": "spai_kernels.hip",
+                 "k_resid": "spai_kernels.hip", "k_compact": "spai_kernels.hip",
+                 "k_spmm_wave_mx": "spai_pcg.hip", "k_spmm_wave_ax": "spai_pcg.hip"}
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary, or None when that summary is missing or was taken on other kernel source."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_lognormal96.md")
-    src = os.path.join(ROOT, "paper_2511_09753_amd", "csrc", "spai_kernels.hip")
+    src = os.path.join(ROOT, "paper_2511_09753_amd", "csrc", KERNEL_SOURCE[kernel])
     if not os.path.exists(path):
         return None
     want = hashlib.sha256(open(src, "rb").read()).hexdigest()
@@ -257,19 +265,37 @@ def main():
     ph_ms = {k: ms1[k] - ms0[k] for k in ms1}
     ph_calls = {k: calls1[k] - calls0[k] for k in calls1}
     cnt = {k: cnt1[k] - cnt0[k] for k in cnt1}
-    spai_ms = sum(v for k, v in ph_ms.items() if k != "pcg")
+    spai_ms = sum(v for k, v in ph_ms.items() if not k.startswith("pcg"))
     log(f"phases (ms over {args.steps} steps): " + ", ".join(f"{k}={v:.1f}" for k, v in ph_ms.items()))
     alg = algorithmic_bytes(cnt, n, nnzA, 4, 4, iters_timed)
     per_iter_ms = {k: ph_ms[k] / max(iters_timed, 1) for k in alg}
+    stats = h.stats()
+
+    def roofline(phase, bytes_per_launch):
+        launch_ms = ph_ms[phase] / max(ph_calls[phase], 1)
+        got = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+        kern = PHASE_KERNEL[phase]
+        return {"bound": "hbm", "kernel": kern, "achieved": got, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": got / HBM_PEAK_GBS, "traffic": measured_traffic(kern),
+                "alg_bytes_per_launch": bytes_per_launch, "avg_launch_ms": launch_ms,
+                "ms_per_step": ph_ms[phase] / args.steps}
+
+    # the SPAI iteration's dominant kernel (bytes per launch from the device counters)
     dom = max(alg, key=lambda k: per_iter_ms[k])
-    dom_launch_ms = ph_ms[dom] / max(ph_calls[dom], 1)
-    launches_per_iter = ph_calls[dom] / max(iters_timed, 1)
-    dom_bytes = alg[dom] / max(launches_per_iter, 1e-9)
-    achieved = dom_bytes / (dom_launch_ms * 1e-3) / 1e9
+    roof_spai = roofline(dom, alg[dom] / max(ph_calls[dom] / max(iters_timed, 1), 1e-9))
+    # the PCG products (event-timed inside the solve): read the matrix and X once, write Y
+    # once, X and Y n x nrhs float64; M in padded columns (4-byte index + 4-byte value,
+    # 12-byte descriptor), A as CSR with float64 values
+    roofs = {"spai": roof_spai}
+    if ph_calls.get("pcg_mx"):
+        vec = 2 * n * args.nrhs * 8
+        roofs["pcg_mx"] = roofline("pcg_mx", stats["nnz_m"] * 8 + 12 * n + vec)
+        roofs["pcg_ax"] = roofline("pcg_ax", nnzA * 12 + 8 * (n + 1) + vec)
+    # the step's dominant kernel: the most time per step
+    top = max(roofs.values(), key=lambda r: r["ms_per_step"])
     it_bytes = lomr_alg_bytes(cnt, n, nnzA, 4, 4, iters_timed)
     it_gbs = it_bytes / (spai_ms / max(iters_timed, 1) * 1e-3) / 1e9
     r_mixed = float(hist[-1])
-    stats = h.stats()
     log(f"mixed: ||I-AM||_F after {done} its = {r_mixed:.6e}, nnz(M)={stats['nnz_m']}, "
         f"nnz(P)={stats['nnz_p']}; SPAI {spai_ms / max(iters_timed, 1):.3f} ms/it")
     if pcg:
@@ -301,7 +327,7 @@ def main():
         torch.cuda.synchronize()
         T64 = time.perf_counter() - t
         m1, c1, k1 = h64.profile()
-        spai64 = sum(m1[k] - m0[k] for k in m1 if k != "pcg")
+        spai64 = sum(m1[k] - m0[k] for k in m1 if not k.startswith("pcg"))
         r64 = float(hist64[-1])
         h64.close()
         # mixed until ||I - A M||_F <= r64 (1 + 1e-5), at most 60 iterations
@@ -311,7 +337,7 @@ def main():
         dn, histm, _ = hm.iterate(60)
         a1, _, q1 = hm.profile()
         reach = next((i + 1 for i, r in enumerate(histm) if r <= r64 * (1 + 1e-5)), None)
-        mixed_ms_per_it = sum(a1[k] - a0[k] for k in a1 if k != "pcg") / max(q1["iters"] - q0["iters"], 1)
+        mixed_ms_per_it = sum(a1[k] - a0[k] for k in a1 if not k.startswith("pcg")) / max(q1["iters"] - q0["iters"], 1)
         f64_ms_per_it = spai64 / max(k1["iters"] - k0["iters"], 1)
         hm.close()
         f64 = {
@@ -338,7 +364,7 @@ def main():
         hj.reset()
         _, histj, _ = hj.iterate(args.iters)
         j1, _, k1 = hj.profile()
-        jms = sum(j1[k] - j0[k] for k in j1 if k != "pcg") / max(k1["iters"] - k0["iters"], 1)
+        jms = sum(j1[k] - j0[k] for k in j1 if not k.startswith("pcg")) / max(k1["iters"] - k0["iters"], 1)
         hj.close()
         jac = {"method": "LOMR_SPD (Pi = D_A^-1), mixed", "spai_ms_per_iter": jms,
                "resid_fro": float(histj[-1]), "iters": args.iters}
@@ -356,7 +382,7 @@ def main():
         s1, _, q1 = hs.profile()
         its = max(q1["iters"] - q0["iters"], 1)
         score = {"method": "LOMR, Appendix A score in the global cap, mixed",
-                 "spai_ms_per_iter": sum(s1[k] - s0[k] for k in s1 if k != "pcg") / its,
+                 "spai_ms_per_iter": sum(s1[k] - s0[k] for k in s1 if not k.startswith("pcg")) / its,
                  "select_ms_per_iter": (s1["select"] - s0["select"]) / its,
                  "resid_fro": float(hists[-1]), "resid_fro_magnitude_rule": r_mixed,
                  "iters": args.iters}
@@ -387,17 +413,15 @@ def main():
                         f"2 nnz(A), {args.iters} iterations, then PCG with {args.nrhs} RHS to 1e-8",
             "global_batch": args.nrhs, "seq_len": 0, "parallelism": "none (1 GPU)",
         },
-        "roofline": {
-            "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"k_{dom}"),
-            "alg_bytes_per_launch": dom_bytes, "avg_launch_ms": dom_launch_ms,
-        },
+        "roofline": top,
+        "roofline_per_kernel": roofs,
         "iteration_alg_bytes": it_bytes,
         "iteration_alg_gbs": it_gbs,
         "cpu_baseline": cpu,
         "spai_ms_per_iter": spai_ms / max(iters_timed, 1),
         "pcg_ms_per_step": ph_ms["pcg"] / args.steps,
-        "phase_ms_per_iter": {k: v / max(iters_timed, 1) for k, v in ph_ms.items() if k != "pcg"},
+        "phase_ms_per_iter": {k: v / max(iters_timed, 1) for k, v in ph_ms.items()
+                              if not k.startswith("pcg")},
         "alg_gbs_per_phase": {k: alg[k] / (per_iter_ms[k] * 1e-3) / 1e9 if per_iter_ms[k] > 0 else None
                               for k in alg},
         "resid_fro": r_mixed,

@@ -255,7 +255,9 @@ enum {
   SPAI_PH_BOUNDS = 5,   /* per-column output bounds and their prefix sums           */
   SPAI_PH_SCALAR = 6,   /* fixed-order reductions and step sizes                    */
   SPAI_PH_PCG = 7,      /* spai_pcg                                                 */
-  SPAI_NPHASES = 8
+  SPAI_PH_PCG_AX = 8,   /* inside spai_pcg: the products q = A p (part of SPAI_PH_PCG) */
+  SPAI_PH_PCG_MX = 9,   /* inside spai_pcg: the products z = M r (part of SPAI_PH_PCG) */
+  SPAI_NPHASES = 10
 };
 enum {
   SPAI_CNT_CAND_M = 0, SPAI_CNT_CAND_P = 1, SPAI_CNT_CAND_PT = 2,   /* candidates formed */

@@ -566,8 +566,16 @@ struct Engine : EngineBase {
       dX = x2;
     }
     tb(SPAI_PH_PCG);
-    rc = pcg_run(pa, pm, nrhs, dB, dX, rtol, max_iter, iters, relres, d_order, s);
+    PcgTiming tm;
+    rc = pcg_run(pa, pm, nrhs, dB, dX, rtol, max_iter, iters, relres, d_order, s,
+                 prof ? &tm : nullptr);
     te();
+    if (prof) {
+      ph_ms[SPAI_PH_PCG_AX] += tm.ms[0];
+      ph_calls[SPAI_PH_PCG_AX] += tm.calls[0];
+      ph_ms[SPAI_PH_PCG_MX] += tm.ms[1];
+      ph_calls[SPAI_PH_PCG_MX] += tm.calls[1];
+    }
     if (rc < 0) return rc;
     if (!on_device) {
       HIPCHK(hipMemcpyAsync(X, dX, sizeof(double) * tot, hipMemcpyDeviceToHost, s));

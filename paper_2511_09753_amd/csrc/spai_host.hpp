@@ -78,8 +78,16 @@ struct PcgMat {
 
 // preconditioned CG on device-resident operands (B, X on the device); `order` (device,
 // n rows, or null for the natural order) is the order in which the products visit rows
+// accumulated event-timed milliseconds and launches of the products inside the PCG
+// iterations: [0] q = A p, [1] z = M r
+struct PcgTiming {
+  double ms[2] = {0.0, 0.0};
+  int64_t calls[2] = {0, 0};
+};
+
 int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double* dX, double rtol,
-            int max_iter, int* iters, double* relres, const int32_t* order, hipStream_t s);
+            int max_iter, int* iters, double* relres, const int32_t* order, hipStream_t s,
+            PcgTiming* timing);
 
 // extreme Ritz values of S (symmetric) after up to `steps` Lanczos steps with full
 // reorthogonalisation from the device vector dv0: out = {theta_min, theta_max, res_min,

@@ -447,6 +447,41 @@ struct Solver {
   RhsState* S;
   int* nactive;
   const int32_t* order = nullptr;   // row visiting order of the products (null: natural)
+  // optional timing of the products inside the iterations: HIP events recorded on the
+  // solver's stream around each A p (kind 0) and M r (kind 1), read back per chunk
+  PcgTiming* timing = nullptr;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_kind;
+  int ev_used = 0;
+
+  void timed_spmm(int kind, const Mat& K, const double* X, double* Y, double* out) {
+    if (!timing || ev_used + 2 > (int)ev.size()) {
+      spmm(K, X, Y, out);
+      return;
+    }
+    (void)hipEventRecord(ev[ev_used], s);
+    if (K.val32) spmm_v<float>(K, X, Y, out ? part : nullptr);
+    else spmm_v<double>(K, X, Y, out ? part : nullptr);
+    (void)hipEventRecord(ev[ev_used + 1], s);
+    ev_kind[ev_used / 2] = kind;
+    ev_used += 2;
+    if (out)
+      hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(kThreads), 0, s, part, spmm_grid, nrhs,
+                         out);
+  }
+  // after a synchronisation: add the recorded product times to the totals
+  void collect_timing() {
+    for (int i = 0; i + 1 < ev_used; i += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) {
+        timing->ms[ev_kind[i / 2]] += ms;
+        timing->calls[ev_kind[i / 2]] += 1;
+      } else {
+        (void)hipGetLastError();
+      }
+    }
+    ev_used = 0;
+  }
 
   static int pow2(int w) {
     int R = 1;
@@ -510,7 +545,7 @@ struct Solver {
 
   void iteration(double rtol) {
     const dim3 gs((nrhs + 63) / 64), bs(64);
-    spmm(A, p, q, tmp);                                       // q = A p, (p, q)
+    timed_spmm(0, A, p, q, tmp);                              // q = A p, (p, q)
     hipLaunchKernelGGL(k_alpha, gs, bs, 0, s, S, tmp, nrhs, nactive);
     if (nrhs <= 64) {                                            // r update fused with ||r||^2
       hipLaunchKernelGGL(k_axpy, dim3(kGrid), dim3(kThreads), 0, s, r, q, S, n, nrhs, pow2(nrhs),
@@ -521,7 +556,7 @@ struct Solver {
       dot(r, r, nullptr, tmp);
     }
     hipLaunchKernelGGL(k_conv, gs, bs, 0, s, S, tmp, rtol, nrhs, nactive);
-    spmm(M, r, z, tmp);                                       // z = M r, (r, z)
+    timed_spmm(1, M, r, z, tmp);                              // z = M r, (r, z)
     hipLaunchKernelGGL(k_beta, gs, bs, 0, s, S, tmp, nrhs);
     if (nrhs <= 64)                                              // x += alpha p, p = z + beta p
       hipLaunchKernelGGL(k_pupd, dim3(kGrid), dim3(kThreads), 0, s, p, x, z, S, n, nrhs, pow2(nrhs));
@@ -566,10 +601,17 @@ using namespace spai;
 namespace spai {
 
 int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double* dX, double rtol,
-            int max_iter, int* iters, double* relres, const int32_t* order, hipStream_t s) {
+            int max_iter, int* iters, double* relres, const int32_t* order, hipStream_t s,
+            PcgTiming* timing) {
   int rc;
   DevPool pool;
   Solver S{};
+  struct EvGuard {
+    std::vector<hipEvent_t>* v;
+    ~EvGuard() {
+      for (hipEvent_t e : *v) (void)hipEventDestroy(e);
+    }
+  } evg{&S.ev};
   S.A = A;
   S.M = M;
   S.n = A.n;
@@ -583,6 +625,17 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
     return rc;
   S.b = dB;
   S.x = dX;
+  if (timing) {                         // two products per iteration, 8 iterations per chunk
+    S.timing = timing;
+    S.ev.resize(32, nullptr);
+    S.ev_kind.resize(16, 0);
+    for (auto& e : S.ev)
+      if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        e = nullptr;
+        S.timing = nullptr;
+      }
+  }
   HIPCHK(hipMemsetAsync(S.nactive, 0, sizeof(int), s));
   HIPCHK(hipMemsetAsync(S.S, 0, sizeof(RhsState) * nrhs, s));
   const dim3 gs((nrhs + 63) / 64), bs(64);
@@ -602,6 +655,7 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
     int nact = 0;
     HIPCHK(hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (S.timing) S.collect_timing();
     if (nact == 0) break;
     const int k = std::min(chunk, max_iter - it);
     for (int t = 0; t < k; ++t) S.iteration(rtol);
@@ -616,6 +670,7 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
   std::vector<RhsState> hs(nrhs);
   HIPCHK(hipMemcpyAsync(hs.data(), S.S, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (S.timing) S.collect_timing();
   bool indef = false, unconv = false;
   for (int r = 0; r < nrhs; ++r) {
     if (iters) iters[r] = hs[r].iters;
@@ -664,7 +719,7 @@ extern "C" int pcg_solve(const spai_csr_t* A, const spai_csr_t* M, int nrhs, con
     if ((rc = pool.alloc(&d_order, hA.n))) return rc;
     HIPCHK(hipMemcpyAsync(d_order, ord.data(), sizeof(int32_t) * hA.n, hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
-    rc = pcg_run(dA, dM, nrhs, dB, dX, rtol, max_iter, iters, relres, d_order, s);
+    rc = pcg_run(dA, dM, nrhs, dB, dX, rtol, max_iter, iters, relres, d_order, s, nullptr);
     if (rc < 0) return rc;
     if (!A->on_device) {
       HIPCHK(hipMemcpyAsync(X, dX, sizeof(double) * tot, hipMemcpyDeviceToHost, s));

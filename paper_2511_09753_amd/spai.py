@@ -57,7 +57,8 @@ EXPORTS = [
     "spai_profile", "spai_spectrum", "spai_csr_spectrum",
 ]
 A_FORMATS = {"auto": 0, "csr": 1, "ell": 2}
-PHASES = ["dots", "update", "resid", "select", "compact", "bounds", "scalar", "pcg"]
+PHASES = ["dots", "update", "resid", "select", "compact", "bounds", "scalar", "pcg", "pcg_ax",
+          "pcg_mx"]
 COUNTS = ["cand_m", "cand_p", "cand_pt", "kept_m", "kept_p", "kept_pt", "resid", "iters"]
 
 _lib = None

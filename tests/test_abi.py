@@ -142,3 +142,10 @@ def test_missing_library_fails_loudly(monkeypatch):
         S.load()
     with pytest.raises(RuntimeError):
         S.SPAI(sp.identity(3, format="csr") * 2.0, "mr")
+
+
+def test_phase_and_counter_tables_match_the_header(S):
+    text = open(os.path.join(ROOT, "include", "spai.h")).read()
+    nph = int(re.search(r"SPAI_NPHASES\s*=\s*(\d+)", text).group(1))
+    ncnt = int(re.search(r"SPAI_NCOUNTS\s*=\s*(\d+)", text).group(1))
+    assert len(S.PHASES) == nph and len(S.COUNTS) == ncnt
