@@ -99,15 +99,22 @@ __device__ __forceinline__ void accumulate_row(double& y, VT cv, int cc, int e0,
 }
 
 // Y[:, c0:c0+64) = K X[:, c0:c0+64) and, when dot is set, per-block partials of
-// sum_i X[i, r] Y[i, r] (X[i, :] taken from the row's own diagonal gather).
-// One wave per row, lane r owning right-hand side c0 + r, so every gather is one
-// 512-byte line of X.  The row's entries are loaded by the lanes together (one per
+// sum_i X[i, r] Y[i, r] (X[i, :] taken from the row's own diagonal gather), stored
+// transposed: part[r * gridDim.x + block].
+// One wave per row at a time, lane r owning right-hand side c0 + r, so every gather is
+// one 512-byte line of X.  The row's entries are loaded by the lanes together (one per
 // lane) and broadcast with readlane, so the row's gathers (up to 16 in flight) wait on
 // a single entry load; the next row's entries and the descriptor of the row after it
 // are loaded while the current row's gathers are in flight.  Row i's sum runs over its
 // entries in stored (ascending column) order.  The rows are split into eight
-// contiguous ranges, one per XCD (workgroups are dealt round-robin over the XCDs), so
-// the rows that gather the same row of X run on one XCD close together in time.
+// contiguous ranges, one per XCD (workgroups are dealt round-robin over the XCDs), and
+// each wave takes kRowsPerWave consecutive positions of its range.  The launch is not
+// persistent: workgroups are dispatched in order as others finish, so the positions in
+// flight stay within a few thousand of each other and the rows of X they gather stay in
+// the XCD's L2 (a persistent grid whose waves walk the range with a fixed stride drifts
+// apart and gathers rows again from beyond L2).
+constexpr int kRowsPerWave = 16;
+
 template <typename VT, int LAY>
 __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, double* Y,
                                                         int dot, int nrhs, int c0,
@@ -120,19 +127,21 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
   const int64_t per = (A.n + 7) / 8;
   const int64_t r0 = xcd * per;
   const int64_t r1 = r0 + per < A.n ? r0 + per : A.n;
-  const int64_t stride = nb * WPB;
+  (void)nb;
+  const int64_t stride = 1;
   const bool on = c0 + lane < nrhs;
   const int64_t cofs = c0 + lane;
   const unsigned loff = on ? (unsigned)lane * 8u : 0u;   // idle lanes re-read column c0
   auto rowof = [&](int64_t k) -> int64_t { return order ? (int64_t)order[k] : k; };
   double acc = 0.0;
-  int64_t k = r0 + kb * WPB + wv;
+  int64_t k = r0 + (kb * WPB + wv) * kRowsPerWave;
+  const int64_t kend = k + kRowsPerWave < r1 ? k + kRowsPerWave : r1;
   // position k: row i, its descriptor (a, b) and first 64 entries (ec, ev), one per lane;
   // position k + stride: row ni and descriptor (na, nbe); position k + 2 stride: row mi
   int64_t i = 0, ni = 0, mi = 0, a = 0, b = 0, na = 0, nbe = 0;
   int ec = -1;
   VT ev = 0;
-  if (k < r1) {
+  if (k < kend) {
     i = rowof(k);
     a = row_lo<LAY>(A, i);
     b = row_hi<LAY>(A, i);
@@ -141,28 +150,28 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
       ev = entry_val<VT>(A, a + lane);
     }
   }
-  if (k + stride < r1) {
+  if (k + stride < kend) {
     ni = rowof(k + stride);
     na = row_lo<LAY>(A, ni);
     nbe = row_hi<LAY>(A, ni);
   }
-  if (k + 2 * stride < r1) mi = rowof(k + 2 * stride);
-  for (; k < r1; k += stride) {
+  if (k + 2 * stride < kend) mi = rowof(k + 2 * stride);
+  for (; k < kend; k += stride) {
     const int64_t kn = k + stride;
     const int cnt = __popcll(__ballot(ec >= 0));   // ELL padding (column -1) sits last
     int nc = -1;
     VT nv = 0;
     int64_t ma = 0, mb = 0, li = 0;
     auto prefetch = [&]() {
-      if (kn < r1 && na + lane < nbe) {
+      if (kn < kend && na + lane < nbe) {
         nc = A.col[na + lane];
         nv = entry_val<VT>(A, na + lane);
       }
-      if (kn + stride < r1) {
+      if (kn + stride < kend) {
         ma = row_lo<LAY>(A, mi);
         mb = row_hi<LAY>(A, mi);
       }
-      if (kn + 2 * stride < r1) li = rowof(kn + 2 * stride);
+      if (kn + 2 * stride < kend) li = rowof(kn + 2 * stride);
     };
     // X[i, :] for the dot: the row's own (diagonal) gather
     const int diag = dot ? (int)i : -1;
@@ -224,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
   if (threadIdx.x < 64 && c0 + (int)threadIdx.x < nrhs) {
     double sum = 0.0;
     for (int w = 0; w < WPB; ++w) sum += sh[w * 64 + threadIdx.x];
-    part[(int64_t)blockIdx.x * nrhs + c0 + threadIdx.x] = sum;
+    part[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = sum;
   }
 }
 
@@ -261,6 +270,23 @@ __global__ __launch_bounds__(kThreads) void k_dot_rows(const double* Xa, const d
 }
 
 // one workgroup per right-hand side: fixed strided partial sums, then a fixed tree
+// out[r] = sum_b part[r * nblocks + b] in a fixed order (the products' transposed partials)
+__global__ __launch_bounds__(kThreads) void k_reduce_rows(const double* part, int nblocks,
+                                                          double* out) {
+  __shared__ double sh[kThreads];
+  const int r = blockIdx.x;
+  const double* p = part + (int64_t)r * nblocks;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kThreads) s += p[b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = sh[0];
+}
+
 __global__ __launch_bounds__(kThreads) void k_reduce_parts(const double* part, int nblocks,
                                                            int nrhs, double* out) {
   __shared__ double sh[kThreads];
@@ -466,8 +492,7 @@ struct Solver {
     ev_kind[ev_used / 2] = kind;
     ev_used += 2;
     if (out)
-      hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(kThreads), 0, s, part, spmm_grid, nrhs,
-                         out);
+      hipLaunchKernelGGL(k_reduce_rows, dim3(nrhs), dim3(kThreads), 0, s, part, spmm_grid, out);
   }
   // after a synchronisation: add the recorded product times to the totals
   void collect_timing() {
@@ -489,31 +514,17 @@ struct Solver {
     return R;
   }
 
-  int spmm_grid = kGrid;   // workgroups of the last product (blocks of its partials)
-
-  // the product kernel walks its rows in a persistent grid: as many workgroups as fit
-  // on the chip at once (a multiple of the 8 XCDs), at most kGrid
-  template <typename VT, int LAY>
-  static int resident_spmm_grid() {
-    static int grid = 0;
-    if (grid) return grid;
-    int dev = 0, cus = 0, per = 0;
-    int g = kGrid;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_spmm_wave<VT, LAY>, kThreads, 0) ==
-            hipSuccess &&
-        per > 0 && cus > 0)
-      g = std::min(kGrid, std::max(8, per * cus / 8 * 8));
-    else
-      (void)hipGetLastError();
-    grid = g;
-    return g;
+  // workgroups of a product: 8 XCD ranges of ceil(n / 8) positions, kRowsPerWave
+  // positions per wave, kThreads / 64 waves per workgroup (blocks of its partials)
+  static int spmm_blocks(int64_t n) {
+    const int64_t per = (n + 7) / 8, rows = (int64_t)(kThreads / 64) * kRowsPerWave;
+    return (int)(8 * ((per + rows - 1) / rows));
   }
+  int spmm_grid = 8;
 
   template <typename VT, int LAY>
   void spmm_as(const Mat& K, const double* X, double* Y, double* pt) {
-    spmm_grid = resident_spmm_grid<VT, LAY>();
+    spmm_grid = spmm_blocks(n);
     for (int c0 = 0; c0 < nrhs; c0 += 64)
       hipLaunchKernelGGL((k_spmm_wave<VT, LAY>), dim3(spmm_grid), dim3(kThreads), 0, s, K, X, Y,
                          pt ? 1 : 0, nrhs, c0, order, pt);
@@ -529,8 +540,7 @@ struct Solver {
     if (K.val32) spmm_v<float>(K, X, Y, out ? part : nullptr);
     else spmm_v<double>(K, X, Y, out ? part : nullptr);
     if (out)
-      hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(kThreads), 0, s, part, spmm_grid, nrhs,
-                         out);
+      hipLaunchKernelGGL(k_reduce_rows, dim3(nrhs), dim3(kThreads), 0, s, part, spmm_grid, out);
   }
 
   void dot(const double* Xa, const double* Xb, const double* Xc, double* out) {
@@ -620,7 +630,8 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
   S.order = order;
   const int64_t tot = S.n * nrhs;
   if ((rc = pool.alloc(&S.r, tot)) || (rc = pool.alloc(&S.z, tot)) || (rc = pool.alloc(&S.p, tot)) ||
-      (rc = pool.alloc(&S.q, tot)) || (rc = pool.alloc(&S.part, (int64_t)kGrid * nrhs)) ||
+      (rc = pool.alloc(&S.q, tot)) ||
+      (rc = pool.alloc(&S.part, (int64_t)std::max<int64_t>(kGrid, Solver::spmm_blocks(S.n)) * nrhs)) ||
       (rc = pool.alloc(&S.tmp, nrhs)) || (rc = pool.alloc(&S.S, nrhs)) || (rc = pool.alloc(&S.nactive, 1)))
     return rc;
   S.b = dB;
