@@ -200,6 +200,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pcg", action="store_true", help="(diagnostics only) skip the PCG leg")
     ap.add_argument("--no-jacobi", action="store_true", help="skip the Pi-weighted LOMR leg")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the heuristic-score and spectrum legs")
     ap.add_argument("--exp05", action="store_true",
@@ -249,6 +250,12 @@ def main():
     t0 = time.perf_counter()
     h = make("mixed", True)
     log(f"create (validate + upload + pools): {time.perf_counter() - t0:.2f} s")
+    tuned = None
+    if not args.no_autotune:                  # per-column tiles for this workload (setup)
+        t0 = time.perf_counter()
+        tiles, tms = h.autotune(warm_iters=5, reps=2)
+        tuned = {"tiles": tiles, "launch_ms": tms, "seconds": time.perf_counter() - t0}
+        log("autotune:", json.dumps(tuned))
     for _ in range(args.warmup):
         step(h, args.iters)
     ms0, calls0, cnt0 = h.profile()
@@ -428,6 +435,7 @@ def main():
         "pcg_iters_max": int(pcg[0].max()) if pcg else None,
         "mixed_vs_f64": f64,
         "jacobi_lomr": jac,
+        "autotune": tuned,
         "score_lomr": score,
         "spectrum_of_m": spec,
     }

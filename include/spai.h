@@ -238,6 +238,19 @@ int spai_spectrum(spai_handle_t* h, int steps, const double* v0, int on_device, 
                   int* steps_done);
 
 /*
+ * spai_autotune — pick the per-column tiles (the boundary between a kernel's LDS tiers)
+ *   for this handle's workload: restart from M_0, run warm_iters iterations (at most
+ *   max_iter), time every candidate small tile of the residual, dots and update kernels
+ *   on that state (best of reps launches each), keep the fastest, and restart from M_0
+ *   (as spai_reset).  Results do not depend on the tiles (every column's arithmetic
+ *   and summation order are the same in every tier); batched handles recapture their
+ *   graph.  chosen (may be NULL): 6 ints, L and H of the residual, dots and update
+ *   tiles; best_ms (may be NULL): 3 doubles, their measured launch times.
+ *   Synchronises the stream.
+ */
+int spai_autotune(spai_handle_t* h, int warm_iters, int reps, int* chosen, double* best_ms);
+
+/*
  * spai_csr_spectrum — the same for an exactly symmetric CSR matrix S (for instance
  *   A, or an exported M); v0 is on the device when S->on_device.  Returns
  *   SPAI_ERR_NOT_SYMMETRIC for a matrix that is not exactly symmetric.

@@ -175,6 +175,7 @@ struct EngineBase {
   virtual int profile(double* ms, int64_t* calls, int64_t* counts) = 0;
   virtual int spectrum(int steps, const double* v0, int on_device, double* out,
                        int* steps_done) = 0;
+  virtual int autotune(int warm_iters, int reps, int* chosen, double* best_ms) = 0;
 };
 
 template <typename T>
@@ -583,6 +584,118 @@ struct Engine : EngineBase {
     HIPCHK(hipStreamSynchronize(s));
     collect();
     return rc;
+  }
+
+  // Tile autotuner: run warm_iters iterations, then time every candidate small tile of
+  // the residual, dots and update kernels (all three tiers of one launch, best of reps)
+  // on that state, keep the fastest of each, and restart from M_0.  A tile only moves
+  // the boundary between the tiers (which columns a kernel defers to its larger tiles);
+  // every column's arithmetic and every sum's order are the same in all tiers, so the
+  // results do not depend on the choice.
+  int autotune(int warm_iters, int reps, int* chosen, double* best_ms) override {
+    if (warm_iters < 0 || reps < 1) return fail(SPAI_ERR_ARG, "spai_autotune: bad arguments");
+    int rc;
+    if ((rc = init_iterate())) return rc;
+    const int warm = std::min(warm_iters, max_iter);
+    if (warm > 0) {
+      int done = 0;
+      rc = iterate(warm, &done, nullptr);
+      if (rc < 0) return rc;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return fail(SPAI_ERR_HIP, "spai_autotune: event creation failed");
+    }
+    auto timed = [&](auto&& launch) -> double {
+      double best = 1e300;
+      for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(e0, s);
+        launch();
+        (void)hipEventRecord(e1, s);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+          best = std::min(best, (double)ms);
+        else
+          (void)hipGetLastError();
+      }
+      return best;
+    };
+    const bool ell = A.eshift >= 0;
+    constexpr size_t kMaxLds = 64 * 1024;
+    // residual: R = I - A M on the current M (rewrites R with the same values)
+    launch_bound_resid<T>(A, M, ub, n, st, s);
+    launch_scan(ub, off, total, n, scantmp, s);
+    Tile bestR = tRs;
+    double tR = 1e300;
+    for (int L : {64, 128, 256})
+      for (int H : {512, 1024}) {
+        const Tile t{L, H};
+        if (resid_tile_bytes(t, ell) > kMaxLds) continue;
+        const double ms = timed([&] {
+          launch_resid<T>(A, M, R, off, total, colnorm, opts.jacobi, colrz, big[0], st, t, tRl,
+                          tRh, s);
+        });
+        if (ms < tR) { tR = ms; bestR = t; }
+      }
+    // dots: A R, A P on the current R, P (per-column partials only)
+    const int useR = method != SPAI_CG, useP = method != SPAI_MR;
+    Tile bestD = tDs;
+    double tD = 1e300;
+    for (int L : {128, 256, 512})
+      for (int H : {512, 1024}) {
+        const Tile t{L, H};
+        if (dots_tile_bytes(t, ell) > kMaxLds) continue;
+        const double ms = timed([&] {
+          launch_dots<T>(A, R, P, useR, useP, opts.jacobi, colpart, big[1], st, t, tDl, tDh, s);
+        });
+        if (ms < tD) { tD = ms; bestD = t; }
+      }
+    // update: the candidates of M (and P) written to the next buffers
+    const UpdMode md = method == SPAI_MR ? mode(1, 1, 0, 0)
+                       : method == SPAI_CG ? mode(1, 2, 0, 0) : mode(1, 1, 2, 1);
+    launch_bound_update<T>(A, M, R, P, PT, md, ub, n, st, s);
+    launch_scan(ub, off, total, n, scantmp, s);
+    Tile bestU = tUs;
+    double tU = 1e300;
+    for (int L : {256, 384, 512})
+      for (int H : {512, 1024}) {
+        const Tile t{L, H};
+        if (update_tile_bytes(t) > kMaxLds) continue;
+        const double ms = timed([&] {
+          launch_update<T>(A, M, R, P, PT, md, off, total, kcol, tM, tP, big[2], seg, st, t, tUl,
+                           tUh, s);
+        });
+        if (ms < tU) { tU = ms; bestU = t; }
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipGetLastError());
+    if ((rc = check_err())) return rc;
+    tRs = bestR;
+    tDs = bestD;
+    tUs = bestU;
+    if (chosen) {
+      chosen[0] = tRs.L; chosen[1] = tRs.H;
+      chosen[2] = tDs.L; chosen[3] = tDs.H;
+      chosen[4] = tUs.L; chosen[5] = tUs.H;
+    }
+    if (best_ms) {
+      best_ms[0] = tR < 1e300 ? tR : 0.0;
+      best_ms[1] = tD < 1e300 ? tD : 0.0;
+      best_ms[2] = tU < 1e300 ? tU : 0.0;
+    }
+    if (graph_exec) {                   // the captured iteration holds the old tiles
+      (void)hipGraphExecDestroy(graph_exec);
+      graph_exec = nullptr;
+    }
+    if (graph) {
+      (void)hipGraphDestroy(graph);
+      graph = nullptr;
+    }
+    return init_iterate();
   }
 
   int spectrum(int steps, const double* v0, int on_device, double* out,
@@ -1126,6 +1239,17 @@ int spai_spectrum(spai_handle_t* h, int steps, const double* v0, int on_device, 
   if (!h) return fail(SPAI_ERR_ARG, "null handle");
   try {
     return h->eng->spectrum(steps, v0, on_device, out, steps_done);
+  } catch (const std::bad_alloc&) {
+    return fail(SPAI_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_autotune(spai_handle_t* h, int warm_iters, int reps, int* chosen, double* best_ms) {
+  if (!h) return fail(SPAI_ERR_ARG, "null handle");
+  try {
+    return h->eng->autotune(warm_iters, reps, chosen, best_ms);
   } catch (const std::bad_alloc&) {
     return fail(SPAI_ERR_NOMEM, "host allocation failed");
   } catch (...) {

@@ -54,7 +54,7 @@ EXPORTS = [
     "spai_default_opts", "spai_create", "spai_iterate", "spai_get", "spai_stats",
     "spai_destroy", "pcg_solve", "spai_loss_fwd", "spai_loss_bwd", "spai_create_batched",
     "spai_batched_resid", "spai_last_error", "spai_status_string", "spai_reset", "spai_pcg",
-    "spai_profile", "spai_spectrum", "spai_csr_spectrum",
+    "spai_profile", "spai_spectrum", "spai_csr_spectrum", "spai_autotune",
 ]
 A_FORMATS = {"auto": 0, "csr": 1, "ell": 2}
 PHASES = ["dots", "update", "resid", "select", "compact", "bounds", "scalar", "pcg", "pcg_ax",
@@ -102,6 +102,7 @@ def load():
     lib.spai_pcg.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int, P, P, C.c_int]
     lib.spai_profile.argtypes = [P, P, P, P]
     lib.spai_spectrum.argtypes = [P, C.c_int, P, C.c_int, P, C.POINTER(C.c_int)]
+    lib.spai_autotune.argtypes = [P, C.c_int, C.c_int, P, P]
     lib.spai_csr_spectrum.argtypes = [C.POINTER(CsrT), C.c_int, P, P, C.POINTER(C.c_int),
                                       C.POINTER(OptsT)]
     lib.spai_last_error.restype = C.c_char_p
@@ -329,6 +330,18 @@ class SPAI:
         _check(load().spai_spectrum(self.h, int(steps), ptr, dev, out.ctypes.data,
                                     C.byref(done)))
         return float(out[0]), float(out[1]), float(out[2]), float(out[3]), done.value
+
+    def autotune(self, warm_iters=5, reps=2):
+        """Pick the per-column tiles for this workload (see spai_autotune) and restart from
+        M_0.  Returns {"resid": (L, H), "dots": (L, H), "update": (L, H)} and the best
+        launch times in ms."""
+        ch = np.zeros(6, dtype=np.int32)
+        ms = np.zeros(3, dtype=np.float64)
+        _check(load().spai_autotune(self.h, int(warm_iters), int(reps), ch.ctypes.data,
+                                    ms.ctypes.data))
+        tiles = {"resid": (int(ch[0]), int(ch[1])), "dots": (int(ch[2]), int(ch[3])),
+                 "update": (int(ch[4]), int(ch[5]))}
+        return tiles, {"resid": float(ms[0]), "dots": float(ms[1]), "update": float(ms[2])}
 
     def batched_resid(self):
         out = np.zeros(self.nseg, dtype=np.float64)

@@ -698,3 +698,39 @@ def test_score_drop_mixed_and_differs_from_magnitude():
     _, hist_mag, _ = h.iterate(iters)
     h.close()
     assert rel_err(hist_mag, hist) > 1e-4
+
+
+# ----------------------------------------------------------------------------
+# tile autotuner
+# ----------------------------------------------------------------------------
+
+def test_autotune_leaves_results_unchanged():
+    """Tuned tiles move columns between the tiers only: the residual history and the
+    iterate are bitwise those of the default tiles, for a single and a batched handle."""
+    S = _spai()
+    A = W.lognormal3d(14, 23)
+    runs = []
+    for tune in (False, True):
+        h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=10,
+                   options=S.Options(precision="mixed"))
+        if tune:
+            tiles, ms = h.autotune(warm_iters=4, reps=1)
+            assert tiles["resid"][0] in (64, 128, 256) and tiles["dots"][0] in (128, 256, 512)
+            assert tiles["update"][0] in (256, 384, 512)
+            assert all(t[1] in (512, 1024) for t in tiles.values())
+            assert all(v > 0 for v in ms.values())
+        _, hist, _ = h.iterate(10)
+        runs.append((hist, h.get()))
+        h.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and (runs[0][1] != runs[1][1]).nnz == 0
+    mats = W.batch_geometric(4, 77, 300, 900)
+    runs = []
+    for tune in (False, True):
+        h = S.SPAI(None, "mr", "column", 4.0, False, max_iter=8, batch=mats)
+        if tune:
+            h.iterate(3)                       # capture a graph first: autotune recaptures
+            h.autotune(warm_iters=3, reps=1)
+        _, hist, _ = h.iterate(8)
+        runs.append((hist, h.batched_resid(), h.get()))
+        h.close()
+    assert np.array_equal(runs[0][1], runs[1][1]) and (runs[0][2] != runs[1][2]).nnz == 0
