@@ -298,6 +298,9 @@ int spai_profile(spai_handle_t* h, double* phase_ms, int64_t* phase_calls, int64
  *   true relative residual ||b - A x||_2 / ||b||_2 at exit.
  * Returns SPAI_OK when every RHS converged, SPAI_MAXITER when some did not,
  *   PCG_INDEFINITE when some RHS met (r, z) <= 0 or (p, A p) <= 0, or an error.
+ * On a stream other than the null stream the iterations run as replays of one HIP
+ *   graph of 8 iterations (captured on first use; the host reads the count of active
+ *   right-hand sides between replays); results equal the eager launches bit for bit.
  * Synchronises the stream.
  */
 int pcg_solve(const spai_csr_t* A, const spai_csr_t* M, int nrhs, const double* B,

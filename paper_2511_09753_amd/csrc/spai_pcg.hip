@@ -659,9 +659,23 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
   hipLaunchKernelGGL(k_set_rz, gs, bs, 0, s, S.S, S.tmp, nrhs);
   hipLaunchKernelGGL(k_copy, dim3(kGrid), dim3(kThreads), 0, s, S.p, S.z, tot);
   HIPCHK(hipGetLastError());
-  // iterate in chunks, checking the running count between chunks
+  // iterate in chunks, checking the running count between chunks.  On a stream of
+  // its own (not the null stream) and without the per-product timing, a full chunk is
+  // captured once as a HIP graph and replayed: every launch of an iteration has fixed
+  // arguments, and converged right-hand sides are masked on the device.
   int it = 0;
   const int chunk = 8;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  struct GraphGuard {
+    hipGraph_t* g;
+    hipGraphExec_t* e;
+    ~GraphGuard() {
+      if (*e) (void)hipGraphExecDestroy(*e);
+      if (*g) (void)hipGraphDestroy(*g);
+    }
+  } gguard{&graph, &gexec};
+  bool use_graph = s != nullptr && !S.timing;
   while (it < max_iter) {
     int nact = 0;
     HIPCHK(hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -669,7 +683,27 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
     if (S.timing) S.collect_timing();
     if (nact == 0) break;
     const int k = std::min(chunk, max_iter - it);
-    for (int t = 0; t < k; ++t) S.iteration(rtol);
+    if (use_graph && k == chunk && !gexec) {
+      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        for (int t = 0; t < k; ++t) S.iteration(rtol);
+        if (hipStreamEndCapture(s, &graph) != hipSuccess ||
+            hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+          (void)hipGetLastError();
+          if (graph) (void)hipGraphDestroy(graph);
+          graph = nullptr;
+          gexec = nullptr;
+          return fail(SPAI_ERR_HIP, "pcg: capturing the iteration graph failed");
+        }
+      } else {
+        (void)hipGetLastError();
+        use_graph = false;
+      }
+    }
+    if (use_graph && k == chunk && gexec) {
+      HIPCHK(hipGraphLaunch(gexec, s));
+    } else {
+      for (int t = 0; t < k; ++t) S.iteration(rtol);
+    }
     HIPCHK(hipGetLastError());
     it += k;
   }

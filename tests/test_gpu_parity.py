@@ -734,3 +734,39 @@ def test_autotune_leaves_results_unchanged():
         runs.append((hist, h.batched_resid(), h.get()))
         h.close()
     assert np.array_equal(runs[0][1], runs[1][1]) and (runs[0][2] != runs[1][2]).nnz == 0
+
+
+def test_pcg_graph_replay_matches_eager():
+    """On a stream of its own the PCG iterations replay a captured graph of 8 iterations;
+    the solution and iteration counts equal the eager solve's bit for bit (several
+    replays, with host reads and synchronisations between them), for a single and a
+    batched handle."""
+    import torch
+    S = _spai()
+    A = W.lognormal3d(16, 41)
+    B = W.rhs(A.shape[0], 5, 13)
+    h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=12)
+    h.iterate(12)
+    M = h.get()
+    X0, it0, rel0, rc0 = h.pcg(B, rtol=1e-9)         # null stream: eager
+    h.close()
+    st = torch.cuda.Stream()
+    h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=12, options=S.Options(stream=st))
+    h.iterate(12)
+    X1, it1, rel1, rc1 = h.pcg(B, rtol=1e-9)         # own stream: graph replays
+    h.close()
+    assert max(it0) > 16                                # at least two full chunks replayed
+    assert rc0 == rc1 and list(it0) == list(it1) and np.array_equal(X0, X1)
+    X2, it2, _, _ = S.pcg_solve(A, M, B, rtol=1e-9, options=S.Options(stream=st))
+    assert list(it2) == list(it0) and np.array_equal(X2, X0)
+    mats = W.batch_geometric(3, 55, 400, 900)
+    hb = S.SPAI(None, "mr", "column", 4.0, False, max_iter=6, batch=mats)
+    hb.iterate(6)
+    Mb = hb.get()
+    nb = sum(m.shape[0] for m in mats)
+    Bb = W.rhs(nb, 3, 17)
+    Xb, itb, _, rcb = hb.pcg(Bb, rtol=1e-9)          # batched handles run on their own stream
+    hb.close()
+    Ab = sp.block_diag(mats, format="csr")
+    Xe, ite, _, rce = S.pcg_solve(Ab, Mb, Bb, rtol=1e-9)
+    assert rcb == rce and list(itb) == list(ite) and np.array_equal(Xb, Xe)
