@@ -251,6 +251,23 @@ int spai_spectrum(spai_handle_t* h, int steps, const double* v0, int on_device, 
 int spai_autotune(spai_handle_t* h, int warm_iters, int reps, int* chosen, double* best_ms);
 
 /*
+ * spai_get_state / spai_set_state — checkpoint and resume a handle.  The state holds the
+ *   current iterate M, for CG and LOMR the direction P (and its transpose P^T), the
+ *   residual R (and, for the implicit Pi-weighted form, R beside Z), every matrix's
+ *   scalars (step sizes, ||R||^2, (R, Z), iteration count, stop flag) and the iteration
+ *   budget used, as one self-describing host buffer (lists as compact CSC).
+ *   spai_get_state: buf = NULL returns the size in *size; else *size is the capacity
+ *   of buf on entry and the bytes written on return.
+ *   spai_set_state: restores a state taken from a handle of the same problem and
+ *   configuration (n, matrices, method, precision, Pi weighting, residual form,
+ *   symmetrization); the next spai_iterate continues exactly as the original handle
+ *   would have.  A mismatch, a truncated buffer or lists larger than this handle's
+ *   pools return SPAI_ERR_ARG.  Both synchronise the stream.
+ */
+int spai_get_state(spai_handle_t* h, void* buf, size_t* size);
+int spai_set_state(spai_handle_t* h, const void* buf, size_t size);
+
+/*
  * spai_csr_spectrum — the same for an exactly symmetric CSR matrix S (for instance
  *   A, or an exported M); v0 is on the device when S->on_device.  Returns
  *   SPAI_ERR_NOT_SYMMETRIC for a matrix that is not exactly symmetric.

@@ -162,6 +162,87 @@ DevPool::~DevPool() {
 
 namespace {
 
+// ---- column lists <-> compact CSC on the host ---------------------------------------
+
+// out[colptr[j] ..] = the entries of column j (colptr: exclusive prefix of the lengths)
+template <typename T>
+__global__ void k_pack_cols(Cols<T> C, const int64_t* colptr, int64_t n, int32_t* idx, T* val) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t b = C.beg[j], o = colptr[j];
+  const int len = C.len[j];
+  for (int e = 0; e < len; ++e) {
+    idx[o + e] = C.idx[b + e];
+    val[o + e] = C.val[b + e];
+  }
+}
+
+// download column lists as compact CSC (one packing kernel, three copies)
+template <typename T>
+int download_cols(const Cols<T>& C, int64_t n, hipStream_t s, std::vector<int64_t>& colptr,
+                  std::vector<int32_t>& idx, std::vector<T>& val) {
+  std::vector<int32_t> len((size_t)n);
+  HIPCHK(hipMemcpyAsync(len.data(), C.len, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  colptr.assign((size_t)n + 1, 0);
+  for (int64_t j = 0; j < n; ++j) colptr[j + 1] = colptr[j] + len[j];
+  const int64_t nnz = colptr[n];
+  idx.resize((size_t)nnz);
+  val.resize((size_t)nnz);
+  DevPool tmp;
+  int rc;
+  int64_t* dptr;
+  int32_t* didx;
+  T* dval;
+  if ((rc = tmp.alloc(&dptr, n + 1)) || (rc = tmp.alloc(&didx, nnz)) || (rc = tmp.alloc(&dval, nnz)))
+    return rc;
+  HIPCHK(hipMemcpyAsync(dptr, colptr.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_pack_cols<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C, dptr, n,
+                     didx, dval);
+  HIPCHK(hipGetLastError());
+  if (nnz) {
+    HIPCHK(hipMemcpyAsync(idx.data(), didx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(val.data(), dval, sizeof(T) * nnz, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return SPAI_OK;
+}
+
+// upload compact CSC into column lists (columns laid out from offset 0)
+template <typename T>
+int upload_cols(Cols<T>& C, int64_t n, hipStream_t s, const int64_t* colptr, const int32_t* idx,
+                const T* val) {
+  const int64_t nnz = colptr[n];
+  if (nnz > C.cap) return fail(SPAI_ERR_ARG, "state: a list exceeds this handle's pool");
+  std::vector<int32_t> len((size_t)n);
+  for (int64_t j = 0; j < n; ++j) {
+    const int64_t l = colptr[j + 1] - colptr[j];
+    if (l < 0 || l > INT32_MAX) return fail(SPAI_ERR_ARG, "state: bad column pointers");
+    len[(size_t)j] = (int32_t)l;
+  }
+  for (int64_t q = 0; q < nnz; ++q)
+    if (idx[q] < 0 || idx[q] >= n) return fail(SPAI_ERR_ARG, "state: row index out of range");
+  HIPCHK(hipMemcpyAsync(C.beg, colptr, sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(C.len, len.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+  if (nnz) {
+    HIPCHK(hipMemcpyAsync(C.idx, idx, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(C.val, val, sizeof(T) * nnz, hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return SPAI_OK;
+}
+
+// serialized handle state: header, per-matrix scalars, then the lists as compact CSC
+struct StateHeader {
+  char magic[8];
+  int32_t version, value_bytes;
+  int64_t n;
+  int32_t nseg, method, jacobi, implicit, symmetrize, nlists;
+  int64_t iters_host, total_iters;
+  int64_t nnz[5];
+};
+constexpr char kStateMagic[8] = {'S', 'P', 'A', 'I', 'S', 'T', 'A', 'T'};
+
 struct EngineBase {
   virtual ~EngineBase() {}
   virtual int iterate(int k, int* done, double* hist) = 0;
@@ -176,6 +257,8 @@ struct EngineBase {
   virtual int spectrum(int steps, const double* v0, int on_device, double* out,
                        int* steps_done) = 0;
   virtual int autotune(int warm_iters, int reps, int* chosen, double* best_ms) = 0;
+  virtual int get_state(void* buf, size_t* size) = 0;
+  virtual int set_state(const void* buf, size_t size) = 0;
 };
 
 template <typename T>
@@ -586,6 +669,131 @@ struct Engine : EngineBase {
     return rc;
   }
 
+  // the lists a state holds: M, and for CG / LOMR P and P^T, R, and the implicit
+  // Pi-weighted form's R beside Z
+  void state_lists(const DevState& h, Cols<T>* out[5], int& k) {
+    k = 0;
+    out[k++] = &M.b[h.curM];
+    if (method != SPAI_MR) {
+      out[k++] = &P.b[h.curP];
+      out[k++] = &PT.b[h.curP];
+    }
+    out[k++] = &R;
+    if (implicit && opts.jacobi) out[k++] = &Rraw;
+  }
+
+  int get_state(void* buf, size_t* size) override {
+    if (!size) return fail(SPAI_ERR_ARG, "spai_get_state: null size");
+    HIPCHK(hipStreamSynchronize(s));
+    DevState h;
+    HIPCHK(hipMemcpy(&h, st, sizeof(DevState), hipMemcpyDeviceToHost));
+    Cols<T>* lists[5];
+    int nl = 0;
+    state_lists(h, lists, nl);
+    StateHeader hd{};
+    std::memcpy(hd.magic, kStateMagic, 8);
+    hd.version = 1;
+    hd.value_bytes = (int32_t)sizeof(T);
+    hd.n = n;
+    hd.nseg = nseg;
+    hd.method = method;
+    hd.jacobi = opts.jacobi;
+    hd.implicit = implicit ? 1 : 0;
+    hd.symmetrize = opts.symmetrize;
+    hd.nlists = nl;
+    hd.iters_host = iters_host;
+    hd.total_iters = total_iters;
+    std::vector<std::vector<int64_t>> cp(nl);
+    std::vector<std::vector<int32_t>> ix(nl);
+    std::vector<std::vector<T>> vl(nl);
+    int rc;
+    for (int l = 0; l < nl; ++l) {
+      if ((rc = download_cols<T>(*lists[l], n, s, cp[l], ix[l], vl[l]))) return rc;
+      hd.nnz[l] = cp[l][n];
+    }
+    size_t need = sizeof(StateHeader) + sizeof(SegState) * (size_t)nseg;
+    for (int l = 0; l < nl; ++l)
+      need += sizeof(int64_t) * (size_t)(n + 1) + (sizeof(int32_t) + sizeof(T)) * (size_t)hd.nnz[l];
+    if (!buf) {
+      *size = need;
+      return SPAI_OK;
+    }
+    if (*size < need) return fail(SPAI_ERR_ARG, "spai_get_state: buffer too small");
+    *size = need;
+    char* o = (char*)buf;
+    std::memcpy(o, &hd, sizeof(hd));
+    o += sizeof(hd);
+    HIPCHK(hipMemcpy(o, segst, sizeof(SegState) * nseg, hipMemcpyDeviceToHost));
+    o += sizeof(SegState) * nseg;
+    for (int l = 0; l < nl; ++l) {
+      std::memcpy(o, cp[l].data(), sizeof(int64_t) * (n + 1));
+      o += sizeof(int64_t) * (n + 1);
+      std::memcpy(o, ix[l].data(), sizeof(int32_t) * hd.nnz[l]);
+      o += sizeof(int32_t) * hd.nnz[l];
+      std::memcpy(o, vl[l].data(), sizeof(T) * hd.nnz[l]);
+      o += sizeof(T) * hd.nnz[l];
+    }
+    return SPAI_OK;
+  }
+
+  int set_state(const void* buf, size_t size) override {
+    if (!buf || size < sizeof(StateHeader)) return fail(SPAI_ERR_ARG, "spai_set_state: bad buffer");
+    StateHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (std::memcmp(hd.magic, kStateMagic, 8) != 0 || hd.version != 1)
+      return fail(SPAI_ERR_ARG, "spai_set_state: not a state of this library");
+    if (hd.value_bytes != (int32_t)sizeof(T) || hd.n != n || hd.nseg != nseg ||
+        hd.method != method || hd.jacobi != opts.jacobi || hd.implicit != (implicit ? 1 : 0) ||
+        hd.symmetrize != opts.symmetrize)
+      return fail(SPAI_ERR_ARG, "spai_set_state: state of a different problem or configuration");
+    if (hd.iters_host < 0 || hd.iters_host > max_iter)
+      return fail(SPAI_ERR_ARG, "spai_set_state: iterations beyond this handle's max_iter");
+    HIPCHK(hipStreamSynchronize(s));
+    DevState h;
+    HIPCHK(hipMemcpy(&h, st, sizeof(DevState), hipMemcpyDeviceToHost));
+    Cols<T>* lists[5];
+    int nl = 0;
+    state_lists(h, lists, nl);
+    if (hd.nlists != nl) return fail(SPAI_ERR_ARG, "spai_set_state: list count differs");
+    size_t need = sizeof(StateHeader) + sizeof(SegState) * (size_t)nseg;
+    for (int l = 0; l < nl; ++l) {
+      if (hd.nnz[l] < 0) return fail(SPAI_ERR_ARG, "spai_set_state: bad sizes");
+      need += sizeof(int64_t) * (size_t)(n + 1) + (sizeof(int32_t) + sizeof(T)) * (size_t)hd.nnz[l];
+    }
+    if (size < need) return fail(SPAI_ERR_ARG, "spai_set_state: truncated buffer");
+    const char* o = (const char*)buf + sizeof(hd);
+    std::vector<SegState> g((size_t)nseg);
+    std::memcpy(g.data(), o, sizeof(SegState) * nseg);
+    o += sizeof(SegState) * nseg;
+    bool any = false;
+    for (auto& x : g) {
+      if (x.iters < 0) return fail(SPAI_ERR_ARG, "spai_set_state: bad iteration count");
+      any = any || !x.stop;
+    }
+    int rc;
+    for (int l = 0; l < nl; ++l) {
+      std::vector<int64_t> cp((size_t)n + 1);
+      std::memcpy(cp.data(), o, sizeof(int64_t) * (n + 1));
+      o += sizeof(int64_t) * (n + 1);
+      if (cp[0] != 0 || cp[n] != hd.nnz[l]) return fail(SPAI_ERR_ARG, "spai_set_state: bad column pointers");
+      const int32_t* ix = (const int32_t*)o;
+      o += sizeof(int32_t) * hd.nnz[l];
+      std::vector<T> vl((size_t)hd.nnz[l]);
+      std::memcpy(vl.data(), o, sizeof(T) * hd.nnz[l]);
+      o += sizeof(T) * hd.nnz[l];
+      std::vector<int32_t> ixv(ix, ix + hd.nnz[l]);
+      if ((rc = upload_cols<T>(*lists[l], n, s, cp.data(), ixv.data(), vl.data()))) return rc;
+    }
+    HIPCHK(hipMemcpy(segst, g.data(), sizeof(SegState) * nseg, hipMemcpyHostToDevice));
+    h.any_active = any ? 1 : 0;
+    h.iter_active = any ? 1 : 0;
+    h.err = 0;
+    HIPCHK(hipMemcpy(st, &h, sizeof(DevState), hipMemcpyHostToDevice));
+    iters_host = (int)hd.iters_host;
+    total_iters = hd.total_iters;
+    return SPAI_OK;
+  }
+
   // Tile autotuner: run warm_iters iterations, then time every candidate small tile of
   // the residual, dots and update kernels (all three tiers of one launch, best of reps)
   // on that state, keep the fastest of each, and restart from M_0.  A tile only moves
@@ -940,9 +1148,7 @@ struct Engine : EngineBase {
     DevState h;
     HIPCHK(hipMemcpy(&h, st, sizeof(DevState), hipMemcpyDeviceToHost));
     const Cols<T>& C = M.b[h.curM];
-    std::vector<int64_t> beg(n);
     std::vector<int32_t> len(n);
-    HIPCHK(hipMemcpy(beg.data(), C.beg, sizeof(int64_t) * n, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(len.data(), C.len, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
     int64_t nnz = 0;
     for (int64_t j = 0; j < n; ++j) nnz += len[j];
@@ -950,17 +1156,13 @@ struct Engine : EngineBase {
     out->nnz = nnz;
     if (!out->rowptr) return SPAI_OK;
     if (out->capacity < nnz) return fail(SPAI_ERR_ARG, "output capacity below nnz(M)");
-    // gather the columns (CSC), then transpose to CSR on the host
-    std::vector<int32_t> ci(nnz);
-    std::vector<T> cv(nnz);
+    // gather the columns (CSC, packed on the device), then transpose to CSR on the host
+    std::vector<int64_t> cpk;
+    std::vector<int32_t> ci;
+    std::vector<T> cv;
+    int rcp;
+    if ((rcp = download_cols<T>(C, n, s, cpk, ci, cv))) return rcp;
     int64_t o = 0;
-    for (int64_t j = 0; j < n; ++j) {
-      if (len[j]) {
-        HIPCHK(hipMemcpy(ci.data() + o, C.idx + beg[j], sizeof(int32_t) * len[j], hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(cv.data() + o, C.val + beg[j], sizeof(T) * len[j], hipMemcpyDeviceToHost));
-      }
-      o += len[j];
-    }
     std::vector<int64_t> rp(n + 1, 0);
     for (int64_t q = 0; q < nnz; ++q) rp[ci[q] + 1]++;
     for (int64_t i = 0; i < n; ++i) rp[i + 1] += rp[i];
@@ -1239,6 +1441,28 @@ int spai_spectrum(spai_handle_t* h, int steps, const double* v0, int on_device, 
   if (!h) return fail(SPAI_ERR_ARG, "null handle");
   try {
     return h->eng->spectrum(steps, v0, on_device, out, steps_done);
+  } catch (const std::bad_alloc&) {
+    return fail(SPAI_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_get_state(spai_handle_t* h, void* buf, size_t* size) {
+  if (!h) return fail(SPAI_ERR_ARG, "null handle");
+  try {
+    return h->eng->get_state(buf, size);
+  } catch (const std::bad_alloc&) {
+    return fail(SPAI_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_set_state(spai_handle_t* h, const void* buf, size_t size) {
+  if (!h) return fail(SPAI_ERR_ARG, "null handle");
+  try {
+    return h->eng->set_state(buf, size);
   } catch (const std::bad_alloc&) {
     return fail(SPAI_ERR_NOMEM, "host allocation failed");
   } catch (...) {

@@ -54,7 +54,8 @@ EXPORTS = [
     "spai_default_opts", "spai_create", "spai_iterate", "spai_get", "spai_stats",
     "spai_destroy", "pcg_solve", "spai_loss_fwd", "spai_loss_bwd", "spai_create_batched",
     "spai_batched_resid", "spai_last_error", "spai_status_string", "spai_reset", "spai_pcg",
-    "spai_profile", "spai_spectrum", "spai_csr_spectrum", "spai_autotune",
+    "spai_profile", "spai_spectrum", "spai_csr_spectrum", "spai_autotune", "spai_get_state",
+    "spai_set_state",
 ]
 A_FORMATS = {"auto": 0, "csr": 1, "ell": 2}
 PHASES = ["dots", "update", "resid", "select", "compact", "bounds", "scalar", "pcg", "pcg_ax",
@@ -103,6 +104,8 @@ def load():
     lib.spai_profile.argtypes = [P, P, P, P]
     lib.spai_spectrum.argtypes = [P, C.c_int, P, C.c_int, P, C.POINTER(C.c_int)]
     lib.spai_autotune.argtypes = [P, C.c_int, C.c_int, P, P]
+    lib.spai_get_state.argtypes = [P, P, C.POINTER(C.c_size_t)]
+    lib.spai_set_state.argtypes = [P, P, C.c_size_t]
     lib.spai_csr_spectrum.argtypes = [C.POINTER(CsrT), C.c_int, P, P, C.POINTER(C.c_int),
                                       C.POINTER(OptsT)]
     lib.spai_last_error.restype = C.c_char_p
@@ -330,6 +333,19 @@ class SPAI:
         _check(load().spai_spectrum(self.h, int(steps), ptr, dev, out.ctypes.data,
                                     C.byref(done)))
         return float(out[0]), float(out[1]), float(out[2]), float(out[3]), done.value
+
+    def get_state(self) -> bytes:
+        """Checkpoint: the handle's iterate, directions, residual and scalars as bytes."""
+        size = C.c_size_t(0)
+        _check(load().spai_get_state(self.h, None, C.byref(size)))
+        buf = C.create_string_buffer(size.value)
+        _check(load().spai_get_state(self.h, buf, C.byref(size)))
+        return buf.raw[: size.value]
+
+    def set_state(self, state: bytes):
+        """Resume from a checkpoint of a handle with the same problem and configuration."""
+        buf = C.create_string_buffer(bytes(state), len(state))
+        _check(load().spai_set_state(self.h, buf, len(state)))
 
     def autotune(self, warm_iters=5, reps=2):
         """Pick the per-column tiles for this workload (see spai_autotune) and restart from

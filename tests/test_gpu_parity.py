@@ -770,3 +770,58 @@ def test_pcg_graph_replay_matches_eager():
     Ab = sp.block_diag(mats, format="csr")
     Xe, ite, _, rce = S.pcg_solve(Ab, Mb, Bb, rtol=1e-9)
     assert rcb == rce and list(itb) == list(ite) and np.array_equal(Xb, Xe)
+
+
+# ----------------------------------------------------------------------------
+# checkpoint / resume
+# ----------------------------------------------------------------------------
+
+def _resume_case(S, make_handle, k1, k2):
+    h1 = make_handle()
+    h1.iterate(k1)
+    state = h1.get_state()
+    _, hist_a, _ = h1.iterate(k2)
+    m_a = h1.get()
+    h2 = make_handle()
+    h2.set_state(state)
+    _, hist_b, _ = h2.iterate(k2)
+    m_b = h2.get()
+    assert np.array_equal(hist_a, hist_b) and (m_a != m_b).nnz == 0
+    assert h1.stats()["iters"] == h2.stats()["iters"] == k1 + k2
+    h1.set_state(state)                                     # rewind the original handle
+    _, hist_c, _ = h1.iterate(k2)
+    assert np.array_equal(hist_a, hist_c)
+    h1.close()
+    return h2, state
+
+
+@pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
+@pytest.mark.parametrize("variant", ["f64", "mixed-jacobi", "implicit-jacobi"])
+def test_checkpoint_resume_bitwise(method, variant):
+    """A handle restored from a state continues exactly as the one it came from."""
+    S = _spai()
+    A = W.lognormal3d(9, 12)
+    if variant == "f64":
+        mk = lambda: S.SPAI(A, method, "global", 2.0, True, max_iter=12)
+    elif variant == "mixed-jacobi":
+        mk = lambda: S.SPAI(A, method, "column", 3.0, True, max_iter=12,
+                            options=S.Options(precision="mixed", jacobi=True))
+    else:
+        mk = lambda: S.SPAI(A, method, "none", 0, False, max_iter=12,
+                            options=S.Options(jacobi=True, **IMPLICIT))
+    h2, state = _resume_case(S, mk, 4, 5)
+    other = S.SPAI(A, "mr" if method != "mr" else "cg", "global", 2.0, True, max_iter=12)
+    with pytest.raises(S.SpaiError):
+        other.set_state(state)                              # another method
+    with pytest.raises(S.SpaiError):
+        h2.set_state(state[:-8])                            # truncated
+    other.close()
+    h2.close()
+
+
+def test_checkpoint_resume_batched():
+    S = _spai()
+    mats = W.batch_geometric(3, 31, 300, 700)
+    mk = lambda: S.SPAI(None, "mr", "column", 4.0, False, max_iter=10, batch=mats)
+    h2, _ = _resume_case(S, mk, 3, 4)
+    h2.close()
