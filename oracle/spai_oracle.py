@@ -13,6 +13,12 @@ unit of the objective (Section 2).  Support means the set of nonzero entries,
 as in the definitions of supp(P) and supp(M) (Section 6.1, Appendix A): stored
 zeros are removed.
 
+Every function here is pinned by tests/test_oracle_pins.py against what the paper
+and the mathematics fix (closed forms, the theorems of Sections 2-5, brute force on
+small inputs, library routines for special cases).  Parity unpinned: whole trajectories
+with dropping (the drop rules and the steps are pinned one by one, their composition
+over many iterations has no independent reference).
+
 Readings of points the paper leaves open (each is an argument, shared with the
 GPU library's options):
 
