@@ -9,8 +9,8 @@ memory before the timed region.  Prints one JSON line (rank 0).
 
 Extra legs (not timed as steps): the float64 path on the same workload and the
 mixed-vs-float64 time to equal ||I - A M||_F, the Pi-weighted LOMR, the Appendix A
-heuristic drop score under the same cap, Lanczos extremes of the final M, and the CPU
-oracle on a bounded sample.
+heuristic drop score under the same cap, Lanczos extremes of the final M, the batched
+form on 256 random geometric-graph matrices, and the CPU oracle on a bounded sample.
 """
 import argparse
 import json
@@ -54,14 +54,15 @@ def algorithmic_bytes(c, n, nnzA, s_val, s_aval, iters):
     }
 
 
-def lomr_alg_bytes(c, n, nnzA, s_val, s_aval, iters):
+def lomr_alg_bytes(c, n, nnzA, s_val, s_aval, iters, with_p=True):
     """Whole-iteration algorithmic bytes of LOMR (each operand of the iteration read once,
-    each output written once): 2E(A) + 3E(R) + 3E(P) + 3E(M), E(X) = nnz(X)(s + 4) + 8(n + 1)."""
+    each output written once): 2E(A) + 3E(R) + 3E(P) + 3E(M), E(X) = nnz(X)(s + 4) + 8(n + 1);
+    MR (with_p False) has no P term."""
     def E(nnz, s):
         return nnz * (s + 4) + 8 * (n + 1)
     it = max(iters, 1)
-    return (2 * E(nnzA, s_aval) + 3 * E(c["resid"] / it, s_val) + 3 * E(c["kept_p"] / it, s_val)
-            + 3 * E(c["kept_m"] / it, s_val))
+    return (2 * E(nnzA, s_aval) + 3 * E(c["resid"] / it, s_val)
+            + (3 * E(c["kept_p"] / it, s_val) if with_p else 0) + 3 * E(c["kept_m"] / it, s_val))
 
 
 # kernel of each timed phase, and the source file its code lives in
@@ -188,6 +189,60 @@ def cpu_baseline(A, budget_s=20.0):
                       f"(global cap 2 nnz(A)), {dt:.1f} s, single-threaded scipy"}
 
 
+def batched_leg(S, W, torch, np, iters=20, nrhs=8):
+    """The batched form on random-graph SPD matrices: 256 geometric-graph Laplacians with
+    diagonal shifts (n ~ U{500..20000}) as one handle, MR, column cap 4, float32 values
+    with float64 sums, tiles autotuned, 20 iterations from M_0 replayed from the handle's
+    HIP graph and timed as a whole (a batched handle has no per-phase events); then PCG
+    with the block-diagonal A and M on nrhs right-hand sides."""
+    wl = W.workload("geo256")
+    mats = wl.A
+    n = sum(A.shape[0] for A in mats)
+    nnz = sum(A.nnz for A in mats)
+    log(f"batched: {len(mats)} geometric-graph matrices, n={n}, nnz={nnz}")
+    h = S.SPAI(None, "mr", "column", 4.0, False, max_iter=iters,
+               options=S.Options(precision="mixed"), batch=mats)
+    tiles, _ = h.autotune(warm_iters=3, reps=2)
+    h.reset()
+    h.iterate(iters)                                  # warm-up (graph capture)
+    _, _, k0 = h.profile()
+    h.reset()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    done, _, _ = h.iterate(iters)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t
+    _, _, k1 = h.profile()
+    res = h.batched_resid()
+    its = max(k1["iters"] - k0["iters"], 1)
+    cnt = {k: k1[k] - k0[k] for k in k1}
+    it_bytes = lomr_alg_bytes(cnt, n, nnz, 4, 4, its, with_p=False)
+    ms_it = T / max(done, 1) * 1e3
+    got = it_bytes / (ms_it * 1e-3) / 1e9
+    B = torch.from_numpy(W.rhs(n, nrhs, W.seed_for(4, 1))).cuda()
+    h.pcg(B, rtol=1e-8, max_iter=10000)               # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, pit, rel, rc = h.pcg(B, rtol=1e-8, max_iter=10000)
+    torch.cuda.synchronize()
+    Tp = time.perf_counter() - t
+    h.close()
+    out = {
+        "workload": f"{len(mats)} random geometric-graph Laplacians + shift, n={n}, nnz={nnz}; "
+                    f"MR, column cap 4, float32 values, float64 sums, {iters} iterations",
+        "iters": done, "iters_per_s": done / T, "ms_per_iter": ms_it,
+        "tiles": tiles,
+        "iteration_alg_bytes": it_bytes,
+        "roofline": {"bound": "hbm", "kernel": "whole iteration (graph replay)", "achieved": got,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": got / HBM_PEAK_GBS},
+        "resid_fro_max": float(res.max()), "resid_fro_median": float(np.median(res)),
+        "pcg": {"nrhs": nrhs, "iters_max": int(pit.max()), "iters_min": int(pit.min()),
+                "max_true_rel_res": float(rel.max()), "status": int(rc), "seconds": Tp},
+    }
+    log("batched:", json.dumps(out))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +258,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiles")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the heuristic-score and spectrum legs")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched random-graph leg")
     ap.add_argument("--exp05", action="store_true",
                     help="run the Experiment 05/06 protocol on the paper's recipe matrices and exit")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="BYTES",
@@ -396,6 +453,9 @@ def main():
         hs.close()
         log("score drop:", json.dumps(score))
 
+    # ---------------- batched form: 256 random geometric-graph Laplacians in one handle
+    batched = None if args.no_batched else batched_leg(S, W, torch, np)
+
     cpu = None if args.no_cpu else cpu_baseline(A)
     if cpu:
         log("cpu baseline:", json.dumps(cpu))
@@ -438,6 +498,7 @@ def main():
         "autotune": tuned,
         "score_lomr": score,
         "spectrum_of_m": spec,
+        "batched_geo256": batched,
     }
     print(json.dumps(out), flush=True)
 

@@ -4,7 +4,8 @@
 // Every right-hand side runs its own textbook recurrence in float64; the block of
 // vectors is row-major (n x nrhs, the nrhs values of a row contiguous), so one
 // wavefront reads the 64 values of a row of X as one coalesced 512-byte line and the
-// SpMM gathers whole rows.  Frobenius-free per-RHS dots are reduced per workgroup in
+// SpMM gathers whole rows (with at most 32 right-hand sides, pow2(nrhs) lanes share a
+// row instead).  Frobenius-free per-RHS dots are reduced per workgroup in
 // a fixed order and then across workgroups in a fixed order (deterministic).
 #include <hip/hip_runtime.h>
 
@@ -234,6 +235,88 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
     double sum = 0.0;
     for (int w = 0; w < WPB; ++w) sum += sh[w * 64 + threadIdx.x];
     part[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = sum;
+  }
+}
+
+// The product for at most 32 right-hand sides.  A wave of k_spmm_wave would leave
+// 64 - nrhs lanes idle; here R = pow2(nrhs) lanes share a row (lane r owns right-hand
+// side r), so a workgroup has kThreads / R rows in flight, and each lane sums its row's
+// entries in stored order, eight entries and their gathers issued together (the order
+// of k_spmm_wave: the rows of Y are the same bit for bit).  Positions are dealt as in
+// k_spmm_wave: eight contiguous XCD ranges, each workgroup a contiguous chunk of
+// narrow_chunk(R) positions, its lanes taking them kThreads / R at a time.  With dot
+// set, per-block partials of sum_i X[i, r] Y[i, r], stored transposed as there.
+template <int R>
+constexpr int narrow_rpt() { return R / 4 > 4 ? R / 4 : 4; }   // rows per lane
+template <int R>
+constexpr int narrow_chunk() { return (kThreads / R) * narrow_rpt<R>(); }
+
+template <typename VT, int LAY, int R>
+__global__ __launch_bounds__(kThreads) void k_spmm_narrow(Mat A, const double* X, double* Y,
+                                                          int dot, int nrhs,
+                                                          const int32_t* order, double* part) {
+  static_assert(narrow_chunk<R>() >= (kThreads / 64) * kRowsPerWave,
+                "no more workgroups than the partial buffer holds");
+  __shared__ double sh[kThreads];
+  constexpr int G = kThreads / R;
+  constexpr int RPT = narrow_rpt<R>();
+  const int t = threadIdx.x;
+  const int r = t % R, g = t / R;
+  const int64_t xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
+  const int64_t per = (A.n + 7) / 8;
+  const int64_t r0 = xcd * per;
+  const int64_t r1 = r0 + per < A.n ? r0 + per : A.n;
+  const int64_t base = r0 + kb * (int64_t)narrow_chunk<R>();
+  double acc = 0.0;
+  if (r < nrhs) {
+    for (int j = 0; j < RPT; ++j) {
+      const int64_t k = base + (int64_t)j * G + g;
+      if (k >= r1) break;
+      const int64_t i = order ? (int64_t)order[k] : k;
+      const int64_t a = row_lo<LAY>(A, i), b = row_hi<LAY>(A, i);
+      double y = 0.0, xd = 0.0;
+      bool found = false;
+      for (int64_t q0 = a; q0 < b; q0 += 8) {
+        int cc[8];
+        VT vv[8];
+        double xx[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          cc[u] = -1;
+          vv[u] = 0;
+          if (q0 + u < b) {
+            cc[u] = A.col[q0 + u];
+            vv[u] = entry_val<VT>(A, q0 + u);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xx[u] = cc[u] >= 0 ? X[(int64_t)cc[u] * nrhs + r] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (cc[u] >= 0) {               // ELL padding (column -1) sits last
+            y += (double)vv[u] * xx[u];
+            if (cc[u] == (int)i) {
+              xd = xx[u];
+              found = true;
+            }
+          }
+        if (cc[7] < 0) break;
+      }
+      Y[i * nrhs + r] = y;
+      if (dot) {
+        // a row without a diagonal entry loads X[i, r] after all
+        const double wx = found ? xd : X[i * nrhs + r];
+        acc += wx * y;
+      }
+    }
+  }
+  if (!part) return;
+  sh[t] = acc;
+  __syncthreads();
+  if (t < R && t < nrhs) {
+    double sum = 0.0;
+    for (int w = 0; w < G; ++w) sum += sh[w * R + t];
+    part[(int64_t)t * gridDim.x + blockIdx.x] = sum;
   }
 }
 
@@ -522,8 +605,24 @@ struct Solver {
   }
   int spmm_grid = 8;
 
+  template <typename VT, int LAY, int R>
+  void spmm_narrow(const Mat& K, const double* X, double* Y, double* pt) {
+    const int64_t per = (n + 7) / 8;
+    spmm_grid = (int)(8 * ((per + narrow_chunk<R>() - 1) / narrow_chunk<R>()));
+    hipLaunchKernelGGL((k_spmm_narrow<VT, LAY, R>), dim3(spmm_grid), dim3(kThreads), 0, s, K, X,
+                       Y, pt ? 1 : 0, nrhs, order, pt);
+  }
   template <typename VT, int LAY>
   void spmm_as(const Mat& K, const double* X, double* Y, double* pt) {
+    switch (nrhs <= 32 ? pow2(nrhs) : 0) {   // few right-hand sides: rows share a wave
+      case 1: return spmm_narrow<VT, LAY, 1>(K, X, Y, pt);
+      case 2: return spmm_narrow<VT, LAY, 2>(K, X, Y, pt);
+      case 4: return spmm_narrow<VT, LAY, 4>(K, X, Y, pt);
+      case 8: return spmm_narrow<VT, LAY, 8>(K, X, Y, pt);
+      case 16: return spmm_narrow<VT, LAY, 16>(K, X, Y, pt);
+      case 32: return spmm_narrow<VT, LAY, 32>(K, X, Y, pt);
+      default: break;
+    }
     spmm_grid = spmm_blocks(n);
     for (int c0 = 0; c0 < nrhs; c0 += 64)
       hipLaunchKernelGGL((k_spmm_wave<VT, LAY>), dim3(spmm_grid), dim3(kThreads), 0, s, K, X, Y,
