@@ -189,6 +189,15 @@ def cpu_baseline(A, budget_s=20.0):
                       f"(global cap 2 nnz(A)), {dt:.1f} s, single-threaded scipy"}
 
 
+def state_min_bytes(c, n, nnzA, s_val, s_aval, iters):
+    """State-only lower bound of a LOMR iteration: A once, M and P read and written once,
+    R recomputed per column and never stored: E(A) + 2E(M) + 2E(P)."""
+    def E(nnz, s):
+        return nnz * (s + 4) + 8 * (n + 1)
+    it = max(iters, 1)
+    return E(nnzA, s_aval) + 2 * E(c["kept_m"] / it, s_val) + 2 * E(c["kept_p"] / it, s_val)
+
+
 def batched_leg(S, W, torch, np, iters=20, nrhs=8):
     """The batched form on random-graph SPD matrices: 256 geometric-graph Laplacians with
     diagonal shifts (n ~ U{500..20000}) as one handle, MR, column cap 4, float32 values
@@ -359,6 +368,8 @@ def main():
     top = max(roofs.values(), key=lambda r: r["ms_per_step"])
     it_bytes = lomr_alg_bytes(cnt, n, nnzA, 4, 4, iters_timed)
     it_gbs = it_bytes / (spai_ms / max(iters_timed, 1) * 1e-3) / 1e9
+    min_bytes = state_min_bytes(cnt, n, nnzA, 4, 4, iters_timed)
+    min_gbs = min_bytes / (spai_ms / max(iters_timed, 1) * 1e-3) / 1e9
     r_mixed = float(hist[-1])
     log(f"mixed: ||I-AM||_F after {done} its = {r_mixed:.6e}, nnz(M)={stats['nnz_m']}, "
         f"nnz(P)={stats['nnz_p']}; SPAI {spai_ms / max(iters_timed, 1):.3f} ms/it")
@@ -381,6 +392,7 @@ def main():
     # ---------------- float64 path and time to equal residual
     f64 = None
     if not args.no_f64:
+        M_mixed = h.get()                           # the mixed path's final iterate
         h.close()
         h64 = make("f64", True)
         step(h64, args.iters)                       # warm-up
@@ -393,7 +405,12 @@ def main():
         m1, c1, k1 = h64.profile()
         spai64 = sum(m1[k] - m0[k] for k in m1 if not k.startswith("pcg"))
         r64 = float(hist64[-1])
+        M_f64 = h64.get()
         h64.close()
+        # both final iterates' ||I - A M||_F evaluated in float64 (the loss entry point)
+        ev_mixed = math.sqrt(S.loss_fwd(A, M_mixed))
+        ev_f64 = math.sqrt(S.loss_fwd(A, M_f64))
+        del M_mixed, M_f64
         # mixed until ||I - A M||_F <= r64 (1 + 1e-5), at most 60 iterations
         hm = make("mixed", True)
         a0, _, q0 = hm.profile()
@@ -406,6 +423,7 @@ def main():
         hm.close()
         f64 = {
             "f64_resid_fro_30": r64, "mixed_resid_fro_30": r_mixed,
+            "f64_evaluated_resid_fro_30": {"f64_path": ev_f64, "mixed_path": ev_mixed},
             "rel_diff_30": abs(r_mixed - r64) / r64,
             "f64_spai_ms_per_iter": f64_ms_per_it, "mixed_spai_ms_per_iter": mixed_ms_per_it,
             "per_iter_speedup": f64_ms_per_it / mixed_ms_per_it,
@@ -484,6 +502,8 @@ def main():
         "roofline_per_kernel": roofs,
         "iteration_alg_bytes": it_bytes,
         "iteration_alg_gbs": it_gbs,
+        "iteration_min_bytes": min_bytes,
+        "iteration_min_gbs": min_gbs,
         "cpu_baseline": cpu,
         "spai_ms_per_iter": spai_ms / max(iters_timed, 1),
         "pcg_ms_per_step": ph_ms["pcg"] / args.steps,
