@@ -184,9 +184,17 @@ def cpu_baseline(A, budget_s=20.0):
         if dt * 2.5 > budget_s or its >= 4:
             break
         its += 1
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")),
+                         model)
+    except OSError:
+        pass
     return {"value": its / dt, "unit": "SPAI iters/s", "cores": 1, "kind": "oracle",
             "sample": f"{its} FP64 LOMR iteration(s) from M_0 on the 96^3 lognormal matrix "
-                      f"(global cap 2 nnz(A)), {dt:.1f} s, single-threaded scipy"}
+                      f"(global cap 2 nnz(A)), {dt:.1f} s, single-threaded scipy on one core of "
+                      f"{os.cpu_count()} ({model})"}
 
 
 def state_min_bytes(c, n, nnzA, s_val, s_aval, iters):
