@@ -78,9 +78,9 @@ def measured_traffic(kernel):
     summary, or None when that summary is missing or was taken on other kernel source."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_lognormal96.md")
-    src = os.path.join(ROOT, "paper_2511_09753_amd", "csrc", KERNEL_SOURCE[kernel])
-    if not os.path.exists(path):
+    if kernel not in KERNEL_SOURCE or not os.path.exists(path):
         return None
+    src = os.path.join(ROOT, "paper_2511_09753_amd", "csrc", KERNEL_SOURCE[kernel])
     want = hashlib.sha256(open(src, "rb").read()).hexdigest()
     vals = {}
     for line in open(path):
