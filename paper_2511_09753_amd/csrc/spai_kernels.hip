@@ -478,7 +478,15 @@ __global__ void k_bound_resid(Csr A, Pair<T> Mp, int64_t* ub, int64_t n, const D
   const int64_t b = M.beg[j];
   const int lm = M.len[j];
   int64_t s = 1;
-  for (int e = 0; e < lm; ++e) {
+  int e = 0;
+  for (; e + 4 <= lm; e += 4) {       // four entries' loads in flight together
+    int l[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) l[u] = M.idx[b + e + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += A.rowptr[l[u] + 1] - A.rowptr[l[u]];
+  }
+  for (; e < lm; ++e) {
     const int l = M.idx[b + e];
     s += A.rowptr[l + 1] - A.rowptr[l];
   }
@@ -1110,29 +1118,32 @@ void launch_bound_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> 
                      R, P, PT, md, ub, n, st);
 }
 
-// (b+1)-th largest of the magnitudes v[0..cnt) in LDS (0 if cnt <= b), same on all lanes
-__device__ inline double kth_largest(const double* v, int cnt, int b) {
-  double t = 0.0;
-  if (cnt > b) {
-    for (int e = lane_id(); e < cnt; e += SPAI_WAVE) {
-      const double x = v[e];
-      int r = 0;
-      for (int f = 0; f < cnt; ++f) {
-        const double y = v[f];
-        r += (y > x) || (y == x && f < e);
-      }
-      if (r == b) t = x;
-    }
-  }
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) t = fmax(t, __shfl_xor(t, d, SPAI_WAVE));
-  return t;
-}
-
-// the same from a candidate column in global memory, skipping the entry with row `skip`
+// (b+1)-th largest magnitude of a candidate column in global memory (0 if it has at
+// most b entries), skipping the entry with row `skip`; the same on all lanes.
+// Up to 64 candidates: one per lane, loaded once, the others' magnitudes broadcast from
+// their lanes (the same comparisons in the same order as the general loop below).
 template <typename T>
 __device__ inline double kth_largest_cols(const int32_t* idx, const T* val, int cnt, int skip,
                                           int b) {
+  if (cnt <= SPAI_WAVE) {
+    const int lane = lane_id();
+    const bool have = lane < cnt;
+    const bool use = have && idx[lane] != skip;
+    const double x = have ? fabs((double)val[lane]) : 0.0;
+    const unsigned long long um = __ballot(use);
+    double t = 0.0;
+    if (__popcll(um) > b) {
+      int r = 0;
+      for (int f = 0; f < cnt; ++f) {
+        const double y = __shfl(x, f, SPAI_WAVE);
+        if ((um >> f) & 1ull) r += (y > x) || (y == x && f < lane);
+      }
+      if (use && r == b) t = x;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) t = fmax(t, __shfl_xor(t, d, SPAI_WAVE));
+    return t;
+  }
   int m = 0;
   for (int e = lane_id(); e < cnt; e += SPAI_WAVE) m += idx[e] != skip;
   m = wave_sum_int(m);
