@@ -241,14 +241,29 @@ int spai_spectrum(spai_handle_t* h, int steps, const double* v0, int on_device, 
  * spai_autotune — pick the per-column tiles (the boundary between a kernel's LDS tiers)
  *   for this handle's workload: restart from M_0, run warm_iters iterations (at most
  *   max_iter), time every candidate small tile of the residual, dots and update kernels
- *   on that state (best of reps launches each), keep the fastest, and restart from M_0
+ *   on that state (best of reps launches each), keep the fastest where it beats the
+ *   handle's current tile by at least 3% (else the current one), and restart from M_0
  *   (as spai_reset).  Results do not depend on the tiles (every column's arithmetic
  *   and summation order are the same in every tier); batched handles recapture their
- *   graph.  chosen (may be NULL): 6 ints, L and H of the residual, dots and update
- *   tiles; best_ms (may be NULL): 3 doubles, their measured launch times.
+ *   graph.  The update kernel's resident tier is also timed with its registers capped
+ *   at five waves per SIMD (faster where columns are small).  chosen (may be NULL):
+ *   7 ints, L and H of the residual, dots and update tiles, then the update tier's
+ *   waves-per-SIMD cap (5, or 0 for the compiler's choice); best_ms (may be NULL):
+ *   3 doubles, their measured launch times.
  *   Synchronises the stream.
  */
 int spai_autotune(spai_handle_t* h, int warm_iters, int reps, int* chosen, double* best_ms);
+
+/*
+ * spai_set_tiles — use the given per-column tiles from the next launch on, for
+ *   instance those a previous spai_autotune reported for the same workload.  tiles:
+ *   7 host ints in the layout of spai_autotune's chosen.  Accepted: every H a power of
+ *   two >= 512; the residual and dots L a power of two >= 32, the update L >= 32; the
+ *   update's waves 0 or 5; each tile within 64 KB of LDS.  Anything else returns
+ *   SPAI_ERR_ARG and leaves the tiles unchanged.  Results do not depend on the tiles;
+ *   a batched handle recaptures its graph.  Synchronises the stream.
+ */
+int spai_set_tiles(spai_handle_t* h, const int* tiles);
 
 /*
  * spai_get_state / spai_set_state — checkpoint and resume a handle.  The state holds the

@@ -257,6 +257,7 @@ struct EngineBase {
   virtual int spectrum(int steps, const double* v0, int on_device, double* out,
                        int* steps_done) = 0;
   virtual int autotune(int warm_iters, int reps, int* chosen, double* best_ms) = 0;
+  virtual int set_tiles(const int* tiles) = 0;
   virtual int get_state(void* buf, size_t* size) = 0;
   virtual int set_state(const void* buf, size_t size) = 0;
 };
@@ -794,12 +795,51 @@ struct Engine : EngineBase {
     return SPAI_OK;
   }
 
+  static bool same_tile(const Tile& a, const Tile& b) {
+    return a.L == b.L && a.H == b.H && a.waves == b.waves;
+  }
+
+  // Tiles chosen by the caller (for instance those a previous spai_autotune reported):
+  // checked against what the kernels assume, then used from the next launch on.
+  int set_tiles(const int* c) override {
+    if (!c) return fail(SPAI_ERR_ARG, "spai_set_tiles: null tiles");
+    auto pow2 = [](int x) { return x > 0 && (x & (x - 1)) == 0; };
+    // H: the key set's insertion batches assume H >= 512 (limit + 256 < H); the
+    // residual's and dots' position maps hold next_pow2(2 L) slots, so their L is a
+    // power of two; every tile fits the 64 KB of LDS a workgroup may take.
+    const bool ell = A.eshift >= 0;
+    constexpr size_t kMaxLds = 64 * 1024;
+    Tile r{c[0], c[1]}, d{c[2], c[3]}, u{c[4], c[5]};
+    u.waves = c[6];
+    const bool ok = pow2(r.L) && r.L >= 32 && pow2(d.L) && d.L >= 32 && u.L >= 32 &&
+                    pow2(r.H) && r.H >= 512 && pow2(d.H) && d.H >= 512 && pow2(u.H) &&
+                    u.H >= 512 && (u.waves == 0 || u.waves == 5) &&
+                    resid_tile_bytes(r, ell) <= kMaxLds && dots_tile_bytes(d, ell) <= kMaxLds &&
+                    update_tile_bytes(u) <= kMaxLds;
+    if (!ok) return fail(SPAI_ERR_ARG, "spai_set_tiles: tile outside what the kernels accept");
+    HIPCHK(hipStreamSynchronize(s));
+    tRs = r;
+    tDs = d;
+    tUs = u;
+    if (graph_exec) {                   // a captured iteration holds the old tiles
+      (void)hipGraphExecDestroy(graph_exec);
+      graph_exec = nullptr;
+    }
+    if (graph) {
+      (void)hipGraphDestroy(graph);
+      graph = nullptr;
+    }
+    return SPAI_OK;
+  }
+
   // Tile autotuner: run warm_iters iterations, then time every candidate small tile of
   // the residual, dots and update kernels (all three tiers of one launch, best of reps)
-  // on that state, keep the fastest of each, and restart from M_0.  A tile only moves
-  // the boundary between the tiers (which columns a kernel defers to its larger tiles);
-  // every column's arithmetic and every sum's order are the same in all tiers, so the
-  // results do not depend on the choice.
+  // on that one state, and restart from M_0.  A candidate replaces the handle's current
+  // tile only when it is at least 3% faster: one state is a noisy stand-in for a whole
+  // run, and near-ties measured on it have gone either way over the iterations that
+  // follow.  A tile only moves the boundary between the tiers (which columns a kernel
+  // defers to its larger tiles); every column's arithmetic and every sum's order are the
+  // same in all tiers, so the results do not depend on the choice.
   int autotune(int warm_iters, int reps, int* chosen, double* best_ms) override {
     if (warm_iters < 0 || reps < 1) return fail(SPAI_ERR_ARG, "spai_autotune: bad arguments");
     int rc;
@@ -837,7 +877,7 @@ struct Engine : EngineBase {
     launch_bound_resid<T>(A, M, ub, n, st, s);
     launch_scan(ub, off, total, n, scantmp, s);
     Tile bestR = tRs;
-    double tR = 1e300;
+    double tR = 1e300, curR = 1e300;
     for (int L : {64, 128, 256})
       for (int H : {512, 1024}) {
         const Tile t{L, H};
@@ -846,12 +886,13 @@ struct Engine : EngineBase {
           launch_resid<T>(A, M, R, off, total, colnorm, opts.jacobi, colrz, big[0], st, t, tRl,
                           tRh, s);
         });
+        if (same_tile(t, tRs)) curR = ms;
         if (ms < tR) { tR = ms; bestR = t; }
       }
     // dots: A R, A P on the current R, P (per-column partials only)
     const int useR = method != SPAI_CG, useP = method != SPAI_MR;
     Tile bestD = tDs;
-    double tD = 1e300;
+    double tD = 1e300, curD = 1e300;
     for (int L : {128, 256, 512})
       for (int H : {512, 1024}) {
         const Tile t{L, H};
@@ -859,6 +900,7 @@ struct Engine : EngineBase {
         const double ms = timed([&] {
           launch_dots<T>(A, R, P, useR, useP, opts.jacobi, colpart, big[1], st, t, tDl, tDh, s);
         });
+        if (same_tile(t, tDs)) curD = ms;
         if (ms < tD) { tD = ms; bestD = t; }
       }
     // update: the candidates of M (and P) written to the next buffers
@@ -867,28 +909,33 @@ struct Engine : EngineBase {
     launch_bound_update<T>(A, M, R, P, PT, md, ub, n, st, s);
     launch_scan(ub, off, total, n, scantmp, s);
     Tile bestU = tUs;
-    double tU = 1e300;
+    double tU = 1e300, curU = 1e300;
     for (int L : {256, 384, 512})
-      for (int H : {512, 1024}) {
-        const Tile t{L, H};
-        if (update_tile_bytes(t) > kMaxLds) continue;
-        const double ms = timed([&] {
-          launch_update<T>(A, M, R, P, PT, md, off, total, kcol, tM, tP, big[2], seg, st, t, tUl,
-                           tUh, s);
-        });
-        if (ms < tU) { tU = ms; bestU = t; }
-      }
+      for (int H : {512, 1024})
+        for (int waves : {0, 5}) {           // 5: the register-capped resident tier
+          Tile t{L, H};
+          t.waves = waves;
+          if (update_tile_bytes(t) > kMaxLds) continue;
+          const double ms = timed([&] {
+            launch_update<T>(A, M, R, P, PT, md, off, total, kcol, tM, tP, big[2], seg, st, t,
+                             tUl, tUh, s);
+          });
+          if (same_tile(t, tUs)) curU = ms;
+          if (ms < tU) { tU = ms; bestU = t; }
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIPCHK(hipGetLastError());
     if ((rc = check_err())) return rc;
-    tRs = bestR;
-    tDs = bestD;
-    tUs = bestU;
+    constexpr double kGain = 0.97;   // a candidate must beat the current tile by 3%
+    if (tR < kGain * curR) tRs = bestR; else if (curR < 1e300) tR = curR;
+    if (tD < kGain * curD) tDs = bestD; else if (curD < 1e300) tD = curD;
+    if (tU < kGain * curU) tUs = bestU; else if (curU < 1e300) tU = curU;
     if (chosen) {
       chosen[0] = tRs.L; chosen[1] = tRs.H;
       chosen[2] = tDs.L; chosen[3] = tDs.H;
       chosen[4] = tUs.L; chosen[5] = tUs.H;
+      chosen[6] = tUs.waves;
     }
     if (best_ms) {
       best_ms[0] = tR < 1e300 ? tR : 0.0;
@@ -1465,6 +1512,15 @@ int spai_set_state(spai_handle_t* h, const void* buf, size_t size) {
     return h->eng->set_state(buf, size);
   } catch (const std::bad_alloc&) {
     return fail(SPAI_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_set_tiles(spai_handle_t* h, const int* tiles) {
+  if (!h) return fail(SPAI_ERR_ARG, "null handle");
+  try {
+    return h->eng->set_tiles(tiles);
   } catch (...) {
     return fail(SPAI_ERR_HIP, "unexpected exception");
   }

@@ -80,7 +80,11 @@ struct BigList {
   int64_t scratch_stride = 0;
 };
 
-struct Tile { int L, H, DG = 0; }; // per-column tile: list entries, hash slots, neighbours (0: default)
+struct Tile {      // per-column tile
+  int L, H;        // list entries, hash slots
+  int DG = 0;      // update: neighbour columns (0: default)
+  int waves = 0;   // update, resident tier: 5 = registers capped at five waves per SIMD
+};
 constexpr int kHugeGrid = 64;      // workgroups of the huge-tile pass
 
 struct UpdMode {

@@ -1167,12 +1167,11 @@ __device__ inline double kth_largest_cols(const int32_t* idx, const T* val, int 
 }
 
 template <typename T, bool GS>
-__global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp,
-                                                      Pair<T> PTp, UpdMode md, const int64_t* off,
-                                                      const int64_t* total, const int32_t* kcol,
-                                                      double* tM, double* tP, BigList big,
-                                                      Seg seg, DevState* st, int tier, int L,
-                                                      int H, int DG) {
+__device__ __forceinline__ void update_body(Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp,
+                                            Pair<T> PTp, UpdMode md, const int64_t* off,
+                                            const int64_t* total, const int32_t* kcol,
+                                            double* tM, double* tP, BigList big, Seg seg,
+                                            DevState* st, int tier, int L, int H, int DG) {
   if (!st->any_active || !st->iter_active) return;
   extern __shared__ char smem[];
   Carve cv(tile_base<GS>(smem, big));
@@ -1487,6 +1486,30 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T>
   }
 }
 
+template <typename T, bool GS>
+__global__ __launch_bounds__(SPAI_WAVE) void k_update(Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp,
+                                                      Pair<T> PTp, UpdMode md, const int64_t* off,
+                                                      const int64_t* total, const int32_t* kcol,
+                                                      double* tM, double* tP, BigList big,
+                                                      Seg seg, DevState* st, int tier, int L,
+                                                      int H, int DG) {
+  update_body<T, GS>(A, Mp, R, Pp, PTp, md, off, total, kcol, tM, tP, big, seg, st, tier, L, H,
+                     DG);
+}
+
+// The same resident tier with registers capped at five waves per SIMD (a few spills):
+// slower on large columns, faster where columns are small and more columns in flight
+// pay; the register allocation does not change the arithmetic, so the tile autotuner
+// may pick either.
+template <typename T>
+__global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5))) void k_update_w5(
+    Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp, Pair<T> PTp, UpdMode md, const int64_t* off,
+    const int64_t* total, const int32_t* kcol, double* tM, double* tP, BigList big, Seg seg,
+    DevState* st, int tier, int L, int H, int DG) {
+  update_body<T, false>(A, Mp, R, Pp, PTp, md, off, total, kcol, tM, tP, big, seg, st, tier, L, H,
+                        DG);
+}
+
 static int update_deg(Tile t) { return t.DG ? t.DG : (t.L >= 2048 ? 256 : 64); }
 
 static size_t update_lds(Tile t, bool) {
@@ -1504,10 +1527,16 @@ void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, Up
                    Tile huge, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
-  hipLaunchKernelGGL((k_update<T, false>),
-                     dim3(resident_grid(k_update<T, false>, update_lds(small, true))),
-                     dim3(SPAI_WAVE), update_lds(small, true), s, A, M, R, P, PT, md, off, total,
-                     kcol, tM, tP, big, seg, st, 0, small.L, small.H, update_deg(small));
+  if (small.waves == 5)
+    hipLaunchKernelGGL((k_update_w5<T>),
+                       dim3(resident_grid(k_update_w5<T>, update_lds(small, true))),
+                       dim3(SPAI_WAVE), update_lds(small, true), s, A, M, R, P, PT, md, off,
+                       total, kcol, tM, tP, big, seg, st, 0, small.L, small.H, update_deg(small));
+  else
+    hipLaunchKernelGGL((k_update<T, false>),
+                       dim3(resident_grid(k_update<T, false>, update_lds(small, true))),
+                       dim3(SPAI_WAVE), update_lds(small, true), s, A, M, R, P, PT, md, off,
+                       total, kcol, tM, tP, big, seg, st, 0, small.L, small.H, update_deg(small));
   hipLaunchKernelGGL((k_update<T, false>), dim3(256), dim3(SPAI_WAVE), update_lds(large, false), s,
                      A, M, R, P, PT, md, off, total, kcol, tM, tP, big, seg, st, 1, large.L,
                      large.H, update_deg(large));

@@ -55,7 +55,7 @@ EXPORTS = [
     "spai_destroy", "pcg_solve", "spai_loss_fwd", "spai_loss_bwd", "spai_create_batched",
     "spai_batched_resid", "spai_last_error", "spai_status_string", "spai_reset", "spai_pcg",
     "spai_profile", "spai_spectrum", "spai_csr_spectrum", "spai_autotune", "spai_get_state",
-    "spai_set_state",
+    "spai_set_state", "spai_set_tiles",
 ]
 A_FORMATS = {"auto": 0, "csr": 1, "ell": 2}
 PHASES = ["dots", "update", "resid", "select", "compact", "bounds", "scalar", "pcg", "pcg_ax",
@@ -104,6 +104,7 @@ def load():
     lib.spai_profile.argtypes = [P, P, P, P]
     lib.spai_spectrum.argtypes = [P, C.c_int, P, C.c_int, P, C.POINTER(C.c_int)]
     lib.spai_autotune.argtypes = [P, C.c_int, C.c_int, P, P]
+    lib.spai_set_tiles.argtypes = [P, P]
     lib.spai_get_state.argtypes = [P, P, C.POINTER(C.c_size_t)]
     lib.spai_set_state.argtypes = [P, P, C.c_size_t]
     lib.spai_csr_spectrum.argtypes = [C.POINTER(CsrT), C.c_int, P, P, C.POINTER(C.c_int),
@@ -349,15 +350,23 @@ class SPAI:
 
     def autotune(self, warm_iters=5, reps=2):
         """Pick the per-column tiles for this workload (see spai_autotune) and restart from
-        M_0.  Returns {"resid": (L, H), "dots": (L, H), "update": (L, H)} and the best
-        launch times in ms."""
-        ch = np.zeros(6, dtype=np.int32)
+        M_0.  Returns {"resid": (L, H), "dots": (L, H), "update": (L, H, waves)} (waves: 5
+        when the update's resident tier runs capped at five waves per SIMD, else 0) and the
+        best launch times in ms."""
+        ch = np.zeros(7, dtype=np.int32)
         ms = np.zeros(3, dtype=np.float64)
         _check(load().spai_autotune(self.h, int(warm_iters), int(reps), ch.ctypes.data,
                                     ms.ctypes.data))
         tiles = {"resid": (int(ch[0]), int(ch[1])), "dots": (int(ch[2]), int(ch[3])),
-                 "update": (int(ch[4]), int(ch[5]))}
+                 "update": (int(ch[4]), int(ch[5]), int(ch[6]))}
         return tiles, {"resid": float(ms[0]), "dots": float(ms[1]), "update": float(ms[2])}
+
+    def set_tiles(self, tiles):
+        """Use the given tiles (the dict autotune returns) from the next launch on."""
+        r, d, u = tiles["resid"], tiles["dots"], tiles["update"]
+        ch = np.array([r[0], r[1], d[0], d[1], u[0], u[1], u[2] if len(u) > 2 else 0],
+                      dtype=np.int32)
+        _check(load().spai_set_tiles(self.h, ch.ctypes.data))
 
     def batched_resid(self):
         out = np.zeros(self.nseg, dtype=np.float64)
