@@ -135,9 +135,9 @@ def test_aniso256_full_against_stored_oracle(method):
         assert st["nnz_p"] == gold["nnz_p"][-1]
 
 
-@pytest.mark.parametrize("nrhs", [1, 4, 8, 16, 32, 48, 80])
+@pytest.mark.parametrize("nrhs", [1, 2, 4, 8, 16, 32, 48, 80])
 def test_pcg_multi_rhs_aniso(nrhs):
-    """Every width path of the block PCG: the narrow product with 1, 4, 8, 16 and 32
+    """Every width path of the block PCG: the narrow product with 1, 2, 4, 8, 16 and 32
     lanes per row (1 to 32 right-hand sides), one wave per row (48) and more than 64
     right-hand sides (80, chunks of 64 and the flat vector updates)."""
     S = _spai()
