@@ -15,9 +15,12 @@ zeros are removed.
 
 Every function here is pinned by tests/test_oracle_pins.py against what the paper
 and the mathematics fix (closed forms, the theorems of Sections 2-5, brute force on
-small inputs, library routines for special cases).  Parity unpinned: whole trajectories
-with dropping (the drop rules and the steps are pinned one by one, their composition
-over many iterations has no independent reference).
+small inputs, library routines for special cases).  Whole MR trajectories with
+dropping are pinned where they have a closed form (a constant-diagonal A under a cap
+that leaves room for the diagonal only: every iterate is a multiple of I).  Parity
+unpinned: trajectories with dropping that keep off-diagonal entries (the drop rules and
+the steps are pinned one by one, their composition over many iterations has no
+independent reference).
 
 Readings of points the paper leaves open (each is an argument, shared with the
 GPU library's options):

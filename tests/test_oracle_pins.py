@@ -775,3 +775,64 @@ def test_score_drop_run_stays_symmetric_and_capped():
         r = O.run(meth, A, rule, 6)
         assert r.M.nnz <= rule.m and abs(r.M - r.M.T).max() == 0.0
         assert r.resid[-1] < r.resid[0]
+
+
+# ----------------------------------------------------------------------------
+# a whole trajectory with dropping, in closed form
+# ----------------------------------------------------------------------------
+
+def _constant_diagonal_spd():
+    """SPD matrices whose diagonal is one constant a: a shifted periodic 1D Laplacian,
+    a shifted 4x4 torus Laplacian, and a random symmetric pattern on a dominant diagonal."""
+    n = 10
+    C = sp.diags([2.3 * np.ones(n), -np.ones(n - 1), -np.ones(n - 1)], [0, 1, -1]).tolil()
+    C[0, n - 1] = C[n - 1, 0] = -1.0
+    g = 4
+    T = sp.lil_matrix((g * g, g * g))
+    for x in range(g):
+        for y in range(g):
+            i = x * g + y
+            T[i, i] = 4.5
+            for j in (((x + 1) % g) * g + y, x * g + (y + 1) % g):
+                T[i, j] = T[j, i] = -1.0
+    rng = np.random.default_rng(9)
+    B = sp.random(14, 14, density=0.3, random_state=rng, data_rvs=lambda k: rng.uniform(-1, 1, k))
+    B = sp.triu(B, 1)
+    B = B + B.T
+    R = B + sp.identity(14) * (abs(B).sum(axis=1).max() + 0.5)
+    return [sp.csr_matrix(C), sp.csr_matrix(T), sp.csr_matrix(R)]
+
+
+@pytest.mark.parametrize("which", [0, 1, 2])
+@pytest.mark.parametrize("cap", ["global", "column"])
+def test_mr_with_diagonal_only_cap_follows_scalar_recurrence(which, cap):
+    """MR (Algorithm 1) with the drop rule of Section 6.1 and Appendix A, on an SPD A
+    whose diagonal is a constant a, under a cap that leaves room for the diagonal only
+    (global m = n, or one entry per column).  Every iterate is then m_i I: R_i = I - m_i A
+    commutes with A, the drop removes the whole off-diagonal part of m_i I + alpha_i R_i,
+    and the diagonal is kept, so
+        m_0 = tr A / tr A^2,   m_{i+1} = m_i + alpha_i (1 - a m_i),
+        alpha_i = <R_i, A R_i> / <A R_i, A R_i> = (t1 - 2 m t2 + m^2 t3) / (t2 - 2 m t3 + m^2 t4),
+        ||R_i||_F^2 = n - 2 m t1 + m^2 t2,   t_k = tr(A^k).
+    A mistake anywhere in the loop (the step size, the order of update, symmetrization and
+    drop, the diagonal exemption, the residual) leaves this scalar trajectory."""
+    A = _constant_diagonal_spd()[which]
+    n = A.shape[0]
+    a = A.diagonal()[0]
+    assert np.all(A.diagonal() == a)
+    D = A.toarray()
+    t1, t2, t3, t4 = (np.trace(np.linalg.matrix_power(D, k)) for k in (1, 2, 3, 4))
+    iters = 8
+    m = t1 / t2
+    want = [math.sqrt(n - 2 * m * t1 + m * m * t2)]
+    for _ in range(iters):
+        alpha = (t1 - 2 * m * t2 + m * m * t3) / (t2 - 2 * m * t3 + m * m * t4)
+        m = m + alpha * (1.0 - a * m)
+        want.append(math.sqrt(n - 2 * m * t1 + m * m * t2))
+    rule = (O.DropRule(mode="global", m=n) if cap == "global"
+            else O.DropRule(mode="column", k=np.ones(n, dtype=np.int64)))
+    res = O.mr(A, rule, iters)
+    assert res.iters == iters
+    assert np.allclose(res.resid, want, rtol=1e-12, atol=0.0)
+    M = sp.csr_matrix(res.M)
+    assert M.nnz == n and np.allclose(M.diagonal(), m, rtol=1e-12, atol=0.0)
