@@ -450,6 +450,59 @@ def test_diagonal_matrix(method):
     assert np.max(np.abs(Mg.diagonal() * d - 1.0)) <= 1e-15
 
 
+def _diag_cap_trajectory(A, iters):
+    """||R_i||_F of MR with a diagonal-only cap on a constant-diagonal SPD A, from the
+    scalar recurrence m_{i+1} = m_i + alpha_i (1 - a m_i) written through tr(A^k)."""
+    import math
+    D = A.toarray()
+    n, a = D.shape[0], D[0, 0]
+    t1, t2, t3, t4 = (np.trace(np.linalg.matrix_power(D, k)) for k in (1, 2, 3, 4))
+    m = t1 / t2
+    out = [math.sqrt(n - 2 * m * t1 + m * m * t2)]
+    for _ in range(iters):
+        alpha = (t1 - 2 * m * t2 + m * m * t3) / (t2 - 2 * m * t3 + m * m * t4)
+        m = m + alpha * (1.0 - a * m)
+        out.append(math.sqrt(n - 2 * m * t1 + m * m * t2))
+    return np.array(out), m
+
+
+def _ring(n, a):
+    C = sp.diags([a * np.ones(n), -np.ones(n - 1), -np.ones(n - 1)], [0, 1, -1]).tolil()
+    C[0, n - 1] = C[n - 1, 0] = -1.0
+    return sp.csr_matrix(C)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("mixed", TOL_MIXED)])
+def test_diagonal_cap_trajectory_closed_form(precision, tol):
+    """MR with a cap that leaves room for the diagonal only, on constant-diagonal SPD
+    matrices: every iterate is m_i I and ||I - A M_i||_F follows a closed-form scalar
+    recurrence (Algorithm 1 with the drop of Section 6.1), checked on the device without
+    the oracle: a single handle with the global cap m = n, and a batched handle of rings
+    of different sizes and diagonals under a column cap of one, each matrix following its
+    own recurrence through its own step sizes."""
+    S = _spai()
+    iters = 8
+    A = _ring(40, 2.3)
+    want, m_last = _diag_cap_trajectory(A, iters)
+    h = S.SPAI(A, "mr", "global", 40, False, max_iter=iters,
+               options=S.Options(precision=precision))
+    r0 = h.stats()["resid"]
+    _, hist, _ = h.iterate(iters)
+    M = sp.csr_matrix(h.get())
+    h.close()
+    assert rel_err([r0] + list(hist), want) <= tol
+    assert M.nnz == 40 and np.allclose(M.diagonal(), m_last, rtol=max(tol, 1e-12))
+    mats = [_ring(n, a) for n, a in ((30, 2.1), (57, 2.5), (64, 3.0), (25, 2.05))]
+    hb = S.SPAI(None, "mr", "column", 1.0, False, max_iter=iters, batch=mats,
+                options=S.Options(precision=precision))
+    hb.iterate(iters)
+    res = hb.batched_resid()
+    hb.close()
+    for b, Ab in enumerate(mats):
+        wb, _ = _diag_cap_trajectory(Ab, iters)
+        assert abs(res[b] - wb[-1]) <= tol * wb[-1]
+
+
 @pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
 @pytest.mark.parametrize("name", ["laplace8", "lognormal6"])
 def test_column_cap_one(name, method):
