@@ -450,6 +450,40 @@ def test_diagonal_matrix(method):
     assert np.max(np.abs(Mg.diagonal() * d - 1.0)) <= 1e-15
 
 
+def test_theorems_on_the_device():
+    """What the mathematics fixes without dropping, checked on the device with no oracle:
+    matrix CG ends in as many steps as A has distinct eigenvalues (9 for the 4 x 4
+    Dirichlet Laplacian, 3 for a diagonal with 3 values) and reaches A^{-1}; MR contracts
+    by at least sqrt(1 - lambda_min^2 / tr(A^2)) per step (Theorem 2.1); MR and LOMR never
+    raise ||I - A M||_F."""
+    import math
+    S = _spai()
+    opt = S.Options(symmetrize=False)
+
+    def run(A, method, iters):
+        h = S.SPAI(A, method, "none", 0.0, False, max_iter=iters, options=opt)
+        r0 = h.stats()["resid"]
+        _, hist, _ = h.iterate(iters)
+        M = h.get()
+        h.close()
+        return np.concatenate(([r0], hist)), M
+
+    hist, _ = run(W.laplace2d(4), "cg", 9)
+    assert len(hist) == 10 and hist[8] > 1e-6 and hist[9] < 1e-10 * hist[0]
+    D = sp.csr_matrix(sp.diags(np.array([1.0, 2.0, 5.0, 1.0, 2.0, 5.0, 5.0])))
+    hist, M = run(D, "cg", 3)
+    assert hist[2] > 1e-6 and hist[3] < 1e-12 * hist[0]
+    assert np.allclose(M.toarray(), np.diag(1.0 / D.diagonal()), rtol=1e-12, atol=1e-14)
+    A = W.laplace2d(8)
+    lam_min = np.linalg.eigvalsh(A.toarray()).min()
+    C = math.sqrt(1.0 - lam_min ** 2 / (A.multiply(A)).sum())
+    for method in ("mr", "lomr"):
+        hist, _ = run(A, method, 25)
+        assert all(b <= a * (1 + 1e-13) for a, b in zip(hist[:-1], hist[1:])), method
+        if method == "mr":
+            assert all(b <= C * a * (1 + 1e-12) for a, b in zip(hist[:-1], hist[1:]))
+
+
 def _diag_cap_trajectory(A, iters):
     """||R_i||_F of MR with a diagonal-only cap on a constant-diagonal SPD A, from the
     scalar recurrence m_{i+1} = m_i + alpha_i (1 - a m_i) written through tr(A^k)."""
