@@ -10,7 +10,8 @@ memory before the timed region.  Prints one JSON line (rank 0).
 Extra legs (not timed as steps): the float64 path on the same workload and the
 mixed-vs-float64 time to equal ||I - A M||_F, the Pi-weighted LOMR, the Appendix A
 heuristic drop score under the same cap, Lanczos extremes of the final M, the batched
-form on 256 random geometric-graph matrices, and the CPU oracle on a bounded sample.
+form on 256 random geometric-graph matrices, the loss and its gradients on the
+512 x 512 9-point grid, and the CPU oracle on a bounded sample.
 """
 import argparse
 import json
@@ -260,6 +261,53 @@ def batched_leg(S, W, torch, np, iters=20, nrhs=8):
     return out
 
 
+def loss_leg(S, W, torch, np, reps=5):
+    """The differentiation form: f = ||I - A M||_F^2 and its gradients in the values of A
+    and M through the autograd function, on the 512 x 512 9-point grid graph with M on
+    the pattern of A^2 (n = 262,144), inputs resident on the device; FP64 and the FP32
+    form (float64 sums).  Median of reps calls; algorithmic bytes: A and M read once
+    (index 4 + value 8 bytes, 8-byte row pointers), the two gradients written once."""
+    import scipy.sparse as sp
+    wl = W.workload("grid9_512")
+    A = sp.csr_matrix(wl.A)
+    M = sp.csr_matrix(W.loss_m_values(A, wl.extra["pattern"], W.seed_for(5, 1)))
+    n = A.shape[0]
+    dev = torch.device("cuda")
+
+    def pattern(X):
+        return torch.sparse_csr_tensor(torch.from_numpy(X.indptr.astype(np.int64)),
+                                       torch.from_numpy(X.indices.astype(np.int64)),
+                                       torch.from_numpy(X.data), size=X.shape).to(dev)
+    Ap, Mp = pattern(A), pattern(M)
+    FroLoss = S.fro_loss_function()
+    read = A.nnz * 12 + M.nnz * 12 + 16 * (n + 1)
+    out = {"workload": f"9-point grid graph 512x512 (n={n}, nnz(A)={A.nnz}), M on pattern(A^2) "
+                       f"(nnz={M.nnz})", "alg_bytes_fwd": read,
+           "alg_bytes_fwd_bwd": 2 * read + 8 * (A.nnz + M.nnz)}
+    for prec in ("f64", "mixed"):
+        opts = S.Options(precision=prec)
+        fwd, both = [], []
+        for r in range(reps + 1):
+            a = torch.tensor(A.data, device=dev, requires_grad=True)
+            m = torch.tensor(M.data, device=dev, requires_grad=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L = FroLoss.apply(a, m, Ap, Mp, opts)
+            float(L.detach())
+            t1 = time.perf_counter()
+            L.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if r:                                   # the first call warms up
+                fwd.append(t1 - t0)
+                both.append(t2 - t0)
+        f, b = float(np.median(fwd)), float(np.median(both))
+        out[prec] = {"loss": float(L.detach()), "fwd_ms": f * 1e3, "fwd_bwd_ms": b * 1e3,
+                     "fwd_gbs": read / f / 1e9, "fwd_bwd_gbs": out["alg_bytes_fwd_bwd"] / b / 1e9}
+    log("loss:", json.dumps(out))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -482,6 +530,9 @@ def main():
     # ---------------- batched form: 256 random geometric-graph Laplacians in one handle
     batched = None if args.no_batched else batched_leg(S, W, torch, np)
 
+    # ---------------- differentiation form: the loss and its gradients
+    loss = None if args.no_extras else loss_leg(S, W, torch, np)
+
     cpu = None if args.no_cpu else cpu_baseline(A)
     if cpu:
         log("cpu baseline:", json.dumps(cpu))
@@ -527,6 +578,7 @@ def main():
         "score_lomr": score,
         "spectrum_of_m": spec,
         "batched_geo256": batched,
+        "loss_grid9_512": loss,
     }
     print(json.dumps(out), flush=True)
 
