@@ -570,6 +570,8 @@ def main():
                               if not k.startswith("pcg")},
         "alg_gbs_per_phase": {k: alg[k] / (per_iter_ms[k] * 1e-3) / 1e9 if per_iter_ms[k] > 0 else None
                               for k in alg},
+        "alg_bytes_per_iter": alg,
+        "phase_calls_per_iter": {k: ph_calls[k] / max(iters_timed, 1) for k in alg},
         "resid_fro": r_mixed,
         "pcg_iters_max": int(pcg[0].max()) if pcg else None,
         "mixed_vs_f64": f64,

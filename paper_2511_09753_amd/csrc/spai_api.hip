@@ -302,7 +302,7 @@ struct Engine : EngineBase {
   int* seg_of = nullptr;
   int64_t* seg_beg = nullptr;
   Seg seg;
-  Tile tRs{128, 512}, tRl{1024, 4096}, tDs{256, 512}, tDl{1024, 4096}, tUs{384, 512},
+  Tile tRs{128, 512}, tRl{1024, 4096}, tDs{128, 512, 0, 5}, tDl{1024, 4096}, tUs{384, 512},
       tUl{2048, 4096};
   Tile tRh{0, 0}, tDh{0, 0}, tUh{0, 0};   // huge tiles (device-memory scratch), sized from n
   Tile tSs{128, 1024}, tSl{1024, 8192}, tSh{0, 0};   // heuristic-score tiles
@@ -815,9 +815,10 @@ struct Engine : EngineBase {
     constexpr size_t kMaxLds = 64 * 1024;
     Tile r{c[0], c[1]}, d{c[2], c[3]}, u{c[4], c[5]};
     u.waves = c[6];
+    d.waves = c[7];
     const bool ok = pow2(r.L) && r.L >= 32 && pow2(d.L) && d.L >= 32 && u.L >= 32 &&
                     pow2(r.H) && r.H >= 512 && pow2(d.H) && d.H >= 512 && pow2(u.H) &&
-                    u.H >= 512 && (u.waves == 0 || u.waves == 5) &&
+                    u.H >= 512 && (u.waves == 0 || u.waves == 5) && (d.waves == 0 || d.waves == 5) &&
                     resid_tile_bytes(r, ell) <= kMaxLds && dots_tile_bytes(d, ell) <= kMaxLds &&
                     update_tile_bytes(u) <= kMaxLds;
     if (!ok) return fail(SPAI_ERR_ARG, "spai_set_tiles: tile outside what the kernels accept");
@@ -898,15 +899,17 @@ struct Engine : EngineBase {
     Tile bestD = tDs;
     double tD = 1e300, curD = 1e300;
     for (int L : {128, 256, 512})
-      for (int H : {512, 1024}) {
-        const Tile t{L, H};
-        if (dots_tile_bytes(t, ell) > kMaxLds) continue;
-        const double ms = timed([&] {
-          launch_dots<T>(A, R, P, useR, useP, opts.jacobi, colpart, big[1], st, t, tDl, tDh, s);
-        });
-        if (same_tile(t, tDs)) curD = ms;
-        if (ms < tD) { tD = ms; bestD = t; }
-      }
+      for (int H : {512, 1024})
+        for (int waves : {0, 5}) {           // 5: the register-capped resident tier
+          Tile t{L, H};
+          t.waves = waves;
+          if (dots_tile_bytes(t, ell) > kMaxLds) continue;
+          const double ms = timed([&] {
+            launch_dots<T>(A, R, P, useR, useP, opts.jacobi, colpart, big[1], st, t, tDl, tDh, s);
+          });
+          if (same_tile(t, tDs)) curD = ms;
+          if (ms < tD) { tD = ms; bestD = t; }
+        }
     // update: the candidates of M (and P) written to the next buffers
     const UpdMode md = method == SPAI_MR ? mode(1, 1, 0, 0)
                        : method == SPAI_CG ? mode(1, 2, 0, 0) : mode(1, 1, 2, 1);
@@ -940,6 +943,7 @@ struct Engine : EngineBase {
       chosen[2] = tDs.L; chosen[3] = tDs.H;
       chosen[4] = tUs.L; chosen[5] = tUs.H;
       chosen[6] = tUs.waves;
+      chosen[7] = tDs.waves;
     }
     if (best_ms) {
       best_ms[0] = tR < 1e300 ? tR : 0.0;

@@ -83,7 +83,7 @@ struct BigList {
 struct Tile {      // per-column tile
   int L, H;        // list entries, hash slots
   int DG = 0;      // update: neighbour columns (0: default)
-  int waves = 0;   // update, resident tier: 5 = registers capped at five waves per SIMD
+  int waves = 0;   // dots, update: 5 = resident tier with registers capped at five waves per SIMD
 };
 constexpr int kHugeGrid = 64;      // workgroups of the huge-tile pass
 

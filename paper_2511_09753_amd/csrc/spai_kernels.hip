@@ -680,10 +680,9 @@ size_t resid_tile_bytes(Tile t, bool ell) { return resid_lds(t, ell); }
 // ============================================================================
 
 template <typename T, bool GS>
-__global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp, int useR,
-                                                    int useP, int weighted, double* colpart,
-                                                    BigList big, DevState* st, int tier, int L,
-                                                    int H) {
+__device__ __forceinline__ void dots_body(Csr A, Cols<T> R, Pair<T> Pp, int useR, int useP,
+                                          int weighted, double* colpart, BigList big,
+                                          DevState* st, int tier, int L, int H) {
   if (!st->any_active || !st->iter_active) return;
   extern __shared__ char smem[];
   const bool ell = A.eshift >= 0;
@@ -815,6 +814,23 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp
   }
 }
 
+template <typename T, bool GS>
+__global__ __launch_bounds__(SPAI_WAVE) void k_dots(Csr A, Cols<T> R, Pair<T> Pp, int useR,
+                                                    int useP, int weighted, double* colpart,
+                                                    BigList big, DevState* st, int tier, int L,
+                                                    int H) {
+  dots_body<T, GS>(A, R, Pp, useR, useP, weighted, colpart, big, st, tier, L, H);
+}
+
+// The resident tier with registers capped at five waves per SIMD (spills): slower on
+// large columns, faster on small ones; a tuning candidate like k_update_w5.
+template <typename T>
+__global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5))) void k_dots_w5(
+    Csr A, Cols<T> R, Pair<T> Pp, int useR, int useP, int weighted, double* colpart, BigList big,
+    DevState* st, int tier, int L, int H) {
+  dots_body<T, false>(A, R, Pp, useR, useP, weighted, colpart, big, st, tier, L, H);
+}
+
 static size_t dots_lds(Tile t, bool ell) {
   return (size_t)t.L * 4 + (size_t)t.H * 4 + (size_t)t.L * 8 + (size_t)t.L * 16 +
          (ell ? 0 : (size_t)t.L * 12) + 64;
@@ -827,9 +843,15 @@ void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, int wei
   const bool ell = A.eshift >= 0;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
-  hipLaunchKernelGGL((k_dots<T, false>), dim3(resident_grid(k_dots<T, false>, dots_lds(small, ell))),
-                     dim3(SPAI_WAVE), dots_lds(small, ell), s, A, R, P, useR, useP, weighted,
-                     colpart, big, st, 0, small.L, small.H);
+  if (small.waves == 5)
+    hipLaunchKernelGGL((k_dots_w5<T>), dim3(resident_grid(k_dots_w5<T>, dots_lds(small, ell))),
+                       dim3(SPAI_WAVE), dots_lds(small, ell), s, A, R, P, useR, useP, weighted,
+                       colpart, big, st, 0, small.L, small.H);
+  else
+    hipLaunchKernelGGL((k_dots<T, false>),
+                       dim3(resident_grid(k_dots<T, false>, dots_lds(small, ell))),
+                       dim3(SPAI_WAVE), dots_lds(small, ell), s, A, R, P, useR, useP, weighted,
+                       colpart, big, st, 0, small.L, small.H);
   hipLaunchKernelGGL((k_dots<T, false>), dim3(256), dim3(SPAI_WAVE), dots_lds(large, ell), s, A, R, P,
                      useR, useP, weighted, colpart, big, st, 1, large.L, large.H);
   hipLaunchKernelGGL((k_dots<T, true>), dim3(kHugeGrid), dim3(SPAI_WAVE), 0, s, A, R, P, useR, useP,

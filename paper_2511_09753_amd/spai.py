@@ -350,22 +350,22 @@ class SPAI:
 
     def autotune(self, warm_iters=5, reps=2):
         """Pick the per-column tiles for this workload (see spai_autotune) and restart from
-        M_0.  Returns {"resid": (L, H), "dots": (L, H), "update": (L, H, waves)} (waves: 5
-        when the update's resident tier runs capped at five waves per SIMD, else 0) and the
-        best launch times in ms."""
-        ch = np.zeros(7, dtype=np.int32)
+        M_0.  Returns {"resid": (L, H), "dots": (L, H, waves), "update": (L, H, waves)}
+        (waves: 5 when that kernel's resident tier runs capped at five waves per SIMD, else
+        0) and the best launch times in ms."""
+        ch = np.zeros(8, dtype=np.int32)
         ms = np.zeros(3, dtype=np.float64)
         _check(load().spai_autotune(self.h, int(warm_iters), int(reps), ch.ctypes.data,
                                     ms.ctypes.data))
-        tiles = {"resid": (int(ch[0]), int(ch[1])), "dots": (int(ch[2]), int(ch[3])),
+        tiles = {"resid": (int(ch[0]), int(ch[1])), "dots": (int(ch[2]), int(ch[3]), int(ch[7])),
                  "update": (int(ch[4]), int(ch[5]), int(ch[6]))}
         return tiles, {"resid": float(ms[0]), "dots": float(ms[1]), "update": float(ms[2])}
 
     def set_tiles(self, tiles):
         """Use the given tiles (the dict autotune returns) from the next launch on."""
         r, d, u = tiles["resid"], tiles["dots"], tiles["update"]
-        ch = np.array([r[0], r[1], d[0], d[1], u[0], u[1], u[2] if len(u) > 2 else 0],
-                      dtype=np.int32)
+        ch = np.array([r[0], r[1], d[0], d[1], u[0], u[1], u[2] if len(u) > 2 else 0,
+                       d[2] if len(d) > 2 else 0], dtype=np.int32)
         _check(load().spai_set_tiles(self.h, ch.ctypes.data))
 
     def batched_resid(self):

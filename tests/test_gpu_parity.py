@@ -805,6 +805,7 @@ def test_autotune_leaves_results_unchanged():
             tiles, ms = h.autotune(warm_iters=4, reps=1)
             assert tiles["resid"][0] in (64, 128, 256) and tiles["dots"][0] in (128, 256, 512)
             assert tiles["update"][0] in (256, 384, 512) and tiles["update"][2] in (0, 5)
+            assert tiles["dots"][2] in (0, 5)
             assert all(t[1] in (512, 1024) for t in tiles.values())
             assert all(v > 0 for v in ms.values())
         _, hist, _ = h.iterate(10)
@@ -825,7 +826,7 @@ def test_autotune_leaves_results_unchanged():
 
 
 def test_set_tiles_leaves_results_unchanged():
-    """Tiles set by hand -- the register-capped update tier, and tiles small enough to
+    """Tiles set by hand -- the register-capped dots and update tiers, and tiles small enough to
     send many columns to the larger tiers -- give the default tiles' residual history
     and iterate bit for bit, for a single and a batched handle; tiles the kernels do not
     accept are refused and change nothing."""
@@ -833,9 +834,9 @@ def test_set_tiles_leaves_results_unchanged():
     A = W.lognormal3d(14, 23)
     default = None
     cases = [None,
-             {"resid": (128, 512), "dots": (256, 512), "update": (384, 512, 5)},
-             {"resid": (32, 512), "dots": (32, 512), "update": (32, 512, 0)},
-             {"resid": (32, 512), "dots": (64, 1024), "update": (64, 1024, 5)}]
+             {"resid": (128, 512), "dots": (256, 512, 5), "update": (384, 512, 5)},
+             {"resid": (32, 512), "dots": (32, 512, 0), "update": (32, 512, 0)},
+             {"resid": (32, 512), "dots": (64, 1024, 5), "update": (64, 1024, 5)}]
     for tiles in cases:
         h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=10,
                    options=S.Options(precision="mixed"))
@@ -850,7 +851,7 @@ def test_set_tiles_leaves_results_unchanged():
             assert np.array_equal(run[0], default[0]) and (run[1] != default[1]).nnz == 0, tiles
     mats = W.batch_geometric(4, 77, 300, 900)
     runs = []
-    for tiles in (None, {"resid": (64, 512), "dots": (64, 512), "update": (64, 512, 5)}):
+    for tiles in (None, {"resid": (64, 512), "dots": (64, 512, 5), "update": (64, 512, 5)}):
         h = S.SPAI(None, "mr", "column", 4.0, False, max_iter=8, batch=mats)
         h.iterate(2)                       # a captured graph exists: set_tiles recaptures
         if tiles:
@@ -865,6 +866,7 @@ def test_set_tiles_leaves_results_unchanged():
                 {"resid": (128, 768)},                    # H not a power of two
                 {"dots": (100, 512)},                     # dots L not a power of two
                 {"update": (384, 512, 3)},                # no such waves cap
+                {"dots": (256, 512, 4)},                  # no such waves cap
                 {"update": (16, 512, 0)},                 # L below 32
                 {"dots": (8192, 8192)}):                  # more than 64 KB of LDS
         t = dict(good, **bad)
