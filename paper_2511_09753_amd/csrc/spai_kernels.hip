@@ -636,7 +636,7 @@ int g_grid_cols = 2048;   // fallback persistent grid of the per-column kernels
 // resident at once given its LDS tile (queried once per kernel and tile), rounded
 // down to a multiple of the 8 XCDs.
 template <typename K>
-static int resident_grid(K kernel, size_t lds) {
+static int resident_grid(K kernel, size_t lds, int threads = SPAI_WAVE) {
   static std::mutex mu;
   static std::map<std::pair<const void*, size_t>, int> cache;
   std::lock_guard<std::mutex> lock(mu);
@@ -647,7 +647,7 @@ static int resident_grid(K kernel, size_t lds) {
   int grid = g_grid_cols;
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, SPAI_WAVE, lds) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) == hipSuccess &&
       per > 0 && cus > 0) {
     grid = std::max(8, (per * cus) / 8 * 8);
   } else {
@@ -1637,9 +1637,11 @@ __device__ __forceinline__ int64_t group_src(const Group64& g, int c, int x) {
 
 // histogram of the top key bits (63..52; for magnitudes bit 63 is 0) of the candidates,
 // counting diagonal entries apart.  SC: the keys are the signed scores sc[] stored beside
-// the candidates instead of their magnitudes.
+// the candidates instead of their magnitudes.  Four waves per workgroup share one LDS
+// histogram, each walking its own 64-column groups: the histogram's LDS no longer limits
+// the waves in flight (one wave per histogram allowed five per SIMD, 7% slower).
 template <typename T, bool SC>
-__global__ __launch_bounds__(SPAI_WAVE) void k_sel_hist_exp(Pair<T> Xp, const double* sc,
+__global__ __launch_bounds__(4 * SPAI_WAVE) void k_sel_hist_exp(Pair<T> Xp, const double* sc,
                                                             int excl_diag,
                                                             unsigned long long* hist, int64_t n,
                                                             DevState* st) {
@@ -1647,12 +1649,13 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_sel_hist_exp(Pair<T> Xp, const do
   constexpr int NB = SC ? 4096 : 2048;
   __shared__ unsigned int h[NB];
   const int lane = lane_id();
-  for (int i = lane; i < NB; i += SPAI_WAVE) h[i] = 0;
+  const int wv = threadIdx.x / SPAI_WAVE;
+  for (int i = threadIdx.x; i < NB; i += 4 * SPAI_WAVE) h[i] = 0;
   __syncthreads();
   const Cols<T> X = Xp.nxt();
   long long diag = 0;
   const int64_t ng = (n + 63) / 64;
-  for (int64_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
+  for (int64_t gi = (int64_t)blockIdx.x * 4 + wv; gi < ng; gi += (int64_t)gridDim.x * 4) {
     const Group64 g = group_load(X, gi * 64, n);
     for (int x0 = 0; x0 < g.T; x0 += SPAI_WAVE * kGU) {
       int col[kGU], idx[kGU];
@@ -1687,7 +1690,7 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_sel_hist_exp(Pair<T> Xp, const do
     }
   }
   __syncthreads();
-  for (int i = lane; i < NB; i += SPAI_WAVE)
+  for (int i = threadIdx.x; i < NB; i += 4 * SPAI_WAVE)
     if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
   diag = wave_sum_ll(diag);
   if (lane == 0 && diag) atomicAdd((unsigned long long*)&st->sel_diag, (unsigned long long)diag);
@@ -1886,13 +1889,15 @@ void launch_global_select(Pair<T> X, int exclude_diag, int64_t m, double eta, in
   hipLaunchKernelGGL(k_sel_reset, dim3(1), dim3(1024), 0, s, hist, 8192, st);
   const int ng = (int)std::min<int64_t>((n + 63) / 64, 1 << 30);
   if (score)
-    hipLaunchKernelGGL((k_sel_hist_exp<T, true>),
-                       dim3(std::min(ng, resident_grid(k_sel_hist_exp<T, true>, 0))),
-                       dim3(SPAI_WAVE), 0, s, X, score, exclude_diag, hist, n, st);
+    hipLaunchKernelGGL(
+        (k_sel_hist_exp<T, true>),
+        dim3(std::min((ng + 3) / 4, resident_grid(k_sel_hist_exp<T, true>, 0, 4 * SPAI_WAVE))),
+        dim3(4 * SPAI_WAVE), 0, s, X, score, exclude_diag, hist, n, st);
   else
-    hipLaunchKernelGGL((k_sel_hist_exp<T, false>),
-                       dim3(std::min(ng, resident_grid(k_sel_hist_exp<T, false>, 0))),
-                       dim3(SPAI_WAVE), 0, s, X, score, exclude_diag, hist, n, st);
+    hipLaunchKernelGGL(
+        (k_sel_hist_exp<T, false>),
+        dim3(std::min((ng + 3) / 4, resident_grid(k_sel_hist_exp<T, false>, 0, 4 * SPAI_WAVE))),
+        dim3(4 * SPAI_WAVE), 0, s, X, score, exclude_diag, hist, n, st);
   hipLaunchKernelGGL(k_sel_find_exp, dim3(1), dim3(1024), 0, s, hist, exclude_diag, m, sk, thr,
                      st);
   if (score)
