@@ -836,3 +836,169 @@ def test_mr_with_diagonal_only_cap_follows_scalar_recurrence(which, cap):
     assert np.allclose(res.resid, want, rtol=1e-12, atol=0.0)
     M = sp.csr_matrix(res.M)
     assert M.nnz == n and np.allclose(M.diagonal(), m, rtol=1e-12, atol=0.0)
+
+
+# ----------------------------------------------------------------------------
+# per-column cap (a reading: the paper's caps are global) by brute force
+# ----------------------------------------------------------------------------
+
+def _best_subset(idx, mags, size):
+    """The subset of `idx` of the given size with the largest total magnitude, by
+    enumeration: eq. (hard thresholding) restricted to one column (drop the set of
+    minimal total magnitude)."""
+    idx = list(idx)
+    if len(idx) <= size:
+        return set(idx)
+    best, best_set = None, None
+    for S in itertools.combinations(idx, size):
+        s = sum(mags[i] for i in S)
+        if best is None or s > best:
+            best, best_set = s, set(S)
+    return best_set
+
+
+def _random_sym_with_diag(n, seed, density=0.45):
+    """Symmetric matrix with continuous random off-diagonal values (no ties) and a
+    nonzero diagonal."""
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((n, n))
+    B[rng.random((n, n)) > density] = 0.0
+    B = np.triu(B, 1)
+    return sp.csc_matrix(B + B.T + np.diag(rng.uniform(0.5, 2.0, n))), rng
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_column_cap_direction_equals_brute_force(seed):
+    """D_P under a per-column cap k_c: column c keeps exactly the k_c entries of largest
+    magnitude (every column solved by subset enumeration).  A reading that kept the
+    smallest entries, or k_c - 1 / k_c + 1 of them, fails here."""
+    rng = np.random.default_rng(500 + seed)
+    n = 7
+    X = sp.random(n, n, density=0.6, random_state=rng, format="csc")
+    X.data = rng.standard_normal(X.nnz)
+    k = rng.integers(1, 5, n)
+    kept = O.drop_direction(X, O.DropRule(mode="column", k=k, u=0.0))
+    rows, cols, vals = O._entries(O._csc(X))
+    mags = np.abs(vals)
+    want = set()
+    for c in range(n):
+        ids = [i for i in range(len(vals)) if cols[i] == c]
+        want |= {(rows[i], c) for i in _best_subset(ids, mags, int(k[c]))}
+    got = set(zip(kept.tocoo().row.tolist(), kept.tocoo().col.tolist()))
+    assert got == {(int(r), int(c)) for r, c in want}
+    assert np.all(np.diff(kept.indptr) == np.minimum(k, np.diff(O._csc(X).indptr)))
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("symmetrize", [True, False])
+def test_column_cap_main_equals_brute_force(seed, symmetrize):
+    """D_M under a per-column cap k_j that counts the diagonal (the diagonal is exempt
+    and always kept, so column j selects its k_j - 1 largest off-diagonal entries, by
+    enumeration).  On the symmetrized iterate an off-diagonal (r, c) survives only when
+    it is selected in column c and its mirror is selected in column r (the intersection
+    of the row and column selections, which keeps M symmetric); without symmetrization
+    the column selection alone decides."""
+    n = 7
+    X, rng = _random_sym_with_diag(n, 600 + seed)
+    if not symmetrize:                 # an unsymmetric input: perturb the upper triangle
+        U = sp.triu(X, 1).tocsc()
+        U.data = U.data * rng.uniform(0.5, 1.5, U.nnz)
+        X = sp.csc_matrix(sp.tril(X) + U)
+    k = rng.integers(1, 5, n)
+    kept = O.drop_main(X, O.DropRule(mode="column", k=k, u=0.0, symmetrize=symmetrize))
+    Xs = O._csc((X + X.T) * 0.5) if symmetrize else O._csc(X)
+    rows, cols, vals = O._entries(Xs)
+    mags = np.abs(vals)
+    sel = {}
+    for c in range(n):
+        ids = [i for i in range(len(vals)) if cols[i] == c and rows[i] != c]
+        sel[c] = {int(rows[i]) for i in _best_subset(ids, mags, int(k[c]) - 1)}
+    want = {(c, c) for c in range(n)}
+    for i in range(len(vals)):
+        r, c = int(rows[i]), int(cols[i])
+        if r != c and r in sel[c] and (not symmetrize or c in sel[r]):
+            want.add((r, c))
+    got = set(zip(kept.tocoo().row.tolist(), kept.tocoo().col.tolist()))
+    assert got == want
+    if symmetrize:
+        assert (abs(kept - kept.T)).nnz == 0
+    assert np.all(np.diff(kept.indptr) <= k)
+
+
+def test_column_cap_with_exact_ties_drops_the_tied_cluster():
+    """Ties at a column's cut: with t_c the (k_c + 1)-th largest magnitude, the whole tie
+    cluster at t_c goes (the tie band), never more than k_c entries stay, and entries
+    strictly above the cluster stay."""
+    vals = np.array([4.0, -3.0, 2.0, -2.0, 2.0, 1.0])
+    X = sp.csc_matrix((vals, (np.arange(6), np.zeros(6, dtype=int))), shape=(6, 1))
+    for kk, want in [(1, [4.0]), (2, [-3.0, 4.0]), (3, [-3.0, 4.0]), (4, [-3.0, 4.0]),
+                     (5, [-3.0, -2.0, 2.0, 2.0, 4.0]), (6, sorted(vals.tolist()))]:
+        P = O.drop_direction(X, O.DropRule(mode="column", k=np.array([kk])))
+        assert sorted(P.data.tolist()) == want, kk
+
+
+# ----------------------------------------------------------------------------
+# LOMR degeneracy (Theorem 4.2: c_i is a 2 x 2 Gram determinant)
+# ----------------------------------------------------------------------------
+
+def test_lomr_coefficients_fall_back_to_the_mr_step_when_degenerate():
+    """When A P_{i-1} is (nearly) parallel to A R_i the 2-D problem of Definition 4.1 is
+    singular: the step taken is the MR step, the dense 1-D least-squares minimiser of
+    ||R - delta A R||_F, with gamma = 0.  Away from degeneracy the coefficients are the
+    2-D least-squares minimiser over span{R, P}."""
+    A, _ = random_spd(8, 11, cond=20.0)
+    rng = np.random.default_rng(12)
+    R = sp.random(8, 8, density=0.5, random_state=rng, format="csc")
+    R.data = rng.standard_normal(R.nnz)
+    E = sp.csc_matrix(rng.standard_normal((8, 8)))
+    Ad, Rd = _dense(A), _dense(R)
+
+    def coefs(P):
+        AR, AP = O._csc(A @ R), O._csc(A @ P)
+        return O.lomr_coefficients(O.frob(R, AR), O.frob(AR, AR), O.frob(AR, AP),
+                                   O.frob(R, AP), O.frob(AP, AP), False)
+
+    d_mr = np.linalg.lstsq((Ad @ Rd).reshape(-1, 1), Rd.ravel(), rcond=None)[0][0]
+    for eps in (0.0, 1e-10):                      # collinear, and within the guard
+        d, g, fb = coefs(O._csc(3.0 * R + eps * E))
+        assert fb and g == 0.0
+        assert d == pytest.approx(d_mr, rel=1e-12)
+    d, g, fb = coefs(sp.csc_matrix((8, 8)))       # a direction dropped to zero
+    assert fb and g == 0.0 and d == pytest.approx(d_mr, rel=1e-12)
+    P = O._csc(3.0 * R + 1e-3 * E)                # well conditioned: the 2-D minimiser
+    d, g, fb = coefs(P)
+    Pd = _dense(P)
+    G = np.stack([(Ad @ Rd).ravel(), (Ad @ Pd).ravel()], axis=1)
+    d_ls, g_ls = np.linalg.lstsq(G, Rd.ravel(), rcond=None)[0]
+    assert not fb
+    assert d == pytest.approx(d_ls, rel=1e-6) and g == pytest.approx(g_ls, rel=1e-6)
+
+
+@pytest.mark.parametrize("cap", ["global", "column"])
+def test_lomr_with_zero_direction_takes_mr_steps_in_closed_form(cap):
+    """LOMR on the 8 x 8 Dirichlet Laplacian (constant diagonal 4) under a cap that leaves
+    room for the diagonal only.  In every column of delta_0 R_0 = delta_0 (I - cA) the
+    off-diagonal magnitudes (c) tie above the diagonal one (|1 - 4c|), so the tie band
+    drops P_0 to zero, A P_0 = 0 makes the Gram determinant zero, and every later step is
+    the MR step (gamma = 0) with P staying zero.  The trajectory is then MR's, whose
+    residuals follow the closed-form scalar recurrence through tr(A^k)."""
+    A = W.laplace2d(8)
+    n = A.shape[0]
+    D = A.toarray()
+    t1, t2, t3, t4 = (np.trace(np.linalg.matrix_power(D, k)) for k in (1, 2, 3, 4))
+    iters = 9
+    m = t1 / t2
+    assert m > abs(1 - 4 * m)                     # the ties sit above the diagonal
+    want = [math.sqrt(n - 2 * m * t1 + m * m * t2)]
+    for _ in range(iters):
+        alpha = (t1 - 2 * m * t2 + m * m * t3) / (t2 - 2 * m * t3 + m * m * t4)
+        m = m + alpha * (1.0 - 4.0 * m)
+        want.append(math.sqrt(n - 2 * m * t1 + m * m * t2))
+    rule = (O.DropRule(mode="global", m=n) if cap == "global"
+            else O.DropRule(mode="column", k=np.ones(n, dtype=np.int64)))
+    res = O.lomr(A, rule, iters)
+    assert res.iters == iters
+    assert np.allclose(res.resid, want, rtol=1e-12, atol=0.0)
+    assert [s["mr_fallback"] for s in res.scalars] == [False] + [True] * (iters - 1)
+    assert all(s["gamma"] == 0.0 for s in res.scalars[1:])
+    assert res.nnz_p == [0] * (iters + 1)
