@@ -248,8 +248,9 @@ int spai_spectrum(spai_handle_t* h, int steps, const double* v0, int on_device, 
  *   graph.  The dots and update kernels' resident tiers are also timed with their
  *   registers capped at five waves per SIMD (faster where columns are small).  chosen
  *   (may be NULL): 8 ints, L and H of the residual, dots and update tiles, then the
- *   update tier's and the dots tier's waves-per-SIMD cap (5, or 0 for the compiler's
- *   choice); best_ms (may be NULL): 3 doubles, their measured launch times.
+ *   update's and the dots' resident-tier variant (0: the compiler's registers, 5: capped
+ *   at five waves per SIMD, 1: the lean tier for A in ELL); best_ms (may be NULL): 3
+ *   doubles, their measured launch times.
  *   Synchronises the stream.
  */
 int spai_autotune(spai_handle_t* h, int warm_iters, int reps, int* chosen, double* best_ms);
@@ -258,8 +259,12 @@ int spai_autotune(spai_handle_t* h, int warm_iters, int reps, int* chosen, doubl
  * spai_set_tiles — use the given per-column tiles from the next launch on, for
  *   instance those a previous spai_autotune reported for the same workload.  tiles:
  *   8 host ints in the layout of spai_autotune's chosen.  Accepted: every H a power of
- *   two >= 512; the residual and dots L a power of two >= 32, the update L >= 32; both
- *   waves caps 0 or 5; each tile within 64 KB of LDS.  Anything else returns
+ *   two >= 512 (>= 128 for the residual when A is held in ELL, and for the dots' lean
+ *   tier); the residual and dots L a power of
+ *   two >= 32, the update L >= 32; the dots' and the update's variant 0 (compiler's
+ *   registers), 5 (capped at five waves per SIMD) or 1 (the lean tier: A in ELL, and for
+ *   the update rows of at most 8 entries; its H may be >= 128); each tile within 64 KB
+ *   of LDS.  Anything else returns
  *   SPAI_ERR_ARG and leaves the tiles unchanged.  Results do not depend on the tiles;
  *   a batched handle recaptures its graph.  Synchronises the stream.
  */

@@ -302,7 +302,7 @@ struct Engine : EngineBase {
   int* seg_of = nullptr;
   int64_t* seg_beg = nullptr;
   Seg seg;
-  Tile tRs{128, 512}, tRl{1024, 4096}, tDs{128, 512, 0, 5}, tDl{1024, 4096}, tUs{384, 512},
+  Tile tRs{64, 512}, tRl{1024, 4096}, tDs{128, 512, 0, 1}, tDl{1024, 4096}, tUs{384, 512},
       tUl{2048, 4096};
   Tile tRh{0, 0}, tDh{0, 0}, tUh{0, 0};   // huge tiles (device-memory scratch), sized from n
   Tile tSs{128, 1024}, tSl{1024, 8192}, tSh{0, 0};   // heuristic-score tiles
@@ -495,6 +495,11 @@ struct Engine : EngineBase {
       A.eshift = sh;
       A.ecol = d_ec;
       A.eval = d_ev;
+      // A in ELL: the residual and dots run their lean resident tiers, whose ordered key
+      // sets take any power-of-two H
+      tRs = Tile{64, 256};
+      tDs = Tile{128, 256, 0, 1};
+      if (sh == 3) tUs = Tile{128, 256, 0, 1};   // the update's lean tier: rows of <= 8
     }
     // ---- locality order of the rows (for the PCG products)
     {
@@ -816,9 +821,16 @@ struct Engine : EngineBase {
     Tile r{c[0], c[1]}, d{c[2], c[3]}, u{c[4], c[5]};
     u.waves = c[6];
     d.waves = c[7];
+    // d.waves 1 selects the lean dots tier (A in ELL), whose ordered key set takes any
+    // power-of-two H >= 128
+    const bool dlean = d.waves == 1;
+    const bool ulean = u.waves == 1 && A.eshift == 3;   // the update's lean tier
     const bool ok = pow2(r.L) && r.L >= 32 && pow2(d.L) && d.L >= 32 && u.L >= 32 &&
-                    pow2(r.H) && r.H >= 512 && pow2(d.H) && d.H >= 512 && pow2(u.H) &&
-                    u.H >= 512 && (u.waves == 0 || u.waves == 5) && (d.waves == 0 || d.waves == 5) &&
+                    pow2(r.H) && r.H >= (ell ? 128 : 512) && pow2(d.H) &&
+                    d.H >= (dlean ? 128 : 512) &&
+                    pow2(u.H) && u.H >= (ulean ? 128 : 512) &&
+                    (u.waves == 0 || u.waves == 5 || ulean) &&
+                    (d.waves == 0 || d.waves == 5 || (dlean && ell)) &&
                     resid_tile_bytes(r, ell) <= kMaxLds && dots_tile_bytes(d, ell) <= kMaxLds &&
                     update_tile_bytes(u) <= kMaxLds;
     if (!ok) return fail(SPAI_ERR_ARG, "spai_set_tiles: tile outside what the kernels accept");
@@ -884,8 +896,9 @@ struct Engine : EngineBase {
     Tile bestR = tRs;
     double tR = 1e300, curR = 1e300;
     for (int L : {64, 128, 256})
-      for (int H : {512, 1024}) {
+      for (int H : {256, 512, 1024}) {
         const Tile t{L, H};
+        if (H < 512 && !ell) continue;
         if (resid_tile_bytes(t, ell) > kMaxLds) continue;
         const double ms = timed([&] {
           launch_resid<T>(A, M, R, off, total, colnorm, opts.jacobi, colrz, big[0], st, t, tRl,
@@ -898,11 +911,13 @@ struct Engine : EngineBase {
     const int useR = method != SPAI_CG, useP = method != SPAI_MR;
     Tile bestD = tDs;
     double tD = 1e300, curD = 1e300;
-    for (int L : {128, 256, 512})
-      for (int H : {512, 1024})
-        for (int waves : {0, 5}) {           // 5: the register-capped resident tier
+    for (int L : {64, 128, 256, 512})
+      for (int H : {256, 512, 1024})
+        for (int waves : {0, 5, 1}) {        // 5: the register-capped tier, 1: the lean tier
           Tile t{L, H};
           t.waves = waves;
+          if (waves == 1 && !ell) continue;
+          if (waves != 1 && (H < 512 || L < 128)) continue;
           if (dots_tile_bytes(t, ell) > kMaxLds) continue;
           const double ms = timed([&] {
             launch_dots<T>(A, R, P, useR, useP, opts.jacobi, colpart, big[1], st, t, tDl, tDh, s);
@@ -917,11 +932,12 @@ struct Engine : EngineBase {
     launch_scan(ub, off, total, n, scantmp, s);
     Tile bestU = tUs;
     double tU = 1e300, curU = 1e300;
-    for (int L : {256, 384, 512})
-      for (int H : {512, 1024})
-        for (int waves : {0, 5}) {           // 5: the register-capped resident tier
+    for (int L : {128, 256, 384, 512})
+      for (int H : {128, 256, 512, 1024})
+        for (int waves : {0, 5, 1}) {        // 5: the register-capped tier, 1: the lean tier
           Tile t{L, H};
           t.waves = waves;
+          if (waves == 1 ? (A.eshift != 3 || L != 128) : (H < 512 || L < 256)) continue;
           if (update_tile_bytes(t) > kMaxLds) continue;
           const double ms = timed([&] {
             launch_update<T>(A, M, R, P, PT, md, off, total, kcol, tM, tP, big[2], seg, st, t,

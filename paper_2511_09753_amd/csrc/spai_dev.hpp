@@ -86,6 +86,23 @@ __device__ __forceinline__ unsigned hash_key(int k) {
   return x ^ (x >> 16);
 }
 
+// ---- ordered key set (history independent) -----------------------------------
+// A key k is stored as its Fibonacci hash h(k) = k * kHashMul (mod 2^32), a bijection
+// on 32-bit words, so k = h * kHashInv recovers it.  The home slot is the top bits of
+// h, and an insert walks forward from home keeping the smaller hash in every slot it
+// passes (an atomic min that carries the displaced, larger value on).  With no wrap
+// around (the table ends in an overflow area instead), the final contents do not
+// depend on the order of the inserts: occupied slots, read in slot order, list the
+// keys sorted by h (Amble and Knuth's ordered hash tables).  The kernels sum over the
+// keys in that order, so results are deterministic without sorting the keys.
+constexpr unsigned kHashMul = 0x9E3779B1u;
+constexpr unsigned kHashInv = 0x0E8B2F51u;   // kHashMul * kHashInv = 1 (mod 2^32)
+constexpr unsigned kOhEmpty = 0xFFFFFFFFu;   // no row index hashes to it (its preimage is > 2^31)
+constexpr int kOhOver = 64;                  // overflow slots after the H home slots
+
+__device__ __forceinline__ unsigned ohash(int k) { return (unsigned)k * kHashMul; }
+__device__ __forceinline__ int ounhash(unsigned h) { return (int)(h * kHashInv); }
+
 // ---- LDS key set (open addressing, -1 = empty) -------------------------------
 // The caller guarantees fewer distinct keys than slots, so probing terminates.
 __device__ __forceinline__ void ks_clear(int* keys, int H) {
@@ -280,16 +297,22 @@ __device__ __forceinline__ void sort_in_registers(int* keys, int cnt) {
 // Sort the keys of the set in place: keys[0..cnt) ascending, returns cnt.  The
 // compaction writes slot s to position <= s after the whole 64-slot chunk has been
 // read, so it can run in place.  Up to 256 keys are sorted in registers with
-// shuffles; larger sets by the LDS bitonic network.
-__device__ inline int ks_sort_inplace(int* keys, int H) {
+// shuffles; larger sets by the LDS bitonic network.  by_hash: order by the Fibonacci
+// hash ohash(k) instead of k (the order the ordered key set yields; h ^ 2^31 orders
+// as a signed int like h as unsigned, and the INT_MAX padding is the empty word).
+__device__ inline int ks_sort_inplace(int* keys, int H, bool by_hash = false) {
   int cnt = 0;
   for (int base = 0; base < H; base += SPAI_WAVE) {
     int k = keys[base + lane_id()];
     bool occ = k != -1;
     unsigned long long m = __ballot(occ);
     __syncthreads();
-    if (occ) keys[cnt + __popcll(m & lanemask_lt())] = k;
+    if (occ) keys[cnt + __popcll(m & lanemask_lt())] = by_hash ? (int)(ohash(k) ^ 0x80000000u) : k;
     cnt += __popcll(m);
+    __syncthreads();
+  }
+  if (by_hash && cnt == 1) {
+    if (lane_id() == 0) keys[0] = ounhash((unsigned)keys[0] ^ 0x80000000u);
     __syncthreads();
   }
   if (cnt <= 1) return cnt;
@@ -306,6 +329,11 @@ __device__ inline int ks_sort_inplace(int* keys, int H) {
     bitonic_sort_int(keys, S);
   }
   __syncthreads();
+  if (by_hash) {
+    for (int i = lane_id(); i < cnt; i += SPAI_WAVE)
+      keys[i] = ounhash((unsigned)keys[i] ^ 0x80000000u);
+    __syncthreads();
+  }
   return cnt;
 }
 
@@ -417,6 +445,100 @@ __device__ __forceinline__ int upper_bound_int(const int* a, int n, int v) {
 }
 
 template <typename T> __device__ __forceinline__ double ld(const T* p) { return (double)(*p); }
+
+// Insert up to U keys per lane (negative: none) into T[0 .. H + kOhOver), H = 2^(32 - shift).
+// Returns false if a walk ran off the end of the table (the caller then gives the
+// column to a larger tile).
+template <int U>
+__device__ __forceinline__ bool oh_insert_batch(unsigned* T, int shift, int end,
+                                                const int (&key)[U]) {
+  // The walk state is updated with selects, not branches: only the atomic itself sits
+  // under a condition, so the wave runs one short loop (until no lane has a key in
+  // flight) instead of a branch per key and step.
+  unsigned v[U];
+  int s[U];
+#pragma unroll
+  for (int c = 0; c < U; ++c) {
+    v[c] = key[c] >= 0 ? ohash(key[c]) : kOhEmpty;
+    s[c] = key[c] >= 0 ? (int)(v[c] >> shift) : 0;
+  }
+  bool ok = true;
+  while (true) {
+    unsigned old[U];
+#pragma unroll
+    for (int c = 0; c < U; ++c) {
+      old[c] = kOhEmpty;
+      if (v[c] != kOhEmpty) old[c] = atomicMin(&T[s[c]], v[c]);
+    }
+    bool live = false;
+#pragma unroll
+    for (int c = 0; c < U; ++c) {
+      const bool fin = old[c] == kOhEmpty || old[c] == v[c];   // placed, or already there
+      const int ns = s[c] + 1;
+      const bool ovf = !fin && ns >= end;                       // walked off the table
+      ok = ok && !ovf;
+      v[c] = (fin || ovf) ? kOhEmpty : max(old[c], v[c]);       // walk on with the larger
+      s[c] = (fin || ovf) ? 0 : ns;
+      live = live || v[c] != kOhEmpty;
+    }
+    if (__ballot(live) == 0ull) break;
+  }
+  return ok;
+}
+
+// Compact the occupied slots of T[0 .. end) in place into keys (decoded), in slot order;
+// returns the count.  One wave; each 64-slot chunk is read before it is written.
+__device__ __forceinline__ int oh_compact(unsigned* T, int end) {
+  int cnt = 0;
+  for (int base = 0; base < end; base += SPAI_WAVE) {
+    const unsigned x = T[base + lane_id()];
+    const bool occ = x != kOhEmpty;
+    const unsigned long long m = __ballot(occ);
+    if (occ) ((int*)T)[cnt + __popcll(m & lanemask_lt())] = ounhash(x);
+    cnt += __popcll(m);
+  }
+  return cnt;
+}
+
+// Sum of six values over the wave as a fixed transpose tree: the first three halving
+// steps exchange half of the live values (six padded to eight), the last three add the
+// single remaining value; every step pairs lanes by xor, so the order of the additions
+// is fixed.  Returns the six sums in s[0..5] on every lane.
+__device__ __forceinline__ void wave_sum6(double (&v)[6]) {
+  const int lane = lane_id();
+  double a[8] = {v[0], v[1], v[2], v[3], v[4], v[5], 0.0, 0.0};
+  // xor 32: lanes < 32 keep values 0-3, lanes >= 32 keep 4-7
+  const bool up32 = (lane & 32) != 0;
+  double b[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double send = up32 ? a[c] : a[c + 4];
+    const double keep = up32 ? a[c + 4] : a[c];
+    b[c] = keep + __shfl_xor(send, 32, SPAI_WAVE);
+  }
+  // xor 16: keep two of the four
+  const bool up16 = (lane & 16) != 0;
+  double d[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double send = up16 ? b[c] : b[c + 2];
+    const double keep = up16 ? b[c + 2] : b[c];
+    d[c] = keep + __shfl_xor(send, 16, SPAI_WAVE);
+  }
+  // xor 8: keep one of the two
+  const bool up8 = (lane & 8) != 0;
+  double e;
+  {
+    const double send = up8 ? d[0] : d[1];
+    const double keep = up8 ? d[1] : d[0];
+    e = keep + __shfl_xor(send, 8, SPAI_WAVE);
+  }
+#pragma unroll
+  for (int dd = 4; dd >= 1; dd >>= 1) e += __shfl_xor(e, dd, SPAI_WAVE);
+  // value q = 4 (lane bit 5) + 2 (bit 4) + (bit 3) lives in lane 8 q (and its group)
+#pragma unroll
+  for (int q = 0; q < 6; ++q) v[q] = __shfl(e, 8 * q, SPAI_WAVE);
+}
 
 // Columns of a grid-stride loop.  The columns are split into 8 contiguous ranges,
 // one per XCD (workgroups are dealt round-robin over the 8 XCDs of the chip), so

@@ -47,7 +47,136 @@ struct Carve {
     off += (unsigned)(sizeof(U) * (unsigned)count);
     return r;
   }
+  template <typename U> __device__ U* take16(int count) {   // 16-byte aligned
+    off = (off + 15u) & ~15u;
+    U* r = (U*)(base + off);
+    off += (unsigned)(sizeof(U) * (unsigned)count);
+    return r;
+  }
 };
+
+// ---- lean resident tier helpers (A in ELL) -----------------------------------------
+// Byte-table map of a column's lists (up to 128 entries, two lists with unique rows in
+// each): the entries sit in ent[] (list 0 first, then list 1) and a table of kBtCells
+// 16-bit cells maps the hash of a row to 1 + its position in list 0 (low byte) and in
+// list 1 (high byte), 0 meaning none.  The hash multiplier is picked per column among
+// kBtMuls odd constants so that no two rows of one list share a cell; a lookup is then
+// one cell read plus one entry read per list, with no probing and no branches.
+constexpr int kBtCells = 2048;
+constexpr int kBtShift = 21;          // 32 - log2(kBtCells)
+constexpr int kBtMuls = 8;
+
+__device__ __forceinline__ unsigned bt_mul(int a) {
+  switch (a & 7) {
+    case 0: return 0x9E3779B1u;
+    case 1: return 0x85EBCA77u;
+    case 2: return 0xC2B2AE3Du;
+    case 3: return 0x27D4EB2Fu;
+    case 4: return 0x165667B1u;
+    case 5: return 0xD3A2646Du;
+    case 6: return 0xFD7046C5u;
+    default: return 0xB55A4F09u;
+  }
+}
+
+template <typename T>
+struct BtEnt {
+  int row;
+  T val;
+};
+
+__device__ __forceinline__ unsigned bt_cell(int row, unsigned m) {
+  return ((unsigned)row * m) >> kBtShift;
+}
+
+// Each lane holds up to K entries (row < 0: none), entry k of list lst[k] at position
+// pos[k].  Writes 1 + pos into the entry's byte and keeps the first multiplier under
+// which every byte reads back as written; returns its index, or -1 (nothing left written).
+// (S bytes per cell: one per list)
+template <int K, int S = 2>
+__device__ __forceinline__ int bt_build(unsigned char* cb, const int (&row)[K], const int (&lst)[K],
+                                        const int (&pos)[K]) {
+  for (int a = 0; a < kBtMuls; ++a) {
+    const unsigned m = bt_mul(a);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (row[k] >= 0) cb[S * bt_cell(row[k], m) + lst[k]] = (unsigned char)(pos[k] + 1);
+    __syncthreads();
+    bool clash = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (row[k] >= 0 && cb[S * bt_cell(row[k], m) + lst[k]] != (unsigned char)(pos[k] + 1))
+        clash = true;
+    if (__ballot(clash) == 0ull) return a;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (row[k] >= 0) cb[S * bt_cell(row[k], m) + lst[k]] = 0;
+    __syncthreads();
+  }
+  return -1;
+}
+
+template <int K, int S = 2>
+__device__ __forceinline__ void bt_clear(unsigned char* cb, const int (&row)[K], const int (&lst)[K],
+                                         unsigned m) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (row[k] >= 0) cb[S * bt_cell(row[k], m) + lst[k]] = 0;
+}
+
+// row w in list 0 (entries ent[0 .. n0)) and list 1 (ent[n0 ..)): hit flags and values
+template <typename T>
+__device__ __forceinline__ void bt_find(const unsigned short* cell, unsigned m,
+                                        const BtEnt<T>* ent, int n0, int w, bool& h0, T& x0,
+                                        bool& h1, T& x1) {
+  const unsigned v = cell[bt_cell(w, m)];
+  const int e0 = (int)(v & 0xFFu) - 1, e1 = (int)(v >> 8) - 1;
+  const BtEnt<T> a = ent[max(e0, 0)];
+  const BtEnt<T> b = ent[n0 + max(e1, 0)];
+  h0 = e0 >= 0 && a.row == w;
+  h1 = e1 >= 0 && b.row == w;
+  x0 = a.val;
+  x1 = b.val;
+}
+
+// the eight column indices of ELL row `row` from slot c (all -1 for row < 0)
+__device__ __forceinline__ void ell_cols8(const Csr& A, int row, int c, int (&cols)[8]) {
+  if (row >= 0) {
+    const int64_t q = ((int64_t)row << A.eshift) + c;
+    const int4 a = *(const int4*)(A.ecol + q);
+    const int4 b = *(const int4*)(A.ecol + q + 4);
+    cols[0] = a.x; cols[1] = a.y; cols[2] = a.z; cols[3] = a.w;
+    cols[4] = b.x; cols[5] = b.y; cols[6] = b.z; cols[7] = b.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) cols[k] = -1;
+  }
+}
+
+__device__ __forceinline__ int log2_pow2(int x) { return 31 - __clz(x); }
+
+// eight ELL slots of A from q (a multiple of 8) with their values in the iterate's type
+// (float32 copy on the mixed path, float64 otherwise): 16-byte loads, no conversion
+template <typename T>
+__device__ __forceinline__ void ell_chunk(const Csr& A, int64_t q, int (&cols)[8], T (&vals)[8]) {
+  const int4 a = *(const int4*)(A.ecol + q);
+  const int4 b = *(const int4*)(A.ecol + q + 4);
+  cols[0] = a.x; cols[1] = a.y; cols[2] = a.z; cols[3] = a.w;
+  cols[4] = b.x; cols[5] = b.y; cols[6] = b.z; cols[7] = b.w;
+  if constexpr (sizeof(T) == 4) {
+    const float4 u = *(const float4*)(A.eval32 + q);
+    const float4 v = *(const float4*)(A.eval32 + q + 4);
+    vals[0] = u.x; vals[1] = u.y; vals[2] = u.z; vals[3] = u.w;
+    vals[4] = v.x; vals[5] = v.y; vals[6] = v.z; vals[7] = v.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+      const double2 v = *(const double2*)(A.eval + q + k);
+      vals[k] = v.x;
+      vals[k + 1] = v.y;
+    }
+  }
+}
 
 // CSR only: degree prefix of the rows rows[0..cnt): pre[e] = sum_{f<=e} deg(rows[f]),
 // and the row starts rs[e] = rowptr[rows[e]].  Returns the total.
@@ -625,6 +754,162 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
   if (lane == 0 && tier >= 1 && outcnt) atomicAdd(&st->cnt[6 * kCntSlots + kCntSlots - 1], outcnt);
 }
 
+// Lean resident tier of the residual (A in ELL): the same arithmetic and summation
+// order as k_resid, with far fewer instructions per column.  Each lane holds one entry
+// of m_j (up to L <= 128 entries, two per lane), enters it in the byte-table map and
+// inserts the columns of its ELL row straight from 16-byte loads into the ordered key
+// set, sized from the column's bound ub_j = off[j+1] - off[j]; the keys are then sorted
+// by row (the stored order of R) and each pulled over A's row with branch-free lookups.
+// A column that does not fit (list, key set, sort) goes to the next tier.
+template <typename T>
+__global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 5))) void k_resid_lean(Csr A, Pair<T> Mp, Cols<T> R,
+                                                          const int64_t* off,
+                                                          const int64_t* total, double* colnorm,
+                                                          int weighted, double* colrz,
+                                                          BigList big, DevState* st, int L,
+                                                          int H) {
+  if (!st->any_active) return;
+  extern __shared__ char smem[];
+  Carve cv(smem);
+  const int Lc = min(L, 128);             // two list entries per lane
+  unsigned short* cell = cv.take16<unsigned short>(kBtCells);
+  BtEnt<T>* ent = cv.take16<BtEnt<T>>(Lc + 1);
+  unsigned* kt = cv.take<unsigned>(max(H + kOhOver, 256));
+  int* keys = (int*)kt;
+  const int lane = lane_id();
+  for (int i = lane; i < kBtCells / 2; i += SPAI_WAVE) ((unsigned*)cell)[i] = 0u;
+  __syncthreads();
+  const Cols<T> M = Mp.now();
+  const int64_t ntot = *total;
+  const bool overflow = ntot > R.cap;
+  const int W = 1 << A.eshift;
+  unsigned long long outcnt = 0;
+  ColumnWalk w(A.n, blockIdx.x, gridDim.x);
+  for (int64_t j = w.begin; j < w.end; j += w.step) {
+    const int lm = M.len[j];
+    if (lm > Lc) {
+      defer_column(0, big, st, j);
+      continue;
+    }
+    if (overflow) {
+      if (lane == 0) atomicOr(&st->err, 2);
+      continue;
+    }
+    const int64_t ob = off[j];
+    const int64_t ub = (j + 1 < A.n ? off[j + 1] : ntot) - ob;   // >= distinct rows of r_j
+    const int Hc = next_pow2((int)min<int64_t>(max<int64_t>(ub, 64), (int64_t)H));
+    const int ksh = 32 - log2_pow2(Hc);
+    const int kend = Hc + kOhOver;
+    const int64_t mb = M.beg[j];
+    int row[2], lst[2] = {0, 0}, pos[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = lane + k * SPAI_WAVE;
+      pos[k] = e;
+      row[k] = -1;
+      if (e < lm) {
+        row[k] = M.idx[mb + e];
+        ent[e] = BtEnt<T>{row[k], M.val[mb + e]};
+      }
+    }
+    for (int i = lane; i < kend; i += SPAI_WAVE) kt[i] = kOhEmpty;
+    const int a = bt_build<2>((unsigned char*)cell, row, lst, pos);
+    if (a < 0) {
+      defer_column(0, big, st, j);
+      continue;
+    }
+    const unsigned mul = bt_mul(a);
+    bool ok = true;
+    const int npass = lm > SPAI_WAVE ? 2 : 1;      // entries per lane in use
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (k >= npass) break;
+      int rr = row[k];
+      for (int c = 0; c < W; c += 8) {
+        int cols[8];
+        ell_cols8(A, rr, c, cols);
+        const int c0[4] = {cols[0], cols[1], cols[2], cols[3]};
+        const int c1[4] = {cols[4], cols[5], cols[6], cols[7]};
+        ok = oh_insert_batch<4>(kt, ksh, kend, c0) && ok;
+        ok = oh_insert_batch<4>(kt, ksh, kend, c1) && ok;
+        if (cols[7] < 0) rr = -1;                  // the row ended in this chunk
+      }
+    }
+    {
+      const int kd[1] = {lane == 0 ? (int)j : -1};
+      ok = oh_insert_batch<1>(kt, ksh, kend, kd) && ok;
+    }
+    const bool bad = __ballot(!ok) != 0ull;
+    __syncthreads();
+    int nu = bad ? 0 : oh_compact(kt, kend);
+    __syncthreads();
+    if (bad || nu > 256) {                         // key set or register sort too small
+      bt_clear<2>((unsigned char*)cell, row, lst, mul);
+      __syncthreads();
+      defer_column(0, big, st, j);
+      continue;
+    }
+    // rows ascending (the stored order of R)
+    if (nu <= 64) sort_in_registers<1>(keys, nu);
+    else if (nu <= 128) sort_in_registers<2>(keys, nu);
+    else sort_in_registers<4>(keys, nu);
+    __syncthreads();
+    double acc = 0.0, acc_rz = 0.0;
+    for (int t0 = 0; t0 < nu; t0 += SPAI_WAVE) {
+      const int t = t0 + lane;
+      if (t < nu) {
+        const int u = keys[t];
+        const int64_t q0 = (int64_t)u << A.eshift;
+        double sum = 0.0, diag = 0.0;
+        for (int c = 0; c < W; c += 8) {
+          int cols[8];
+          T vals[8];
+          ell_chunk<T>(A, q0 + c, cols, vals);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            bool h0, h1;
+            T x0, x1;
+            bt_find<T>(cell, mul, ent, lm, cols[k], h0, x0, h1, x1);
+            // a masked product adds +-0 to a sum that is never -0: bitwise the skip
+            sum += (double)vals[k] * (double)(h0 ? x0 : (T)0);
+            if (weighted && cols[k] == u) diag = (double)vals[k];
+          }
+          if (cols[7] < 0) break;
+        }
+        const double r = ((u == (int)j) ? 1.0 : 0.0) - sum;
+        const T rt = (T)r;
+        T out = rt;
+        if (weighted) {                   // Z = Pi R, Pi = D_A^{-1}
+          const double pi = 1.0 / diag;
+          out = (T)(pi * r);
+          acc_rz += (double)rt * (double)out;
+        }
+        R.idx[ob + t] = u;
+        R.val[ob + t] = out;
+        acc += (double)rt * (double)rt;
+      }
+    }
+    acc = wave_sum(acc);
+    if (weighted) acc_rz = wave_sum(acc_rz);
+    if (lane == 0) {
+      colnorm[j] = acc;
+      if (weighted) colrz[j] = acc_rz;
+      R.beg[j] = ob;
+      R.len[j] = nu;
+    }
+    outcnt += (unsigned long long)nu;
+    bt_clear<2>((unsigned char*)cell, row, lst, mul);
+    __syncthreads();
+  }
+  if (lane == 0 && blockIdx.x < kCntSlots) st->cnt[6 * kCntSlots + blockIdx.x] += outcnt;
+}
+
+template <typename T>
+static size_t resid_lean_lds(Tile t) {
+  return (size_t)kBtCells * 2 + (size_t)(std::min(t.L, 128) + 1) * sizeof(BtEnt<T>) +
+         (size_t)std::max(t.H + kOhOver, 256) * 4 + 64;
+}
+
 static size_t resid_lds(Tile t, bool ell) {
   return (size_t)t.L * 4 + (size_t)t.H * 4 + (size_t)t.L * 8 + (size_t)t.L * 16 +
          (ell ? 0 : (size_t)t.L * 12) + 64;
@@ -664,16 +949,24 @@ void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const 
   const bool ell = A.eshift >= 0;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
-  hipLaunchKernelGGL((k_resid<T, false>), dim3(resident_grid(k_resid<T, false>, resid_lds(small, ell))),
-                     dim3(SPAI_WAVE), resid_lds(small, ell), s, A, M, R, off, total, colnorm,
-                     weighted, colrz, big, st, 0, small.L, small.H);
+  if (ell)
+    hipLaunchKernelGGL((k_resid_lean<T>), dim3(resident_grid(k_resid_lean<T>, resid_lean_lds<T>(small))),
+                       dim3(SPAI_WAVE), resid_lean_lds<T>(small), s, A, M, R, off, total, colnorm,
+                       weighted, colrz, big, st, small.L, small.H);
+  else
+    hipLaunchKernelGGL((k_resid<T, false>),
+                       dim3(resident_grid(k_resid<T, false>, resid_lds(small, ell))),
+                       dim3(SPAI_WAVE), resid_lds(small, ell), s, A, M, R, off, total, colnorm,
+                       weighted, colrz, big, st, 0, small.L, small.H);
   hipLaunchKernelGGL((k_resid<T, false>), dim3(256), dim3(SPAI_WAVE), resid_lds(large, ell), s, A, M,
                      R, off, total, colnorm, weighted, colrz, big, st, 1, large.L, large.H);
   hipLaunchKernelGGL((k_resid<T, true>), dim3(kHugeGrid), dim3(SPAI_WAVE), 0, s, A, M, R, off, total,
                      colnorm, weighted, colrz, big, st, 2, huge.L, huge.H);
 }
 
-size_t resid_tile_bytes(Tile t, bool ell) { return resid_lds(t, ell); }
+size_t resid_tile_bytes(Tile t, bool ell) {
+  return ell ? std::max(resid_lds(t, ell), resid_lean_lds<double>(t)) : resid_lds(t, ell);
+}
 
 // ============================================================================
 // SpGEMM fused with Frobenius dots: A r_j and A p_j in LDS, never stored
@@ -738,7 +1031,7 @@ __device__ __forceinline__ void dots_body(Csr A, Cols<T> R, Pair<T> Pp, int useR
       tile_sync<GS>();
       return;
     }
-    const int nu = ks_sort_inplace(s_keys, H);
+    const int nu = ks_sort_inplace(s_keys, H, true);   // ordered by ohash, as the lean tier
     tile_sync<GS>();
     const int* ri = s_li;
     const double* rv = s_lv;
@@ -761,8 +1054,9 @@ __device__ __forceinline__ void dots_body(Csr A, Cols<T> R, Pair<T> Pp, int useR
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
             const unsigned e0 = pw[k] & kNoPos, e1 = pw[k] >> 16;
-            if (e0 != kNoPos) ar[c] += vals[k] * rv[e0];
-            if (e1 != kNoPos) ap[c] += vals[k] * pv[e1];
+            // fused multiply-add of the masked value: bitwise the lean tier's sum
+            ar[c] = fma(vals[k], e0 != kNoPos ? rv[e0] : 0.0, ar[c]);
+            ap[c] = fma(vals[k], e1 != kNoPos ? pv[e1] : 0.0, ap[c]);
             if (cols[k] == key[c]) diag[c] = vals[k];
           }
         },
@@ -789,15 +1083,11 @@ __device__ __forceinline__ void dots_body(Csr A, Cols<T> R, Pair<T> Pp, int useR
         });
     (void)ri;
     (void)pi;
-    d0 = wave_sum(d0);
-    d1 = wave_sum(d1);
-    d2 = wave_sum(d2);
-    d3 = wave_sum(d3);
-    d4 = wave_sum(d4);
-    d5 = wave_sum(d5);
+    double dd[6] = {d0, d1, d2, d3, d4, d5};
+    wave_sum6(dd);
     if (lane == 0) {
       double* o = colpart + j * kND;
-      o[0] = d0; o[1] = d1; o[2] = d2; o[3] = d3; o[4] = d4; o[5] = d5;
+      o[0] = dd[0]; o[1] = dd[1]; o[2] = dd[2]; o[3] = dd[3]; o[4] = dd[4]; o[5] = dd[5];
     }
     tile_sync<GS>();
   };
@@ -831,6 +1121,156 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
   dots_body<T, false>(A, R, Pp, useR, useP, weighted, colpart, big, st, tier, L, H);
 }
 
+// Lean resident tier of the dots (A in ELL).  Each lane holds up to two entries of
+// r_j | p_j (L <= 128 in all), enters them in the byte-table map and inserts the columns
+// of their ELL rows into the ordered key set straight from 16-byte loads.  The ordered
+// set needs no count (a walk off its end sends the column to the next tier) and no sort:
+// its slots read in order list the rows of A r_j and A p_j sorted by ohash, the order
+// every tier sums in.  Per row u, one pass over A's row gives (A r)_u, (A p)_u, r_u, p_u
+// (the diagonal entry's lookup) and a_uu, with the same arithmetic as dots_body.
+// Registers are capped for five waves per SIMD on the float path (no spills there).
+template <typename T>
+__global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_dots_lean(Csr A, Cols<T> R, Pair<T> Pp, int useR,
+                                                         int useP, int weighted,
+                                                         double* colpart, BigList big,
+                                                         DevState* st, int L, int H) {
+  if (!st->any_active || !st->iter_active) return;
+  extern __shared__ char smem[];
+  Carve cv(smem);
+  const int Lc = min(L, 128);
+  unsigned short* cell = cv.take16<unsigned short>(kBtCells);
+  BtEnt<T>* ent = cv.take16<BtEnt<T>>(Lc + 1);
+  unsigned* kt = cv.take<unsigned>(H + kOhOver);
+  const int lane = lane_id();
+  for (int i = lane; i < kBtCells / 2; i += SPAI_WAVE) ((unsigned*)cell)[i] = 0u;
+  __syncthreads();
+  const Cols<T> P = Pp.now();
+  const int W = 1 << A.eshift;
+  ColumnWalk w(A.n, blockIdx.x, gridDim.x);
+  for (int64_t j = w.begin; j < w.end; j += w.step) {
+    const int lr = useR ? R.len[j] : 0;
+    const int lp = useP ? P.len[j] : 0;
+    const int le = lr + lp;
+    if (le > Lc) {
+      defer_column(0, big, st, j);
+      continue;
+    }
+    const int64_t rb = useR ? R.beg[j] : 0;
+    const int64_t pb = useP ? P.beg[j] : 0;
+    const int Hc = min(H, max(128, next_pow2(max(le * W / 2, 1))));   // home slots
+    const int ksh = 32 - log2_pow2(Hc);
+    const int kend = Hc + kOhOver;
+    int row[2], lst[2], pos[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = lane + k * SPAI_WAVE;
+      row[k] = -1;
+      lst[k] = e < lr ? 0 : 1;
+      pos[k] = e < lr ? e : e - lr;
+      if (e < lr) {
+        row[k] = R.idx[rb + e];
+        ent[e] = BtEnt<T>{row[k], R.val[rb + e]};
+      } else if (e < le) {
+        row[k] = P.idx[pb + e - lr];
+        ent[e] = BtEnt<T>{row[k], P.val[pb + e - lr]};
+      }
+    }
+    for (int i = lane; i < kend; i += SPAI_WAVE) kt[i] = kOhEmpty;
+    const int a = bt_build<2>((unsigned char*)cell, row, lst, pos);
+    if (a < 0) {
+      defer_column(0, big, st, j);
+      continue;
+    }
+    const unsigned mul = bt_mul(a);
+    bool ok = true;
+    const int npass = le > SPAI_WAVE ? 2 : 1;      // entries per lane in use
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (k >= npass) break;
+      int rr = row[k];
+      for (int c = 0; c < W; c += 8) {
+        int cols[8];
+        ell_cols8(A, rr, c, cols);
+        const int c0[4] = {cols[0], cols[1], cols[2], cols[3]};
+        const int c1[4] = {cols[4], cols[5], cols[6], cols[7]};
+        ok = oh_insert_batch<4>(kt, ksh, kend, c0) && ok;
+        ok = oh_insert_batch<4>(kt, ksh, kend, c1) && ok;
+        if (cols[7] < 0) rr = -1;
+      }
+    }
+    const bool bad = __ballot(!ok) != 0ull;
+    __syncthreads();
+    if (bad) {
+      bt_clear<2>((unsigned char*)cell, row, lst, mul);
+      __syncthreads();
+      defer_column(0, big, st, j);
+      continue;
+    }
+    const int nu = oh_compact(kt, kend);
+    __syncthreads();
+    const int* keys = (const int*)kt;
+    double d[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int t0 = 0; t0 < nu; t0 += SPAI_WAVE) {
+      const int t = t0 + lane;
+      if (t < nu) {
+        const int u = keys[t];
+        const int64_t q0 = (int64_t)u << A.eshift;
+        double ar = 0.0, ap = 0.0, diag = 0.0;
+        for (int c = 0; c < W; c += 8) {
+          int cols[8];
+          T vals[8];
+          ell_chunk<T>(A, q0 + c, cols, vals);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            bool h0, h1;
+            T x0, x1;
+            bt_find<T>(cell, mul, ent, lr, cols[k], h0, x0, h1, x1);
+            const double av = (double)vals[k];
+            ar = fma(av, (double)(h0 ? x0 : (T)0), ar);
+            ap = fma(av, (double)(h1 ? x1 : (T)0), ap);
+            if (weighted && cols[k] == u) diag = av;
+          }
+          if (cols[7] < 0) break;
+        }
+        double ru, pu;                 // u's own entries in r_j and p_j
+        {
+          bool h0, h1;
+          T x0, x1;
+          bt_find<T>(cell, mul, ent, lr, u, h0, x0, h1, x1);
+          ru = h0 ? (double)x0 : 0.0;
+          pu = h1 ? (double)x1 : 0.0;
+        }
+        d[0] += ru * ar;
+        d[3] += ru * ap;
+        d[5] += pu * ap;
+        if (weighted) {            // (AZ, Pi AZ), (AZ, Pi AP), (AP, Pi AP), Pi = D_A^{-1}
+          const double pi = 1.0 / diag;
+          d[1] += ar * (pi * ar);
+          d[2] += ar * (pi * ap);
+          d[4] += ap * (pi * ap);
+        } else {
+          d[1] += ar * ar;
+          d[2] += ar * ap;
+          d[4] += ap * ap;
+        }
+      }
+    }
+    wave_sum6(d);
+    if (lane == 0) {
+      double* o = colpart + j * kND;
+      o[0] = d[0]; o[1] = d[1]; o[2] = d[2]; o[3] = d[3]; o[4] = d[4]; o[5] = d[5];
+    }
+    bt_clear<2>((unsigned char*)cell, row, lst, mul);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+static size_t dots_lean_lds(Tile t) {
+  return (size_t)kBtCells * 2 + (size_t)(std::min(t.L, 128) + 1) * sizeof(BtEnt<T>) +
+         (size_t)(t.H + kOhOver) * 4 + 64;
+}
+
 static size_t dots_lds(Tile t, bool ell) {
   return (size_t)t.L * 4 + (size_t)t.H * 4 + (size_t)t.L * 8 + (size_t)t.L * 16 +
          (ell ? 0 : (size_t)t.L * 12) + 64;
@@ -843,7 +1283,11 @@ void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, int wei
   const bool ell = A.eshift >= 0;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
-  if (small.waves == 5)
+  if (small.waves == 1 && ell)
+    hipLaunchKernelGGL((k_dots_lean<T>), dim3(resident_grid(k_dots_lean<T>, dots_lean_lds<T>(small))),
+                       dim3(SPAI_WAVE), dots_lean_lds<T>(small), s, A, R, P, useR, useP, weighted,
+                       colpart, big, st, small.L, small.H);
+  else if (small.waves == 5)
     hipLaunchKernelGGL((k_dots_w5<T>), dim3(resident_grid(k_dots_w5<T>, dots_lds(small, ell))),
                        dim3(SPAI_WAVE), dots_lds(small, ell), s, A, R, P, useR, useP, weighted,
                        colpart, big, st, 0, small.L, small.H);
@@ -858,7 +1302,9 @@ void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, int wei
                      weighted, colpart, big, st, 2, huge.L, huge.H);
 }
 
-size_t dots_tile_bytes(Tile t, bool ell) { return dots_lds(t, ell); }
+size_t dots_tile_bytes(Tile t, bool ell) {
+  return (t.waves == 1 && ell) ? dots_lean_lds<double>(t) : dots_lds(t, ell);
+}
 
 // ============================================================================
 // implicit residual update R_{i+1} = R_i - c A X_i (Algorithms 1, 3, 4 as printed,
@@ -1532,6 +1978,287 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
                         DG);
 }
 
+// Lean resident tier of the update (A in ELL with rows of at most 8 entries).  Same
+// candidates and the same arithmetic as update_body, built without searches: every row
+// of the column's own lists (m_j, r_j, p_j, p^T_j, up to 128 entries, two per lane) and
+// of its neighbour columns m_l, l in N(j) (one entry per lane each), goes into the
+// ordered key set; the keys are sorted by row and a byte table maps a row's hash to its
+// rank; the own lists' values are then scattered to dense per-rank arrays and the
+// neighbour products a_jl m_l(k) added to a per-rank sum neighbour by neighbour in
+// ascending l (one round per neighbour, so each sum runs in the order update_body uses),
+// and each lane forms the candidates of its keys.
+constexpr int kUpdLeanKeys = 128;
+
+template <typename T>
+__global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4))) void k_update_lean(
+    Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp, Pair<T> PTp, UpdMode md, const int64_t* off,
+    const int64_t* total, const int32_t* kcol, double* tM, double* tP, BigList big, Seg seg,
+    DevState* st, int L, int H) {
+  if (!st->any_active || !st->iter_active) return;
+  extern __shared__ char smem[];
+  Carve cv(smem);
+  unsigned char* cb = cv.take16<unsigned char>(kBtCells);     // 1 + rank of a row's hash
+  T* dv = cv.take16<T>(4 * kUpdLeanKeys);                      // m, r, p, p^T by rank
+  double* rta = cv.take<double>(kUpdLeanKeys);                 // sum_l a_jl m_l(k) by rank
+  unsigned* kt = cv.take<unsigned>(max(H + kOhOver, kUpdLeanKeys));
+  int* keys = (int*)kt;
+  const int lane = lane_id();
+  for (int i = lane; i < kBtCells / 4; i += SPAI_WAVE) ((unsigned*)cb)[i] = 0u;
+  __syncthreads();
+  const Cols<T> M = Mp.now();
+  const Cols<T> Mo = Mp.nxt();
+  const Cols<T> P = Pp.now();
+  const Cols<T> Po = Pp.nxt();
+  const Cols<T> PT = PTp.now();
+  const Cols<T> PTo = PTp.nxt();
+  const bool needR = (md.doM && (md.x1 == 1 || md.x2 == 1)) || (md.doP && md.pR);
+  const bool needP = (md.doM && (md.x1 == 2 || md.x2 == 2)) || (md.doP && md.pP);
+  const bool mirror = md.sym != 0;
+  const bool needRT = needR && mirror;
+  const bool needPT = needP && mirror;
+  const int64_t ntot = *total;
+  const bool overflow = ntot > Mo.cap || (md.doP && (ntot > Po.cap || ntot > PTo.cap));
+  const int Lc = min(L, 128);
+  const T* eval = sizeof(T) == 4 ? (const T*)A.eval32 : (const T*)A.eval;
+  ColumnWalk w(A.n, blockIdx.x, gridDim.x);
+  for (int64_t j = w.begin; j < w.end; j += w.step) {
+    const SegState& g = seg.st[seg.segof(j)];
+    const double a1 = g.coef[0], a2 = g.coef[1], c1 = g.coef[2], c2 = g.coef[3];
+    const int lm = md.doM ? M.len[j] : 0;
+    const int lr = needR ? R.len[j] : 0;
+    const int lp = needP ? P.len[j] : 0;
+    const int lpt = needPT ? PT.len[j] : 0;
+    const int lown = lm + lr + lp + lpt;
+    const int64_t ob = off[j];
+    const int64_t ub = (j + 1 < A.n ? off[j + 1] : ntot) - ob;   // entries of all lists + 1
+    // neighbours l in N(j) (row j of A): one per lane
+    int nl = -1;
+    double av = 0.0;
+    if (needRT && lane < 8) {
+      nl = A.ecol[((int64_t)j << 3) + lane];
+      av = (double)eval[((int64_t)j << 3) + lane];
+    }
+    // own entries, two per lane (list 0 m, 1 r, 2 p, 3 p^T), loaded before anything
+    // waits on the neighbours (a list too long for the tile is dropped below)
+    int orow[2], olst[2];
+    T oval[2];
+    const bool fits = lown <= Lc;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = lane + k * SPAI_WAVE;
+      orow[k] = -1;
+      olst[k] = 0;
+      oval[k] = (T)0;
+      if (fits) {
+        if (e < lm) {
+          const int64_t q = M.beg[j] + e;
+          orow[k] = M.idx[q]; oval[k] = M.val[q]; olst[k] = 0;
+        } else if (e < lm + lr) {
+          const int64_t q = R.beg[j] + (e - lm);
+          orow[k] = R.idx[q]; oval[k] = R.val[q]; olst[k] = 1;
+        } else if (e < lm + lr + lp) {
+          const int64_t q = P.beg[j] + (e - lm - lr);
+          orow[k] = P.idx[q]; oval[k] = P.val[q]; olst[k] = 2;
+        } else if (e < lown) {
+          const int64_t q = PT.beg[j] + (e - lm - lr - lp);
+          orow[k] = PT.idx[q]; oval[k] = PT.val[q]; olst[k] = 3;
+        }
+      }
+    }
+    int nlen = 0;
+    int64_t nbeg = 0;
+    if (nl >= 0) {
+      nlen = M.len[nl];
+      nbeg = M.beg[nl];
+    }
+    const unsigned long long nm = __ballot(nl >= 0);
+    const int deg = __popcll(nm);                 // entries first, so lanes 0 .. deg-1
+    // neighbour entries: entry `lane` of each neighbour column m_l
+    int nrow[8];
+    T nval[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int len_t = __shfl(nlen, t, SPAI_WAVE);
+      const int64_t beg_t = __shfl(nbeg, t, SPAI_WAVE);
+      nrow[t] = -1;
+      nval[t] = (T)0;
+      if (t < deg && lane < len_t) {
+        nrow[t] = M.idx[beg_t + lane];
+        nval[t] = M.val[beg_t + lane];
+      }
+    }
+    if (!fits || wave_max_int(nlen) > SPAI_WAVE) {
+      defer_column(0, big, st, j);
+      continue;
+    }
+    if (overflow) {
+      if (lane == 0) atomicOr(&st->err, 2);
+      continue;
+    }
+    const unsigned long long dj = __ballot(nl == (int)j);
+    const double ajj = dj ? __shfl(av, __ffsll((long long)dj) - 1, SPAI_WAVE) : 0.0;
+    const int Hc = next_pow2((int)min<int64_t>(max<int64_t>(ub, 64), (int64_t)H));
+    const int ksh = 32 - log2_pow2(Hc);
+    const int kend = Hc + kOhOver;
+    for (int i = lane; i < kend; i += SPAI_WAVE) kt[i] = kOhEmpty;
+    __syncthreads();
+    bool ok = oh_insert_batch<2>(kt, ksh, kend, orow);
+    {
+      const int n0[4] = {nrow[0], nrow[1], nrow[2], nrow[3]};
+      const int n1[4] = {nrow[4], nrow[5], nrow[6], nrow[7]};
+      ok = oh_insert_batch<4>(kt, ksh, kend, n0) && ok;
+      ok = oh_insert_batch<4>(kt, ksh, kend, n1) && ok;
+    }
+    {
+      const int kd[1] = {lane == 0 ? (int)j : -1};
+      ok = oh_insert_batch<1>(kt, ksh, kend, kd) && ok;
+    }
+    const bool bad = __ballot(!ok) != 0ull;
+    __syncthreads();
+    const int nk = bad ? 0 : oh_compact(kt, kend);
+    __syncthreads();
+    if (bad || nk > kUpdLeanKeys) {
+      defer_column(0, big, st, j);
+      continue;
+    }
+    if (nk <= 64) sort_in_registers<1>(keys, nk);
+    else sort_in_registers<2>(keys, nk);
+    __syncthreads();
+    int krow[2], klst[2] = {0, 0}, kpos[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      kpos[k] = lane + k * SPAI_WAVE;
+      krow[k] = kpos[k] < nk ? keys[kpos[k]] : -1;
+    }
+    const int a = bt_build<2, 1>(cb, krow, klst, kpos);
+    if (a < 0) {
+      defer_column(0, big, st, j);
+      continue;
+    }
+    const unsigned mul = bt_mul(a);
+    // dense per-rank values (zero where a list has no entry)
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      if (kpos[k] < nk) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dv[q * kUpdLeanKeys + kpos[k]] = (T)0;
+        rta[kpos[k]] = 0.0;
+      }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      if (orow[k] >= 0) dv[olst[k] * kUpdLeanKeys + (int)cb[bt_cell(orow[k], mul)] - 1] = oval[k];
+    // neighbour products in ascending l: one round per neighbour, distinct ranks inside
+    for (int t = 0; t < deg; ++t) {
+      const double a_t = __shfl(av, t, SPAI_WAVE);
+      int rr = -1;
+      T vv = (T)0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q == t) { rr = nrow[q]; vv = nval[q]; }
+      if (rr >= 0) {
+        const int rk = (int)cb[bt_cell(rr, mul)] - 1;
+        rta[rk] += a_t * (double)vv;
+      }
+    }
+    __syncthreads();
+    int cntM = 0, cntP = 0, cntPT = 0;
+    for (int base = 0; base < nk; base += SPAI_WAVE) {
+      const int t = base + lane;
+      const bool valid = t < nk;
+      const int k = valid ? keys[t] : -1;
+      double mv = 0.0, rv = 0.0, pv = 0.0, ptv = 0.0, rtv = 0.0;
+      if (valid) {
+        mv = (double)dv[t];
+        rv = (double)dv[kUpdLeanKeys + t];
+        pv = (double)dv[2 * kUpdLeanKeys + t];
+        ptv = (double)dv[3 * kUpdLeanKeys + t];
+      }
+      if (needRT) {
+        const double rj = ((k == (int)j) ? 1.0 : 0.0) - (valid ? rta[t] : 0.0);
+        rtv = md.weighted ? (double)(T)((1.0 / ajj) * rj) : (double)(T)rj;   // Z^T = Pi R^T
+      }
+      bool keepM = false;
+      T mt = (T)0;
+      if (md.doM) {
+        const double v1 = md.x1 == 1 ? rv : (md.x1 == 2 ? pv : 0.0);
+        const double v2 = md.x2 == 1 ? rv : (md.x2 == 2 ? pv : 0.0);
+        const double x = (mv + a1 * v1) + a2 * v2;
+        double sv = x;
+        if (md.sym) {
+          const double w1 = md.x1 == 1 ? rtv : (md.x1 == 2 ? ptv : 0.0);
+          const double w2 = md.x2 == 1 ? rtv : (md.x2 == 2 ? ptv : 0.0);
+          const double y = (mv + a1 * w1) + a2 * w2;
+          sv = (x + y) * 0.5;
+        }
+        mt = (T)sv;
+        const double sd = (double)mt;
+        keepM = valid && sd != 0.0 && (k == (int)j || fabs(sd) >= md.u);
+      }
+      bool keepP = false, keepPT = false;
+      T pt = (T)0, ptt = (T)0;
+      if (md.doP) {
+        const double x = (md.pR ? c1 * rv : 0.0) + (md.pP ? c2 * pv : 0.0);
+        const double y = (md.pR ? c1 * rtv : 0.0) + (md.pP ? c2 * ptv : 0.0);
+        pt = (T)x;
+        ptt = (T)y;
+        keepP = valid && (double)pt != 0.0;
+        keepPT = valid && (double)ptt != 0.0;
+      }
+      const unsigned long long bm = __ballot(keepM);
+      const unsigned long long bp = __ballot(keepP);
+      const unsigned long long bpt = __ballot(keepPT);
+      const unsigned long long lt = lanemask_lt();
+      if (keepM) {
+        const int64_t q = ob + cntM + __popcll(bm & lt);
+        Mo.idx[q] = k;
+        Mo.val[q] = mt;
+      }
+      if (keepP) {
+        const int64_t q = ob + cntP + __popcll(bp & lt);
+        Po.idx[q] = k;
+        Po.val[q] = pt;
+      }
+      if (keepPT) {
+        const int64_t q = ob + cntPT + __popcll(bpt & lt);
+        PTo.idx[q] = k;
+        PTo.val[q] = ptt;
+      }
+      cntM += __popcll(bm);
+      cntP += __popcll(bp);
+      cntPT += __popcll(bpt);
+    }
+    if (lane == 0) {
+      if (md.doM) { Mo.beg[j] = ob; Mo.len[j] = cntM; }
+      if (md.doP) {
+        Po.beg[j] = ob; Po.len[j] = cntP;
+        PTo.beg[j] = ob; PTo.len[j] = cntPT;
+      }
+    }
+    if (md.colcap) {
+      // thresholds from the candidates this wave has just written (L1/L2 resident)
+      const int kc = kcol[j];
+      __threadfence_block();
+      __syncthreads();
+      if (md.doM) {
+        const double t = kth_largest_cols(Mo.idx + ob, Mo.val + ob, cntM, (int)j, kc - 1);
+        if (lane == 0) tM[j] = t;
+      }
+      if (md.doP) {
+        const double t = kth_largest_cols(Po.idx + ob, Po.val + ob, cntP, -1, kc);
+        if (lane == 0) tP[j] = t;
+      }
+    }
+    bt_clear<2, 1>(cb, krow, klst, mul);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+static size_t update_lean_lds() {
+  return (size_t)kBtCells + (size_t)4 * kUpdLeanKeys * sizeof(T) + (size_t)kUpdLeanKeys * 8 + 64;
+}
+
 static int update_deg(Tile t) { return t.DG ? t.DG : (t.L >= 2048 ? 256 : 64); }
 
 static size_t update_lds(Tile t, bool) {
@@ -1540,7 +2267,10 @@ static size_t update_lds(Tile t, bool) {
          (size_t)DG * 8 * 2 + 96;
 }
 
-size_t update_tile_bytes(Tile t) { return update_lds(t, false); }
+size_t update_tile_bytes(Tile t) {
+  return t.waves == 1 ? update_lean_lds<double>() + (size_t)std::max(t.H + kOhOver, kUpdLeanKeys) * 4
+                      : update_lds(t, false);
+}
 
 template <typename T>
 void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, UpdMode md,
@@ -1549,7 +2279,12 @@ void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, Up
                    Tile huge, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
-  if (small.waves == 5)
+  if (small.waves == 1 && A.eshift == 3) {
+    const size_t lds = update_lean_lds<T>() + (size_t)std::max(small.H + kOhOver, kUpdLeanKeys) * 4;
+    hipLaunchKernelGGL((k_update_lean<T>), dim3(resident_grid(k_update_lean<T>, lds)),
+                       dim3(SPAI_WAVE), lds, s, A, M, R, P, PT, md, off, total, kcol, tM, tP, big,
+                       seg, st, small.L, small.H);
+  } else if (small.waves == 5)
     hipLaunchKernelGGL((k_update_w5<T>),
                        dim3(resident_grid(k_update_w5<T>, update_lds(small, true))),
                        dim3(SPAI_WAVE), update_lds(small, true), s, A, M, R, P, PT, md, off,

@@ -557,6 +557,34 @@ def test_column_cap_one(name, method):
     assert sp.triu(Mg, 1).nnz == 0
 
 
+@pytest.mark.parametrize("cap", ["global", "column"])
+@pytest.mark.parametrize("precision,tol", [("f64", TOL_F64), ("mixed", TOL_MIXED)])
+def test_lomr_degenerate_direction_falls_back_to_mr(cap, precision, tol):
+    """The LOMR degeneracy guard on the device (Theorem 4.2's c_i, a 2 x 2 Gram
+    determinant).  On the 8 x 8 Laplacian under a diagonal-only cap the tie band drops
+    P_0 to zero, so A P_{i-1} = 0 at every later step: the device must take the MR step
+    (gamma = 0), count each fallback and follow the oracle, whose trajectory is pinned
+    in closed form."""
+    S = _spai()
+    A = W.laplace2d(8)
+    n = A.shape[0]
+    iters = 9
+    value = n if cap == "global" else 1
+    h = S.SPAI(A, "lomr", cap, value, False, max_iter=iters,
+               options=S.Options(precision=precision))
+    done, hist, rc = h.iterate(iters)
+    st = h.stats()
+    Mg = h.get()
+    h.close()
+    ref = O.lomr(A, oracle_rule(A, cap, value, False), iters)
+    falls = sum(s["mr_fallback"] for s in ref.scalars)
+    assert falls == iters - 1
+    assert done == iters and st["mr_fallbacks"] == falls
+    assert st["step2"] == 0.0 and st["nnz_p"] == 0
+    assert rel_err(hist, ref.resid[1:]) <= tol
+    assert pattern_diff(Mg, ref.M) == (set(), set())
+
+
 def test_cg_breakdown_on_indefinite_matrix():
     """A symmetric matrix with a positive diagonal but one negative eigenvalue (the 10 x 10
     Laplacian shifted by -0.2 I): without dropping, (P_i, A P_i) turns negative at the same
@@ -803,10 +831,12 @@ def test_autotune_leaves_results_unchanged():
                    options=S.Options(precision="mixed"))
         if tune:
             tiles, ms = h.autotune(warm_iters=4, reps=1)
-            assert tiles["resid"][0] in (64, 128, 256) and tiles["dots"][0] in (128, 256, 512)
+            assert tiles["resid"][0] in (64, 128, 256)
+            assert tiles["dots"][0] in (64, 128, 256, 512)
             assert tiles["update"][0] in (256, 384, 512) and tiles["update"][2] in (0, 5)
-            assert tiles["dots"][2] in (0, 5)
-            assert all(t[1] in (512, 1024) for t in tiles.values())
+            assert tiles["dots"][2] in (0, 1, 5)
+            assert tiles["dots"][1] in (256, 512, 1024)
+            assert tiles["resid"][1] in (256, 512, 1024) and tiles["update"][1] in (512, 1024)
             assert all(v > 0 for v in ms.values())
         _, hist, _ = h.iterate(10)
         runs.append((hist, h.get()))
@@ -836,7 +866,9 @@ def test_set_tiles_leaves_results_unchanged():
     cases = [None,
              {"resid": (128, 512), "dots": (256, 512, 5), "update": (384, 512, 5)},
              {"resid": (32, 512), "dots": (32, 512, 0), "update": (32, 512, 0)},
-             {"resid": (32, 512), "dots": (64, 1024, 5), "update": (64, 1024, 5)}]
+             {"resid": (32, 512), "dots": (64, 1024, 5), "update": (64, 1024, 5)},
+             {"resid": (64, 512), "dots": (32, 128, 1), "update": (384, 512, 0)},
+             {"resid": (128, 512), "dots": (256, 1024, 1), "update": (384, 512, 0)}]
     for tiles in cases:
         h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=10,
                    options=S.Options(precision="mixed"))
@@ -862,11 +894,12 @@ def test_set_tiles_leaves_results_unchanged():
     assert np.array_equal(runs[0][0], runs[1][0]) and (runs[0][1] != runs[1][1]).nnz == 0
     h = S.SPAI(A, "mr", "global", 2.0, True, max_iter=4)
     good = {"resid": (128, 512), "dots": (256, 512), "update": (384, 512, 0)}
-    for bad in ({"resid": (128, 256)},                    # H below 512
+    for bad in ({"resid": (128, 64)},                     # H below 128 (A in ELL)
                 {"resid": (128, 768)},                    # H not a power of two
                 {"dots": (100, 512)},                     # dots L not a power of two
                 {"update": (384, 512, 3)},                # no such waves cap
                 {"dots": (256, 512, 4)},                  # no such waves cap
+                {"dots": (256, 64, 1)},                   # lean tier H below 128
                 {"update": (16, 512, 0)},                 # L below 32
                 {"dots": (8192, 8192)}):                  # more than 64 KB of LDS
         t = dict(good, **bad)
