@@ -62,12 +62,13 @@ struct Carve {
 // list 1 (high byte), 0 meaning none.  The hash multiplier is picked per column among
 // kBtMuls odd constants so that no two rows of one list share a cell; a lookup is then
 // one cell read plus one entry read per list, with no probing and no branches.
-constexpr int kBtCells = 2048;
-constexpr int kBtShift = 21;          // 32 - log2(kBtCells)
-constexpr int kBtMuls = 8;
+constexpr int kBtCells = 1024;
+constexpr int kBtShift = 22;          // 32 - log2(kBtCells)
+constexpr int kBtMuls = 16;
 
+// odd multipliers (a column retries with the next one while two of its rows share a cell)
 __device__ __forceinline__ unsigned bt_mul(int a) {
-  switch (a & 7) {
+  switch (a & 15) {
     case 0: return 0x9E3779B1u;
     case 1: return 0x85EBCA77u;
     case 2: return 0xC2B2AE3Du;
@@ -75,7 +76,15 @@ __device__ __forceinline__ unsigned bt_mul(int a) {
     case 4: return 0x165667B1u;
     case 5: return 0xD3A2646Du;
     case 6: return 0xFD7046C5u;
-    default: return 0xB55A4F09u;
+    case 7: return 0xB55A4F09u;
+    case 8: return 0x7FEB352Du;
+    case 9: return 0x846CA68Bu;
+    case 10: return 0x2C1B3C6Du;
+    case 11: return 0x297A2D39u;
+    case 12: return 0xA136AAADu;
+    case 13: return 0x9E6C63D1u;
+    case 14: return 0x1B873593u;
+    default: return 0xCC9E2D51u;
   }
 }
 
@@ -1990,7 +1999,7 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
 constexpr int kUpdLeanKeys = 128;
 
 template <typename T>
-__global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4))) void k_update_lean(
+__global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) void k_update_lean(
     Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp, Pair<T> PTp, UpdMode md, const int64_t* off,
     const int64_t* total, const int32_t* kcol, double* tM, double* tP, BigList big, Seg seg,
     DevState* st, int L, int H) {
