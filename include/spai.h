@@ -353,6 +353,25 @@ int spai_loss_fwd(const spai_csr_t* A, const spai_csr_t* M, double* L,
                   const spai_opts_t* opts);
 
 /*
+ * spai_loss_fwd_noalloc — spai_loss_fwd for callers that cannot allocate memory (code
+ *   under HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ *   the same kernels and summation order, so *L equals spai_loss_fwd's value bitwise,
+ *   but nothing is allocated, nothing is copied to the host and the stream is not
+ *   synchronised.  A and M: CSR on the device (on_device = 1), float64 values, at most
+ *   2^21 rows.  L: one device double, receives f(M); err: one device int, set to 0,
+ *   and nonzero when the call is complete if a row or column exceeded the per-column
+ *   tile (L is then not valid).  The per-row partial sums live in a fixed device array
+ *   of this library (2^21 + 512 doubles, about 16 MB per GPU, held until the process
+ *   ends) shared by every call on that GPU: calls that overlap on one GPU race and must
+ *   be ordered by the caller (one stream, or events).  Work is enqueued on
+ *   opts->stream.  Returns SPAI_ERR_ARG, without launching anything, for null
+ *   pointers, unequal or empty shapes, host matrices, more than 2^21 rows, or
+ *   opts->precision other than SPAI_PREC_F64.
+ */
+int spai_loss_fwd_noalloc(const spai_csr_t* A, const spai_csr_t* M, double* L, int* err,
+                          const spai_opts_t* opts);
+
+/*
  * spai_loss_bwd — gradients of f in the stored values of A and of M:
  *   gA = dL * (-2 R M^T) on the pattern of A, gM = dL * (-2 A^T R) on the pattern
  *   of M, R = I - A M recomputed per column (for symmetric A, gM is the gradient

@@ -9,6 +9,9 @@
 // wavefront in LDS and sum in fixed orders, so the results are deterministic.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -433,6 +436,35 @@ int loss_bwd_t(LossCall& c, double dL, double* gA, double* gM, bool host_out) {
   return SPAI_OK;
 }
 
+// ---- allocation-free forward loss ---------------------------------------------------
+// Scratch of spai_loss_fwd_noalloc: the per-row partial sums (at most kNoAllocRows rows)
+// and the chunk sums of the fixed-order reduction, in a file-scope device array (each
+// GPU holds its own copy until the process ends).  Host code never passes the array's
+// name to a kernel: it takes the array's device address from hipGetSymbolAddress, once
+// per device, and uses that address.
+constexpr int64_t kNoAllocRows = (int64_t)1 << 21;
+constexpr int kNoAllocChunks = 512;
+__device__ __align__(256) double scratch[kNoAllocRows + kNoAllocChunks];
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;   // device -> address of its scratch array
+
+int noalloc_scratch(double** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    it = g_scratch_ptr.emplace(dev, (double*)p).first;
+  }
+  *out = it->second;
+  return SPAI_OK;
+}
+
+__global__ void k_zero_flag(int* p) { *p = 0; }
+
 }  // namespace
 }  // namespace spai
 
@@ -461,6 +493,42 @@ extern "C" int spai_loss_bwd(const spai_csr_t* A, const spai_csr_t* M, double dL
     const bool f32 = opts && opts->precision == SPAI_PREC_MIXED;
     const bool host_out = !A->on_device;
     return f32 ? loss_bwd_t<float>(c, dL, gA, gM, host_out) : loss_bwd_t<double>(c, dL, gA, gM, host_out);
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+extern "C" int spai_loss_fwd_noalloc(const spai_csr_t* A, const spai_csr_t* M, double* L, int* err,
+                                     const spai_opts_t* opts) {
+  try {
+    if (!A || !M || !L || !err) return fail(SPAI_ERR_ARG, "loss_fwd_noalloc: null argument");
+    if (A->n != M->n || A->n < 1) return fail(SPAI_ERR_ARG, "loss_fwd_noalloc: bad shapes");
+    if (!A->on_device || !M->on_device)
+      return fail(SPAI_ERR_ARG, "loss_fwd_noalloc: A and M must be on the device");
+    if (A->n > kNoAllocRows)
+      return fail(SPAI_ERR_ARG, "loss_fwd_noalloc: more than 2^21 rows (the scratch holds 2^21)");
+    if (opts && opts->precision != SPAI_PREC_F64)
+      return fail(SPAI_ERR_ARG, "loss_fwd_noalloc: float64 only (the float32 copies would need "
+                                "scratch of the matrices' size)");
+    hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
+    double* scr = nullptr;
+    int rc = noalloc_scratch(&scr);
+    if (rc) return rc;
+    double* rowpart = scr;
+    double* chunks = scr + kNoAllocRows;
+    const Pat pA{A->n, A->rowptr, A->colind}, pM{M->n, M->rowptr, M->colind};
+    // the flag is cleared by a kernel (no memset node), so the call can be captured
+    hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, s, err);
+    const int Lt = 512, Ht = 1024, DG = 64;
+    hipLaunchKernelGGL(k_loss_rows<double>, dim3(kGridRows), dim3(SPAI_WAVE),
+                       rows_lds(Lt, Ht, DG), s, pA, A->val, pM, M->val, rowpart,
+                       (double*)nullptr, 1.0, err, Lt, Ht, DG);
+    const int64_t chunk = (A->n + kNoAllocChunks - 1) / kNoAllocChunks;
+    const int nb = (int)((A->n + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(nb), dim3(256), 0, s, rowpart, A->n, chunk, chunks);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, chunks, (int64_t)nb, L);
+    HIPCHK(hipGetLastError());
+    return SPAI_OK;
   } catch (...) {
     return fail(SPAI_ERR_HIP, "unexpected exception");
   }

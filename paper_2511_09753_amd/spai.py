@@ -55,7 +55,7 @@ EXPORTS = [
     "spai_destroy", "pcg_solve", "spai_loss_fwd", "spai_loss_bwd", "spai_create_batched",
     "spai_batched_resid", "spai_last_error", "spai_status_string", "spai_reset", "spai_pcg",
     "spai_profile", "spai_spectrum", "spai_csr_spectrum", "spai_autotune", "spai_get_state",
-    "spai_set_state", "spai_set_tiles",
+    "spai_set_state", "spai_set_tiles", "spai_loss_fwd_noalloc",
 ]
 A_FORMATS = {"auto": 0, "csr": 1, "ell": 2}
 PHASES = ["dots", "update", "resid", "select", "compact", "bounds", "scalar", "pcg", "pcg_ax",
@@ -99,6 +99,8 @@ def load():
                                   C.POINTER(OptsT)]
     lib.spai_loss_bwd.argtypes = [C.POINTER(CsrT), C.POINTER(CsrT), C.c_double, P, P,
                                   C.POINTER(OptsT)]
+    lib.spai_loss_fwd_noalloc.argtypes = [C.POINTER(CsrT), C.POINTER(CsrT), P, P,
+                                          C.POINTER(OptsT)]
     lib.spai_reset.argtypes = [P]
     lib.spai_pcg.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int, P, P, C.c_int]
     lib.spai_profile.argtypes = [P, P, P, P]
@@ -443,6 +445,15 @@ def loss_fwd(A, M, options: Options | None = None) -> float:
     a, m = _Csr(A), _Csr(M)
     _check(load().spai_loss_fwd(C.byref(a.c), C.byref(m.c), C.byref(out), C.byref(opts)))
     return out.value
+
+
+def loss_fwd_noalloc(A, M, L, err, options: Options | None = None) -> None:
+    """f(M) into the device tensors L (one float64) and err (one int32) without any
+    allocation or host synchronisation (A, M: torch CSR on the device, float64)."""
+    opts = (options or Options()).c()
+    a, m = _Csr(A), _Csr(M)
+    _check(load().spai_loss_fwd_noalloc(C.byref(a.c), C.byref(m.c), L.data_ptr(),
+                                        err.data_ptr(), C.byref(opts)))
 
 
 def loss_bwd(A, M, dL=1.0, want_a=True, want_m=True, options: Options | None = None):
