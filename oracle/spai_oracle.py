@@ -222,9 +222,26 @@ def pair_scores(A, X) -> sp.csc_matrix:
     return _csc(P)
 
 
-def drop_main(X, rule: DropRule, A=None) -> sp.csc_matrix:
+def _record(info, cand, keep, band, t, rows=None, cols=None, vals=None, thr=None):
+    """What a drop did (diagnostics only, no effect on the result): the candidates it
+    saw, the entries it kept, the band (candidates dropped within the tie band of the
+    cut, |x| >= t (1 - eta) for the threshold t before the tie factor: entries that a
+    last-bit difference in the values cannot move across its edge) and the global
+    threshold t (None otherwise).
+    With info["keep_candidates"] set, also the candidate entries (rows, cols, vals) and
+    each one's threshold before the tie factor (the global t, or the column threshold)."""
+    if info is not None:
+        info.update({"cand": int(cand.sum()), "kept": int(keep.sum()), "band": int(band),
+                     "t": None if t is None else float(t)})
+        if info.get("keep_candidates") and rows is not None:
+            info["candidates"] = (rows[cand], cols[cand], vals[cand],
+                                  None if thr is None else np.asarray(thr)[cand])
+
+
+def drop_main(X, rule: DropRule, A=None, info=None) -> sp.csc_matrix:
     """D_M: the drop rule on the main iterate (Appendix A steps 1-3 + Section 6.1).
-    With rule.score the cap of step 3 ranks by the pair scores of Appendix A (A needed)."""
+    With rule.score the cap of step 3 ranks by the pair scores of Appendix A (A needed).
+    info (optional dict): receives the counts of _record."""
     X = _csc(X)
     n = X.shape[0]
     if rule.symmetrize:                                  # step 1: M := (M + M^T) / 2
@@ -234,6 +251,8 @@ def drop_main(X, rule: DropRule, A=None) -> sp.csc_matrix:
     keep = vals != 0.0
     if rule.u > 0.0:                                     # step 2: off-diagonal |m| < u
         keep &= diag | (np.abs(vals) >= rule.u)
+    cand = keep.copy()
+    band, tcut = 0, None
     if rule.mode == "global":                            # step 3: cap |supp(M)| <= m
         if keep.sum() > rule.m:
             ndiag = int((keep & diag).sum())
@@ -246,15 +265,20 @@ def drop_main(X, rule: DropRule, A=None) -> sp.csc_matrix:
                 Xk = _from_entries(rows[keep], cols[keep], vals[keep], X.shape)
                 Sg = pair_scores(A, Xk)
                 sig = np.asarray(Sg[rows, cols]).ravel()
-                cand = sig[keep & ~diag]
-                if len(cand) > b:
-                    t = np.sort(cand)[::-1][b]
+                cand_s = sig[keep & ~diag]
+                if len(cand_s) > b:
+                    t = np.sort(cand_s)[::-1][b]
                     keep &= diag | (sig > t + rule.eta * abs(t))
+                    band = int((cand & ~keep & (sig >= t - rule.eta * abs(t))).sum())
+                    tcut = t
             else:
                 mags = np.abs(vals[keep & ~diag])
                 if len(mags) > b:
                     t = np.sort(mags)[::-1][b]
                     keep &= diag | (np.abs(vals) > t * (1.0 + rule.eta))
+                    band = int((cand & ~keep & (np.abs(vals) >= t * (1.0 - rule.eta))).sum())
+                    tcut = t
+        thr = None if tcut is None else np.full(len(vals), tcut)
     elif rule.mode == "column":
         k = np.asarray(rule.k, dtype=np.int64)
         if np.any(k < 1):
@@ -263,23 +287,36 @@ def drop_main(X, rule: DropRule, A=None) -> sp.csc_matrix:
         t = _kth_largest_per_column(cols[off], np.abs(vals[off]), n, k - 1)
         thr = np.maximum(t[rows], t[cols]) if rule.symmetrize else t[cols]
         keep &= diag | (np.abs(vals) > thr * (1.0 + rule.eta))
+        band = int((cand & ~keep & (thr > 0) & (np.abs(vals) >= thr * (1.0 - rule.eta))).sum())
+    else:
+        thr = None
+    _record(info, cand, keep, band, tcut, rows, cols, vals, thr)
     return _from_entries(rows[keep], cols[keep], vals[keep], X.shape)
 
 
-def drop_direction(X, rule: DropRule) -> sp.csc_matrix:
-    """D_P: hard thresholding of a search direction (Section 6.1), no diagonal exemption."""
+def drop_direction(X, rule: DropRule, info=None) -> sp.csc_matrix:
+    """D_P: hard thresholding of a search direction (Section 6.1), no diagonal exemption.
+    info (optional dict): receives the counts of _record."""
     X = _csc(X)
     rows, cols, vals = _entries(X)
     keep = vals != 0.0
+    cand = keep.copy()
+    band, tcut, thr = 0, None, None
     if rule.mode == "global":
         if keep.sum() > rule.m:
             mags = np.abs(vals[keep])
             t = np.sort(mags)[::-1][rule.m]
             keep &= np.abs(vals) > t * (1.0 + rule.eta)
+            band = int((cand & ~keep & (np.abs(vals) >= t * (1.0 - rule.eta))).sum())
+            tcut = t
+            thr = np.full(len(vals), t)
     elif rule.mode == "column":
         k = np.asarray(rule.k, dtype=np.int64)
         t = _kth_largest_per_column(cols[keep], np.abs(vals[keep]), X.shape[1], k)
-        keep &= np.abs(vals) > t[cols] * (1.0 + rule.eta)
+        thr = t[cols]
+        keep &= np.abs(vals) > thr * (1.0 + rule.eta)
+        band = int((cand & ~keep & (thr > 0) & (np.abs(vals) >= thr * (1.0 - rule.eta))).sum())
+    _record(info, cand, keep, band, tcut, rows, cols, vals, thr)
     return _from_entries(rows[keep], cols[keep], vals[keep], X.shape)
 
 
@@ -295,6 +332,7 @@ class Result:
     scalars: list = field(default_factory=list)   # per iteration dict
     nnz_m: list = field(default_factory=list)
     nnz_p: list = field(default_factory=list)
+    drops: list = field(default_factory=list)     # per iteration {"M": info, "P": info}
     iters: int = 0
     status: str = "maxiter"
     c: float = 0.0
@@ -305,7 +343,7 @@ def _converged(rnorm, n, tol):
 
 
 def mr(A, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = True,
-       M0=None) -> Result:
+       M0=None, keep_candidates: bool = False) -> Result:
     """Minimal residual with matrix iterates (Algorithm 1).
 
     alpha_i = (R_i, A R_i)_F / ||A R_i||_F^2 ; M_{i+1} = D_M(M_i + alpha_i R_i).
@@ -329,9 +367,11 @@ def mr(A, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = True
             break
         r_ar = frob(R, AR)
         alpha = r_ar / ar_ar
-        M = drop_main(M + alpha * R, rule, A)
+        dm = {"keep_candidates": keep_candidates}
+        M = drop_main(M + alpha * R, rule, A, info=dm)
         R = residual(A, M) if explicit else _csc(R - alpha * AR)
         out.scalars.append({"alpha": alpha, "r_ar": r_ar, "ar_ar": ar_ar})
+        out.drops.append({"M": dm, "P": None})
         out.resid.append(fnorm(R))
         out.nnz_m.append(M.nnz)
         out.iters = i + 1
@@ -373,12 +413,14 @@ def cg(A, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = True
             out.status = "breakdown"
             break
         alpha = rr / p_ap
-        M = drop_main(M + alpha * P, rule, A)
+        dm, dp = {}, {}
+        M = drop_main(M + alpha * P, rule, A, info=dm)
         R = residual(A, M) if explicit else _csc(R - alpha * AP)
         rr_new = frob(R, R)
         beta = rr_new / rr
-        P = drop_direction(R + beta * P, rule)
+        P = drop_direction(R + beta * P, rule, info=dp)
         out.scalars.append({"alpha": alpha, "beta": beta, "p_ap": p_ap, "rr": rr})
+        out.drops.append({"M": dm, "P": dp})
         rr = rr_new
         out.resid.append(math.sqrt(rr))
         out.nnz_m.append(M.nnz)
@@ -404,22 +446,24 @@ def lomr_coefficients(r_ar, ar_ar, ar_ap, r_ap, ap_ap, first: bool):
 
 
 def lomr(A, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = True,
-         M0=None) -> Result:
+         M0=None, P0=None, keep_candidates: bool = False) -> Result:
     """Locally optimal minimal residual (Definition 4.1, Theorem 4.2, Algorithm 4).
 
     M_{i+1} = D_M(M_i + delta_i R_i + gamma_i P_{i-1}), P_i = D_P(delta_i R_i + gamma_i P_{i-1}),
-    with P_{-1} = 0 and the MR step at i = 0.
+    with P_{-1} = 0 and the MR step at i = 0.  Given P0 (the direction P_{i-1} of a run
+    in progress, with M0 its iterate M_i), the run continues from there instead: its
+    first step is a LOMR step over span{R_i, P0}.
     """
     A = sp.csr_matrix(A)
     n = A.shape[0]
     c, Minit = initial_iterate(A)
     M = Minit if M0 is None else _csc(M0)
     R = residual(A, M)
-    P = _csc(sp.csc_matrix((n, n)))
+    P = _csc(sp.csc_matrix((n, n))) if P0 is None else _csc(P0)
     out = Result(M, P, c=c)
     out.resid.append(fnorm(R))
     out.nnz_m.append(M.nnz)
-    out.nnz_p.append(0)
+    out.nnz_p.append(P.nnz)
     if _converged(out.resid[-1], n, tol):
         out.status = "converged"
         return out
@@ -434,14 +478,17 @@ def lomr(A, rule: DropRule, max_iter: int, tol: float = 0.0, explicit: bool = Tr
         ar_ap = frob(AR, AP)
         r_ap = frob(R, AP)
         ap_ap = frob(AP, AP)
-        delta, gamma, fell_back = lomr_coefficients(r_ar, ar_ar, ar_ap, r_ap, ap_ap, i == 0)
-        M = drop_main(M + delta * R + gamma * P, rule, A)
+        first = i == 0 and P0 is None
+        delta, gamma, fell_back = lomr_coefficients(r_ar, ar_ar, ar_ap, r_ap, ap_ap, first)
+        dm, dp = {"keep_candidates": keep_candidates}, {"keep_candidates": keep_candidates}
+        M = drop_main(M + delta * R + gamma * P, rule, A, info=dm)
         Rnew = residual(A, M) if explicit else _csc(R - delta * AR - gamma * AP)
-        P = drop_direction(delta * R + gamma * P, rule)
+        P = drop_direction(delta * R + gamma * P, rule, info=dp)
         R = Rnew
         out.scalars.append({"delta": delta, "gamma": gamma, "r_ar": r_ar, "ar_ar": ar_ar,
                             "ar_ap": ar_ap, "r_ap": r_ap, "ap_ap": ap_ap,
                             "mr_fallback": fell_back})
+        out.drops.append({"M": dm, "P": dp})
         out.resid.append(fnorm(R))
         out.nnz_m.append(M.nnz)
         out.nnz_p.append(P.nnz)

@@ -378,6 +378,39 @@ def test_tie_band_drops_whole_tie_cluster():
     assert sorted(P.data.tolist()) == sorted(vals[:5].tolist())
 
 
+def test_drop_record_counts_by_hand():
+    """The per-drop record (candidates, kept, tie band) on magnitudes whose cut is known
+    by hand: eta = 1e-9, so the band is [t (1 - 1e-9), t (1 + 1e-9)] around the cut t."""
+    vals = np.array([5.0, -4.0, 3.0 + 1e-6, 3.0, -3.0, 3.0 * (1 - 1e-11), 3.0 * (1 - 1e-6),
+                     1.0, 0.0])
+    X = sp.csc_matrix((vals, (np.arange(9), np.zeros(9, dtype=int))), shape=(9, 1))
+    info = {}
+    P = O.drop_direction(X, O.DropRule(mode="global", m=3), info=info)
+    # sorted magnitudes 5, 4, 3+1e-6 | t = 3 (the fourth), 3, 3(1-1e-11), 3(1-1e-6), 1
+    assert info["t"] == 3.0
+    assert (info["cand"], info["kept"], info["band"]) == (8, 3, 3)
+    assert sorted(np.abs(P.data).tolist()) == [3.0 + 1e-6, 4.0, 5.0]
+    # under the cap nothing is dropped and there is no cut
+    info = {}
+    O.drop_direction(X, O.DropRule(mode="global", m=8), info=info)
+    assert (info["cand"], info["kept"], info["band"], info["t"]) == (8, 8, 0, None)
+    # per column (k = 2 in the one column): t = 3 + 1e-6 is the third largest, and only
+    # entries within 1e-9 of it are in the band; 3 and below are more than that away
+    info = {}
+    P = O.drop_direction(X, O.DropRule(mode="column", k=np.array([2])), info=info)
+    assert (info["cand"], info["kept"], info["band"]) == (8, 2, 1)
+    # the main iterate keeps its diagonal out of the ranking: a 2 x 2 block whose
+    # off-diagonal pair ties with a third off-diagonal entry at the cut
+    Y = sp.csc_matrix(np.array([[9.0, 2.0, 0.0], [2.0, 9.0, 2.0 * (1 + 1e-12)],
+                                [0.0, 2.0 * (1 + 1e-12), 9.0]]))
+    info = {}
+    M = O.drop_main(Y, O.DropRule(mode="global", m=5), info=info)
+    # 3 diagonal entries leave room for 2 off-diagonal ones out of four tied at 2:
+    # t = 2, and all four lie in the band, so only the diagonal stays
+    assert (info["cand"], info["kept"], info["band"]) == (7, 3, 4)
+    assert M.nnz == 3 and np.all(M.diagonal() == 9.0)
+
+
 def test_cap_counts():
     A = W.aniso2d(8)
     k = O.cap_counts(A, "column", 3.0, True)
