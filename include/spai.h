@@ -200,6 +200,21 @@ int spai_get(spai_handle_t* h, spai_csr_out_t* M);
 int spai_stats(spai_handle_t* h, int* iters, double* resid_fro, int64_t* nnz_m,
                int64_t* nnz_p, double* step1, double* step2, int* mr_fallbacks);
 
+/*
+ * spai_history — the per-iteration record of the drop rule (the columns of the paper's
+ *   Tables 4-6 and of a run's metrics log), for the iterations run since spai_create or
+ *   spai_reset (after spai_set_state the record resumes at the restored iteration; the
+ *   earlier rows read zero).  rec: 6 int64 per iteration i (0-based), row-major:
+ *   nnz(M_{i+1}); the candidates of M_{i+1} the cap dropped (after symmetrization and the
+ *   small-entry drop, Appendix A steps 1-2); of those, the ones in the tie band of the cut
+ *   (magnitude, or score, at least t - tie_eta |t| for the (b+1)-th largest value t of
+ *   Section 6.1's hard thresholding, or the column threshold under a column cap); then
+ *   the same three for the direction P_i (zero for MR).
+ *   Counts are totals over the matrices of a batched handle.  Fills min(cap, *count)
+ *   rows; *count receives the number of iterations recorded.  Synchronises the stream.
+ */
+int spai_history(spai_handle_t* h, int64_t* rec, int cap, int* count);
+
 /* Release every device buffer of the handle.  NULL is accepted. */
 int spai_destroy(spai_handle_t* h);
 
@@ -281,8 +296,11 @@ int spai_set_tiles(spai_handle_t* h, const int* tiles);
  *   spai_set_state: restores a state taken from a handle of the same problem and
  *   configuration (n, matrices, method, precision, Pi weighting, residual form,
  *   symmetrization); the next spai_iterate continues exactly as the original handle
- *   would have.  A mismatch, a truncated buffer or lists larger than this handle's
- *   pools return SPAI_ERR_ARG.  Both synchronise the stream.
+ *   would have.  A mismatch, a truncated buffer, lists larger than this handle's pools,
+ *   column pointers that do not start at 0 or decrease, rows out of range or not
+ *   strictly ascending within a column return SPAI_ERR_ARG; every list is checked
+ *   before any is uploaded, so the handle is unchanged on error.  Both synchronise the
+ *   stream.
  */
 int spai_get_state(spai_handle_t* h, void* buf, size_t* size);
 int spai_set_state(spai_handle_t* h, const void* buf, size_t size);

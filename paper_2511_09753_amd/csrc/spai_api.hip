@@ -208,20 +208,34 @@ int download_cols(const Cols<T>& C, int64_t n, hipStream_t s, std::vector<int64_
   return SPAI_OK;
 }
 
-// upload compact CSC into column lists (columns laid out from offset 0)
+// check compact CSC lists before any of them is uploaded: column pointers from 0 and
+// non-decreasing, at most the pool's capacity, rows in range and strictly ascending within
+// each column (the per-column kernels' lock-step searches assume ascending rows)
+template <typename T>
+int check_cols(const Cols<T>& C, int64_t n, const int64_t* colptr, const int32_t* idx) {
+  if (colptr[0] != 0) return fail(SPAI_ERR_ARG, "state: bad column pointers");
+  const int64_t nnz = colptr[n];
+  if (nnz < 0 || nnz > C.cap) return fail(SPAI_ERR_ARG, "state: a list exceeds this handle's pool");
+  for (int64_t j = 0; j < n; ++j) {
+    const int64_t l = colptr[j + 1] - colptr[j];
+    if (l < 0 || l > INT32_MAX || colptr[j + 1] > nnz)
+      return fail(SPAI_ERR_ARG, "state: bad column pointers");
+    for (int64_t q = colptr[j]; q < colptr[j + 1]; ++q) {
+      if (idx[q] < 0 || idx[q] >= n) return fail(SPAI_ERR_ARG, "state: row index out of range");
+      if (q > colptr[j] && idx[q] <= idx[q - 1])
+        return fail(SPAI_ERR_ARG, "state: rows not strictly ascending in a column");
+    }
+  }
+  return SPAI_OK;
+}
+
+// upload compact CSC into column lists (columns laid out from offset 0); check_cols first
 template <typename T>
 int upload_cols(Cols<T>& C, int64_t n, hipStream_t s, const int64_t* colptr, const int32_t* idx,
                 const T* val) {
   const int64_t nnz = colptr[n];
-  if (nnz > C.cap) return fail(SPAI_ERR_ARG, "state: a list exceeds this handle's pool");
   std::vector<int32_t> len((size_t)n);
-  for (int64_t j = 0; j < n; ++j) {
-    const int64_t l = colptr[j + 1] - colptr[j];
-    if (l < 0 || l > INT32_MAX) return fail(SPAI_ERR_ARG, "state: bad column pointers");
-    len[(size_t)j] = (int32_t)l;
-  }
-  for (int64_t q = 0; q < nnz; ++q)
-    if (idx[q] < 0 || idx[q] >= n) return fail(SPAI_ERR_ARG, "state: row index out of range");
+  for (int64_t j = 0; j < n; ++j) len[(size_t)j] = (int32_t)(colptr[j + 1] - colptr[j]);
   HIPCHK(hipMemcpyAsync(C.beg, colptr, sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(C.len, len.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
   if (nnz) {
@@ -260,6 +274,7 @@ struct EngineBase {
   virtual int set_tiles(const int* tiles) = 0;
   virtual int get_state(void* buf, size_t* size) = 0;
   virtual int set_state(const void* buf, size_t size) = 0;
+  virtual int history(int64_t* out, int cap, int* count) = 0;
 };
 
 template <typename T>
@@ -298,6 +313,7 @@ struct Engine : EngineBase {
   unsigned long long *selhist = nullptr, *selbuf = nullptr;
   DevState* st = nullptr;
   unsigned long long* cnt = nullptr;
+  unsigned long long* rec = nullptr;   // per-iteration drop record, (max_iter + 1) x kRec
   SegState* segst = nullptr;
   int* seg_of = nullptr;
   int64_t* seg_beg = nullptr;
@@ -516,6 +532,12 @@ struct Engine : EngineBase {
     HIPCHK(hipMemsetAsync(st, 0, sizeof(DevState), s));
     HIPCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * kNCnt * kCntSlots, s));
     HIPCHK(hipMemcpyAsync(&st->cnt, &cnt, sizeof(cnt), hipMemcpyHostToDevice, s));
+    {   // per-iteration drop record (spai_history)
+      const int rcap = max_iter + 1;
+      if ((rc = dalloc(&rec, (int64_t)rcap * kRec))) return rc;
+      HIPCHK(hipMemcpyAsync(&st->rec, &rec, sizeof(rec), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(&st->rec_cap, &rcap, sizeof(int), hipMemcpyHostToDevice, s));
+    }
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipMemsetAsync(segst, 0, sizeof(SegState) * nseg, s));
     HIPCHK(hipMemcpyAsync(seg_beg, seg_beg_h.data(), sizeof(int64_t) * (nseg + 1), hipMemcpyHostToDevice, s));
@@ -598,6 +620,7 @@ struct Engine : EngineBase {
 
   // M_0 = c I, R_0, and CG's P_0
   int init_iterate() {
+    launch_rec_clear(st, 0, s);
     launch_trace_parts(A, colpart, s);
     launch_reduce(colpart, 2, n, seg, nseg > 1 ? seg_beg : nullptr, red, blockpart, s);
     launch_init_state(seg, red, nseg > 1 ? seg_beg : nullptr, n, cvec, method, st, s);
@@ -781,19 +804,27 @@ struct Engine : EngineBase {
       any = any || !x.stop;
     }
     int rc;
+    // every list is read and checked before the first one is uploaded, so a bad state
+    // leaves the handle unchanged
+    std::vector<std::vector<int64_t>> cps((size_t)nl);
+    std::vector<std::vector<int32_t>> ixs((size_t)nl);
+    std::vector<std::vector<T>> vls((size_t)nl);
     for (int l = 0; l < nl; ++l) {
-      std::vector<int64_t> cp((size_t)n + 1);
-      std::memcpy(cp.data(), o, sizeof(int64_t) * (n + 1));
+      cps[l].resize((size_t)n + 1);
+      std::memcpy(cps[l].data(), o, sizeof(int64_t) * (n + 1));
       o += sizeof(int64_t) * (n + 1);
-      if (cp[0] != 0 || cp[n] != hd.nnz[l]) return fail(SPAI_ERR_ARG, "spai_set_state: bad column pointers");
-      const int32_t* ix = (const int32_t*)o;
+      if (cps[l][n] != hd.nnz[l]) return fail(SPAI_ERR_ARG, "spai_set_state: bad column pointers");
+      ixs[l].resize((size_t)hd.nnz[l]);
+      std::memcpy(ixs[l].data(), o, sizeof(int32_t) * hd.nnz[l]);
       o += sizeof(int32_t) * hd.nnz[l];
-      std::vector<T> vl((size_t)hd.nnz[l]);
-      std::memcpy(vl.data(), o, sizeof(T) * hd.nnz[l]);
+      vls[l].resize((size_t)hd.nnz[l]);
+      std::memcpy(vls[l].data(), o, sizeof(T) * hd.nnz[l]);
       o += sizeof(T) * hd.nnz[l];
-      std::vector<int32_t> ixv(ix, ix + hd.nnz[l]);
-      if ((rc = upload_cols<T>(*lists[l], n, s, cp.data(), ixv.data(), vl.data()))) return rc;
+      if ((rc = check_cols<T>(*lists[l], n, cps[l].data(), ixs[l].data()))) return rc;
     }
+    for (int l = 0; l < nl; ++l)
+      if ((rc = upload_cols<T>(*lists[l], n, s, cps[l].data(), ixs[l].data(), vls[l].data())))
+        return rc;
     HIPCHK(hipMemcpy(segst, g.data(), sizeof(SegState) * nseg, hipMemcpyHostToDevice));
     h.any_active = any ? 1 : 0;
     h.iter_active = any ? 1 : 0;
@@ -801,6 +832,32 @@ struct Engine : EngineBase {
     HIPCHK(hipMemcpy(st, &h, sizeof(DevState), hipMemcpyHostToDevice));
     iters_host = (int)hd.iters_host;
     total_iters = hd.total_iters;
+    launch_rec_clear(st, iters_host, s);   // records resume at the restored iteration
+    HIPCHK(hipStreamSynchronize(s));
+    return SPAI_OK;
+  }
+
+  // per-iteration drop record: 6 int64 per iteration i < *count (see spai_history)
+  int history(int64_t* out, int cap, int* count) override {
+    if (!count || cap < 0 || (cap > 0 && !out)) return fail(SPAI_ERR_ARG, "spai_history: bad arguments");
+    HIPCHK(hipStreamSynchronize(s));
+    const int nrec = std::min(iters_host, max_iter + 1);
+    *count = nrec;
+    const int k = std::min(cap, nrec);
+    if (k > 0) {
+      std::vector<unsigned long long> r((size_t)k * kRec);
+      HIPCHK(hipMemcpy(r.data(), rec, sizeof(unsigned long long) * r.size(), hipMemcpyDeviceToHost));
+      for (int i = 0; i < k; ++i) {
+        const unsigned long long* x = &r[(size_t)i * kRec];
+        int64_t* o = out + (size_t)i * 6;
+        o[0] = (int64_t)x[0];              // nnz(M_{i+1}) (kept)
+        o[1] = (int64_t)(x[1] - x[0]);     // M candidates dropped by the cap
+        o[2] = (int64_t)x[2];              // of those, at the cut
+        o[3] = (int64_t)x[3];              // nnz(P_i) (kept; 0 for MR)
+        o[4] = (int64_t)(x[4] - x[3]);
+        o[5] = (int64_t)x[5];
+      }
+    }
     return SPAI_OK;
   }
 
@@ -1536,6 +1593,15 @@ int spai_set_state(spai_handle_t* h, const void* buf, size_t size) {
     return h->eng->set_state(buf, size);
   } catch (const std::bad_alloc&) {
     return fail(SPAI_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(SPAI_ERR_HIP, "unexpected exception");
+  }
+}
+
+int spai_history(spai_handle_t* h, int64_t* rec, int cap, int* count) {
+  if (!h) return fail(SPAI_ERR_ARG, "null handle");
+  try {
+    return h->eng->history(rec, cap, count);
   } catch (...) {
     return fail(SPAI_ERR_HIP, "unexpected exception");
   }

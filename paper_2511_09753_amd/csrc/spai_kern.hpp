@@ -45,13 +45,20 @@ struct DevState {
   unsigned long long* cnt;
   // global-cap radix selection
   double thrM, thrP;              // keep |x| > thr (thr already includes 1 + eta)
+  double rawM, rawP;              // the (b+1)-th largest key itself (thrM/P + 2 doubles)
   unsigned long long sel_count;   // keys in the selection buffer
   unsigned long long sel_prefix;  // key bits fixed so far
   long long sel_rank;             // 1-based rank still to find inside the prefix
   long long sel_diag;             // diagonal candidates (excluded, always kept)
   int sel_done;                   // 1: threshold known
   int iter_active;                // 1: the current iteration runs (set by the step kernel)
+  // per-iteration record of the drops (spai_history): rec[i * kRec + f], i = rec_i the
+  // iteration in progress (-1: none), f = kept, seen, band of M (0-2) and of P (3-5)
+  unsigned long long* rec;
+  int rec_i, rec_cap;
+  int rec_next, rec_pad;          // the next iteration's record
 };
+constexpr int kRec = 6;
 
 struct Seg {                       // column -> matrix map for batched handles
   int nseg = 1;
@@ -187,5 +194,7 @@ void launch_scal_post(int method, const Seg& seg, const double* red, const doubl
                       hipStream_t s);
 extern int g_grid_cols;   // persistent grid of the per-column kernels (multiple of 8)
 void launch_flip(int which, DevState* st, hipStream_t s);   // 0: curM, 1: curP
+// zero the drop record; the next iteration's record is `next`
+void launch_rec_clear(DevState* st, int next, hipStream_t s);
 
 }  // namespace spai

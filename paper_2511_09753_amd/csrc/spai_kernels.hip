@@ -30,6 +30,10 @@
 
 namespace spai {
 
+static_assert(offsetof(DevState, rawM) == offsetof(DevState, thrM) + 2 * sizeof(double) &&
+                  offsetof(DevState, rawP) == offsetof(DevState, thrP) + 2 * sizeof(double),
+              "the selection writes the raw key two doubles after its threshold");
+
 __device__ __forceinline__ double aval(const Csr& A, int64_t q) {
   return A.val32 ? (double)A.val32[q] : A.val[q];
 }
@@ -367,6 +371,21 @@ __device__ __forceinline__ char* tile_base(char* smem, const BigList& big) {
 // counters are cleared by a kernel, never by a memset node, so that the
 // iteration sequence can be captured in a HIP graph
 __global__ void k_zero_int(int* p) { *p = 0; }
+
+// clear the drop record (a kernel, not a memset node: the iteration may be captured)
+__global__ void k_rec_clear(DevState* st, int next) {
+  const int64_t total = (int64_t)st->rec_cap * kRec;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x)
+    st->rec[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rec_i = -1;
+    st->rec_next = next;
+  }
+}
+void launch_rec_clear(DevState* st, int next, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_clear, dim3(64), dim3(256), 0, s, st, next);
+}
 
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
@@ -2485,11 +2504,13 @@ __global__ __launch_bounds__(1024) void k_sel_find_exp(const unsigned long long*
   if (b < 0) {                      // cap below the diagonal count: keep only the diagonal
     st->sel_done = 1;
     *thr = INFINITY;
+    thr[2] = INFINITY;
     return;
   }
   if (total <= b) {                  // |supp| within the cap: nothing to drop
     st->sel_done = 1;
     *thr = signed_keys ? -INFINITY : 0.0;
+    thr[2] = *thr;
     return;
   }
   st->sel_prefix = (unsigned long long)bin << 52;
@@ -2599,13 +2620,15 @@ __global__ __launch_bounds__(1024) void k_sel_find_buf(const unsigned long long*
     st->sel_rank = rank - above;
   }
   if (shift == 0) {
+    double t;
     if (signed_keys) {                 // keep score > t + eta |t|
-      const double t = ord_value(st->sel_prefix);
+      t = ord_value(st->sel_prefix);
       *thr = t + eta * fabs(t);
     } else {                           // keep |x| > t (1 + eta)
-      const double t = __longlong_as_double((long long)st->sel_prefix);
+      t = __longlong_as_double((long long)st->sel_prefix);
       *thr = t * (1.0 + eta);
     }
+    thr[2] = t;                        // rawM / rawP, two doubles after thrM / thrP
     st->sel_done = 1;
   }
 }
@@ -2858,8 +2881,9 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
   const Cols<T> X = Xp.nxt();
   const int lane = lane_id();
   const double gt = global ? *gthr : 0.0;
+  const double graw = global ? gthr[2] : 0.0;      // the cut before the tie factor
   const bool need_tk = colcap && ((kind == 0 && sym) || kind == 2);
-  unsigned long long kept = 0, seen = 0;
+  unsigned long long kept = 0, seen = 0, band = 0;
   const int64_t ng = (n + 63) / 64;
   for (int64_t gi = blockIdx.x; gi < ng; gi += gridDim.x) {
     const Group64 g = group_load(X, gi * 64, n);
@@ -2911,12 +2935,16 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
           if (kind == 0 && k == j) {
             keep = true;
           } else if (global) {
-            keep = (score ? sv[u] : a) > gt;
+            const double key = score ? sv[u] : a;
+            keep = key > gt;
+            // dropped within the tie band of the cut (a relative eta below it)
+            band += (!keep && key >= graw - eta * fabs(graw)) ? 1ull : 0ull;
           } else if (colcap) {
             double t = tcj;
             if (kind == 0 && sym) t = fmax(t, tk[u]);
             if (kind == 2) t = tk[u];
             keep = a > t * (1.0 + eta);
+            band += (!keep && t > 0.0 && a >= t * (1.0 - eta)) ? 1ull : 0ull;
           } else {
             keep = true;
           }
@@ -2947,9 +2975,19 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
   }
   kept = (unsigned long long)wave_sum_ll((long long)kept);
   seen = (unsigned long long)wave_sum_ll((long long)seen);
+  band = (unsigned long long)wave_sum_ll((long long)band);
   if (lane == 0 && blockIdx.x < kCntSlots) {
     st->cnt[(3 + kind) * kCntSlots + blockIdx.x] += kept;
     st->cnt[kind * kCntSlots + blockIdx.x] += seen;
+  }
+  // the iteration's record (M and P; P^T mirrors P); integer sums, so the order of the
+  // workgroups' atomics does not matter
+  const int ri = st->rec_i;
+  if (lane == 0 && kind < 2 && st->rec && ri >= 0 && ri < st->rec_cap) {
+    unsigned long long* r = st->rec + (int64_t)ri * kRec + 3 * kind;
+    atomicAdd(&r[0], kept);
+    atomicAdd(&r[1], seen);
+    atomicAdd(&r[2], band);
   }
 }
 
@@ -2972,6 +3010,7 @@ __global__ void k_scal_step(int method, Seg seg, const double* red, DevState* st
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= seg.nseg) return;
   SegState& g = seg.st[s];
+  if (s == 0) st->rec_i = st->rec_next++;   // the drops of this iteration go to this record
   const double* d = red + (int64_t)s * kND;
   for (int i = 0; i < kND; ++i) g.dots[i] = d[i];
   if (!g.stop) {

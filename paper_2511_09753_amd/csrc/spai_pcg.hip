@@ -253,7 +253,7 @@ constexpr int narrow_chunk() { return (kThreads / R) * narrow_rpt<R>(); }
 
 template <typename VT, int LAY, int R>
 __global__ __launch_bounds__(kThreads) void k_spmm_narrow(Mat A, const double* X, double* Y,
-                                                          int dot, int nrhs,
+                                                          int dot, int nrhs, int c0, int ld,
                                                           const int32_t* order, double* part) {
   static_assert(narrow_chunk<R>() >= (kThreads / 64) * kRowsPerWave,
                 "no more workgroups than the partial buffer holds");
@@ -268,6 +268,10 @@ __global__ __launch_bounds__(kThreads) void k_spmm_narrow(Mat A, const double* X
   const int64_t r1 = r0 + per < A.n ? r0 + per : A.n;
   const int64_t base = r0 + kb * (int64_t)narrow_chunk<R>();
   double acc = 0.0;
+  // columns c0 .. c0 + nrhs of blocks whose rows are ld doubles apart (ld = nrhs, c0 = 0
+  // for a whole block; a wide block is taken R columns at a time)
+  X += c0;
+  Y += c0;
   if (r < nrhs) {
     for (int j = 0; j < RPT; ++j) {
       const int64_t k = base + (int64_t)j * G + g;
@@ -290,7 +294,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_narrow(Mat A, const double* X
           }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) xx[u] = cc[u] >= 0 ? X[(int64_t)cc[u] * nrhs + r] : 0.0;
+        for (int u = 0; u < 8; ++u) xx[u] = cc[u] >= 0 ? X[(int64_t)cc[u] * ld + r] : 0.0;
 #pragma unroll
         for (int u = 0; u < 8; ++u)
           if (cc[u] >= 0) {               // ELL padding (column -1) sits last
@@ -302,10 +306,10 @@ __global__ __launch_bounds__(kThreads) void k_spmm_narrow(Mat A, const double* X
           }
         if (cc[7] < 0) break;
       }
-      Y[i * nrhs + r] = y;
+      Y[i * ld + r] = y;
       if (dot) {
         // a row without a diagonal entry loads X[i, r] after all
-        const double wx = found ? xd : X[i * nrhs + r];
+        const double wx = found ? xd : X[i * ld + r];
         acc += wx * y;
       }
     }
@@ -316,7 +320,7 @@ __global__ __launch_bounds__(kThreads) void k_spmm_narrow(Mat A, const double* X
   if (t < R && t < nrhs) {
     double sum = 0.0;
     for (int w = 0; w < G; ++w) sum += sh[w * R + t];
-    part[(int64_t)t * gridDim.x + blockIdx.x] = sum;
+    part[(int64_t)(c0 + t) * gridDim.x + blockIdx.x] = sum;
   }
 }
 
@@ -606,11 +610,12 @@ struct Solver {
   int spmm_grid = 8;
 
   template <typename VT, int LAY, int R>
-  void spmm_narrow(const Mat& K, const double* X, double* Y, double* pt) {
+  void spmm_narrow(const Mat& K, const double* X, double* Y, double* pt, int c0 = 0,
+                   int cw = 0) {
     const int64_t per = (n + 7) / 8;
     spmm_grid = (int)(8 * ((per + narrow_chunk<R>() - 1) / narrow_chunk<R>()));
     hipLaunchKernelGGL((k_spmm_narrow<VT, LAY, R>), dim3(spmm_grid), dim3(kThreads), 0, s, K, X,
-                       Y, pt ? 1 : 0, nrhs, order, pt);
+                       Y, pt ? 1 : 0, cw ? cw : nrhs, c0, nrhs, order, pt);
   }
   template <typename VT, int LAY>
   void spmm_as(const Mat& K, const double* X, double* Y, double* pt) {

@@ -55,7 +55,7 @@ EXPORTS = [
     "spai_destroy", "pcg_solve", "spai_loss_fwd", "spai_loss_bwd", "spai_create_batched",
     "spai_batched_resid", "spai_last_error", "spai_status_string", "spai_reset", "spai_pcg",
     "spai_profile", "spai_spectrum", "spai_csr_spectrum", "spai_autotune", "spai_get_state",
-    "spai_set_state", "spai_set_tiles", "spai_loss_fwd_noalloc",
+    "spai_set_state", "spai_set_tiles", "spai_loss_fwd_noalloc", "spai_history",
 ]
 A_FORMATS = {"auto": 0, "csr": 1, "ell": 2}
 PHASES = ["dots", "update", "resid", "select", "compact", "bounds", "scalar", "pcg", "pcg_ax",
@@ -107,6 +107,7 @@ def load():
     lib.spai_spectrum.argtypes = [P, C.c_int, P, C.c_int, P, C.POINTER(C.c_int)]
     lib.spai_autotune.argtypes = [P, C.c_int, C.c_int, P, P]
     lib.spai_set_tiles.argtypes = [P, P]
+    lib.spai_history.argtypes = [P, P, C.c_int, C.POINTER(C.c_int)]
     lib.spai_get_state.argtypes = [P, P, C.POINTER(C.c_size_t)]
     lib.spai_set_state.argtypes = [P, P, C.c_size_t]
     lib.spai_csr_spectrum.argtypes = [C.POINTER(CsrT), C.c_int, P, P, C.POINTER(C.c_int),
@@ -279,6 +280,17 @@ class SPAI:
                                  C.byref(s1), C.byref(s2), C.byref(fb)))
         return {"iters": it.value, "resid": res.value, "nnz_m": nm.value, "nnz_p": npp.value,
                 "step1": s1.value, "step2": s2.value, "mr_fallbacks": fb.value}
+
+    def history(self):
+        """Per-iteration drop record: dict of arrays nnz_m, dropped_m, band_m, nnz_p,
+        dropped_p, band_p (one entry per iteration run since create/reset)."""
+        cnt = C.c_int()
+        _check(load().spai_history(self.h, None, 0, C.byref(cnt)))
+        rec = np.zeros((max(cnt.value, 1), 6), dtype=np.int64)
+        _check(load().spai_history(self.h, rec.ctypes.data, cnt.value, C.byref(cnt)))
+        rec = rec[:cnt.value]
+        names = ["nnz_m", "dropped_m", "band_m", "nnz_p", "dropped_p", "band_p"]
+        return {k: rec[:, c].copy() for c, k in enumerate(names)}
 
     def reset(self):
         """Restart from M_0 with the same A, method, cap and options."""

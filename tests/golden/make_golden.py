@@ -3,8 +3,11 @@
 Calls only the CPU oracle (and the seeded input generators); nothing here comes from
 the HIP library.  Usage: python tests/golden/make_golden.py [aniso256] [lognormal96]
 Output: tests/golden/<name>.json with, per method, the residual history
-||I - A M_i||_F (i = 0..iters), nnz(M_i), nnz(P_i) and the step sizes.
+||I - A M_i||_F (i = 0..iters), nnz(M_i), nnz(P_i), the step sizes, the per-iteration
+record of the drop rule (candidates, kept, tie band, global cut) and SHA-256 digests of
+the final patterns of M and P (CSC, rows ascending in each column).
 """
+import hashlib
 import json
 import os
 import sys
@@ -19,6 +22,19 @@ from paper_2511_09753_amd import workloads as W           # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+def pattern_digest(X):
+    """SHA-256 of a sparse pattern: CSC column pointers (int64) then row indices (int32),
+    little-endian, rows ascending within each column."""
+    import numpy as np
+    import scipy.sparse as sp
+    C = sp.csc_matrix(X)
+    C.sort_indices()
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(C.indptr, dtype="<i8").tobytes())
+    h.update(np.ascontiguousarray(C.indices, dtype="<i4").tobytes())
+    return h.hexdigest()
+
+
 def record(res):
     return {
         "resid": res.resid,
@@ -27,6 +43,9 @@ def record(res):
         "iters": res.iters,
         "status": res.status,
         "steps": [{k: v for k, v in s.items() if isinstance(v, float)} for s in res.scalars],
+        "drops": res.drops,
+        "pattern_m": pattern_digest(res.M),
+        "pattern_p": pattern_digest(res.P) if res.P is not None else None,
     }
 
 

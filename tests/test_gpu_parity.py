@@ -12,8 +12,9 @@ import scipy.sparse as sp
 
 from oracle import spai_oracle as O
 from paper_2511_09753_amd import workloads as W
-from tests.helpers import (GOLDEN, TOL_F64, TOL_MIXED, oracle_rule, pattern_diff, rel_err,
-                           require_gpu, value_err)
+from tests.helpers import (GOLDEN, TOL_F64, TOL_MIXED, far_from_cut, history_array,
+                           history_from_oracle, oracle_rule, parse_state, pattern_diff, rel_err,
+                           require_gpu, state_matrix, value_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -33,8 +34,19 @@ def _run_gpu(S, A, method, mode, value, relative, iters, precision="f64", tol=0.
     done, hist, rc = h.iterate(iters)
     M = h.get()
     st = h.stats()
+    st["history"] = history_array(h)
     h.close()
     return r0, hist, M, st, rc
+
+
+def _assert_history(st, ref):
+    """The device's per-iteration drop record (spai_history) equals the oracle's: kept,
+    dropped by the cap and dropped at the cut, for M and P."""
+    want = history_from_oracle(ref)
+    got = st["history"]
+    assert got.shape[0] >= want.shape[0]
+    assert np.array_equal(got[:want.shape[0]], want), (got[:3], want[:3])
+    assert not got[want.shape[0]:].any()
 
 
 SMALL = [
@@ -63,6 +75,7 @@ def test_small_parity_f64(name, make, method, mode, value, relative):
     assert not only_g and not only_o, (len(only_g), len(only_o))
     assert value_err(Mg, ref.M) <= 1e-9
     assert st["nnz_m"] == ref.M.nnz
+    _assert_history(st, ref)
     # exactly symmetric iterate
     assert abs(Mg - Mg.T).nnz == 0
 
@@ -125,14 +138,39 @@ def test_aniso256_full_against_stored_oracle(method):
     if not os.path.exists(path):
         pytest.skip("stored oracle run not generated")
     gold = json.load(open(path))["methods"][method]
+    from tests.golden.make_golden import pattern_digest
     S = _spai()
     wl = W.workload("aniso256")
-    r0, hist, Mg, st, _ = _run_gpu(S, wl.A, method, "column", 3.0, True, wl.iters)
+    A = wl.A
+    h = S.SPAI(A, method, "column", 3.0, True, max_iter=wl.iters)
+    r0 = h.stats()["resid"]
+    _, hist, _ = h.iterate(wl.iters)
+    st = h.stats()
+    rec = history_array(h)
+    hd, lists = parse_state(h.get_state())
+    h.close()
+    n = A.shape[0]
+    Mg = state_matrix(lists[0], n)
     assert r0 == pytest.approx(gold["resid"][0], rel=1e-14)
     assert rel_err(hist, gold["resid"][1:]) <= TOL_F64
     assert st["nnz_m"] == gold["nnz_m"][-1]
+    # the kept patterns, every iteration's drop record and the final patterns of M and P
+    assert list(rec[:, 0]) == gold["nnz_m"][1:]
+    want = np.array([[d["M"]["kept"], d["M"]["cand"] - d["M"]["kept"], d["M"]["band"]]
+                     for d in gold["drops"]])
+    assert np.array_equal(rec[:, :3], want)
+    assert pattern_digest(Mg) == gold["pattern_m"]
     if method != "mr":
         assert st["nnz_p"] == gold["nnz_p"][-1]
+        assert list(rec[:, 3]) == gold["nnz_p"][1:]
+        assert pattern_digest(state_matrix(lists[1], n)) == gold["pattern_p"]
+    # PCG with this M on the configuration's 4 right-hand sides (Experiment 06): the same
+    # iteration counts as the oracle's PCG with the same M, X within 1e-10
+    B = W.rhs(n, 4, W.seed_for(2, 1))
+    X, it, relres, rc = S.pcg_solve(A, Mg, B, rtol=1e-8)
+    Xo, ito, sto = O.pcg_block(A, Mg, B, rtol=1e-8)
+    assert list(it) == list(ito), (it, ito)
+    assert np.max(np.abs(X - Xo)) <= 1e-10 * np.max(np.abs(Xo))
 
 
 @pytest.mark.parametrize("nrhs", [1, 2, 4, 8, 16, 32, 48, 80])
@@ -182,6 +220,133 @@ def test_mixed_precision_against_f64_oracle():
     # the reported residual is the residual of the returned (float32-valued) M
     R = sp.identity(A.shape[0]) - A @ Mg
     assert np.sqrt((R.multiply(R)).sum()) == pytest.approx(hist[-1], rel=1e-6)
+
+
+@pytest.mark.parametrize("case", ["lognormal12_global", "aniso24_column"])
+def test_mixed_steps_keep_the_oracle_pattern_up_to_the_cut(case):
+    """The mixed path one iteration at a time against one FP64 oracle iteration from the
+    same state (the device's M_i and P_{i-1}, read back with spai_get_state): every entry
+    where the kept patterns of M_{i+1} or P_i differ has an oracle candidate magnitude
+    within 1e-5 (relative) of its keep threshold t (1 + eta) -- the tolerance of the mixed
+    path -- and the reported residual is that of the device's M_{i+1}."""
+    S = _spai()
+    if case == "lognormal12_global":
+        A, mode, value, rel = W.lognormal3d(12, 3000), "global", 2.0, True
+    else:
+        A, mode, value, rel = W.aniso2d(24, 1.0, 0.01), "column", 3.0, True
+    n = A.shape[0]
+    rule = oracle_rule(A, mode, value, rel)
+    iters = 10
+    h = S.SPAI(A, "lomr", mode, value, rel, max_iter=iters,
+               options=S.Options(precision="mixed"))
+    diffs = 0
+    for i in range(iters):
+        hd, lists = parse_state(h.get_state())
+        assert hd["iters_host"] == i and hd["value_bytes"] == 4
+        Mi, Pi = state_matrix(lists[0], n), state_matrix(lists[1], n)
+        ref = O.lomr(A, rule, 1, M0=Mi, P0=Pi if i > 0 else None, keep_candidates=True)
+        _, hist, _ = h.iterate(1)
+        hd2, lists2 = parse_state(h.get_state())
+        Mg, Pg = state_matrix(lists2[0], n), state_matrix(lists2[1], n)
+        # the reported residual is that of M_{i+1} (float64 on the CPU); it differs from
+        # the oracle step's only through entries kept or dropped at the cut
+        fro = float(np.sqrt(O.loss(A, Mg)))
+        assert abs(hist[0] - fro) <= 1e-6 * fro
+        for G, Ro, info in ((Mg, ref.M, ref.drops[0]["M"]), (Pg, ref.P, ref.drops[0]["P"])):
+            only_g, only_o = pattern_diff(G, Ro)
+            bad = far_from_cut(only_g | only_o, info, rule.eta, TOL_MIXED)
+            assert not bad, (i, bad[:5])
+            diffs += len(only_g) + len(only_o)
+    h.close()
+    print(case, "entries differing at the cut over", iters, "steps:", diffs)
+
+
+def test_set_state_rejects_a_corrupted_list_and_leaves_the_handle():
+    """A state whose second list (P) is corrupted -- rows out of order in a column, or a
+    row out of range -- is refused, and the handle continues exactly as an untouched one."""
+    S = _spai()
+    A = W.lognormal3d(9, 77)
+    h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=10)
+    h.iterate(4)
+    good = h.get_state()
+    _, ref, _ = h.iterate(4)
+    hd, lists = parse_state(good)
+    cp, ix, _ = lists[1]
+    j = int(np.nonzero(np.diff(cp) >= 2)[0][0])            # a column of P with two rows
+    q = int(cp[j])
+    base = hd["list_offsets"][1] + 8 * (hd["n"] + 1)
+    for kind in ("order", "range"):
+        bad = bytearray(good)
+        r = np.frombuffer(bad, dtype=np.int32, count=hd["nnz"][1], offset=base)
+        if kind == "order":
+            r[q], r[q + 1] = r[q + 1], r[q]
+        else:
+            r[q] = hd["n"]
+        with pytest.raises(S.SpaiError):
+            h.set_state(bytes(bad))
+    h.set_state(good)
+    _, again, _ = h.iterate(4)
+    h.close()
+    assert np.array_equal(again, ref)
+    # a fresh handle restored and then offered the corrupted state continues the same way
+    h2 = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=10)
+    h2.set_state(good)
+    bad = bytearray(good)
+    np.frombuffer(bad, dtype=np.int32, count=hd["nnz"][1], offset=base)[q] = -1
+    with pytest.raises(S.SpaiError):
+        h2.set_state(bytes(bad))
+    _, again2, _ = h2.iterate(4)
+    h2.close()
+    assert np.array_equal(again2, ref)
+
+
+def test_device_pool_limit_reports_nomem_and_the_handle_stays_usable():
+    """SPAI_ERR_NOMEM from opts.device_pool_limit: limits below the handle's pools fail
+    spai_create; under a limit that leaves room for half a 2048-step Lanczos basis,
+    that basis fails spai_spectrum, and the handle then iterates and runs the spectrum
+    exactly as an unlimited one does."""
+    S = _spai()
+    A = W.lognormal3d(32, 5)
+    n = A.shape[0]
+    def make(lim):
+        try:
+            return S.SPAI(A, "lomr", "global", 2.0, True, max_iter=6,
+                          options=S.Options(device_pool_limit=lim))
+        except S.SpaiError as e:
+            assert e.code == -5                             # SPAI_ERR_NOMEM
+            return None
+
+    lo, hi = 16 << 20, 32 << 20                             # bracket the handle's pools
+    while True:
+        h = make(hi)
+        if h is not None:
+            h.close()
+            break
+        lo, hi = hi, 2 * hi
+        assert hi <= (16 << 30)
+    while hi - lo > (8 << 20):                              # to within 8 MB
+        mid = (lo + hi) // 2
+        h = make(mid)
+        if h is None:
+            lo = mid
+        else:
+            h.close()
+            hi = mid
+    steps = 2048
+    basis = 8 * n * (steps + 1)
+    lim_handle = make(hi + basis // 2)                      # room for half the basis only
+    assert lim_handle is not None
+    v0 = np.random.default_rng(3).standard_normal(n)
+    with pytest.raises(S.SpaiError) as e:
+        lim_handle.spectrum(v0, steps=steps)
+    assert e.value.code == -5
+    free = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=6)
+    _, h1, _ = free.iterate(6)
+    _, h2, _ = lim_handle.iterate(6)
+    assert np.array_equal(h1, h2)
+    assert free.spectrum(v0, steps=20) == lim_handle.spectrum(v0, steps=20)
+    free.close()
+    lim_handle.close()
 
 
 def test_stopping_tolerance():
