@@ -603,11 +603,14 @@ struct Engine : EngineBase {
                                           update_tile_bytes(tUh)});
       if (opts.drop_score) stride = std::max<int64_t>(stride, (int64_t)score_tile_bytes(tSh, ell));
       stride = (stride + 255) / 256 * 256;
+      const int grid2 = (int)std::min<int64_t>(
+          kHugeGridMax, std::max<int64_t>(kHugeGridMin, kHugeBudget / stride / 8 * 8));
       char* scr;
-      if ((rc = dalloc(&scr, stride * kHugeGrid))) return rc;
+      if ((rc = dalloc(&scr, stride * grid2))) return rc;
       for (int b = 0; b < 3; ++b) {
         big[b].scratch = scr;
         big[b].scratch_stride = stride;
+        big[b].grid2 = grid2;
       }
     }
     if (global) {

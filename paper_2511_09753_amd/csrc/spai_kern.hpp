@@ -85,6 +85,7 @@ struct BigList {
   int* count2 = nullptr;
   char* scratch = nullptr;
   int64_t scratch_stride = 0;
+  int grid2 = 64;                  // workgroups of the huge-tile pass (scratch slices)
 };
 
 struct Tile {      // per-column tile
@@ -92,7 +93,10 @@ struct Tile {      // per-column tile
   int DG = 0;      // update: neighbour columns (0: default)
   int waves = 0;   // dots, update: 5 = resident tier with registers capped at five waves per SIMD
 };
-constexpr int kHugeGrid = 64;      // workgroups of the huge-tile pass
+// workgroups of the huge-tile pass: as many scratch slices as fit kHugeBudget bytes,
+// between kHugeGridMin and kHugeGridMax (a multiple of 8, so every XCD gets as many)
+constexpr int kHugeGridMin = 64, kHugeGridMax = 2048;
+constexpr int64_t kHugeBudget = (int64_t)2 << 30;
 
 struct UpdMode {
   int doM;       // form the (symmetrized, small-dropped) M candidates

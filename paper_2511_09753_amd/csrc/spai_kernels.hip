@@ -988,7 +988,7 @@ void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const 
                        weighted, colrz, big, st, 0, small.L, small.H);
   hipLaunchKernelGGL((k_resid<T, false>), dim3(256), dim3(SPAI_WAVE), resid_lds(large, ell), s, A, M,
                      R, off, total, colnorm, weighted, colrz, big, st, 1, large.L, large.H);
-  hipLaunchKernelGGL((k_resid<T, true>), dim3(kHugeGrid), dim3(SPAI_WAVE), 0, s, A, M, R, off, total,
+  hipLaunchKernelGGL((k_resid<T, true>), dim3(big.grid2), dim3(SPAI_WAVE), 0, s, A, M, R, off, total,
                      colnorm, weighted, colrz, big, st, 2, huge.L, huge.H);
 }
 
@@ -1326,7 +1326,7 @@ void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, int wei
                        colpart, big, st, 0, small.L, small.H);
   hipLaunchKernelGGL((k_dots<T, false>), dim3(256), dim3(SPAI_WAVE), dots_lds(large, ell), s, A, R, P,
                      useR, useP, weighted, colpart, big, st, 1, large.L, large.H);
-  hipLaunchKernelGGL((k_dots<T, true>), dim3(kHugeGrid), dim3(SPAI_WAVE), 0, s, A, R, P, useR, useP,
+  hipLaunchKernelGGL((k_dots<T, true>), dim3(big.grid2), dim3(SPAI_WAVE), 0, s, A, R, P, useR, useP,
                      weighted, colpart, big, st, 2, huge.L, huge.H);
 }
 
@@ -1538,7 +1538,7 @@ void launch_resid_impl(const Csr& A, Cols<T> Rin, Cols<T> Xr, Pair<T> P, int xsr
   hipLaunchKernelGGL((k_resid_impl<T, false>), dim3(256), dim3(SPAI_WAVE), dots_lds(large, ell), s,
                      A, Rin, Xr, P, src, seg, off, total, Rout, Zout, weighted, colnorm, colrz, big,
                      st, 1, large.L, large.H);
-  hipLaunchKernelGGL((k_resid_impl<T, true>), dim3(kHugeGrid), dim3(SPAI_WAVE), 0, s, A, Rin, Xr,
+  hipLaunchKernelGGL((k_resid_impl<T, true>), dim3(big.grid2), dim3(SPAI_WAVE), 0, s, A, Rin, Xr,
                      P, src, seg, off, total, Rout, Zout, weighted, colnorm, colrz, big, st, 2,
                      huge.L, huge.H);
 }
@@ -2325,7 +2325,7 @@ void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, Up
   hipLaunchKernelGGL((k_update<T, false>), dim3(256), dim3(SPAI_WAVE), update_lds(large, false), s,
                      A, M, R, P, PT, md, off, total, kcol, tM, tP, big, seg, st, 1, large.L,
                      large.H, update_deg(large));
-  hipLaunchKernelGGL((k_update<T, true>), dim3(kHugeGrid), dim3(SPAI_WAVE), 0, s, A, M, R, P, PT,
+  hipLaunchKernelGGL((k_update<T, true>), dim3(big.grid2), dim3(SPAI_WAVE), 0, s, A, M, R, P, PT,
                      md, off, total, kcol, tM, tP, big, seg, st, 2, huge.L, huge.H,
                      update_deg(huge));
 }
@@ -2855,7 +2855,7 @@ void launch_score(const Csr& A, Pair<T> M, double* sc, double* sig, BigList big,
                      small.H);
   hipLaunchKernelGGL((k_score<T, false>), dim3(256), dim3(SPAI_WAVE), score_lds(large, ell), s, A,
                      M, sc, big, st, 1, large.L, large.H);
-  hipLaunchKernelGGL((k_score<T, true>), dim3(kHugeGrid), dim3(SPAI_WAVE), 0, s, A, M, sc, big, st,
+  hipLaunchKernelGGL((k_score<T, true>), dim3(big.grid2), dim3(SPAI_WAVE), 0, s, A, M, sc, big, st,
                      2, huge.L, huge.H);
   const int ng = (int)std::min<int64_t>((n + 63) / 64, 1 << 30);
   hipLaunchKernelGGL(k_score_pair<T>, dim3(std::min(ng, resident_grid(k_score_pair<T>, 0))),
