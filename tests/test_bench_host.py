@@ -61,3 +61,43 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_state_lists_parses_the_state_layout():
+    """bench.state_lists reads the documented spai_get_state layout: a 104-byte header,
+    152 bytes of scalars per matrix, then each list as CSC (int64 pointers, int32 rows,
+    values of value_bytes)."""
+    import struct
+    import numpy as np
+    import bench
+    n = 3
+    lists = [(np.array([0, 1, 3, 4]), np.array([0, 0, 2, 1]), np.array([1.5, -2.0, 0.25, 3.0])),
+             (np.array([0, 0, 1, 1]), np.array([2]), np.array([7.0]))]
+    for vb, vt in ((8, np.float64), (4, np.float32)):
+        hdr = struct.pack("<8sii q iiiiii qq 5q", b"SPAISTAT", 1, vb, n, 1, 2, 0, 0, 1, 2, 5, 5,
+                          4, 1, 0, 0, 0)
+        buf = hdr + bytes(152)
+        for cp, ix, vl in lists:
+            buf += cp.astype("<i8").tobytes() + ix.astype("<i4").tobytes() + vl.astype(vt).tobytes()
+        got = bench.state_lists(buf)
+        assert len(got) == 2
+        for G, (cp, ix, vl) in zip(got, lists):
+            assert np.array_equal(G.indptr, cp) and np.array_equal(G.indices, ix)
+            assert np.array_equal(G.data, vl.astype(vt).astype(np.float64))
+
+
+def test_state_parsers_agree():
+    """The tests' parse_state and bench.state_lists read the same header fields."""
+    import struct
+    import numpy as np
+    import bench
+    from tests.helpers import parse_state
+    cp, ix, vl = np.array([0, 2, 2]), np.array([0, 1]), np.array([1.0, 2.0])
+    hdr = struct.pack("<8sii q iiiiii qq 5q", b"SPAISTAT", 1, 8, 2, 1, 0, 0, 0, 1, 1, 7, 9,
+                      2, 0, 0, 0, 0)
+    buf = hdr + bytes(152) + cp.astype("<i8").tobytes() + ix.astype("<i4").tobytes() + \
+        vl.astype("<f8").tobytes()
+    hd, lists = parse_state(buf)
+    assert hd["nlists"] == 1 and hd["iters_host"] == 7 and hd["nnz"][0] == 2 and hd["n"] == 2
+    assert np.array_equal(lists[0][1], ix)
+    assert np.array_equal(bench.state_lists(buf)[0].toarray(), np.array([[1.0, 0.0], [2.0, 0.0]]))
