@@ -512,9 +512,9 @@ struct Engine : EngineBase {
       A.ecol = d_ec;
       A.eval = d_ev;
       // A in ELL: the residual and dots run their lean resident tiers, whose ordered key
-      // sets take any power-of-two H
-      tRs = Tile{64, 256};
-      tDs = Tile{128, 256, 0, 1};
+      // sets take any power-of-two H (the tiles the tuner picks on the 96^3 stencil)
+      tRs = Tile{128, 1024};
+      tDs = Tile{256, 1024, 0, 1};
       if (sh == 3) tUs = Tile{128, 256, 0, 1};   // the update's lean tier: rows of <= 8
     }
     // ---- locality order of the rows (for the PCG products)

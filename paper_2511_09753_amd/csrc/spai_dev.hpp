@@ -64,6 +64,12 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, SPAI_WAVE);
   return v;
 }
+// lane l's value of a 64-bit per-lane register, as a wave-uniform value (l constant)
+__device__ __forceinline__ int64_t wave_read64(int64_t v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(uint64_t)v, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 __device__ __forceinline__ int wave_max_int(int v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, SPAI_WAVE));

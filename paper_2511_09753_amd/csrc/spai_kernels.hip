@@ -814,7 +814,11 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
   unsigned long long outcnt = 0;
   ColumnWalk w(A.n, blockIdx.x, gridDim.x);
   for (int64_t j = w.begin; j < w.end; j += w.step) {
+    // the column's descriptors, all loaded before the first is used (one wait)
     const int lm = M.len[j];
+    const int64_t mb = M.beg[j];
+    const int64_t ob = off[j];
+    const int64_t oe = j + 1 < A.n ? off[j + 1] : ntot;
     if (lm > Lc) {
       defer_column(0, big, st, j);
       continue;
@@ -823,22 +827,27 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
       if (lane == 0) atomicOr(&st->err, 2);
       continue;
     }
-    const int64_t ob = off[j];
-    const int64_t ub = (j + 1 < A.n ? off[j + 1] : ntot) - ob;   // >= distinct rows of r_j
+    const int64_t ub = oe - ob;                  // >= distinct rows of r_j
     const int Hc = next_pow2((int)min<int64_t>(max<int64_t>(ub, 64), (int64_t)H));
     const int ksh = 32 - log2_pow2(Hc);
     const int kend = Hc + kOhOver;
-    const int64_t mb = M.beg[j];
+    // both slots' loads unconditional (entry 0 where a lane has none), so they are in
+    // flight together before the first LDS store waits on one
     int row[2], lst[2] = {0, 0}, pos[2];
+    T val[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int e = lane + k * SPAI_WAVE;
       pos[k] = e;
-      row[k] = -1;
-      if (e < lm) {
-        row[k] = M.idx[mb + e];
-        ent[e] = BtEnt<T>{row[k], M.val[mb + e]};
-      }
+      const int64_t q = e < lm ? mb + e : 0;
+      row[k] = M.idx[q];
+      val[k] = M.val[q];
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = lane + k * SPAI_WAVE;
+      if (e < lm) ent[e] = BtEnt<T>{row[k], val[k]};
+      else row[k] = -1;
     }
     for (int i = lane; i < kend; i += SPAI_WAVE) kt[i] = kOhEmpty;
     const int a = bt_build<2>((unsigned char*)cell, row, lst, pos);
@@ -1176,32 +1185,42 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
   const int W = 1 << A.eshift;
   ColumnWalk w(A.n, blockIdx.x, gridDim.x);
   for (int64_t j = w.begin; j < w.end; j += w.step) {
-    const int lr = useR ? R.len[j] : 0;
-    const int lp = useP ? P.len[j] : 0;
+    // the column's descriptors, all loaded before the first is used (one wait; both
+    // lists have their n descriptors whether in use or not)
+    const int lr0 = R.len[j], lp0 = P.len[j];
+    const int64_t rb = R.beg[j], pb = P.beg[j];
+    const int lr = useR ? lr0 : 0;
+    const int lp = useP ? lp0 : 0;
     const int le = lr + lp;
     if (le > Lc) {
       defer_column(0, big, st, j);
       continue;
     }
-    const int64_t rb = useR ? R.beg[j] : 0;
-    const int64_t pb = useP ? P.beg[j] : 0;
     const int Hc = min(H, max(128, next_pow2(max(le * W / 2, 1))));   // home slots
     const int ksh = 32 - log2_pow2(Hc);
     const int kend = Hc + kOhOver;
+    // both slots' loads unconditional, from the list the lane's entry lies in (entry 0
+    // of R where a lane has none), so they are in flight together before the first LDS
+    // store waits on one
     int row[2], lst[2], pos[2];
+    T val[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int e = lane + k * SPAI_WAVE;
-      row[k] = -1;
-      lst[k] = e < lr ? 0 : 1;
-      pos[k] = e < lr ? e : e - lr;
-      if (e < lr) {
-        row[k] = R.idx[rb + e];
-        ent[e] = BtEnt<T>{row[k], R.val[rb + e]};
-      } else if (e < le) {
-        row[k] = P.idx[pb + e - lr];
-        ent[e] = BtEnt<T>{row[k], P.val[pb + e - lr]};
-      }
+      const bool isr = e < lr;
+      lst[k] = isr ? 0 : 1;
+      pos[k] = isr ? e : e - lr;
+      const int* ip = (isr || e >= le) ? R.idx : P.idx;
+      const T* vp = (isr || e >= le) ? R.val : P.val;
+      const int64_t q = isr ? rb + e : (e < le ? pb + (e - lr) : 0);
+      row[k] = ip[q];
+      val[k] = vp[q];
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = lane + k * SPAI_WAVE;
+      if (e < le) ent[e] = BtEnt<T>{row[k], val[k]};
+      else row[k] = -1;
     }
     for (int i = lane; i < kend; i += SPAI_WAVE) kt[i] = kOhEmpty;
     const int a = bt_build<2>((unsigned char*)cell, row, lst, pos);
@@ -2008,7 +2027,7 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
 
 // Lean resident tier of the update (A in ELL with rows of at most 8 entries).  Same
 // candidates and the same arithmetic as update_body, built without searches: every row
-// of the column's own lists (m_j, r_j, p_j, p^T_j, up to 128 entries, two per lane) and
+// of the column's own lists (m_j, r_j, p_j, p^T_j, up to 192 entries, three per lane) and
 // of its neighbour columns m_l, l in N(j) (one entry per lane each), goes into the
 // ordered key set; the keys are sorted by row and a byte table maps a row's hash to its
 // rank; the own lists' values are then scattered to dense per-rank arrays and the
@@ -2016,6 +2035,7 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
 // ascending l (one round per neighbour, so each sum runs in the order update_body uses),
 // and each lane forms the candidates of its keys.
 constexpr int kUpdLeanKeys = 128;
+constexpr int kUpdLeanOwn = 192;   // own-list entries (whatever the tile's L)
 
 template <typename T>
 __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) void k_update_lean(
@@ -2046,75 +2066,109 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
   const bool needPT = needP && mirror;
   const int64_t ntot = *total;
   const bool overflow = ntot > Mo.cap || (md.doP && (ntot > Po.cap || ntot > PTo.cap));
-  const int Lc = min(L, 128);
   const T* eval = sizeof(T) == 4 ? (const T*)A.eval32 : (const T*)A.eval;
-  ColumnWalk w(A.n, blockIdx.x, gridDim.x);
-  for (int64_t j = w.begin; j < w.end; j += w.step) {
-    const SegState& g = seg.st[seg.segof(j)];
-    const double a1 = g.coef[0], a2 = g.coef[1], c1 = g.coef[2], c2 = g.coef[3];
-    const int lm = md.doM ? M.len[j] : 0;
-    const int lr = needR ? R.len[j] : 0;
-    const int lp = needP ? P.len[j] : 0;
-    const int lpt = needPT ? PT.len[j] : 0;
-    const int lown = lm + lr + lp + lpt;
-    const int64_t ob = off[j];
-    const int64_t ub = (j + 1 < A.n ? off[j + 1] : ntot) - ob;   // entries of all lists + 1
-    // neighbours l in N(j) (row j of A): one per lane
+  // A column's descriptors are loaded one column ahead, one value per lane (lanes 0-3
+  // the lengths of m_j, r_j, p_j, p^T_j, lanes 4-7 their starts, lanes 8 and 9 the
+  // column's candidate range off[j] .. off[j+1]) together with row j of A (lanes 0-7:
+  // neighbour l and a_jl), and each neighbour column's length and start once those
+  // have arrived: a column's first loads are then its entries, and its descriptors
+  // arrive while the column before it is computed.
+  struct Pre {
+    int64_t d = 0;
     int nl = -1;
-    double av = 0.0;
-    if (needRT && lane < 8) {
-      nl = A.ecol[((int64_t)j << 3) + lane];
-      av = (double)eval[((int64_t)j << 3) + lane];
-    }
-    // own entries, two per lane (list 0 m, 1 r, 2 p, 3 p^T), loaded before anything
-    // waits on the neighbours (a list too long for the tile is dropped below)
-    int orow[2], olst[2];
-    T oval[2];
-    const bool fits = lown <= Lc;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int e = lane + k * SPAI_WAVE;
-      orow[k] = -1;
-      olst[k] = 0;
-      oval[k] = (T)0;
-      if (fits) {
-        if (e < lm) {
-          const int64_t q = M.beg[j] + e;
-          orow[k] = M.idx[q]; oval[k] = M.val[q]; olst[k] = 0;
-        } else if (e < lm + lr) {
-          const int64_t q = R.beg[j] + (e - lm);
-          orow[k] = R.idx[q]; oval[k] = R.val[q]; olst[k] = 1;
-        } else if (e < lm + lr + lp) {
-          const int64_t q = P.beg[j] + (e - lm - lr);
-          orow[k] = P.idx[q]; oval[k] = P.val[q]; olst[k] = 2;
-        } else if (e < lown) {
-          const int64_t q = PT.beg[j] + (e - lm - lr - lp);
-          orow[k] = PT.idx[q]; oval[k] = PT.val[q]; olst[k] = 3;
-        }
-      }
-    }
+    T av = (T)0;
     int nlen = 0;
     int64_t nbeg = 0;
-    if (nl >= 0) {
-      nlen = M.len[nl];
-      nbeg = M.beg[nl];
+  };
+  auto pre1 = [&](int64_t jj, Pre& p) {
+    p = Pre{};
+    if (lane < 4) {
+      const int* lp = lane == 0 ? M.len : lane == 1 ? R.len : lane == 2 ? P.len : PT.len;
+      p.d = lp[jj];
+    } else if (lane < 8) {
+      const int64_t* bp = lane == 4 ? M.beg : lane == 5 ? R.beg : lane == 6 ? P.beg : PT.beg;
+      p.d = bp[jj];
+    } else if (lane == 8) {
+      p.d = off[jj];
+    } else if (lane == 9) {
+      p.d = jj + 1 < A.n ? off[jj + 1] : ntot;
+    }
+    if (needRT && lane < 8) {
+      p.nl = A.ecol[(jj << 3) + lane];
+      p.av = eval[(jj << 3) + lane];
+    }
+  };
+  auto pre2 = [&](Pre& p) {
+    if (p.nl >= 0) {
+      p.nlen = M.len[p.nl];
+      p.nbeg = M.beg[p.nl];
+    }
+  };
+  ColumnWalk w(A.n, blockIdx.x, gridDim.x);
+  Pre cur, nxt;
+  if (w.begin < w.end) {
+    pre1(w.begin, cur);
+    pre2(cur);
+  }
+  for (int64_t j = w.begin; j < w.end; j += w.step, cur = nxt) {
+    const int lm = md.doM ? (int)wave_read64(cur.d, 0) : 0;
+    const int lr = needR ? (int)wave_read64(cur.d, 1) : 0;
+    const int lp = needP ? (int)wave_read64(cur.d, 2) : 0;
+    const int lpt = needPT ? (int)wave_read64(cur.d, 3) : 0;
+    const int lown = lm + lr + lp + lpt;
+    const int64_t bm = wave_read64(cur.d, 4), br = wave_read64(cur.d, 5);
+    const int64_t bp = wave_read64(cur.d, 6), bpt = wave_read64(cur.d, 7);
+    const int64_t ob = wave_read64(cur.d, 8);
+    const int64_t ub = wave_read64(cur.d, 9) - ob;               // entries of all lists + 1
+    const int nl = cur.nl;                                       // neighbour l in N(j)
+    const double av = (double)cur.av;
+    const int nlen = cur.nlen;
+    const int64_t nbeg = cur.nbeg;
+    const int64_t jn = j + w.step;
+    if (jn < w.end) pre1(jn, nxt);
+    // own entries, up to three per lane (list 0 m, 1 r, 2 p, 3 p^T; an entry's list
+    // follows from its place e), one unconditional load per slot from the list the
+    // lane's entry lies in (entry 0 of m where it has none; bit k of ovalid says which
+    // are real), so all of them are in flight together (a column whose lists hold
+    // more is deferred below)
+    int orow[kUpdLeanOwn / SPAI_WAVE];
+    T oval[kUpdLeanOwn / SPAI_WAVE];
+    unsigned ovalid = 0u;
+    const bool fits = lown <= kUpdLeanOwn;
+#pragma unroll
+    for (int k = 0; k < kUpdLeanOwn / SPAI_WAVE; ++k) {
+      const int e = lane + k * SPAI_WAVE;
+      const bool v = fits && e < lown;
+      const int lst = (e >= lm) + (e >= lm + lr) + (e >= lm + lr + lp);
+      const int* ip = lst == 0 ? M.idx : lst == 1 ? R.idx : lst == 2 ? P.idx : PT.idx;
+      const T* vp = lst == 0 ? M.val : lst == 1 ? R.val : lst == 2 ? P.val : PT.val;
+      const int64_t q0 = lst == 0 ? bm + e : lst == 1 ? br + (e - lm)
+                       : lst == 2 ? bp + (e - lm - lr) : bpt + (e - lm - lr - lp);
+      const int64_t q = v ? q0 : 0;
+      orow[k] = (v ? ip : M.idx)[q];
+      oval[k] = (v ? vp : M.val)[q];
+      ovalid |= (v ? 1u : 0u) << k;
     }
     const unsigned long long nm = __ballot(nl >= 0);
     const int deg = __popcll(nm);                 // entries first, so lanes 0 .. deg-1
-    // neighbour entries: entry `lane` of each neighbour column m_l
+    // neighbour entries: entry `lane` of each neighbour column m_l.  The loads are
+    // unconditional (entry 0 of the list where a lane has none; bit t of nvalid says
+    // which are real), so no conversion or select waits on one of them before all
+    // eight are in flight.
     int nrow[8];
     T nval[8];
+    unsigned nvalid = 0u;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int len_t = __shfl(nlen, t, SPAI_WAVE);
       const int64_t beg_t = __shfl(nbeg, t, SPAI_WAVE);
-      nrow[t] = -1;
-      nval[t] = (T)0;
-      if (t < deg && lane < len_t) {
-        nrow[t] = M.idx[beg_t + lane];
-        nval[t] = M.val[beg_t + lane];
-      }
+      const bool v = t < deg && lane < len_t;
+      const int64_t q = v ? beg_t + lane : 0;
+      nrow[t] = M.idx[q];
+      nval[t] = M.val[q];
+      nvalid |= (v ? 1u : 0u) << t;
     }
+    if (jn < w.end) pre2(nxt);
     if (!fits || wave_max_int(nlen) > SPAI_WAVE) {
       defer_column(0, big, st, j);
       continue;
@@ -2130,10 +2184,17 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
     const int kend = Hc + kOhOver;
     for (int i = lane; i < kend; i += SPAI_WAVE) kt[i] = kOhEmpty;
     __syncthreads();
-    bool ok = oh_insert_batch<2>(kt, ksh, kend, orow);
+    int okey[kUpdLeanOwn / SPAI_WAVE];
+#pragma unroll
+    for (int k = 0; k < kUpdLeanOwn / SPAI_WAVE; ++k) okey[k] = (ovalid >> k) & 1u ? orow[k] : -1;
+    bool ok = oh_insert_batch<kUpdLeanOwn / SPAI_WAVE>(kt, ksh, kend, okey);
     {
-      const int n0[4] = {nrow[0], nrow[1], nrow[2], nrow[3]};
-      const int n1[4] = {nrow[4], nrow[5], nrow[6], nrow[7]};
+      int n0[4], n1[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        n0[t] = (nvalid >> t) & 1u ? nrow[t] : -1;
+        n1[t] = (nvalid >> (t + 4)) & 1u ? nrow[t + 4] : -1;
+      }
       ok = oh_insert_batch<4>(kt, ksh, kend, n0) && ok;
       ok = oh_insert_batch<4>(kt, ksh, kend, n1) && ok;
     }
@@ -2174,8 +2235,12 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
       }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
-      if (orow[k] >= 0) dv[olst[k] * kUpdLeanKeys + (int)cb[bt_cell(orow[k], mul)] - 1] = oval[k];
+    for (int k = 0; k < kUpdLeanOwn / SPAI_WAVE; ++k)
+      if ((ovalid >> k) & 1u) {
+        const int e = lane + k * SPAI_WAVE;
+        const int lst = (e >= lm) + (e >= lm + lr) + (e >= lm + lr + lp);
+        dv[lst * kUpdLeanKeys + (int)cb[bt_cell(orow[k], mul)] - 1] = oval[k];
+      }
     // neighbour products in ascending l: one round per neighbour, distinct ranks inside
     for (int t = 0; t < deg; ++t) {
       const double a_t = __shfl(av, t, SPAI_WAVE);
@@ -2183,13 +2248,17 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
       T vv = (T)0;
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (q == t) { rr = nrow[q]; vv = nval[q]; }
+        if (q == t && ((nvalid >> q) & 1u)) { rr = nrow[q]; vv = nval[q]; }
       if (rr >= 0) {
         const int rk = (int)cb[bt_cell(rr, mul)] - 1;
         rta[rk] += a_t * (double)vv;
       }
     }
     __syncthreads();
+    // the matrix's step sizes, read only now: a load at the top of the column would
+    // make the column's first wait also wait for it
+    const SegState& g = seg.st[seg.segof(j)];
+    const double a1 = g.coef[0], a2 = g.coef[1], c1 = g.coef[2], c2 = g.coef[3];
     int cntM = 0, cntP = 0, cntPT = 0;
     for (int base = 0; base < nk; base += SPAI_WAVE) {
       const int t = base + lane;
