@@ -238,6 +238,165 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
   }
 }
 
+// The product for an even number of right-hand sides: two rows per wave at a time,
+// lanes 0-31 the row at one position and lanes 32-63 the row at the next, lane l of a
+// half owning right-hand sides c0 + 2 (l mod 32) and the one after, so every gather is
+// one 16-byte load per lane and one load instruction serves two rows (half the
+// address-unit work of k_spmm_wave per row).  A half's row entries are loaded 32 at a
+// time (one per lane of the half) and broadcast with readlane; the gathers of both
+// rows are issued in groups of eight before any is used, entries past a row's count
+// repeating its last one so every load is in bounds.  Each row's sum runs over its
+// entries in stored order, and the dot terms are added in position order, so the rows
+// of Y and the dot partials are those of k_spmm_wave bit for bit.  Positions are
+// dealt as in k_spmm_wave (eight XCD ranges, kRowsPerWave consecutive positions per
+// wave, a non-persistent launch).
+template <typename VT, int LAY>
+__global__ __launch_bounds__(kThreads) void k_spmm_pair(Mat A, const double* X, double* Y,
+                                                        int dot, int nrhs, int c0,
+                                                        const int32_t* order, double* part) {
+  constexpr int G = 8;
+  __shared__ double sh[kThreads];
+  constexpr int WPB = kThreads / 64;
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5;
+  const int hl = lane & 31;
+  const int wv = threadIdx.x >> 6;
+  const int64_t xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
+  const int64_t per = (A.n + 7) / 8;
+  const int64_t r0 = xcd * per;
+  const int64_t r1 = r0 + per < A.n ? r0 + per : A.n;
+  const bool on = c0 + 2 * hl < nrhs;
+  const unsigned loff = on ? (unsigned)hl * 16u : 0u;   // idle lanes re-read column c0
+  auto rowof = [&](int64_t k) -> int64_t { return order ? (int64_t)order[k] : k; };
+  double acc0 = 0.0, acc1 = 0.0;
+  const int64_t kbeg = r0 + (kb * WPB + wv) * kRowsPerWave;
+  const int64_t kend = kbeg + kRowsPerWave < r1 ? kbeg + kRowsPerWave : r1;
+  // this half's position k + half: row i, descriptor [a, b), first 32 entries (ec, ev)
+  auto load_pos = [&](int64_t p, int64_t& i, int64_t& a, int64_t& b) {
+    i = -1;
+    a = 0;
+    b = 0;
+    if (p < kend) {
+      i = rowof(p);
+      a = row_lo<LAY>(A, i);
+      b = row_hi<LAY>(A, i);
+    }
+  };
+  auto load_ent = [&](int64_t a, int64_t b, int& cc, VT& cv) {
+    cc = -1;
+    cv = 0;
+    if (a + hl < b) {
+      cc = A.col[a + hl];
+      cv = entry_val<VT>(A, a + hl);
+    }
+  };
+  int64_t i, a, b, ni, na, nb;
+  int ec, nec = -1;
+  VT ev, nev = 0;
+  load_pos(kbeg + half, i, a, b);
+  load_ent(a, b, ec, ev);
+  load_pos(kbeg + 2 + half, ni, na, nb);
+  for (int64_t k = kbeg; k < kend; k += 2) {
+    const bool has = i >= 0;
+    double y0 = 0.0, y1 = 0.0;
+    double2 xd = make_double2(0.0, 0.0);
+    bool found = false;
+    int64_t q0 = 0;                     // entries a + q0 .. a + q0 + 31 are in (ec, ev)
+    bool first = true;
+    for (;;) {
+      const unsigned long long bal = __ballot(ec >= 0);   // ELL padding (column -1) last
+      const int cA = __popcll(bal & 0xffffffffull), cB = __popcll(bal >> 32);
+      const int cmax = cA > cB ? cA : cB;
+      if (first) {                      // the next pair's entries while these are gathered
+        load_ent(na, nb, nec, nev);
+        first = false;
+      }
+      if (cmax == 0) break;
+      const int cmine = half ? cB : cA;
+      for (int e0 = 0; e0 < cmax; e0 += G) {
+        double2 xs[G];
+        int cs[G];
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+          const int e = e0 + t;
+          const int eA = cA ? min(e, cA - 1) : 0, eB = cB ? min(e, cB - 1) : 0;
+          const int colA = __builtin_amdgcn_readlane(ec, eA);
+          const int colB = __builtin_amdgcn_readlane(ec, 32 + eB);
+          int col = half ? colB : colA;
+          cs[t] = col;
+          col = col < 0 ? 0 : col;
+          const char* xrow = (const char*)(X + ((int64_t)col * nrhs + c0));
+          xs[t] = *(const double2*)(xrow + loff);
+        }
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+          const int e = e0 + t;
+          const VT vA = readlane_val(ev, e < 32 ? e : 31);
+          const VT vB = readlane_val(ev, 32 + (e < 32 ? e : 31));
+          if (e < cmine) {
+            const double v = (double)(half ? vB : vA);
+            y0 += v * xs[t].x;
+            y1 += v * xs[t].y;
+            if (cs[t] == (int)i) {
+              xd = xs[t];
+              found = true;
+            }
+          }
+        }
+      }
+      // rows longer than 32 entries: the next 32 of each half's row
+      q0 += 32;
+      if (__ballot(a + q0 < b) == 0ull) break;   // every lane takes part in the ballot
+      load_ent(a + q0, b, ec, ev);
+    }
+    double t0 = 0.0, t1 = 0.0;          // this row's terms of the dot
+    if (has && on) {
+      double2* yr = (double2*)(Y + (i * nrhs + c0 + 2 * hl));
+      *yr = make_double2(y0, y1);
+      if (dot) {
+        // a row without a diagonal entry loads X[i, :] after all
+        const double2 w = found ? xd : *(const double2*)(X + (i * nrhs + c0 + 2 * hl));
+        t0 = w.x * y0;
+        t1 = w.y * y1;
+      }
+    }
+    if (dot) {
+      // both halves add the pair's terms in position order, as k_spmm_wave adds its
+      // rows one after the other, so the partials equal that kernel's bit for bit
+      const double o0 = __shfl_xor(t0, 32, SPAI_WAVE), o1 = __shfl_xor(t1, 32, SPAI_WAVE);
+      const bool hasA = __shfl_xor((int)has, half ? 32 : 0, SPAI_WAVE) != 0;
+      const bool hasB = __shfl_xor((int)has, half ? 0 : 32, SPAI_WAVE) != 0;
+      if (on && hasA) {
+        acc0 += half ? o0 : t0;
+        acc1 += half ? o1 : t1;
+      }
+      if (on && hasB) {
+        acc0 += half ? t0 : o0;
+        acc1 += half ? t1 : o1;
+      }
+    }
+    i = ni;
+    a = na;
+    b = nb;
+    ec = nec;
+    ev = nev;
+    load_pos(k + 4 + half, ni, na, nb);
+  }
+  if (!part) return;
+  // per right-hand side r = 2 (l mod 32) + s, wave w's sum (the same in both halves) at
+  // sh[w 64 + r], reduced over the waves in order as in k_spmm_wave
+  if (half == 0) {
+    sh[wv * 64 + 2 * hl] = acc0;
+    sh[wv * 64 + 2 * hl + 1] = acc1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64 && c0 + (int)threadIdx.x < nrhs) {
+    double sum = 0.0;
+    for (int w = 0; w < WPB; ++w) sum += sh[w * 64 + threadIdx.x];
+    part[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = sum;
+  }
+}
+
 // The product for at most 32 right-hand sides.  A wave of k_spmm_wave would leave
 // 64 - nrhs lanes idle; here R = pow2(nrhs) lanes share a row (lane r owns right-hand
 // side r), so a workgroup has kThreads / R rows in flight, and each lane sums its row's
@@ -629,9 +788,14 @@ struct Solver {
       default: break;
     }
     spmm_grid = spmm_blocks(n);
-    for (int c0 = 0; c0 < nrhs; c0 += 64)
-      hipLaunchKernelGGL((k_spmm_wave<VT, LAY>), dim3(spmm_grid), dim3(kThreads), 0, s, K, X, Y,
-                         pt ? 1 : 0, nrhs, c0, order, pt);
+    for (int c0 = 0; c0 < nrhs; c0 += 64) {
+      if (nrhs % 2 == 0)   // 16-byte gathers, two rows per wave
+        hipLaunchKernelGGL((k_spmm_pair<VT, LAY>), dim3(spmm_grid), dim3(kThreads), 0, s, K, X,
+                           Y, pt ? 1 : 0, nrhs, c0, order, pt);
+      else
+        hipLaunchKernelGGL((k_spmm_wave<VT, LAY>), dim3(spmm_grid), dim3(kThreads), 0, s, K, X,
+                           Y, pt ? 1 : 0, nrhs, c0, order, pt);
+    }
   }
   template <typename VT>
   void spmm_v(const Mat& K, const double* X, double* Y, double* pt) {

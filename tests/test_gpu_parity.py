@@ -173,11 +173,12 @@ def test_aniso256_full_against_stored_oracle(method):
     assert np.max(np.abs(X - Xo)) <= 1e-10 * np.max(np.abs(Xo))
 
 
-@pytest.mark.parametrize("nrhs", [1, 2, 4, 8, 16, 32, 48, 80])
+@pytest.mark.parametrize("nrhs", [1, 2, 4, 8, 16, 32, 33, 48, 66, 80])
 def test_pcg_multi_rhs_aniso(nrhs):
     """Every width path of the block PCG: the narrow product with 1, 2, 4, 8, 16 and 32
-    lanes per row (1 to 32 right-hand sides), one wave per row (48) and more than 64
-    right-hand sides (80, chunks of 64 and the flat vector updates)."""
+    lanes per row (1 to 32 right-hand sides), two rows per wave with 16-byte gathers
+    (an even count above 32: 48, and chunks of 64 with a short last one: 66, 80), one
+    wave per row (an odd count above 32: 33) and the flat vector updates."""
     S = _spai()
     A = W.aniso2d(64, 1.0, 0.01)
     ref = O.lomr(A, oracle_rule(A, "column", 3.0, True), 10)
