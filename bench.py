@@ -69,12 +69,12 @@ def lomr_alg_bytes(c, n, nnzA, s_val, s_aval, iters, with_p=True):
 # kernel of each timed phase (its resident tier; the lean tiers when A is held in ELL),
 # and the source file its code lives in
 PHASE_KERNEL = {"dots": "k_dots", "update": "k_update", "resid": "k_resid", "compact": "k_compact",
-                "pcg_mx": "k_spmm_wave_mx", "pcg_ax": "k_spmm_wave_ax"}
+                "pcg_mx": "k_spmm_pair_mx", "pcg_ax": "k_spmm_pair_ax"}
 KERNEL_SOURCE = {"k_dots": "spai_kernels.hip", "k_update": "spai_kernels.hip",
                  "k_resid": "spai_kernels.hip", "k_compact": "spai_kernels.hip",
                  "k_dots_lean": "spai_kernels.hip", "k_update_lean": "spai_kernels.hip",
                  "k_resid_lean": "spai_kernels.hip",
-                 "k_spmm_wave_mx": "spai_pcg.hip", "k_spmm_wave_ax": "spai_pcg.hip"}
+                 "k_spmm_pair_mx": "spai_pcg.hip", "k_spmm_pair_ax": "spai_pcg.hip"}
 
 
 def phase_kernels(tiles, ell):
@@ -620,6 +620,9 @@ def main():
         M_mixed = h.get()                           # the mixed path's final iterate
         h.close()
         h64 = make("f64", True)
+        tiles64 = None
+        if tuned and not tuned.get("given"):        # each precision with its own tiles
+            tiles64, _ = h64.autotune(warm_iters=max(5, args.iters // 2), reps=2)
         step(h64, args.iters)                       # warm-up
         m0, c0, k0 = h64.profile()
         torch.cuda.synchronize()
@@ -656,6 +659,7 @@ def main():
             "time_to_equal_resid_speedup": (f64_ms_per_it * args.iters) / (mixed_ms_per_it * reach)
             if reach else None,
             "f64_step_s": T64, "f64_pcg_iters_max": int(pcg64[0].max()) if pcg64 else None,
+            "f64_tiles": tiles64,
         }
         log("f64 comparison:", json.dumps(f64))
     else:

@@ -50,7 +50,7 @@ def test_traffic_lookup_needs_a_matching_profile():
     assert bench.measured_traffic("no_such_kernel") is None
     # the committed profiles name the source file hash they were taken on; each
     # reported figure is positive
-    for k in ("k_dots", "k_spmm_wave_mx", "k_spmm_wave_ax"):
+    for k in ("k_update_lean", "k_dots_lean", "k_resid_lean", "k_spmm_pair_mx", "k_spmm_pair_ax"):
         t = bench.measured_traffic(k)
         assert t is None or t > 0
 
