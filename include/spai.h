@@ -136,6 +136,17 @@ typedef struct {
                                (keep score > t + tie_eta |t|, t the (b+1)-th largest).
                                P keeps hard thresholding.  Requires SPAI_CAP_GLOBAL
                                and symmetrize = 1; default 0                      */
+  double floor_frac;        /* global cap on magnitudes, one matrix: the update
+                               writes only the candidates (off-diagonal ones for M)
+                               with |x| >= floor_frac times the previous iteration's
+                               cut t, and counts the others; when this iteration's
+                               cut does not clear the floor by the tie factor
+                               (t (1 - tie_eta) < floor) or there is no cut while
+                               candidates were left out, the update and the
+                               selection run again without the floor.  The kept
+                               sets, values and drop records are those without a
+                               floor; only the candidate traffic changes.  >= 0,
+                               0 disables; default 0.5                            */
 } spai_opts_t;
 
 /* Fill *opts with the defaults. */

@@ -1170,12 +1170,26 @@ struct Engine : EngineBase {
                      s);
     te();
     const double* keyM = (global && md.doM && score) ? sigma : nullptr;
+    // speculative floors (global cap on magnitudes, one matrix): the update has written
+    // only candidates above a fraction of the last cut; where the cut does not clear it,
+    // the update and the selection run once more without floors (masked otherwise)
+    const bool floors = global && nseg == 1 && !score && opts.floor_frac > 0.0;
     if (global) {
       tb(SPAI_PH_SELECT);
       if (keyM) launch_score<T>(A, M, score, sigma, big[2], st, tSs, tSl, tSh, n, s);
       if (md.doM)
         launch_global_select<T>(M, 1, m_global, opts.tie_eta, 0, selhist, selbuf, n, st, s, keyM);
       if (md.doP) launch_global_select<T>(P, 0, m_global, opts.tie_eta, 1, selhist, selbuf, n, st, s);
+      if (floors) {
+        launch_redo_begin(st, s);
+        launch_update<T>(A, M, R, P, PT, md, off, total, kcol, tM, tP, big[2], seg, st, tUs, tUl,
+                         tUh, s);
+        if (md.doM)
+          launch_global_select<T>(M, 1, m_global, opts.tie_eta, 0, selhist, selbuf, n, st, s);
+        if (md.doP)
+          launch_global_select<T>(P, 0, m_global, opts.tie_eta, 1, selhist, selbuf, n, st, s);
+        launch_redo_end(st, s);
+      }
       te();
     }
     tb(SPAI_PH_COMPACT);
@@ -1188,6 +1202,7 @@ struct Engine : EngineBase {
       launch_compact<T>(PT, 2, colcap, 0, global, tP, opts.tie_eta, n, st, s);
       launch_flip(1, st, s);
     }
+    if (floors) launch_floor_next(st, md.doM, md.doP, opts.floor_frac, s);
     te();
   }
 
@@ -1383,6 +1398,7 @@ static void fill_defaults(spai_opts_t* o) {
   o->jacobi = 0;
   o->explicit_residual = 1;
   o->drop_score = 0;
+  o->floor_frac = 0.5;
 }
 
 template <typename T>
@@ -1418,6 +1434,8 @@ static int check_common(int method, spai_cap_t cap, int max_iter, double tol,
   if (o.precision != SPAI_PREC_F64 && o.precision != SPAI_PREC_MIXED)
     return fail(SPAI_ERR_ARG, "unknown precision");
   if (!(o.drop_tol >= 0.0) || !(o.tie_eta >= 0.0)) return fail(SPAI_ERR_ARG, "bad drop_tol / tie_eta");
+  if (!(o.floor_frac >= 0.0) || !std::isfinite(o.floor_frac))
+    return fail(SPAI_ERR_ARG, "floor_frac must be finite and >= 0");
   if (o.jacobi != 0 && o.jacobi != 1) return fail(SPAI_ERR_ARG, "jacobi must be 0 or 1");
   if (o.explicit_residual != 0 && o.explicit_residual != 1)
     return fail(SPAI_ERR_ARG, "explicit_residual must be 0 or 1");

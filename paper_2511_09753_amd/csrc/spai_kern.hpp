@@ -57,6 +57,14 @@ struct DevState {
   unsigned long long* rec;
   int rec_i, rec_cap;
   int rec_next, rec_pad;          // the next iteration's record
+  // speculative floor of the global cap (magnitude keys, one matrix): the lean update
+  // writes the off-diagonal candidates of M (all of P, P^T) only where |x| >= floor and
+  // counts the others in below; the selection sets redo when its cut does not clear
+  // floor / (1 - eta) (or there is no cut while entries were left out), and the update
+  // and the selection then run again without floors.  0: no floor.
+  double floorM, floorP;
+  unsigned long long belowM, belowP;
+  int redo, saved_active;
 };
 constexpr int kRec = 6;
 
@@ -200,5 +208,11 @@ extern int g_grid_cols;   // persistent grid of the per-column kernels (multiple
 void launch_flip(int which, DevState* st, hipStream_t s);   // 0: curM, 1: curP
 // zero the drop record; the next iteration's record is `next`
 void launch_rec_clear(DevState* st, int next, hipStream_t s);
+// the second, floor-free pass of the update and the selection runs only where the first
+// pass's floors were too high: redo_begin masks the iteration unless st->redo (and clears
+// the floors), redo_end restores it; floor_next sets the next iteration's floors
+void launch_redo_begin(DevState* st, hipStream_t s);
+void launch_redo_end(DevState* st, hipStream_t s);
+void launch_floor_next(DevState* st, int doM, int doP, double frac, hipStream_t s);
 
 }  // namespace spai

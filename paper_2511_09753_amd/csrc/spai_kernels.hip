@@ -381,10 +381,46 @@ __global__ void k_rec_clear(DevState* st, int next) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->rec_i = -1;
     st->rec_next = next;
+    st->floorM = st->floorP = 0.0;     // a restarted or restored run starts without floors
+    st->belowM = st->belowP = 0;
+    st->redo = 0;
   }
 }
 void launch_rec_clear(DevState* st, int next, hipStream_t s) {
   hipLaunchKernelGGL(k_rec_clear, dim3(64), dim3(256), 0, s, st, next);
+}
+
+// the floor-free second pass: masked unless the first pass's floors were too high
+__global__ void k_redo_begin(DevState* st) {
+  st->saved_active = st->iter_active;
+  st->iter_active = st->iter_active && st->redo;
+  if (st->redo) {
+    st->floorM = st->floorP = 0.0;
+    st->belowM = st->belowP = 0;
+  }
+}
+__global__ void k_redo_end(DevState* st) { st->iter_active = st->saved_active; }
+// next iteration's floors: a fraction of this iteration's cuts (none without a cut)
+__global__ void k_floor_next(DevState* st, int doM, int doP, double frac) {
+  if (!st->iter_active) return;
+  if (doM) {
+    st->floorM = (st->rawM > 0.0 && isfinite(st->rawM)) ? frac * st->rawM : 0.0;
+    st->belowM = 0;
+  }
+  if (doP) {
+    st->floorP = (st->rawP > 0.0 && isfinite(st->rawP)) ? frac * st->rawP : 0.0;
+    st->belowP = 0;
+  }
+  st->redo = 0;
+}
+void launch_redo_begin(DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_redo_begin, dim3(1), dim3(1), 0, s, st);
+}
+void launch_redo_end(DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_redo_end, dim3(1), dim3(1), 0, s, st);
+}
+void launch_floor_next(DevState* st, int doM, int doP, double frac, hipStream_t s) {
+  hipLaunchKernelGGL(k_floor_next, dim3(1), dim3(1), 0, s, st, doM, doP, frac);
 }
 
 constexpr int kScanThreads = 256;
@@ -2104,6 +2140,10 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
       p.nbeg = M.beg[p.nl];
     }
   };
+  __shared__ unsigned below[2];                   // candidates left out below the floors
+  const double fM = st->floorM, fP = st->floorP;  // 0 unless a global cap set them
+  if (lane < 2) below[lane] = 0u;
+  __syncthreads();
   ColumnWalk w(A.n, blockIdx.x, gridDim.x);
   Pre cur, nxt;
   if (w.begin < w.end) {
@@ -2302,6 +2342,22 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
         keepP = valid && (double)pt != 0.0;
         keepPT = valid && (double)ptt != 0.0;
       }
+      // candidates below the floor are not written (the diagonal always is); they are
+      // counted, and the selection checks that its cut clears the floor
+      const bool wM = keepM && (k == (int)j || fabs((double)mt) >= fM);
+      const bool wP = keepP && fabs((double)pt) >= fP;
+      const bool wPT = keepPT && fabs((double)ptt) >= fP;
+      {
+        const unsigned bM = (unsigned)__popcll(__ballot(keepM && !wM));
+        const unsigned bP = (unsigned)__popcll(__ballot(keepP && !wP));
+        if (lane == 0 && (bM | bP)) {
+          below[0] += bM;
+          below[1] += bP;
+        }
+      }
+      keepM = wM;
+      keepP = wP;
+      keepPT = wPT;
       const unsigned long long bm = __ballot(keepM);
       const unsigned long long bp = __ballot(keepP);
       const unsigned long long bpt = __ballot(keepPT);
@@ -2348,6 +2404,11 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
     }
     bt_clear<2, 1>(cb, krow, klst, mul);
     __syncthreads();
+  }
+  __syncthreads();
+  if (lane == 0) {
+    if (below[0]) atomicAdd(&st->belowM, (unsigned long long)below[0]);
+    if (below[1]) atomicAdd(&st->belowP, (unsigned long long)below[1]);
   }
 }
 
@@ -2583,6 +2644,9 @@ __global__ __launch_bounds__(1024) void k_sel_find_exp(const unsigned long long*
     st->sel_done = 1;
     *thr = signed_keys ? -INFINITY : 0.0;
     thr[2] = *thr;
+    // candidates left out below a floor would have to be kept: run again without it
+    const bool isM = thr == &st->thrM;
+    if ((isM ? st->belowM : st->belowP) > 0) st->redo = 1;
     return;
   }
   st->sel_prefix = (unsigned long long)bin << 52;
@@ -2699,6 +2763,11 @@ __global__ __launch_bounds__(1024) void k_sel_find_buf(const unsigned long long*
     } else {                           // keep |x| > t (1 + eta)
       t = __longlong_as_double((long long)st->sel_prefix);
       *thr = t * (1.0 + eta);
+      // every candidate the cut keeps or counts in its tie band must have been written:
+      // t (1 - eta) must clear the floor under which candidates were left out
+      const bool isM = thr == &st->thrM;
+      const double fl = isM ? st->floorM : st->floorP;
+      if ((isM ? st->belowM : st->belowP) > 0 && t * (1.0 - eta) < fl) st->redo = 1;
     }
     thr[2] = t;                        // rawM / rawP, two doubles after thrM / thrP
     st->sel_done = 1;
@@ -3061,8 +3130,10 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
   const int ri = st->rec_i;
   if (lane == 0 && kind < 2 && st->rec && ri >= 0 && ri < st->rec_cap) {
     unsigned long long* r = st->rec + (int64_t)ri * kRec + 3 * kind;
+    // candidates: the ones written plus (once) those the update left out below a floor
+    const unsigned long long below = blockIdx.x == 0 ? (kind == 0 ? st->belowM : st->belowP) : 0;
     atomicAdd(&r[0], kept);
-    atomicAdd(&r[1], seen);
+    atomicAdd(&r[1], seen + below);
     atomicAdd(&r[2], band);
   }
 }

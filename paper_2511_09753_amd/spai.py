@@ -47,7 +47,8 @@ class OptsT(C.Structure):
     _fields_ = [("precision", C.c_int), ("symmetrize", C.c_int), ("drop_tol", C.c_double),
                 ("tie_eta", C.c_double), ("stream", C.c_void_p),
                 ("device_pool_limit", C.c_int64), ("profile", C.c_int), ("a_format", C.c_int),
-                ("jacobi", C.c_int), ("explicit_residual", C.c_int), ("drop_score", C.c_int)]
+                ("jacobi", C.c_int), ("explicit_residual", C.c_int), ("drop_score", C.c_int),
+                ("floor_frac", C.c_double)]
 
 
 EXPORTS = [
@@ -195,6 +196,7 @@ class Options:
     jacobi: bool = False        # Pi = D_A^{-1}-weighted variants (Algorithms 5, 7, 8)
     explicit_residual: bool = True   # False: the update formulas, no dropping (Section 6.2)
     drop_score: bool = False    # global cap of M by the heuristic score of Appendix A
+    floor_frac: float = 0.5     # candidates below this fraction of the last cut are not written
 
     def c(self):
         o = OptsT()
@@ -210,6 +212,7 @@ class Options:
         o.jacobi = 1 if self.jacobi else 0
         o.explicit_residual = 1 if self.explicit_residual else 0
         o.drop_score = 1 if self.drop_score else 0
+        o.floor_frac = float(self.floor_frac)
         return o
 
 

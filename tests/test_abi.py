@@ -104,6 +104,13 @@ def test_score_drop_needs_global_cap_and_symmetrize(S):
                                   options=S.Options(drop_score=True, symmetrize=False)))
 
 
+def test_floor_frac_must_be_finite_and_nonnegative(S):
+    D = sp.identity(4, format="csr") * 2.0
+    for bad in (-0.5, float("nan"), float("inf")):
+        _expect(S, -1, lambda: S.SPAI(D, "lomr", "global", 8, False,
+                                      options=S.Options(floor_frac=bad)))
+
+
 def test_oracle_and_product_path_are_separate():
     """The oracle imports nothing from the package and the package nothing from the
     oracle; bench.py uses the oracle only in its cpu_baseline leg (and the worker

@@ -262,6 +262,33 @@ def test_mixed_steps_keep_the_oracle_pattern_up_to_the_cut(case):
     print(case, "entries differing at the cut over", iters, "steps:", diffs)
 
 
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+@pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
+def test_candidate_floor_changes_nothing_but_traffic(method, precision):
+    """Under a global cap the update writes only candidates above floor_frac times the
+    last cut.  No floor (0), the default (0.5) and a floor four times the last cut -- which
+    every iteration fails, so the update and the selection run a second time without it
+    -- give the same residual history, iterate and drop record bit for bit, and the
+    FP64 run matches the oracle."""
+    S = _spai()
+    A = W.lognormal3d(12, 41)
+    runs = []
+    for frac in (0.0, 0.5, 4.0):
+        h = S.SPAI(A, method, "global", 2.0, True, max_iter=12,
+                   options=S.Options(precision=precision, floor_frac=frac))
+        _, hist, _ = h.iterate(12)
+        runs.append((hist, h.get(), history_array(h)))
+        h.close()
+    for hist, M, rec in runs[1:]:
+        assert np.array_equal(hist, runs[0][0])
+        assert (M != runs[0][1]).nnz == 0
+        assert np.array_equal(rec, runs[0][2])
+    if precision == "f64":
+        ref = getattr(O, method)(A, oracle_rule(A, "global", 2.0, True), 12)
+        assert rel_err(runs[1][0], ref.resid[1:]) <= TOL_F64
+        assert np.array_equal(runs[1][2], history_from_oracle(ref))
+
+
 def test_set_state_rejects_a_corrupted_list_and_leaves_the_handle():
     """A state whose second list (P) is corrupted -- rows out of order in a column, or a
     row out of range -- is refused, and the handle continues exactly as an untouched one."""
