@@ -84,8 +84,8 @@ def phase_kernels(tiles, ell):
     out = dict(PHASE_KERNEL)
     if ell:
         out["resid"] = "k_resid_lean"
-    if tiles is None:                 # the defaults: lean tiers with A in ELL (rows <= 8)
-        tiles = {"dots": (0, 0, 1 if ell else 0), "update": (0, 0, 1 if ell == 8 else 0)}
+    if tiles is None:                 # the defaults: lean tiers with A in ELL
+        tiles = {"dots": (0, 0, 1 if ell else 0), "update": (0, 0, 1 if ell else 0)}
     if tiles["dots"][2] == 1:
         out["dots"] = "k_dots_lean"
     if tiles["update"][2] == 1:

@@ -288,8 +288,8 @@ int spai_autotune(spai_handle_t* h, int warm_iters, int reps, int* chosen, doubl
  *   two >= 512 (>= 128 for the residual when A is held in ELL, and for the dots' lean
  *   tier); the residual and dots L a power of
  *   two >= 32, the update L >= 32; the dots' and the update's variant 0 (compiler's
- *   registers), 5 (capped at five waves per SIMD) or 1 (the lean tier: A in ELL, and for
- *   the update rows of at most 8 entries; its H may be >= 128); each tile within 64 KB
+ *   registers), 5 (capped at five waves per SIMD) or 1 (the lean tier: A in ELL; the
+ *   update's H may then be >= 128); each tile within 64 KB
  *   of LDS.  Anything else returns
  *   SPAI_ERR_ARG and leaves the tiles unchanged.  Results do not depend on the tiles;
  *   a batched handle recaptures its graph.  Synchronises the stream.

@@ -515,7 +515,7 @@ struct Engine : EngineBase {
       // sets take any power-of-two H (the tiles the tuner picks on the 96^3 stencil)
       tRs = Tile{128, 1024};
       tDs = Tile{256, 1024, 0, 1};
-      if (sh == 3) tUs = Tile{128, 256, 0, 1};   // the update's lean tier: rows of <= 8
+      tUs = Tile{128, 256, 0, 1};                // the update's lean tier
     }
     // ---- locality order of the rows (for the PCG products)
     {
@@ -884,7 +884,7 @@ struct Engine : EngineBase {
     // d.waves 1 selects the lean dots tier (A in ELL), whose ordered key set takes any
     // power-of-two H >= 128
     const bool dlean = d.waves == 1;
-    const bool ulean = u.waves == 1 && A.eshift == 3;   // the update's lean tier
+    const bool ulean = u.waves == 1 && ell;              // the update's lean tier
     const bool ok = pow2(r.L) && r.L >= 32 && pow2(d.L) && d.L >= 32 && u.L >= 32 &&
                     pow2(r.H) && r.H >= (ell ? 128 : 512) && pow2(d.H) &&
                     d.H >= (dlean ? 128 : 512) &&
@@ -997,7 +997,7 @@ struct Engine : EngineBase {
         for (int waves : {0, 5, 1}) {        // 5: the register-capped tier, 1: the lean tier
           Tile t{L, H};
           t.waves = waves;
-          if (waves == 1 ? (A.eshift != 3 || L != 128) : (H < 512 || L < 256)) continue;
+          if (waves == 1 ? (A.eshift < 0 || L != 128) : (H < 512 || L < 256)) continue;
           if (update_tile_bytes(t) > kMaxLds) continue;
           const double ms = timed([&] {
             launch_update<T>(A, M, R, P, PT, md, off, total, kcol, tM, tP, big[2], seg, st, t,

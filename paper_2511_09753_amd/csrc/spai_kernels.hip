@@ -2061,19 +2061,20 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
                         DG);
 }
 
-// Lean resident tier of the update (A in ELL with rows of at most 8 entries).  Same
+// Lean resident tier of the update (A in ELL).  Same
 // candidates and the same arithmetic as update_body, built without searches: every row
 // of the column's own lists (m_j, r_j, p_j, p^T_j, up to 192 entries, three per lane) and
-// of its neighbour columns m_l, l in N(j) (one entry per lane each), goes into the
-// ordered key set; the keys are sorted by row and a byte table maps a row's hash to its
+// of its neighbour columns m_l, l in N(j) (up to 256 entries together, laid out flat over
+// the lanes), goes into the ordered key set; the keys are sorted by row and a byte table maps a row's hash to its
 // rank; the own lists' values are then scattered to dense per-rank arrays and the
 // neighbour products a_jl m_l(k) added to a per-rank sum neighbour by neighbour in
 // ascending l (one round per neighbour, so each sum runs in the order update_body uses),
 // and each lane forms the candidates of its keys.
 constexpr int kUpdLeanKeys = 128;
 constexpr int kUpdLeanOwn = 192;   // own-list entries (whatever the tile's L)
+constexpr int kUpdLeanNbr = 256;   // entries of the neighbour columns together
 
-template <typename T>
+template <typename T, bool FLAT>
 __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) void k_update_lean(
     Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp, Pair<T> PTp, UpdMode md, const int64_t* off,
     const int64_t* total, const int32_t* kcol, double* tM, double* tP, BigList big, Seg seg,
@@ -2103,6 +2104,7 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
   const int64_t ntot = *total;
   const bool overflow = ntot > Mo.cap || (md.doP && (ntot > Po.cap || ntot > PTo.cap));
   const T* eval = sizeof(T) == 4 ? (const T*)A.eval32 : (const T*)A.eval;
+  const int W = 1 << A.eshift;                   // ELL width of A (at most 64)
   // A column's descriptors are loaded one column ahead, one value per lane (lanes 0-3
   // the lengths of m_j, r_j, p_j, p^T_j, lanes 4-7 their starts, lanes 8 and 9 the
   // column's candidate range off[j] .. off[j+1]) together with row j of A (lanes 0-7:
@@ -2129,9 +2131,9 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
     } else if (lane == 9) {
       p.d = jj + 1 < A.n ? off[jj + 1] : ntot;
     }
-    if (needRT && lane < 8) {
-      p.nl = A.ecol[(jj << 3) + lane];
-      p.av = eval[(jj << 3) + lane];
+    if (needRT && lane < W) {
+      p.nl = A.ecol[(jj << A.eshift) + lane];
+      p.av = eval[(jj << A.eshift) + lane];
     }
   };
   auto pre2 = [&](Pre& p) {
@@ -2191,25 +2193,62 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
     }
     const unsigned long long nm = __ballot(nl >= 0);
     const int deg = __popcll(nm);                 // entries first, so lanes 0 .. deg-1
-    // neighbour entries: entry `lane` of each neighbour column m_l.  The loads are
-    // unconditional (entry 0 of the list where a lane has none; bit t of nvalid says
-    // which are real), so no conversion or select waits on one of them before all
-    // eight are in flight.
-    int nrow[8];
-    T nval[8];
-    unsigned nvalid = 0u;
+    // neighbour entries.  FLAT (A's ELL rows wider than 8): laid out flat over the lanes,
+    // entry e of the concatenated neighbour columns m_l (in row j's order) in lane e mod
+    // 64, slot e / 64, its neighbour t found by a binary search over the lanes' exclusive
+    // prefix of the lengths.  Else (rows of at most 8): entry `lane` of each of the eight
+    // neighbour columns in slot t.  The loads are unconditional (entry 0 of m where a
+    // slot has none; ntag is -1 there), so no conversion or select waits on one before
+    // all are in flight.
+    constexpr int NS = FLAT ? kUpdLeanNbr / SPAI_WAVE : 8;   // neighbour slots per lane
+    int nrow[NS], ntag[FLAT ? NS : 1];            // FLAT: slot k's neighbour, or -1
+    T nval[NS];
+    unsigned nvalid = 0u;                         // else: bit t set where slot t is real
+    bool nfits;
+    auto slot_nbr = [&](int k) -> int {           // the neighbour of slot k, or -1
+      if constexpr (FLAT) return ntag[k];
+      else return (nvalid >> k) & 1u ? k : -1;
+    };
+    if constexpr (FLAT) {
+      const int nincl = wave_incl_scan(nlen);     // lengths are 0 on lanes >= deg
+      const int npre = nincl - nlen;
+      const int ne = __builtin_amdgcn_readlane(nincl, SPAI_WAVE - 1);
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int len_t = __shfl(nlen, t, SPAI_WAVE);
-      const int64_t beg_t = __shfl(nbeg, t, SPAI_WAVE);
-      const bool v = t < deg && lane < len_t;
-      const int64_t q = v ? beg_t + lane : 0;
-      nrow[t] = M.idx[q];
-      nval[t] = M.val[q];
-      nvalid |= (v ? 1u : 0u) << t;
+      for (int k = 0; k < NS; ++k) {
+        const int e = lane + k * SPAI_WAVE;
+        int t = 0;                                // the last neighbour starting at or before e
+#pragma unroll
+        for (int step = SPAI_WAVE / 2; step >= 1; step >>= 1) {
+          const int c = t + step;
+          const int pc = __shfl(npre, c < deg ? c : 0, SPAI_WAVE);   // every lane shuffles
+          if (c < deg && pc <= e) t = c;
+        }
+        const bool v = e < ne;
+        // both shuffles on every lane (a shuffle from a lane left out of a branch is
+        // undefined), then the select
+        const int64_t bt = __shfl(nbeg, t, SPAI_WAVE);
+        const int pt = __shfl(npre, t, SPAI_WAVE);
+        const int64_t q = v ? bt + (e - pt) : 0;
+        nrow[k] = M.idx[q];
+        nval[k] = M.val[q];
+        ntag[k] = v ? t : -1;
+      }
+      nfits = ne <= kUpdLeanNbr;
+    } else {
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const int len_t = __shfl(nlen, t, SPAI_WAVE);
+        const int64_t beg_t = __shfl(nbeg, t, SPAI_WAVE);
+        const bool v = t < deg && lane < len_t;
+        const int64_t q = v ? beg_t + lane : 0;
+        nrow[t] = M.idx[q];
+        nval[t] = M.val[q];
+        nvalid |= (v ? 1u : 0u) << t;
+      }
+      nfits = wave_max_int(nlen) <= SPAI_WAVE;
     }
     if (jn < w.end) pre2(nxt);
-    if (!fits || wave_max_int(nlen) > SPAI_WAVE) {
+    if (!fits || !nfits) {
       defer_column(0, big, st, j);
       continue;
     }
@@ -2228,15 +2267,12 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
 #pragma unroll
     for (int k = 0; k < kUpdLeanOwn / SPAI_WAVE; ++k) okey[k] = (ovalid >> k) & 1u ? orow[k] : -1;
     bool ok = oh_insert_batch<kUpdLeanOwn / SPAI_WAVE>(kt, ksh, kend, okey);
-    {
-      int n0[4], n1[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        n0[t] = (nvalid >> t) & 1u ? nrow[t] : -1;
-        n1[t] = (nvalid >> (t + 4)) & 1u ? nrow[t + 4] : -1;
-      }
-      ok = oh_insert_batch<4>(kt, ksh, kend, n0) && ok;
-      ok = oh_insert_batch<4>(kt, ksh, kend, n1) && ok;
+    for (int k0 = 0; k0 < NS; k0 += 4) {           // batches of four keys per lane
+      int nk[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) nk[k] = slot_nbr(k0 + k) >= 0 ? nrow[k0 + k] : -1;
+      ok = oh_insert_batch<4>(kt, ksh, kend, nk) && ok;
     }
     {
       const int kd[1] = {lane == 0 ? (int)j : -1};
@@ -2284,15 +2320,13 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
     // neighbour products in ascending l: one round per neighbour, distinct ranks inside
     for (int t = 0; t < deg; ++t) {
       const double a_t = __shfl(av, t, SPAI_WAVE);
-      int rr = -1;
-      T vv = (T)0;
+      // the entries of m_t: distinct rows, so distinct ranks (a lane's slots too)
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q == t && ((nvalid >> q) & 1u)) { rr = nrow[q]; vv = nval[q]; }
-      if (rr >= 0) {
-        const int rk = (int)cb[bt_cell(rr, mul)] - 1;
-        rta[rk] += a_t * (double)vv;
-      }
+      for (int k = 0; k < NS; ++k)
+        if (slot_nbr(k) == t) {
+          const int rk = (int)cb[bt_cell(nrow[k], mul)] - 1;
+          rta[rk] += a_t * (double)nval[k];
+        }
     }
     __syncthreads();
     // the matrix's step sizes, read only now: a load at the top of the column would
@@ -2437,11 +2471,17 @@ void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, Up
                    Tile huge, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
-  if (small.waves == 1 && A.eshift == 3) {
+  if (small.waves == 1 && A.eshift >= 0) {
     const size_t lds = update_lean_lds<T>() + (size_t)std::max(small.H + kOhOver, kUpdLeanKeys) * 4;
-    hipLaunchKernelGGL((k_update_lean<T>), dim3(resident_grid(k_update_lean<T>, lds)),
-                       dim3(SPAI_WAVE), lds, s, A, M, R, P, PT, md, off, total, kcol, tM, tP, big,
-                       seg, st, small.L, small.H);
+    if (A.eshift > 3)        // ELL rows wider than 8: neighbour entries laid out flat
+      hipLaunchKernelGGL((k_update_lean<T, true>), dim3(resident_grid(k_update_lean<T, true>, lds)),
+                         dim3(SPAI_WAVE), lds, s, A, M, R, P, PT, md, off, total, kcol, tM, tP,
+                         big, seg, st, small.L, small.H);
+    else
+      hipLaunchKernelGGL((k_update_lean<T, false>),
+                         dim3(resident_grid(k_update_lean<T, false>, lds)), dim3(SPAI_WAVE), lds,
+                         s, A, M, R, P, PT, md, off, total, kcol, tM, tP, big, seg, st, small.L,
+                         small.H);
   } else if (small.waves == 5)
     hipLaunchKernelGGL((k_update_w5<T>),
                        dim3(resident_grid(k_update_w5<T>, update_lds(small, true))),
