@@ -1183,7 +1183,7 @@ struct Engine : EngineBase {
       if (floors) {
         launch_redo_begin(st, s);
         launch_update<T>(A, M, R, P, PT, md, off, total, kcol, tM, tP, big[2], seg, st, tUs, tUl,
-                         tUh, s);
+                         tUh, s, true);
         if (md.doM)
           launch_global_select<T>(M, 1, m_global, opts.tie_eta, 0, selhist, selbuf, n, st, s);
         if (md.doP)

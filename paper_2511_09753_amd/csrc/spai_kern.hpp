@@ -171,7 +171,7 @@ template <typename T>
 void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, UpdMode md,
                    const int64_t* off, const int64_t* total, const int32_t* kcol, double* tM,
                    double* tP, BigList big, const Seg& seg, DevState* st, Tile small,
-                   Tile large, Tile huge, hipStream_t s);
+                   Tile large, Tile huge, hipStream_t s, bool second = false);
 // bytes of one workgroup's working set for a tile (the huge tier's scratch slice)
 size_t resid_tile_bytes(Tile t, bool ell);
 size_t dots_tile_bytes(Tile t, bool ell);

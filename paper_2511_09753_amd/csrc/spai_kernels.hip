@@ -2074,7 +2074,9 @@ constexpr int kUpdLeanKeys = 128;
 constexpr int kUpdLeanOwn = 192;   // own-list entries (whatever the tile's L)
 constexpr int kUpdLeanNbr = 256;   // entries of the neighbour columns together
 
-template <typename T, bool FLAT>
+// SECOND: the same kernel under another name for the floor-free second pass (masked
+// unless needed), so that profiles keep the two apart.
+template <typename T, bool FLAT, bool SECOND>
 __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) void k_update_lean(
     Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp, Pair<T> PTp, UpdMode md, const int64_t* off,
     const int64_t* total, const int32_t* kcol, double* tM, double* tP, BigList big, Seg seg,
@@ -2468,20 +2470,18 @@ template <typename T>
 void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, UpdMode md,
                    const int64_t* off, const int64_t* total, const int32_t* kcol, double* tM,
                    double* tP, BigList big, const Seg& seg, DevState* st, Tile small, Tile large,
-                   Tile huge, hipStream_t s) {
+                   Tile huge, hipStream_t s, bool second) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
   if (small.waves == 1 && A.eshift >= 0) {
     const size_t lds = update_lean_lds<T>() + (size_t)std::max(small.H + kOhOver, kUpdLeanKeys) * 4;
-    if (A.eshift > 3)        // ELL rows wider than 8: neighbour entries laid out flat
-      hipLaunchKernelGGL((k_update_lean<T, true>), dim3(resident_grid(k_update_lean<T, true>, lds)),
-                         dim3(SPAI_WAVE), lds, s, A, M, R, P, PT, md, off, total, kcol, tM, tP,
-                         big, seg, st, small.L, small.H);
-    else
-      hipLaunchKernelGGL((k_update_lean<T, false>),
-                         dim3(resident_grid(k_update_lean<T, false>, lds)), dim3(SPAI_WAVE), lds,
-                         s, A, M, R, P, PT, md, off, total, kcol, tM, tP, big, seg, st, small.L,
-                         small.H);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(SPAI_WAVE), lds, s, A, M, R,
+                         P, PT, md, off, total, kcol, tM, tP, big, seg, st, small.L, small.H);
+    };
+    // ELL rows wider than 8: neighbour entries laid out flat
+    if (A.eshift > 3) second ? go(k_update_lean<T, true, true>) : go(k_update_lean<T, true, false>);
+    else second ? go(k_update_lean<T, false, true>) : go(k_update_lean<T, false, false>);
   } else if (small.waves == 5)
     hipLaunchKernelGGL((k_update_w5<T>),
                        dim3(resident_grid(k_update_w5<T>, update_lds(small, true))),
@@ -3356,7 +3356,7 @@ void launch_flip(int which, DevState* st, hipStream_t s) {
   template void launch_update<T>(const Csr&, Pair<T>, Cols<T>, Pair<T>, Pair<T>, UpdMode,         \
                                  const int64_t*, const int64_t*, const int32_t*, double*,         \
                                  double*, BigList, const Seg&, DevState*, Tile, Tile, Tile,       \
-                                 hipStream_t);                                                    \
+                                 hipStream_t, bool);                                              \
   template void launch_global_select<T>(Pair<T>, int, int64_t, double, int, unsigned long long*,  \
                                         unsigned long long*, int64_t, DevState*, hipStream_t,     \
                                         const double*);                                           \
