@@ -2204,19 +2204,14 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
     // neighbour columns in slot t.  The loads are unconditional (entry 0 of m where a
     // slot has none; ntag is -1 there), so no conversion or select waits on one before
     // all are in flight.
-    constexpr int NS = FLAT ? kUpdLeanNbr / SPAI_WAVE : 8;   // neighbour slots per lane
-    int nrow[NS], ntag[FLAT ? NS : 1];            // FLAT: slot k's neighbour, or -1
+    constexpr int NS = kUpdLeanNbr / SPAI_WAVE;   // neighbour slots per lane
+    int nrow[NS], ntag[NS];                       // ntag: slot k's neighbour, or -1
     T nval[NS];
-    unsigned nvalid = 0u;                         // else: bit t set where slot t is real
-    bool nfits;
-    auto slot_nbr = [&](int k) -> int {           // the neighbour of slot k, or -1
-      if constexpr (FLAT) return ntag[k];
-      else return (nvalid >> k) & 1u ? k : -1;
-    };
-    if constexpr (FLAT) {
+    int ne;                                       // entries of all neighbour columns
+    if constexpr (FLAT) {                         // up to 64 neighbours: binary search
       const int nincl = wave_incl_scan(nlen);     // lengths are 0 on lanes >= deg
       const int npre = nincl - nlen;
-      const int ne = __builtin_amdgcn_readlane(nincl, SPAI_WAVE - 1);
+      ne = __builtin_amdgcn_readlane(nincl, SPAI_WAVE - 1);
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
         const int e = lane + k * SPAI_WAVE;
@@ -2237,20 +2232,35 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
         nval[k] = M.val[q];
         ntag[k] = v ? t : -1;
       }
-      nfits = ne <= kUpdLeanNbr;
-    } else {
+    } else {                                      // at most 8 neighbours: scalar prefix sums
+      int pre[8];
+      int acc = 0;
 #pragma unroll
-      for (int t = 0; t < NS; ++t) {
-        const int len_t = __shfl(nlen, t, SPAI_WAVE);
-        const int64_t beg_t = __shfl(nbeg, t, SPAI_WAVE);
-        const bool v = t < deg && lane < len_t;
-        const int64_t q = v ? beg_t + lane : 0;
-        nrow[t] = M.idx[q];
-        nval[t] = M.val[q];
-        nvalid |= (v ? 1u : 0u) << t;
+      for (int c = 0; c < 8; ++c) {
+        pre[c] = acc;
+        acc += __builtin_amdgcn_readlane(nlen, c);
       }
-      nfits = wave_max_int(nlen) <= SPAI_WAVE;
+      ne = acc;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const int e = lane + k * SPAI_WAVE;
+        int t = 0, pt = 0;                        // the last neighbour starting at or before e
+#pragma unroll
+        for (int c = 1; c < 8; ++c)
+          if (c < deg && pre[c] <= e) {
+            t = c;
+            pt = pre[c];
+          }
+        const bool v = e < ne;
+        const int64_t bt = __shfl(nbeg, t, SPAI_WAVE);   // on every lane
+        const int64_t q = v ? bt + (e - pt) : 0;
+        nrow[k] = M.idx[q];
+        nval[k] = M.val[q];
+        ntag[k] = v ? t : -1;
+      }
     }
+    const bool nfits = ne <= kUpdLeanNbr;
+    auto slot_nbr = [&](int k) -> int { return ntag[k]; };   // the neighbour of slot k, or -1
     if (jn < w.end) pre2(nxt);
     if (!fits || !nfits) {
       defer_column(0, big, st, j);
