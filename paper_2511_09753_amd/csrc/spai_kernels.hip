@@ -1293,48 +1293,73 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
     __syncthreads();
     const int* keys = (const int*)kt;
     double d[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int t0 = 0; t0 < nu; t0 += SPAI_WAVE) {
-      const int t = t0 + lane;
-      if (t < nu) {
-        const int u = keys[t];
-        const int64_t q0 = (int64_t)u << A.eshift;
-        double ar = 0.0, ap = 0.0, diag = 0.0;
-        for (int c = 0; c < W; c += 8) {
-          int cols[8];
-          T vals[8];
-          ell_chunk<T>(A, q0 + c, cols, vals);
+    // KP keys per lane per pass (t, t + 64, ...; two on the float path, whose registers
+    // allow it), all their rows of A loaded before any is used; each key's sum runs over
+    // its row as with one key per pass and the partials take the keys in the same order
+    constexpr int KP = sizeof(T) == 4 ? 2 : 1;
+    for (int t0 = 0; t0 < nu; t0 += KP * SPAI_WAVE) {
+      int uk[KP];
+      bool live[KP], has[KP];
+      double ar[KP], ap[KP], dg[KP];
+#pragma unroll
+      for (int h = 0; h < KP; ++h) {
+        ar[h] = 0.0;
+        ap[h] = 0.0;
+        dg[h] = 0.0;
+        const int t = t0 + h * SPAI_WAVE + lane;
+        uk[h] = t < nu ? keys[t] : -1;
+        live[h] = uk[h] >= 0;
+        has[h] = live[h];
+      }
+      for (int c = 0; c < W; c += 8) {
+        int cols[KP][8];
+        T vals[KP][8];
+#pragma unroll
+        for (int h = 0; h < KP; ++h)               // a lane without a key reads row 0
+          ell_chunk<T>(A, ((int64_t)(live[h] ? uk[h] : 0) << A.eshift) + c, cols[h], vals[h]);
+#pragma unroll
+        for (int h = 0; h < KP; ++h) {
+          if (!live[h]) continue;
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
             bool h0, h1;
             T x0, x1;
-            bt_find<T>(cell, mul, ent, lr, cols[k], h0, x0, h1, x1);
-            const double av = (double)vals[k];
-            ar = fma(av, (double)(h0 ? x0 : (T)0), ar);
-            ap = fma(av, (double)(h1 ? x1 : (T)0), ap);
-            if (weighted && cols[k] == u) diag = av;
+            bt_find<T>(cell, mul, ent, lr, cols[h][k], h0, x0, h1, x1);
+            const double av = (double)vals[h][k];
+            ar[h] = fma(av, (double)(h0 ? x0 : (T)0), ar[h]);
+            ap[h] = fma(av, (double)(h1 ? x1 : (T)0), ap[h]);
+            if (weighted && cols[h][k] == uk[h]) dg[h] = av;
           }
-          if (cols[7] < 0) break;
+          if (cols[h][7] < 0) live[h] = false;     // the row ended in this chunk
         }
+        bool any = false;
+#pragma unroll
+        for (int h = 0; h < KP; ++h) any = any || live[h];
+        if (!any) break;
+      }
+#pragma unroll
+      for (int h = 0; h < KP; ++h) {
+        if (!has[h]) continue;
         double ru, pu;                 // u's own entries in r_j and p_j
         {
           bool h0, h1;
           T x0, x1;
-          bt_find<T>(cell, mul, ent, lr, u, h0, x0, h1, x1);
+          bt_find<T>(cell, mul, ent, lr, uk[h], h0, x0, h1, x1);
           ru = h0 ? (double)x0 : 0.0;
           pu = h1 ? (double)x1 : 0.0;
         }
-        d[0] += ru * ar;
-        d[3] += ru * ap;
-        d[5] += pu * ap;
+        d[0] += ru * ar[h];
+        d[3] += ru * ap[h];
+        d[5] += pu * ap[h];
         if (weighted) {            // (AZ, Pi AZ), (AZ, Pi AP), (AP, Pi AP), Pi = D_A^{-1}
-          const double pi = 1.0 / diag;
-          d[1] += ar * (pi * ar);
-          d[2] += ar * (pi * ap);
-          d[4] += ap * (pi * ap);
+          const double pi = 1.0 / dg[h];
+          d[1] += ar[h] * (pi * ar[h]);
+          d[2] += ar[h] * (pi * ap[h]);
+          d[4] += ap[h] * (pi * ap[h]);
         } else {
-          d[1] += ar * ar;
-          d[2] += ar * ap;
-          d[4] += ap * ap;
+          d[1] += ar[h] * ar[h];
+          d[2] += ar[h] * ap[h];
+          d[4] += ap[h] * ap[h];
         }
       }
     }
