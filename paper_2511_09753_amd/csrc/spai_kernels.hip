@@ -61,34 +61,37 @@ struct Carve {
 
 // ---- lean resident tier helpers (A in ELL) -----------------------------------------
 // Byte-table map of a column's lists (up to 128 entries, two lists with unique rows in
-// each): the entries sit in ent[] (list 0 first, then list 1) and a table of kBtCells
-// 16-bit cells maps the hash of a row to 1 + its position in list 0 (low byte) and in
-// list 1 (high byte), 0 meaning none.  The hash multiplier is picked per column among
-// kBtMuls odd constants so that no two rows of one list share a cell; a lookup is then
-// one cell read plus one entry read per list, with no probing and no branches.
+// each): a table of kBtCells 16-bit cells maps the hash of a row to 1 + its position in
+// list 0 (low byte) and in list 1 (high byte), 0 meaning none.  Each list's entries sit
+// in ent[] behind a sentinel entry (a row no lookup asks for, value 0), so the byte is
+// the entry's index in its list's block as it stands.  The hash multiplier is picked per
+// column among kBtMuls odd constants so that no two rows of one list share a cell; a
+// lookup is then one cell read plus one entry read per list, with no probing and no
+// branches.
 constexpr int kBtCells = 1024;
-constexpr int kBtShift = 22;          // 32 - log2(kBtCells)
 constexpr int kBtMuls = 16;
+constexpr int kBtNone = -2;           // the sentinel's row (ELL padding asks for -1)
 
-// odd multipliers (a column retries with the next one while two of its rows share a cell)
+// odd 24-bit multipliers (a column retries with the next one while two of its rows
+// share a cell)
 __device__ __forceinline__ unsigned bt_mul(int a) {
   switch (a & 15) {
-    case 0: return 0x9E3779B1u;
-    case 1: return 0x85EBCA77u;
-    case 2: return 0xC2B2AE3Du;
-    case 3: return 0x27D4EB2Fu;
-    case 4: return 0x165667B1u;
-    case 5: return 0xD3A2646Du;
-    case 6: return 0xFD7046C5u;
-    case 7: return 0xB55A4F09u;
-    case 8: return 0x7FEB352Du;
-    case 9: return 0x846CA68Bu;
-    case 10: return 0x2C1B3C6Du;
-    case 11: return 0x297A2D39u;
-    case 12: return 0xA136AAADu;
-    case 13: return 0x9E6C63D1u;
-    case 14: return 0x1B873593u;
-    default: return 0xCC9E2D51u;
+    case 0: return 0x9E3779u;
+    case 1: return 0x85EBCBu;
+    case 2: return 0xC2B2AFu;
+    case 3: return 0x27D4EBu;
+    case 4: return 0x165667u;
+    case 5: return 0xD3A265u;
+    case 6: return 0xFD7047u;
+    case 7: return 0xB55A4Fu;
+    case 8: return 0x7FEB35u;
+    case 9: return 0x846CA7u;
+    case 10: return 0x2C1B3Du;
+    case 11: return 0x297A2Du;
+    case 12: return 0xA136ABu;
+    case 13: return 0x9E6C63u;
+    case 14: return 0x1B8735u;
+    default: return 0xCC9E2Du;
   }
 }
 
@@ -98,8 +101,27 @@ struct BtEnt {
   T val;
 };
 
+// multiplicative hash on 24-bit words: the top 10 of the low 24 bits of row * m, from
+// one full-rate 24-bit multiply.  A cluster of nearby rows (a column of a matrix with
+// local couplings) spreads over the cells almost like a linear map, so the first
+// multiplier seldom clashes.  Rows equal in their low 24 bits share a cell under every
+// multiplier; a column holding two such rows goes to the next tier.
+// (The multiply is written out: left to itself the compiler sees that only the low 24
+// bits of the operands matter, drops the 24-bit form and emits the quarter-rate 32-bit
+// multiply instead.)
 __device__ __forceinline__ unsigned bt_cell(int row, unsigned m) {
-  return ((unsigned)row * m) >> kBtShift;
+  unsigned p;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(p) : "v"(row), "v"(m));
+  return (p >> 14) & (unsigned)(kBtCells - 1);
+}
+
+// a value masked to zero in the iterate's type, then widened: the opaque copy keeps the
+// compiler from widening first and masking both halves of the double
+template <typename T>
+__device__ __forceinline__ double bt_masked(bool h, T x) {
+  T y = h ? x : (T)0;
+  if constexpr (sizeof(T) == 4) asm("" : "+v"(y));
+  return (double)y;
 }
 
 // Each lane holds up to K entries (row < 0: none), entry k of list lst[k] at position
@@ -137,19 +159,29 @@ __device__ __forceinline__ void bt_clear(unsigned char* cb, const int (&row)[K],
     if (row[k] >= 0) cb[S * bt_cell(row[k], m) + lst[k]] = 0;
 }
 
-// row w in list 0 (entries ent[0 .. n0)) and list 1 (ent[n0 ..)): hit flags and values
+// row w in list 0 (block e0: sentinel, then its entries) and list 1 (block e1): hit
+// flags and values (the value is 0 where the byte is 0: the sentinel's)
 template <typename T>
 __device__ __forceinline__ void bt_find(const unsigned short* cell, unsigned m,
-                                        const BtEnt<T>* ent, int n0, int w, bool& h0, T& x0,
-                                        bool& h1, T& x1) {
+                                        const BtEnt<T>* e0, const BtEnt<T>* e1, int w, bool& h0,
+                                        T& x0, bool& h1, T& x1) {
   const unsigned v = cell[bt_cell(w, m)];
-  const int e0 = (int)(v & 0xFFu) - 1, e1 = (int)(v >> 8) - 1;
-  const BtEnt<T> a = ent[max(e0, 0)];
-  const BtEnt<T> b = ent[n0 + max(e1, 0)];
-  h0 = e0 >= 0 && a.row == w;
-  h1 = e1 >= 0 && b.row == w;
+  const BtEnt<T> a = e0[v & 0xFFu];
+  const BtEnt<T> b = e1[v >> 8];
+  h0 = a.row == w;
+  h1 = b.row == w;
   x0 = a.val;
   x1 = b.val;
+}
+
+// the same for list 0 alone (its bytes only)
+template <typename T>
+__device__ __forceinline__ void bt_find1(const unsigned short* cell, unsigned m,
+                                         const BtEnt<T>* e0, int w, bool& h0, T& x0) {
+  const unsigned v = ((const unsigned char*)cell)[2 * bt_cell(w, m)];
+  const BtEnt<T> a = e0[v];
+  h0 = a.row == w;
+  x0 = a.val;
 }
 
 // the eight column indices of ELL row `row` from slot c (all -1 for row < 0)
@@ -833,15 +865,17 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
                                                           BigList big, DevState* st, int L,
                                                           int H) {
   if (!st->any_active) return;
+  // the map at fixed LDS addresses (their offsets fold into the reads), the key set behind
+  __shared__ __align__(16) unsigned short cell[kBtCells];
+  __shared__ __align__(16) BtEnt<T> ent[128 + 1];
   extern __shared__ char smem[];
   Carve cv(smem);
   const int Lc = min(L, 128);             // two list entries per lane
-  unsigned short* cell = cv.take16<unsigned short>(kBtCells);
-  BtEnt<T>* ent = cv.take16<BtEnt<T>>(Lc + 1);
   unsigned* kt = cv.take<unsigned>(max(H + kOhOver, 256));
   int* keys = (int*)kt;
   const int lane = lane_id();
   for (int i = lane; i < kBtCells / 2; i += SPAI_WAVE) ((unsigned*)cell)[i] = 0u;
+  if (lane == 0) ent[0] = BtEnt<T>{kBtNone, (T)0};    // list 0's sentinel
   __syncthreads();
   const Cols<T> M = Mp.now();
   const int64_t ntot = *total;
@@ -882,7 +916,7 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int e = lane + k * SPAI_WAVE;
-      if (e < lm) ent[e] = BtEnt<T>{row[k], val[k]};
+      if (e < lm) ent[e + 1] = BtEnt<T>{row[k], val[k]};
       else row[k] = -1;
     }
     for (int i = lane; i < kend; i += SPAI_WAVE) kt[i] = kOhEmpty;
@@ -940,11 +974,11 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
           ell_chunk<T>(A, q0 + c, cols, vals);
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
-            bool h0, h1;
-            T x0, x1;
-            bt_find<T>(cell, mul, ent, lm, cols[k], h0, x0, h1, x1);
+            bool h0;
+            T x0;
+            bt_find1<T>(cell, mul, ent, cols[k], h0, x0);
             // a masked product adds +-0 to a sum that is never -0: bitwise the skip
-            sum += (double)vals[k] * (double)(h0 ? x0 : (T)0);
+            sum += (double)vals[k] * bt_masked<T>(h0, x0);
             if (weighted && cols[k] == u) diag = (double)vals[k];
           }
           if (cols[7] < 0) break;
@@ -978,9 +1012,8 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
 }
 
 template <typename T>
-static size_t resid_lean_lds(Tile t) {
-  return (size_t)kBtCells * 2 + (size_t)(std::min(t.L, 128) + 1) * sizeof(BtEnt<T>) +
-         (size_t)std::max(t.H + kOhOver, 256) * 4 + 64;
+static size_t resid_lean_lds(Tile t) {   // dynamic part (the map is static)
+  return (size_t)std::max(t.H + kOhOver, 256) * 4 + 64;
 }
 
 static size_t resid_lds(Tile t, bool ell) {
@@ -1037,8 +1070,12 @@ void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const 
                      colnorm, weighted, colrz, big, st, 2, huge.L, huge.H);
 }
 
+// LDS of the lean tiers' static map (cells, entries with two sentinels, FP64 values)
+constexpr size_t kLeanMapBytes = (size_t)kBtCells * 2 + (size_t)130 * sizeof(BtEnt<double>);
+
 size_t resid_tile_bytes(Tile t, bool ell) {
-  return ell ? std::max(resid_lds(t, ell), resid_lean_lds<double>(t)) : resid_lds(t, ell);
+  return ell ? std::max(resid_lds(t, ell), kLeanMapBytes + resid_lean_lds<double>(t))
+             : resid_lds(t, ell);
 }
 
 // ============================================================================
@@ -1201,21 +1238,23 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
 // its slots read in order list the rows of A r_j and A p_j sorted by ohash, the order
 // every tier sums in.  Per row u, one pass over A's row gives (A r)_u, (A p)_u, r_u, p_u
 // (the diagonal entry's lookup) and a_uu, with the same arithmetic as dots_body.
-// Registers are capped for five waves per SIMD on the float path (no spills there).
+// Registers are capped for five waves per SIMD (no spills at that cap).
 template <typename T>
-__global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void k_dots_lean(Csr A, Cols<T> R, Pair<T> Pp, int useR,
+__global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) void k_dots_lean(Csr A, Cols<T> R, Pair<T> Pp, int useR,
                                                          int useP, int weighted,
                                                          double* colpart, BigList big,
                                                          DevState* st, int L, int H) {
   if (!st->any_active || !st->iter_active) return;
+  // the map at fixed LDS addresses (their offsets fold into the reads), the key set behind
+  __shared__ __align__(16) unsigned short cell[kBtCells];
+  __shared__ __align__(16) BtEnt<T> ent[128 + 2];   // two sentinels
   extern __shared__ char smem[];
   Carve cv(smem);
   const int Lc = min(L, 128);
-  unsigned short* cell = cv.take16<unsigned short>(kBtCells);
-  BtEnt<T>* ent = cv.take16<BtEnt<T>>(Lc + 1);
   unsigned* kt = cv.take<unsigned>(H + kOhOver);
   const int lane = lane_id();
   for (int i = lane; i < kBtCells / 2; i += SPAI_WAVE) ((unsigned*)cell)[i] = 0u;
+  if (lane == 0) ent[0] = BtEnt<T>{kBtNone, (T)0};    // list 0's sentinel
   __syncthreads();
   const Cols<T> P = Pp.now();
   const int W = 1 << A.eshift;
@@ -1255,9 +1294,11 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int e = lane + k * SPAI_WAVE;
-      if (e < le) ent[e] = BtEnt<T>{row[k], val[k]};
+      if (e < le) ent[e + 1 + (e >= lr)] = BtEnt<T>{row[k], val[k]};
       else row[k] = -1;
     }
+    if (lane == 0) ent[lr + 1] = BtEnt<T>{kBtNone, (T)0};   // list 1's sentinel
+    const BtEnt<T>* ent1 = ent + lr + 1;
     for (int i = lane; i < kend; i += SPAI_WAVE) kt[i] = kOhEmpty;
     const int a = bt_build<2>((unsigned char*)cell, row, lst, pos);
     if (a < 0) {
@@ -1324,10 +1365,10 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
           for (int k = 0; k < 8; ++k) {
             bool h0, h1;
             T x0, x1;
-            bt_find<T>(cell, mul, ent, lr, cols[h][k], h0, x0, h1, x1);
+            bt_find<T>(cell, mul, ent, ent1, cols[h][k], h0, x0, h1, x1);
             const double av = (double)vals[h][k];
-            ar[h] = fma(av, (double)(h0 ? x0 : (T)0), ar[h]);
-            ap[h] = fma(av, (double)(h1 ? x1 : (T)0), ap[h]);
+            ar[h] = fma(av, bt_masked<T>(h0, x0), ar[h]);
+            ap[h] = fma(av, bt_masked<T>(h1, x1), ap[h]);
             if (weighted && cols[h][k] == uk[h]) dg[h] = av;
           }
           if (cols[h][7] < 0) live[h] = false;     // the row ended in this chunk
@@ -1344,7 +1385,7 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
         {
           bool h0, h1;
           T x0, x1;
-          bt_find<T>(cell, mul, ent, lr, uk[h], h0, x0, h1, x1);
+          bt_find<T>(cell, mul, ent, ent1, uk[h], h0, x0, h1, x1);
           ru = h0 ? (double)x0 : 0.0;
           pu = h1 ? (double)x1 : 0.0;
         }
@@ -1374,9 +1415,8 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
 }
 
 template <typename T>
-static size_t dots_lean_lds(Tile t) {
-  return (size_t)kBtCells * 2 + (size_t)(std::min(t.L, 128) + 1) * sizeof(BtEnt<T>) +
-         (size_t)(t.H + kOhOver) * 4 + 64;
+static size_t dots_lean_lds(Tile t) {    // dynamic part (the map is static)
+  return (size_t)(t.H + kOhOver) * 4 + 64;
 }
 
 static size_t dots_lds(Tile t, bool ell) {
@@ -1411,7 +1451,7 @@ void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, int wei
 }
 
 size_t dots_tile_bytes(Tile t, bool ell) {
-  return (t.waves == 1 && ell) ? dots_lean_lds<double>(t) : dots_lds(t, ell);
+  return (t.waves == 1 && ell) ? kLeanMapBytes + dots_lean_lds<double>(t) : dots_lds(t, ell);
 }
 
 // ============================================================================
@@ -2109,11 +2149,13 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
     const int64_t* total, const int32_t* kcol, double* tM, double* tP, BigList big, Seg seg,
     DevState* st, int L, int H) {
   if (!st->any_active || !st->iter_active) return;
+  // the fixed-size arrays at fixed LDS addresses (their offsets fold into the accesses),
+  // the key set behind
+  __shared__ __align__(16) unsigned char cb[kBtCells];        // 1 + rank of a row's hash
+  __shared__ __align__(16) T dv[4 * kUpdLeanKeys];            // m, r, p, p^T by rank
+  __shared__ __align__(16) double rta[kUpdLeanKeys];          // sum_l a_jl m_l(k) by rank
   extern __shared__ char smem[];
   Carve cv(smem);
-  unsigned char* cb = cv.take16<unsigned char>(kBtCells);     // 1 + rank of a row's hash
-  T* dv = cv.take16<T>(4 * kUpdLeanKeys);                      // m, r, p, p^T by rank
-  double* rta = cv.take<double>(kUpdLeanKeys);                 // sum_l a_jl m_l(k) by rank
   unsigned* kt = cv.take<unsigned>(max(H + kOhOver, kUpdLeanKeys));
   int* keys = (int*)kt;
   const int lane = lane_id();
@@ -2485,9 +2527,9 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
   }
 }
 
-template <typename T>
+template <typename T>   // the lean update's static arrays
 static size_t update_lean_lds() {
-  return (size_t)kBtCells + (size_t)4 * kUpdLeanKeys * sizeof(T) + (size_t)kUpdLeanKeys * 8 + 64;
+  return (size_t)kBtCells + (size_t)4 * kUpdLeanKeys * sizeof(T) + (size_t)kUpdLeanKeys * 8;
 }
 
 static int update_deg(Tile t) { return t.DG ? t.DG : (t.L >= 2048 ? 256 : 64); }
@@ -2499,8 +2541,9 @@ static size_t update_lds(Tile t, bool) {
 }
 
 size_t update_tile_bytes(Tile t) {
-  return t.waves == 1 ? update_lean_lds<double>() + (size_t)std::max(t.H + kOhOver, kUpdLeanKeys) * 4
-                      : update_lds(t, false);
+  return t.waves == 1
+             ? update_lean_lds<double>() + (size_t)std::max(t.H + kOhOver, kUpdLeanKeys) * 4 + 64
+             : update_lds(t, false);
 }
 
 template <typename T>
@@ -2511,7 +2554,7 @@ void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, Up
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
   if (small.waves == 1 && A.eshift >= 0) {
-    const size_t lds = update_lean_lds<T>() + (size_t)std::max(small.H + kOhOver, kUpdLeanKeys) * 4;
+    const size_t lds = (size_t)std::max(small.H + kOhOver, kUpdLeanKeys) * 4 + 64;   // dynamic part
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(SPAI_WAVE), lds, s, A, M, R,
                          P, PT, md, off, total, kcol, tM, tP, big, seg, st, small.L, small.H);
