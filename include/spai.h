@@ -146,7 +146,7 @@ typedef struct {
                                selection run again without the floor.  The kept
                                sets, values and drop records are those without a
                                floor; only the candidate traffic changes.  >= 0,
-                               0 disables; default 0.5                            */
+                               0 disables; default 0.75                           */
 } spai_opts_t;
 
 /* Fill *opts with the defaults. */

@@ -1398,7 +1398,7 @@ static void fill_defaults(spai_opts_t* o) {
   o->jacobi = 0;
   o->explicit_residual = 1;
   o->drop_score = 0;
-  o->floor_frac = 0.5;
+  o->floor_frac = 0.75;
 }
 
 template <typename T>

@@ -196,7 +196,7 @@ class Options:
     jacobi: bool = False        # Pi = D_A^{-1}-weighted variants (Algorithms 5, 7, 8)
     explicit_residual: bool = True   # False: the update formulas, no dropping (Section 6.2)
     drop_score: bool = False    # global cap of M by the heuristic score of Appendix A
-    floor_frac: float = 0.5     # candidates below this fraction of the last cut are not written
+    floor_frac: float = 0.75    # candidates below this fraction of the last cut are not written
 
     def c(self):
         o = OptsT()

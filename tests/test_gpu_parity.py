@@ -266,14 +266,14 @@ def test_mixed_steps_keep_the_oracle_pattern_up_to_the_cut(case):
 @pytest.mark.parametrize("method", ["mr", "cg", "lomr"])
 def test_candidate_floor_changes_nothing_but_traffic(method, precision):
     """Under a global cap the update writes only candidates above floor_frac times the
-    last cut.  No floor (0), the default (0.5) and a floor four times the last cut -- which
+    last cut.  No floor (0), the default (0.75) and a floor four times the last cut -- which
     every iteration fails, so the update and the selection run a second time without it
     -- give the same residual history, iterate and drop record bit for bit, and the
     FP64 run matches the oracle."""
     S = _spai()
     A = W.lognormal3d(12, 41)
     runs = []
-    for frac in (0.0, 0.5, 4.0):
+    for frac in (0.0, 0.75, 4.0):
         h = S.SPAI(A, method, "global", 2.0, True, max_iter=12,
                    options=S.Options(precision=precision, floor_frac=frac))
         _, hist, _ = h.iterate(12)
