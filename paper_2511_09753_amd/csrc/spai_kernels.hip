@@ -3136,7 +3136,8 @@ void launch_score(const Csr& A, Pair<T> M, double* sc, double* sig, BigList big,
 // entry's place in its column is the column's running count (s_run, LDS) plus the
 // kept entries before it in the same column segment of the round.  It moves only
 // toward the column start, and a batch's entries are all loaded before any is written.
-template <typename T>
+// SC: the keys are the scores stored beside the candidates (score non-null).
+template <typename T, bool SC>
 __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int colcap, int sym,
                                                        int global, const double* tcol,
                                                        const double* gthr, double eta, int64_t n,
@@ -3156,27 +3157,41 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
     const double tl = (colcap && jl < n) ? tcol[jl] : 0.0;   // this lane's column threshold
     s_run[lane] = 0;
     __syncthreads();
-    for (int x0 = 0; x0 < g.T; x0 += SPAI_WAVE * kGUc) {
-      int col[kGUc], idx[kGUc];
-      T val[kGUc];
-      double tk[kGUc], sv[kGUc];
+    // A batch's entries are loaded before the stores of the batch before it go out: one
+    // counter tracks both loads and stores and completes in order, so the first use of
+    // a batch loaded after those stores would also wait for them to be written.  It is
+    // safe because entries only move toward their column's start: no store of a batch
+    // reaches a later batch's entries.
+    constexpr int NSV = SC ? kGUc : 1;               // score keys (none unless SC)
+    int col[kGUc], idx[kGUc], ncol[kGUc], nidx[kGUc];
+    T val[kGUc], nval[kGUc];
+    double sv[NSV], nsv[NSV];
+    auto load_batch = [&](int x0, int (&c_)[kGUc], int (&i_)[kGUc], T (&v_)[kGUc],
+                          double (&s_)[NSV]) {
 #pragma unroll
       for (int u = 0; u < kGUc; ++u) {
         const int x = x0 + u * SPAI_WAVE + lane;
         const int xc = min(x, g.T - 1);            // all lanes shuffle together
         const int c = group_col(g, xc);
         const int64_t src = group_src(g, c, xc);
-        col[u] = c;
-        idx[u] = -1;
-        val[u] = (T)0;
-        tk[u] = 0.0;
-        sv[u] = 0.0;
+        c_[u] = c;
+        i_[u] = -1;
+        v_[u] = (T)0;
+        if constexpr (SC) s_[u] = 0.0;
         if (x < g.T) {
-          idx[u] = X.idx[src];
-          val[u] = X.val[src];
-          if (score) sv[u] = score[src];
+          i_[u] = X.idx[src];
+          v_[u] = X.val[src];
+          if constexpr (SC) s_[u] = score[src];
         }
       }
+    };
+    if (g.T > 0) load_batch(0, col, idx, val, sv);
+    for (int x0 = 0; x0 < g.T; x0 += SPAI_WAVE * kGUc) {
+      const bool more = x0 + SPAI_WAVE * kGUc < g.T;   // wave-uniform
+      if (more) load_batch(x0 + SPAI_WAVE * kGUc, ncol, nidx, nval, nsv);
+      double tk[kGUc];
+#pragma unroll
+      for (int u = 0; u < kGUc; ++u) tk[u] = 0.0;
       if (need_tk) {
 #pragma unroll
         for (int u = 0; u < kGUc; ++u)
@@ -3200,7 +3215,8 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
           if (kind == 0 && k == j) {
             keep = true;
           } else if (global) {
-            const double key = score ? sv[u] : a;
+            double key = a;
+            if constexpr (SC) key = sv[u];
             keep = key > gt;
             // dropped within the tie band of the cut (a relative eta below it)
             band += (!keep && key >= graw - eta * fabs(graw)) ? 1ull : 0ull;
@@ -3230,6 +3246,15 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
         if (last) s_run[c] = base + before + (keep ? 1 : 0);
         __syncthreads();
       }
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < kGUc; ++u) {
+          col[u] = ncol[u];
+          idx[u] = nidx[u];
+          val[u] = nval[u];
+          if constexpr (SC) sv[u] = nsv[u];
+        }
+      }
     }
     if (jl < n) {
       X.len[jl] = s_run[lane];
@@ -3258,14 +3283,39 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
   }
 }
 
+// `per` workgroups per compute unit of the current device
+static int per_cu_grid(int per) {
+  static std::mutex mu;
+  static int cus = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cus <= 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0) {
+      (void)hipGetLastError();
+      cus = 0;
+      return g_grid_cols;
+    }
+  }
+  return per * cus;
+}
+
 template <typename T>
 void launch_compact(Pair<T> X, int kind, int colcap, int sym, int global, const double* tcol,
                     double eta, int64_t n, DevState* st, hipStream_t s, const double* score) {
   const double* gthr = kind == 0 ? &st->thrM : &st->thrP;
   const int ng = (int)std::min<int64_t>((n + 63) / 64, 1 << 30);
-  hipLaunchKernelGGL(k_compact<T>, dim3(std::min(ng, resident_grid(k_compact<T>, 0))),
-                     dim3(SPAI_WAVE), 0, s, X, kind, colcap, sym, global, tcol, gthr, eta, n, st,
-                     score);
+  if (score)
+    hipLaunchKernelGGL((k_compact<T, true>), dim3(std::min(ng, resident_grid(k_compact<T, true>, 0))),
+                       dim3(SPAI_WAVE), 0, s, X, kind, colcap, sym, global, tcol, gthr, eta, n, st,
+                       score);
+  else   // two workgroups per SIMD: more waves in flight made the pass slower at 96^3
+         // (0.52 ms at 8 per compute unit, 0.62 at 16, 0.66 at 4)
+    hipLaunchKernelGGL((k_compact<T, false>),
+                       dim3(std::min({ng, resident_grid(k_compact<T, false>, 0), per_cu_grid(8)})),
+                       dim3(SPAI_WAVE), 0, s, X, kind, colcap, sym, global, tcol, gthr, eta, n, st,
+                       score);
 }
 
 // ============================================================================
