@@ -1040,6 +1040,21 @@ static int resident_grid(K kernel, size_t lds, int threads = SPAI_WAVE) {
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) == hipSuccess &&
       per > 0 && cus > 0) {
+    // The query counts a workgroup's static and dynamic LDS but not the 512-byte granule
+    // the hardware allocates it in: with 8,528 bytes it reports 19 workgroups per compute
+    // unit where 18 fit, and the 19th starts only once another has finished (1.5x the
+    // time of a persistent kernel).  Cap by the rounded size.
+    hipFuncAttributes fa;
+    int lds_cu = 0;
+    if (hipFuncGetAttributes(&fa, (const void*)kernel) == hipSuccess &&
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+            hipSuccess &&
+        lds_cu > 0) {
+      const size_t need = (fa.sharedSizeBytes + lds + 511) / 512 * 512;
+      if (need > 0) per = std::max(1, std::min<int>(per, (int)((size_t)lds_cu / need)));
+    } else {
+      (void)hipGetLastError();
+    }
     grid = std::max(8, (per * cus) / 8 * 8);
   } else {
     (void)hipGetLastError();
@@ -2908,6 +2923,24 @@ __global__ void k_hist_clear(unsigned long long* hist, int nbins, const DevState
   for (int i = threadIdx.x; i < nbins; i += blockDim.x) hist[i] = 0;
 }
 
+// `per` workgroups per compute unit of the current device
+static int per_cu_grid(int per) {
+  static std::mutex mu;
+  static int cus = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cus <= 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0) {
+      (void)hipGetLastError();
+      cus = 0;
+      return g_grid_cols;
+    }
+  }
+  return per * cus;
+}
+
 template <typename T>
 void launch_global_select(Pair<T> X, int exclude_diag, int64_t m, double eta, int which,
                           unsigned long long* hist, unsigned long long* selbuf, int64_t n,
@@ -2916,6 +2949,9 @@ void launch_global_select(Pair<T> X, int exclude_diag, int64_t m, double eta, in
   const int sk = score ? 1 : 0;
   hipLaunchKernelGGL(k_sel_reset, dim3(1), dim3(1024), 0, s, hist, 8192, st);
   const int ng = (int)std::min<int64_t>((n + 63) / 64, 1 << 30);
+  // the magnitude passes run below full occupancy, as the compaction does: 4 four-wave
+  // histogram workgroups and 12 collecting waves per compute unit took 0.55 ms per
+  // iteration at 96^3 against 0.62 ms at the occupancy limit
   if (score)
     hipLaunchKernelGGL(
         (k_sel_hist_exp<T, true>),
@@ -2924,7 +2960,8 @@ void launch_global_select(Pair<T> X, int exclude_diag, int64_t m, double eta, in
   else
     hipLaunchKernelGGL(
         (k_sel_hist_exp<T, false>),
-        dim3(std::min((ng + 3) / 4, resident_grid(k_sel_hist_exp<T, false>, 0, 4 * SPAI_WAVE))),
+        dim3(std::min({(ng + 3) / 4, resident_grid(k_sel_hist_exp<T, false>, 0, 4 * SPAI_WAVE),
+                       per_cu_grid(4)})),
         dim3(4 * SPAI_WAVE), 0, s, X, score, exclude_diag, hist, n, st);
   hipLaunchKernelGGL(k_sel_find_exp, dim3(1), dim3(1024), 0, s, hist, exclude_diag, m, sk, thr,
                      st);
@@ -2934,7 +2971,8 @@ void launch_global_select(Pair<T> X, int exclude_diag, int64_t m, double eta, in
                        dim3(SPAI_WAVE), 0, s, X, score, exclude_diag, selbuf, n, st);
   else
     hipLaunchKernelGGL((k_sel_collect<T, false>),
-                       dim3(std::min(ng, resident_grid(k_sel_collect<T, false>, 0))),
+                       dim3(std::min({ng, resident_grid(k_sel_collect<T, false>, 0),
+                                      per_cu_grid(12)})),
                        dim3(SPAI_WAVE), 0, s, X, score, exclude_diag, selbuf, n, st);
   // float candidates widened to double have zero in the low 29 mantissa bits, so the
   // passes over bits 0..25 would each select bin 0: they stop after bits 26..38
@@ -3281,24 +3319,6 @@ __global__ __launch_bounds__(SPAI_WAVE) void k_compact(Pair<T> Xp, int kind, int
     atomicAdd(&r[1], seen + below);
     atomicAdd(&r[2], band);
   }
-}
-
-// `per` workgroups per compute unit of the current device
-static int per_cu_grid(int per) {
-  static std::mutex mu;
-  static int cus = 0;
-  std::lock_guard<std::mutex> lock(mu);
-  if (cus <= 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0) {
-      (void)hipGetLastError();
-      cus = 0;
-      return g_grid_cols;
-    }
-  }
-  return per * cus;
 }
 
 template <typename T>
