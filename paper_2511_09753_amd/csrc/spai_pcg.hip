@@ -244,7 +244,9 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
 // one 16-byte load per lane and one load instruction serves two rows (half the
 // address-unit work of k_spmm_wave per row).  A half's row entries are loaded 32 at a
 // time (one per lane of the half) and broadcast with readlane; the gathers of both
-// rows are issued in groups of eight before any is used, entries past a row's count
+// rows are issued in groups of four before any is used (groups of eight hold 100
+// registers, five waves per SIMD, and the 64-right-hand-side solve at 96^3 took 6%
+// longer than with four at six waves), entries past a row's count
 // repeating its last one so every load is in bounds.  Each row's sum runs over its
 // entries in stored order, and the dot terms are added in position order, so the rows
 // of Y and the dot partials are those of k_spmm_wave bit for bit.  Positions are
@@ -254,7 +256,7 @@ template <typename VT, int LAY>
 __global__ __launch_bounds__(kThreads) void k_spmm_pair(Mat A, const double* X, double* Y,
                                                         int dot, int nrhs, int c0,
                                                         const int32_t* order, double* part) {
-  constexpr int G = 8;
+  constexpr int G = 4;
   __shared__ double sh[kThreads];
   constexpr int WPB = kThreads / 64;
   const int lane = threadIdx.x & 63;
