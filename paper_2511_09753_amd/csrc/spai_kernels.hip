@@ -557,10 +557,44 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_chunks(const double* col
     lo = (int64_t)blockIdx.x * chunk;
     hi = lo + chunk < n ? lo + chunk : n;
   }
+  // up to kRedNd partials per column summed together: a column's partials are adjacent, and
+  // four columns' loads are in flight before any is added; each partial's sum takes the
+  // columns in the order of one pass per partial (the results are those of that pass)
+  constexpr int kRedNd = 8, kRedU = 4;
+  double acc[kRedNd];
+  const int nd0 = nd < kRedNd ? nd : kRedNd;
+#pragma unroll
+  for (int d = 0; d < kRedNd; ++d) acc[d] = 0.0;
+  {
+    int64_t j = lo + threadIdx.x;
+    for (; j + (kRedU - 1) * kRedThreads < hi; j += kRedU * kRedThreads) {
+      double v[kRedU][kRedNd];
+#pragma unroll
+      for (int u = 0; u < kRedU; ++u)
+#pragma unroll
+        for (int d = 0; d < kRedNd; ++d)
+          if (d < nd0) v[u][d] = colpart[(j + u * kRedThreads) * nd + d];
+#pragma unroll
+      for (int u = 0; u < kRedU; ++u)
+#pragma unroll
+        for (int d = 0; d < kRedNd; ++d)
+          if (d < nd0) acc[d] += v[u][d];
+    }
+    for (; j < hi; j += kRedThreads)
+#pragma unroll
+      for (int d = 0; d < kRedNd; ++d)
+        if (d < nd0) acc[d] += colpart[j * nd + d];
+  }
   for (int d = 0; d < nd; ++d) {
-    double acc = 0.0;
-    for (int64_t j = lo + threadIdx.x; j < hi; j += kRedThreads) acc += colpart[j * nd + d];
-    sh[threadIdx.x] = acc;
+    double a = 0.0;
+    if (d < kRedNd) {
+#pragma unroll
+      for (int e = 0; e < kRedNd; ++e)
+        if (e == d) a = acc[e];
+    } else {
+      for (int64_t j = lo + threadIdx.x; j < hi; j += kRedThreads) a += colpart[j * nd + d];
+    }
+    sh[threadIdx.x] = a;
     __syncthreads();
     for (int w = kRedThreads / 2; w > 0; w >>= 1) {
       if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];

@@ -524,8 +524,17 @@ __global__ __launch_bounds__(kThreads) void k_reduce_rows(const double* part, in
   __shared__ double sh[kThreads];
   const int r = blockIdx.x;
   const double* p = part + (int64_t)r * nblocks;
+  // eight loads in flight per thread, added in the order of the plain loop
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kThreads) s += p[b];
+  int b = threadIdx.x;
+  for (; b + 7 * kThreads < nblocks; b += 8 * kThreads) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[b + u * kThreads];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; b < nblocks; b += kThreads) s += p[b];
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
@@ -539,8 +548,17 @@ __global__ __launch_bounds__(kThreads) void k_reduce_parts(const double* part, i
                                                            int nrhs, double* out) {
   __shared__ double sh[kThreads];
   const int r = blockIdx.x;
+  // eight loads in flight per thread, added in the order of the plain loop
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kThreads) s += part[(int64_t)b * nrhs + r];
+  int b = threadIdx.x;
+  for (; b + 7 * kThreads < nblocks; b += 8 * kThreads) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + u * kThreads) * nrhs + r];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; b < nblocks; b += kThreads) s += part[(int64_t)b * nrhs + r];
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
