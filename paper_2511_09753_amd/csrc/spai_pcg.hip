@@ -518,12 +518,8 @@ __global__ __launch_bounds__(kThreads) void k_dot_rows(const double* Xa, const d
 }
 
 // one workgroup per right-hand side: fixed strided partial sums, then a fixed tree
-// out[r] = sum_b part[r * nblocks + b] in a fixed order (the products' transposed partials)
-__global__ __launch_bounds__(kThreads) void k_reduce_rows(const double* part, int nblocks,
-                                                          double* out) {
-  __shared__ double sh[kThreads];
-  const int r = blockIdx.x;
-  const double* p = part + (int64_t)r * nblocks;
+// sum_b p[b] over the workgroup in a fixed order (on thread 0)
+__device__ double rows_sum(const double* p, int nblocks, double* sh) {
   // eight loads in flight per thread, added in the order of the plain loop
   double s = 0.0;
   int b = threadIdx.x;
@@ -541,14 +537,11 @@ __global__ __launch_bounds__(kThreads) void k_reduce_rows(const double* part, in
     if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[r] = sh[0];
+  return sh[0];
 }
 
-__global__ __launch_bounds__(kThreads) void k_reduce_parts(const double* part, int nblocks,
-                                                           int nrhs, double* out) {
-  __shared__ double sh[kThreads];
-  const int r = blockIdx.x;
-  // eight loads in flight per thread, added in the order of the plain loop
+// sum_b part[b * nrhs + r] in a fixed order (on thread 0)
+__device__ double parts_sum(const double* part, int nblocks, int nrhs, int r, double* sh) {
   double s = 0.0;
   int b = threadIdx.x;
   for (; b + 7 * kThreads < nblocks; b += 8 * kThreads) {
@@ -565,7 +558,24 @@ __global__ __launch_bounds__(kThreads) void k_reduce_parts(const double* part, i
     if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[r] = sh[0];
+  return sh[0];
+}
+
+// out[r] = sum_b part[r * nblocks + b] in a fixed order (the products' transposed partials)
+__global__ __launch_bounds__(kThreads) void k_reduce_rows(const double* part, int nblocks,
+                                                          double* out) {
+  __shared__ double sh[kThreads];
+  const int r = blockIdx.x;
+  const double v = rows_sum(part + (int64_t)r * nblocks, nblocks, sh);
+  if (threadIdx.x == 0) out[r] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce_parts(const double* part, int nblocks,
+                                                           int nrhs, double* out) {
+  __shared__ double sh[kThreads];
+  const int r = blockIdx.x;
+  const double v = parts_sum(part, nblocks, nrhs, r, sh);
+  if (threadIdx.x == 0) out[r] = v;
 }
 
 struct RhsState {
@@ -595,13 +605,12 @@ __global__ void k_set_rz(RhsState* S, const double* rz, int nrhs) {
 }
 
 // alpha = (r, z) / (p, A p), with the indefiniteness checks of the recurrence
-__global__ void k_alpha(RhsState* S, const double* pq, int nrhs, int* nactive) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
-  RhsState& g = S[r];
+// alpha = (r, z) / (p, q) of one right-hand side; a non-positive (r, z) or (p, q) stops it
+// as indefinite
+__device__ void rhs_alpha(RhsState& g, double pq, int* nactive) {
   g.alpha = 0.0;
   if (!g.active) return;
-  g.pq = pq[r];
+  g.pq = pq;
   if (!(g.rz > 0.0) || !(g.pq > 0.0)) {
     g.active = 0;
     g.status = 4;
@@ -648,12 +657,10 @@ __global__ __launch_bounds__(kThreads) void k_axpy(double* __restrict__ rv,
   }
 }
 
-__global__ void k_conv(RhsState* S, const double* rr, double rtol, int nrhs, int* nactive) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
-  RhsState& g = S[r];
+// convergence of one right-hand side on the recursive residual: ||r|| <= rtol ||b||
+__device__ void rhs_conv(RhsState& g, double rr, double rtol, int* nactive) {
   if (!g.active) return;
-  g.rr = rr[r];
+  g.rr = rr;
   if (sqrt(g.rr) <= rtol * g.bnorm) {
     g.active = 0;
     g.status = 1;
@@ -661,14 +668,47 @@ __global__ void k_conv(RhsState* S, const double* rr, double rtol, int nrhs, int
   }
 }
 
-__global__ void k_beta(RhsState* S, const double* rz_new, int nrhs) {
+__global__ void k_conv(RhsState* S, const double* rr, double rtol, int nrhs, int* nactive) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs) return;
-  RhsState& g = S[r];
+  rhs_conv(S[r], rr[r], rtol, nactive);
+}
+
+// beta = (r, z)_new / (r, z)_old of one right-hand side
+__device__ void rhs_beta(RhsState& g, double rz_new) {
   g.beta = 0.0;
   if (!g.active) return;
-  g.beta = rz_new[r] / g.rz;
-  g.rz = rz_new[r];
+  g.beta = rz_new / g.rz;
+  g.rz = rz_new;
+}
+
+// The reductions of an iteration with the scalar step that consumes them (one launch
+// instead of two; the same sums and the same step): step 0 alpha from (p, q), 1 beta from
+// (r, z) -- both from the products' partials -- and convergence from ||r||^2 partials.
+__global__ __launch_bounds__(kThreads) void k_reduce_rows_step(const double* part, int nblocks,
+                                                               double* out, RhsState* S, int step,
+                                                               int* nactive) {
+  __shared__ double sh[kThreads];
+  const int r = blockIdx.x;
+  const double v = rows_sum(part + (int64_t)r * nblocks, nblocks, sh);
+  if (threadIdx.x == 0) {
+    out[r] = v;
+    if (step == 0) rhs_alpha(S[r], v, nactive);
+    else rhs_beta(S[r], v);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce_parts_conv(const double* part, int nblocks,
+                                                                int nrhs, double* out,
+                                                                RhsState* S, double rtol,
+                                                                int* nactive) {
+  __shared__ double sh[kThreads];
+  const int r = blockIdx.x;
+  const double v = parts_sum(part, nblocks, nrhs, r, sh);
+  if (threadIdx.x == 0) {
+    out[r] = v;
+    rhs_conv(S[r], v, rtol, nactive);
+  }
 }
 
 // x += alpha p with this iteration's alpha (zero for right-hand sides that had already
@@ -746,19 +786,20 @@ struct Solver {
   std::vector<int> ev_kind;
   int ev_used = 0;
 
-  void timed_spmm(int kind, const Mat& K, const double* X, double* Y, double* out) {
-    if (!timing || ev_used + 2 > (int)ev.size()) {
-      spmm(K, X, Y, out);
-      return;
+  // Y = K X with the per-RHS dots (X, Y) reduced into out and the scalar step `step` applied
+  // to them in the same launch (0: alpha, 1: beta)
+  void timed_spmm(int kind, const Mat& K, const double* X, double* Y, double* out, int step) {
+    const bool rec = timing && ev_used + 2 <= (int)ev.size();
+    if (rec) (void)hipEventRecord(ev[ev_used], s);
+    if (K.val32) spmm_v<float>(K, X, Y, part);
+    else spmm_v<double>(K, X, Y, part);
+    if (rec) {
+      (void)hipEventRecord(ev[ev_used + 1], s);
+      ev_kind[ev_used / 2] = kind;
+      ev_used += 2;
     }
-    (void)hipEventRecord(ev[ev_used], s);
-    if (K.val32) spmm_v<float>(K, X, Y, out ? part : nullptr);
-    else spmm_v<double>(K, X, Y, out ? part : nullptr);
-    (void)hipEventRecord(ev[ev_used + 1], s);
-    ev_kind[ev_used / 2] = kind;
-    ev_used += 2;
-    if (out)
-      hipLaunchKernelGGL(k_reduce_rows, dim3(nrhs), dim3(kThreads), 0, s, part, spmm_grid, out);
+    hipLaunchKernelGGL(k_reduce_rows_step, dim3(nrhs), dim3(kThreads), 0, s, part, spmm_grid, out,
+                       S, step, nactive);
   }
   // after a synchronisation: add the recorded product times to the totals
   void collect_timing() {
@@ -841,21 +882,21 @@ struct Solver {
     hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(kThreads), 0, s, part, kGrid, nrhs, out);
   }
 
+  // one PCG iteration; each reduction applies the scalar step that consumes it
   void iteration(double rtol) {
     const dim3 gs((nrhs + 63) / 64), bs(64);
-    timed_spmm(0, A, p, q, tmp);                              // q = A p, (p, q)
-    hipLaunchKernelGGL(k_alpha, gs, bs, 0, s, S, tmp, nrhs, nactive);
+    timed_spmm(0, A, p, q, tmp, 0);                           // q = A p, (p, q), alpha
     if (nrhs <= 64) {                                            // r update fused with ||r||^2
       hipLaunchKernelGGL(k_axpy, dim3(kGrid), dim3(kThreads), 0, s, r, q, S, n, nrhs, pow2(nrhs),
                          part);
-      hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(kThreads), 0, s, part, kGrid, nrhs, tmp);
+      hipLaunchKernelGGL(k_reduce_parts_conv, dim3(nrhs), dim3(kThreads), 0, s, part, kGrid, nrhs,
+                         tmp, S, rtol, nactive);               // convergence test
     } else {
       hipLaunchKernelGGL(k_axpy_wide, dim3(kGrid), dim3(kThreads), 0, s, r, q, S, n, nrhs);
       dot(r, r, nullptr, tmp);
+      hipLaunchKernelGGL(k_conv, gs, bs, 0, s, S, tmp, rtol, nrhs, nactive);
     }
-    hipLaunchKernelGGL(k_conv, gs, bs, 0, s, S, tmp, rtol, nrhs, nactive);
-    timed_spmm(1, M, r, z, tmp);                              // z = M r, (r, z)
-    hipLaunchKernelGGL(k_beta, gs, bs, 0, s, S, tmp, nrhs);
+    timed_spmm(1, M, r, z, tmp, 1);                           // z = M r, (r, z), beta
     if (nrhs <= 64)                                              // x += alpha p, p = z + beta p
       hipLaunchKernelGGL(k_pupd, dim3(kGrid), dim3(kThreads), 0, s, p, x, z, S, n, nrhs, pow2(nrhs));
     else
