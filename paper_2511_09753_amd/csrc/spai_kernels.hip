@@ -727,36 +727,42 @@ void launch_zero_cols(int64_t n, Cols<T> X, hipStream_t s) {
 // R = I - A M (explicit residual, Section 6.2) with ||r_j||^2 per column
 // ============================================================================
 
-// upper bound of nnz(r_j): 1 + sum_{l in supp(m_j)} deg(l)
+// upper bound of nnz(r_j): 1 + sum_{l in supp(m_j)} deg(l).  Eight lanes per column read
+// its entries together (two per lane in flight) and add their degrees with shuffles: an
+// integer sum, the same in any order.
+constexpr int kBoundLanes = 8;
 template <typename T>
-__global__ void k_bound_resid(Csr A, Pair<T> Mp, int64_t* ub, int64_t n, const DevState* st) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+__global__ __launch_bounds__(256) void k_bound_resid(Csr A, Pair<T> Mp, int64_t* ub, int64_t n,
+                                                     const DevState* st) {
   if (!st->any_active) return;
+  const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kBoundLanes;
+  const int g = threadIdx.x % kBoundLanes;
   const Cols<T> M = Mp.now();
-  const int64_t b = M.beg[j];
-  const int lm = M.len[j];
-  int64_t s = 1;
-  int e = 0;
-  for (; e + 4 <= lm; e += 4) {       // four entries' loads in flight together
-    int l[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) l[u] = M.idx[b + e + u];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) s += A.rowptr[l[u] + 1] - A.rowptr[l[u]];
+  long long s = 0;
+  if (j < n) {
+    const int64_t b = M.beg[j];
+    const int lm = M.len[j];
+    int e = g;
+    for (; e + kBoundLanes < lm; e += 2 * kBoundLanes) {
+      const int l0 = M.idx[b + e], l1 = M.idx[b + e + kBoundLanes];
+      s += (A.rowptr[l0 + 1] - A.rowptr[l0]) + (A.rowptr[l1 + 1] - A.rowptr[l1]);
+    }
+    if (e < lm) {
+      const int l = M.idx[b + e];
+      s += A.rowptr[l + 1] - A.rowptr[l];
+    }
   }
-  for (; e < lm; ++e) {
-    const int l = M.idx[b + e];
-    s += A.rowptr[l + 1] - A.rowptr[l];
-  }
-  ub[j] = s;
+#pragma unroll
+  for (int d = 1; d < kBoundLanes; d <<= 1) s += __shfl_xor(s, d, SPAI_WAVE);   // all lanes
+  if (j < n && g == 0) ub[j] = 1 + s;
 }
 
 template <typename T>
 void launch_bound_resid(const Csr& A, Pair<T> M, int64_t* ub, int64_t n, const DevState* st,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_bound_resid<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, M,
-                     ub, n, st);
+  const int64_t threads = n * kBoundLanes;
+  hipLaunchKernelGGL(k_bound_resid<T>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, A,
+                     M, ub, n, st);
 }
 
 // five waves per SIMD: measured faster than the compiler's own choice (four) for this
