@@ -2363,19 +2363,24 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
         acc += __builtin_amdgcn_readlane(nlen, c);
       }
       ne = acc;
+      // lane c's neighbour start less its first flat index, so that entry e of neighbour t
+      // sits at nrel[t] + e
+      int mypre = 0;
+#pragma unroll
+      for (int c = 1; c < 8; ++c) mypre = lane == c ? pre[c] : mypre;
+      const int64_t nrel = nbeg - (int64_t)mypre;
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
         const int e = lane + k * SPAI_WAVE;
-        int t = 0, pt = 0;                        // the last neighbour starting at or before e
+        // the last neighbour starting at or before e: the prefix is non-decreasing and
+        // equals ne from neighbour deg on, so for e < ne it is the count of c >= 1 with
+        // pre[c] <= e
+        int t = 0;
 #pragma unroll
-        for (int c = 1; c < 8; ++c)
-          if (c < deg && pre[c] <= e) {
-            t = c;
-            pt = pre[c];
-          }
+        for (int c = 1; c < 8; ++c) t += pre[c] <= e ? 1 : 0;
         const bool v = e < ne;
-        const int64_t bt = __shfl(nbeg, t, SPAI_WAVE);   // on every lane
-        const int64_t q = v ? bt + (e - pt) : 0;
+        const int64_t bt = __shfl(nrel, t, SPAI_WAVE);   // on every lane
+        const int64_t q = v ? bt + e : 0;
         nrow[k] = M.idx[q];
         nval[k] = M.val[q];
         ntag[k] = v ? t : -1;
