@@ -174,11 +174,11 @@ __device__ __forceinline__ void bt_find(const unsigned short* cell, unsigned m,
   x1 = b.val;
 }
 
-// the same for list 0 alone (its bytes only)
+// the same for a map of one list (a byte per cell)
 template <typename T>
-__device__ __forceinline__ void bt_find1(const unsigned short* cell, unsigned m,
+__device__ __forceinline__ void bt_find1(const unsigned char* cell, unsigned m,
                                          const BtEnt<T>* e0, int w, bool& h0, T& x0) {
-  const unsigned v = ((const unsigned char*)cell)[2 * bt_cell(w, m)];
+  const unsigned v = cell[bt_cell(w, m)];
   const BtEnt<T> a = e0[v];
   h0 = a.row == w;
   x0 = a.val;
@@ -906,7 +906,7 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
                                                           int H) {
   if (!st->any_active) return;
   // the map at fixed LDS addresses (their offsets fold into the reads), the key set behind
-  __shared__ __align__(16) unsigned short cell[kBtCells];
+  __shared__ __align__(16) unsigned char cell[kBtCells];   // one list: a byte per cell
   __shared__ __align__(16) BtEnt<T> ent[128 + 1];
   extern __shared__ char smem[];
   Carve cv(smem);
@@ -914,7 +914,7 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
   unsigned* kt = cv.take<unsigned>(max(H + kOhOver, 256));
   int* keys = (int*)kt;
   const int lane = lane_id();
-  for (int i = lane; i < kBtCells / 2; i += SPAI_WAVE) ((unsigned*)cell)[i] = 0u;
+  for (int i = lane; i < kBtCells / 4; i += SPAI_WAVE) ((unsigned*)cell)[i] = 0u;
   if (lane == 0) ent[0] = BtEnt<T>{kBtNone, (T)0};    // list 0's sentinel
   __syncthreads();
   const Cols<T> M = Mp.now();
@@ -960,7 +960,7 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
       else row[k] = -1;
     }
     for (int i = lane; i < kend; i += SPAI_WAVE) kt[i] = kOhEmpty;
-    const int a = bt_build<2>((unsigned char*)cell, row, lst, pos);
+    const int a = bt_build<2, 1>(cell, row, lst, pos);
     if (a < 0) {
       defer_column(0, big, st, j);
       continue;
@@ -991,7 +991,7 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
     int nu = bad ? 0 : oh_compact(kt, kend);
     __syncthreads();
     if (bad || nu > 256) {                         // key set or register sort too small
-      bt_clear<2>((unsigned char*)cell, row, lst, mul);
+      bt_clear<2, 1>(cell, row, lst, mul);
       __syncthreads();
       defer_column(0, big, st, j);
       continue;
@@ -1045,11 +1045,15 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
       R.len[j] = nu;
     }
     outcnt += (unsigned long long)nu;
-    bt_clear<2>((unsigned char*)cell, row, lst, mul);
+    bt_clear<2, 1>(cell, row, lst, mul);
     __syncthreads();
   }
   if (lane == 0 && blockIdx.x < kCntSlots) st->cnt[6 * kCntSlots + blockIdx.x] += outcnt;
 }
+
+// resident workgroups of the lean residual per compute unit at most: at 96^3 the mixed
+// path took 1.44 ms with 21 and 1.86 ms with the 24 its LDS allows
+constexpr int kResidLeanPerCu = 21;
 
 template <typename T>
 static size_t resid_lean_lds(Tile t) {   // dynamic part (the map is static)
@@ -1103,6 +1107,25 @@ static int resident_grid(K kernel, size_t lds, int threads = SPAI_WAVE) {
   return grid;
 }
 
+// `per` workgroups per compute unit of the current device
+static int per_cu_grid(int per) {
+  static std::mutex mu;
+  static int cus = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cus <= 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0) {
+      (void)hipGetLastError();
+      cus = 0;
+      return g_grid_cols;
+    }
+  }
+  return per * cus;
+}
+
+
 template <typename T>
 void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const int64_t* total,
                   double* colnorm, int weighted, double* colrz, BigList big, DevState* st,
@@ -1111,7 +1134,9 @@ void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const 
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
   if (ell)
-    hipLaunchKernelGGL((k_resid_lean<T>), dim3(resident_grid(k_resid_lean<T>, resid_lean_lds<T>(small))),
+    hipLaunchKernelGGL((k_resid_lean<T>),
+                       dim3(std::min(resident_grid(k_resid_lean<T>, resid_lean_lds<T>(small)),
+                                     per_cu_grid(kResidLeanPerCu))),
                        dim3(SPAI_WAVE), resid_lean_lds<T>(small), s, A, M, R, off, total, colnorm,
                        weighted, colrz, big, st, small.L, small.H);
   else
@@ -2966,24 +2991,6 @@ __global__ void k_sel_reset(unsigned long long* hist, int nbins, DevState* st) {
 __global__ void k_hist_clear(unsigned long long* hist, int nbins, const DevState* st) {
   if (st->sel_done) return;
   for (int i = threadIdx.x; i < nbins; i += blockDim.x) hist[i] = 0;
-}
-
-// `per` workgroups per compute unit of the current device
-static int per_cu_grid(int per) {
-  static std::mutex mu;
-  static int cus = 0;
-  std::lock_guard<std::mutex> lock(mu);
-  if (cus <= 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0) {
-      (void)hipGetLastError();
-      cus = 0;
-      return g_grid_cols;
-    }
-  }
-  return per * cus;
 }
 
 template <typename T>
