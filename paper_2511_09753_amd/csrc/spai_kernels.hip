@@ -2220,15 +2220,28 @@ constexpr int kUpdLeanOwn = 192;   // own-list entries (whatever the tile's L)
 constexpr int kUpdLeanNbr = 256;   // entries of the neighbour columns together
 
 // SECOND: the same kernel under another name for the floor-free second pass (masked
-// unless needed), so that profiles keep the two apart.
+// unless needed), so that profiles keep the two apart.  LM: the mode of a symmetrized
+// LOMR step under a global cap (M + a1 R + a2 P and P from R and P) fixed at compile
+// time, so that its flags take no registers and its branches fold; other modes read md.
 // Registers capped for six waves per SIMD on the float path (2% faster at 96^3; the
 // float64 path spills there and keeps five).
-template <typename T, bool FLAT, bool SECOND>
+template <typename T, bool FLAT, bool SECOND, bool LM>
 __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 5))) void k_update_lean(
-    Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp, Pair<T> PTp, UpdMode md, const int64_t* off,
+    Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp, Pair<T> PTp, UpdMode mdin, const int64_t* off,
     const int64_t* total, const int32_t* kcol, double* tM, double* tP, BigList big, Seg seg,
     DevState* st, int L, int H) {
   if (!st->any_active || !st->iter_active) return;
+  UpdMode md = mdin;
+  if constexpr (LM) {
+    md.doM = 1;
+    md.x1 = 1;
+    md.x2 = 2;
+    md.doP = 1;
+    md.pR = 1;
+    md.pP = 1;
+    md.sym = 1;
+    md.colcap = 0;
+  }
   // the fixed-size arrays at fixed LDS addresses (their offsets fold into the accesses),
   // the key set behind
   __shared__ __align__(16) unsigned char cb[kBtCells];        // 1 + rank of a row's hash
@@ -2645,8 +2658,19 @@ void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, Up
                          P, PT, md, off, total, kcol, tM, tP, big, seg, st, small.L, small.H);
     };
     // ELL rows wider than 8: neighbour entries laid out flat
-    if (A.eshift > 3) second ? go(k_update_lean<T, true, true>) : go(k_update_lean<T, true, false>);
-    else second ? go(k_update_lean<T, false, true>) : go(k_update_lean<T, false, false>);
+    const bool lm = md.doM == 1 && md.x1 == 1 && md.x2 == 2 && md.doP == 1 && md.pR == 1 &&
+                    md.pP == 1 && md.sym == 1 && md.colcap == 0;
+    if (lm) {
+      if (A.eshift > 3)
+        second ? go(k_update_lean<T, true, true, true>) : go(k_update_lean<T, true, false, true>);
+      else
+        second ? go(k_update_lean<T, false, true, true>) : go(k_update_lean<T, false, false, true>);
+    } else {
+      if (A.eshift > 3)
+        second ? go(k_update_lean<T, true, true, false>) : go(k_update_lean<T, true, false, false>);
+      else
+        second ? go(k_update_lean<T, false, true, false>) : go(k_update_lean<T, false, false, false>);
+    }
   } else if (small.waves == 5)
     hipLaunchKernelGGL((k_update_w5<T>),
                        dim3(resident_grid(k_update_w5<T>, update_lds(small, true))),
