@@ -896,8 +896,10 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
 // inserts the columns of its ELL row straight from 16-byte loads into the ordered key
 // set, sized from the column's bound ub_j = off[j+1] - off[j]; the keys are then sorted
 // by row (the stored order of R) and each pulled over A's row with branch-free lookups.
-// A column that does not fit (list, key set, sort) goes to the next tier.
-template <typename T>
+// A column that does not fit (list, key set, sort) goes to the next tier.  WT: the
+// Pi-weighted form (weighted != 0), fixed at compile time so that the unweighted pull
+// carries no diagonal tracking.
+template <typename T, bool WT>
 __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 5))) void k_resid_lean(Csr A, Pair<T> Mp, Cols<T> R,
                                                           const int64_t* off,
                                                           const int64_t* total, double* colnorm,
@@ -905,6 +907,7 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
                                                           BigList big, DevState* st, int L,
                                                           int H) {
   if (!st->any_active) return;
+  weighted = WT ? 1 : 0;
   // the map at fixed LDS addresses (their offsets fold into the reads), the key set behind
   __shared__ __align__(16) unsigned char cell[kBtCells];   // one list: a byte per cell
   __shared__ __align__(16) BtEnt<T> ent[128 + 1];
@@ -1133,13 +1136,17 @@ void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const 
   const bool ell = A.eshift >= 0;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
-  if (ell)
-    hipLaunchKernelGGL((k_resid_lean<T>),
-                       dim3(std::min(resident_grid(k_resid_lean<T>, resid_lean_lds<T>(small)),
-                                     per_cu_grid(kResidLeanPerCu))),
-                       dim3(SPAI_WAVE), resid_lean_lds<T>(small), s, A, M, R, off, total, colnorm,
-                       weighted, colrz, big, st, small.L, small.H);
-  else
+  if (ell) {
+    auto go = [&](auto KR) {
+      hipLaunchKernelGGL((KR),
+                         dim3(std::min(resident_grid(KR, resid_lean_lds<T>(small)),
+                                       per_cu_grid(kResidLeanPerCu))),
+                         dim3(SPAI_WAVE), resid_lean_lds<T>(small), s, A, M, R, off, total, colnorm,
+                         weighted, colrz, big, st, small.L, small.H);
+    };
+    if (weighted) go(k_resid_lean<T, true>);
+    else go(k_resid_lean<T, false>);
+  } else
     hipLaunchKernelGGL((k_resid<T, false>),
                        dim3(resident_grid(k_resid<T, false>, resid_lds(small, ell))),
                        dim3(SPAI_WAVE), resid_lds(small, ell), s, A, M, R, off, total, colnorm,
@@ -1318,13 +1325,15 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5, 5)
 // its slots read in order list the rows of A r_j and A p_j sorted by ohash, the order
 // every tier sums in.  Per row u, one pass over A's row gives (A r)_u, (A p)_u, r_u, p_u
 // (the diagonal entry's lookup) and a_uu, with the same arithmetic as dots_body.
-// Registers are capped for five waves per SIMD (no spills at that cap).
-template <typename T>
+// Registers are capped for five waves per SIMD (no spills at that cap).  WT: the
+// Pi-weighted form, fixed at compile time (as in k_resid_lean).
+template <typename T, bool WT>
 __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) void k_dots_lean(Csr A, Cols<T> R, Pair<T> Pp, int useR,
                                                          int useP, int weighted,
                                                          double* colpart, BigList big,
                                                          DevState* st, int L, int H) {
   if (!st->any_active || !st->iter_active) return;
+  weighted = WT ? 1 : 0;
   // the map at fixed LDS addresses (their offsets fold into the reads), the key set behind
   __shared__ __align__(16) unsigned short cell[kBtCells];
   __shared__ __align__(16) BtEnt<T> ent[128 + 2];   // two sentinels
@@ -1511,11 +1520,15 @@ void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, int wei
   const bool ell = A.eshift >= 0;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
-  if (small.waves == 1 && ell)
-    hipLaunchKernelGGL((k_dots_lean<T>), dim3(resident_grid(k_dots_lean<T>, dots_lean_lds<T>(small))),
-                       dim3(SPAI_WAVE), dots_lean_lds<T>(small), s, A, R, P, useR, useP, weighted,
-                       colpart, big, st, small.L, small.H);
-  else if (small.waves == 5)
+  if (small.waves == 1 && ell) {
+    auto go = [&](auto KD) {
+      hipLaunchKernelGGL((KD), dim3(resident_grid(KD, dots_lean_lds<T>(small))),
+                         dim3(SPAI_WAVE), dots_lean_lds<T>(small), s, A, R, P, useR, useP, weighted,
+                         colpart, big, st, small.L, small.H);
+    };
+    if (weighted) go(k_dots_lean<T, true>);
+    else go(k_dots_lean<T, false>);
+  } else if (small.waves == 5)
     hipLaunchKernelGGL((k_dots_w5<T>), dim3(resident_grid(k_dots_w5<T>, dots_lds(small, ell))),
                        dim3(SPAI_WAVE), dots_lds(small, ell), s, A, R, P, useR, useP, weighted,
                        colpart, big, st, 0, small.L, small.H);
