@@ -779,6 +779,9 @@ struct Solver {
   RhsState* S;
   int* nactive;
   const int32_t* order = nullptr;   // row visiting order of the products (null: natural)
+  // workgroups of the x, p update: 5 per compute unit (20 waves; the 64-right-hand-side solve
+  // at 96^3 took 352 ms, against 361 ms with the full 2048 and 363 ms with 3 per unit)
+  int pupd_grid = kGrid;
   // optional timing of the products inside the iterations: HIP events recorded on the
   // solver's stream around each A p (kind 0) and M r (kind 1), read back per chunk
   PcgTiming* timing = nullptr;
@@ -898,7 +901,8 @@ struct Solver {
     }
     timed_spmm(1, M, r, z, tmp, 1);                           // z = M r, (r, z), beta
     if (nrhs <= 64)                                              // x += alpha p, p = z + beta p
-      hipLaunchKernelGGL(k_pupd, dim3(kGrid), dim3(kThreads), 0, s, p, x, z, S, n, nrhs, pow2(nrhs));
+      hipLaunchKernelGGL(k_pupd, dim3(pupd_grid), dim3(kThreads), 0, s, p, x, z, S, n, nrhs,
+                         pow2(nrhs));
     else
       hipLaunchKernelGGL(k_pupd_wide, dim3(kGrid), dim3(kThreads), 0, s, p, x, z, S, n, nrhs);
   }
@@ -965,6 +969,15 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
     return rc;
   S.b = dB;
   S.x = dX;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0)
+      S.pupd_grid = 5 * cus;
+    else
+      (void)hipGetLastError();
+  }
   if (timing) {                         // two products per iteration, 8 iterations per chunk
     S.timing = timing;
     S.ev.resize(32, nullptr);
