@@ -402,7 +402,11 @@ __device__ __forceinline__ char* tile_base(char* smem, const BigList& big) {
 
 // counters are cleared by a kernel, never by a memset node, so that the
 // iteration sequence can be captured in a HIP graph
-__global__ void k_zero_int(int* p) { *p = 0; }
+// the deferred-column counters of a tiered launch, both zeroed by one launch
+__global__ void k_zero_counts(int* a, int* b) {
+  *a = 0;
+  *b = 0;
+}
 
 // clear the drop record (a kernel, not a memset node: the iteration may be captured)
 __global__ void k_rec_clear(DevState* st, int next) {
@@ -1134,8 +1138,7 @@ void launch_resid(const Csr& A, Pair<T> M, Cols<T> R, const int64_t* off, const 
                   double* colnorm, int weighted, double* colrz, BigList big, DevState* st,
                   Tile small, Tile large, Tile huge, hipStream_t s) {
   const bool ell = A.eshift >= 0;
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
+  hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(1), 0, s, big.count, big.count2);
   if (ell) {
     auto go = [&](auto KR) {
       hipLaunchKernelGGL((KR),
@@ -1518,8 +1521,7 @@ void launch_dots(const Csr& A, Cols<T> R, Pair<T> P, int useR, int useP, int wei
                  double* colpart, BigList big, DevState* st, Tile small, Tile large, Tile huge,
                  hipStream_t s) {
   const bool ell = A.eshift >= 0;
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
+  hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(1), 0, s, big.count, big.count2);
   if (small.waves == 1 && ell) {
     auto go = [&](auto KD) {
       hipLaunchKernelGGL((KD), dim3(resident_grid(KD, dots_lean_lds<T>(small))),
@@ -1742,8 +1744,7 @@ void launch_resid_impl(const Csr& A, Cols<T> Rin, Cols<T> Xr, Pair<T> P, int xsr
                        DevState* st, Tile small, Tile large, Tile huge, hipStream_t s) {
   const bool ell = A.eshift >= 0;
   const ImplSrc src{xsrc, cidx};
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
+  hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(1), 0, s, big.count, big.count2);
   hipLaunchKernelGGL((k_resid_impl<T, false>),
                      dim3(resident_grid(k_resid_impl<T, false>, dots_lds(small, ell))),
                      dim3(SPAI_WAVE), dots_lds(small, ell), s, A, Rin, Xr, P, src, seg, off, total,
@@ -2662,8 +2663,7 @@ void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, Up
                    const int64_t* off, const int64_t* total, const int32_t* kcol, double* tM,
                    double* tP, BigList big, const Seg& seg, DevState* st, Tile small, Tile large,
                    Tile huge, hipStream_t s, bool second) {
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
+  hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(1), 0, s, big.count, big.count2);
   if (small.waves == 1 && A.eshift >= 0) {
     const size_t lds = (size_t)std::max(small.H + kOhOver, kUpdLeanKeys) * 4 + 64;   // dynamic part
     auto go = [&](auto kern) {
@@ -2866,14 +2866,18 @@ __device__ inline void find_bin_desc(const unsigned long long* hist, int nbins, 
 }
 
 // find the exponent bin of the (b+1)-th largest; b = m - (diagonal count if excluded)
-__global__ __launch_bounds__(1024) void k_sel_find_exp(const unsigned long long* hist,
+__global__ __launch_bounds__(1024) void k_sel_find_exp(unsigned long long* hist,
                                                        int excl_diag, int64_t m, int signed_keys,
                                                        double* thr, DevState* st) {
   if (!st->any_active || !st->iter_active) return;
   const long long b = m - (excl_diag ? st->sel_diag : 0);
   long long total, above;
   int bin;
-  find_bin_desc(hist, signed_keys ? 4096 : 2048, b + 1, &total, &bin, &above);
+  const int nb = signed_keys ? 4096 : 2048;
+  find_bin_desc(hist, nb, b + 1, &total, &bin, &above);
+  // every read of the histogram is done (the search ends on a barrier): clear it for the
+  // first pass over the collected keys (the bins above nb were never written)
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
   if (threadIdx.x != 0) return;
   st->sel_count = 0;
   if (b < 0) {                      // cap below the diagonal count: keep only the diagonal
@@ -2984,7 +2988,7 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_hist_buf(const unsigned lon
     if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
 }
 
-__global__ __launch_bounds__(1024) void k_sel_find_buf(const unsigned long long* hist, int shift,
+__global__ __launch_bounds__(1024) void k_sel_find_buf(unsigned long long* hist, int shift,
                                                        int last, double eta, int signed_keys,
                                                        double* thr, DevState* st) {
   if (!st->any_active || !st->iter_active || st->sel_done) return;
@@ -2992,6 +2996,7 @@ __global__ __launch_bounds__(1024) void k_sel_find_buf(const unsigned long long*
   long long total, above;
   int bin;
   find_bin_desc(hist, 8192, rank, &total, &bin, &above);
+  for (int i = threadIdx.x; i < 8192; i += blockDim.x) hist[i] = 0;   // for the next pass
   if (threadIdx.x != 0) return;
   if (bin >= 0) {
     st->sel_prefix |= (unsigned long long)bin << shift;
@@ -3023,11 +3028,6 @@ __global__ void k_sel_reset(unsigned long long* hist, int nbins, DevState* st) {
     st->sel_count = 0;
     st->sel_done = 0;
   }
-}
-
-__global__ void k_hist_clear(unsigned long long* hist, int nbins, const DevState* st) {
-  if (st->sel_done) return;
-  for (int i = threadIdx.x; i < nbins; i += blockDim.x) hist[i] = 0;
 }
 
 template <typename T>
@@ -3067,7 +3067,6 @@ void launch_global_select(Pair<T> X, int exclude_diag, int64_t m, double eta, in
   // passes over bits 0..25 would each select bin 0: they stop after bits 26..38
   const int last = (sizeof(T) == 4 && !score) ? 26 : 0;
   for (int shift = 39; shift >= last; shift -= 13) {
-    hipLaunchKernelGGL(k_hist_clear, dim3(1), dim3(1024), 0, s, hist, 8192, st);
     hipLaunchKernelGGL(k_sel_hist_buf, dim3(256), dim3(kSelThreads), 0, s, selbuf, shift, hist,
                        st);
     hipLaunchKernelGGL(k_sel_find_buf, dim3(1), dim3(1024), 0, s, hist, shift, last, eta, sk,
@@ -3240,8 +3239,7 @@ template <typename T>
 void launch_score(const Csr& A, Pair<T> M, double* sc, double* sig, BigList big, DevState* st,
                   Tile small, Tile large, Tile huge, int64_t n, hipStream_t s) {
   const bool ell = A.eshift >= 0;
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count);
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, big.count2);
+  hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(1), 0, s, big.count, big.count2);
   hipLaunchKernelGGL((k_score<T, false>), dim3(resident_grid(k_score<T, false>, score_lds(small, ell))),
                      dim3(SPAI_WAVE), score_lds(small, ell), s, A, M, sc, big, st, 0, small.L,
                      small.H);
