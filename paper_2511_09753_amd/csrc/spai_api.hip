@@ -1193,16 +1193,13 @@ struct Engine : EngineBase {
       te();
     }
     tb(SPAI_PH_COMPACT);
-    if (md.doM) {
-      launch_compact<T>(M, 0, colcap, md.sym, global, tM, opts.tie_eta, n, st, s, keyM);
-      launch_flip(0, st, s);
-    }
+    if (md.doM) launch_compact<T>(M, 0, colcap, md.sym, global, tM, opts.tie_eta, n, st, s, keyM);
     if (md.doP) {
       launch_compact<T>(P, 1, colcap, 0, global, tP, opts.tie_eta, n, st, s);
       launch_compact<T>(PT, 2, colcap, 0, global, tP, opts.tie_eta, n, st, s);
-      launch_flip(1, st, s);
     }
-    if (floors) launch_floor_next(st, md.doM, md.doP, opts.floor_frac, s);
+    // each compaction reads only its own pair, so both flips (and the floors) go last
+    launch_drop_finish(st, md.doM, md.doP, floors ? 1 : 0, opts.floor_frac, s);
     te();
   }
 

@@ -205,14 +205,15 @@ void launch_scal_post(int method, const Seg& seg, const double* red, const doubl
                       double tol, double* hist, int hist_cap, int setup, DevState* st,
                       hipStream_t s);
 extern int g_grid_cols;   // persistent grid of the per-column kernels (multiple of 8)
-void launch_flip(int which, DevState* st, hipStream_t s);   // 0: curM, 1: curP
 // zero the drop record; the next iteration's record is `next`
 void launch_rec_clear(DevState* st, int next, hipStream_t s);
 // the second, floor-free pass of the update and the selection runs only where the first
 // pass's floors were too high: redo_begin masks the iteration unless st->redo (and clears
-// the floors), redo_end restores it; floor_next sets the next iteration's floors
+// the floors), redo_end restores it; drop_finish sets the next iteration's floors
 void launch_redo_begin(DevState* st, hipStream_t s);
 void launch_redo_end(DevState* st, hipStream_t s);
-void launch_floor_next(DevState* st, int doM, int doP, double frac, hipStream_t s);
+// the new M (doM) and P (doP) become current; with floors, the next iteration's floors
+// are set from this iteration's cuts
+void launch_drop_finish(DevState* st, int doM, int doP, int floors, double frac, hipStream_t s);
 
 }  // namespace spai

@@ -437,8 +437,7 @@ __global__ void k_redo_begin(DevState* st) {
 }
 __global__ void k_redo_end(DevState* st) { st->iter_active = st->saved_active; }
 // next iteration's floors: a fraction of this iteration's cuts (none without a cut)
-__global__ void k_floor_next(DevState* st, int doM, int doP, double frac) {
-  if (!st->iter_active) return;
+__device__ void floor_next_body(DevState* st, int doM, int doP, double frac) {
   if (doM) {
     st->floorM = (st->rawM > 0.0 && isfinite(st->rawM)) ? frac * st->rawM : 0.0;
     st->belowM = 0;
@@ -454,9 +453,6 @@ void launch_redo_begin(DevState* st, hipStream_t s) {
 }
 void launch_redo_end(DevState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_redo_end, dim3(1), dim3(1), 0, s, st);
-}
-void launch_floor_next(DevState* st, int doM, int doP, double frac, hipStream_t s) {
-  hipLaunchKernelGGL(k_floor_next, dim3(1), dim3(1), 0, s, st, doM, doP, frac);
 }
 
 constexpr int kScanThreads = 256;
@@ -3560,13 +3556,17 @@ void launch_scal_post(int method, const Seg& seg, const double* red, const doubl
                      red_rz, tol, hist, hist_cap, setup, st);
 }
 
-__global__ void k_flip(int which, DevState* st) {
+// the end of a drop in one launch: the new M (doM) and P (doP) become current, and with
+// floors the next iteration's floors are set
+__global__ void k_drop_finish(DevState* st, int doM, int doP, int floors, double frac) {
   if (!st->iter_active) return;
-  if (which == 0) st->curM ^= 1; else st->curP ^= 1;
+  if (doM) st->curM ^= 1;
+  if (doP) st->curP ^= 1;
+  if (floors) floor_next_body(st, doM, doP, frac);
 }
 
-void launch_flip(int which, DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_flip, dim3(1), dim3(1), 0, s, which, st);
+void launch_drop_finish(DevState* st, int doM, int doP, int floors, double frac, hipStream_t s) {
+  hipLaunchKernelGGL(k_drop_finish, dim3(1), dim3(1), 0, s, st, doM, doP, floors, frac);
 }
 
 // ---- explicit instantiations
