@@ -246,7 +246,8 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, 
 // time (one per lane of the half) and broadcast with readlane; the gathers of both
 // rows are issued in groups of four before any is used (groups of eight hold 100
 // registers, five waves per SIMD, and the 64-right-hand-side solve at 96^3 took 6%
-// longer than with four at six waves), entries past a row's count
+// longer than with four at six waves) -- of two for A in ELL, whose short rows do best
+// with more, smaller groups (350 against 353 ms per solve) --, entries past a row's count
 // repeating its last one so every load is in bounds.  Each row's sum runs over its
 // entries in stored order, and the dot terms are added in position order, so the rows
 // of Y and the dot partials are those of k_spmm_wave bit for bit.  Positions are
@@ -256,7 +257,7 @@ template <typename VT, int LAY>
 __global__ __launch_bounds__(kThreads) void k_spmm_pair(Mat A, const double* X, double* Y,
                                                         int dot, int nrhs, int c0,
                                                         const int32_t* order, double* part) {
-  constexpr int G = 4;
+  constexpr int G = LAY == kLayEll ? 2 : 4;
   __shared__ double sh[kThreads];
   constexpr int WPB = kThreads / 64;
   const int lane = threadIdx.x & 63;
