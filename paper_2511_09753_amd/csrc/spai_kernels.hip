@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 
 #include "spai_dev.hpp"
@@ -2230,19 +2231,20 @@ constexpr int kUpdLeanOwn = 192;   // own-list entries (whatever the tile's L)
 constexpr int kUpdLeanNbr = 256;   // entries of the neighbour columns together
 
 // SECOND: the same kernel under another name for the floor-free second pass (masked
-// unless needed), so that profiles keep the two apart.  LM: the mode of a symmetrized
-// LOMR step under a global cap (M + a1 R + a2 P and P from R and P) fixed at compile
-// time, so that its flags take no registers and its branches fold; other modes read md.
+// unless needed), so that profiles keep the two apart.  LM: a mode fixed at compile time,
+// so that its flags take no registers and its branches fold -- 1: the symmetrized LOMR
+// step under a global cap (M + a1 R + a2 P, and P from R and P), 2: the symmetrized MR
+// step (M + a1 R, no P; either cap); 0: every mode, read from md.
 // Registers capped for six waves per SIMD on the float path (2% faster at 96^3; the
 // float64 path spills there and keeps five).
-template <typename T, bool FLAT, bool SECOND, bool LM>
+template <typename T, bool FLAT, bool SECOND, int LM>
 __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 5))) void k_update_lean(
     Csr A, Pair<T> Mp, Cols<T> R, Pair<T> Pp, Pair<T> PTp, UpdMode mdin, const int64_t* off,
     const int64_t* total, const int32_t* kcol, double* tM, double* tP, BigList big, Seg seg,
     DevState* st, int L, int H) {
   if (!st->any_active || !st->iter_active) return;
   UpdMode md = mdin;
-  if constexpr (LM) {
+  if constexpr (LM == 1) {
     md.doM = 1;
     md.x1 = 1;
     md.x2 = 2;
@@ -2251,6 +2253,12 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
     md.pP = 1;
     md.sym = 1;
     md.colcap = 0;
+  } else if constexpr (LM == 2) {
+    md.doM = 1;
+    md.x1 = 1;
+    md.x2 = 0;
+    md.doP = 0;
+    md.sym = 1;
   }
   // the fixed-size arrays at fixed LDS addresses (their offsets fold into the accesses),
   // the key set behind
@@ -2667,19 +2675,19 @@ void launch_update(const Csr& A, Pair<T> M, Cols<T> R, Pair<T> P, Pair<T> PT, Up
                          P, PT, md, off, total, kcol, tM, tP, big, seg, st, small.L, small.H);
     };
     // ELL rows wider than 8: neighbour entries laid out flat
-    const bool lm = md.doM == 1 && md.x1 == 1 && md.x2 == 2 && md.doP == 1 && md.pR == 1 &&
-                    md.pP == 1 && md.sym == 1 && md.colcap == 0;
-    if (lm) {
+    const bool lomr = md.doM == 1 && md.x1 == 1 && md.x2 == 2 && md.doP == 1 && md.pR == 1 &&
+                      md.pP == 1 && md.sym == 1 && md.colcap == 0;
+    const bool mr = md.doM == 1 && md.x1 == 1 && md.x2 == 0 && md.doP == 0 && md.sym == 1;
+    auto pick = [&](auto lmc) {
+      constexpr int L2 = decltype(lmc)::value;
       if (A.eshift > 3)
-        second ? go(k_update_lean<T, true, true, true>) : go(k_update_lean<T, true, false, true>);
+        second ? go(k_update_lean<T, true, true, L2>) : go(k_update_lean<T, true, false, L2>);
       else
-        second ? go(k_update_lean<T, false, true, true>) : go(k_update_lean<T, false, false, true>);
-    } else {
-      if (A.eshift > 3)
-        second ? go(k_update_lean<T, true, true, false>) : go(k_update_lean<T, true, false, false>);
-      else
-        second ? go(k_update_lean<T, false, true, false>) : go(k_update_lean<T, false, false, false>);
-    }
+        second ? go(k_update_lean<T, false, true, L2>) : go(k_update_lean<T, false, false, L2>);
+    };
+    if (lomr) pick(std::integral_constant<int, 1>{});
+    else if (mr) pick(std::integral_constant<int, 2>{});
+    else pick(std::integral_constant<int, 0>{});
   } else if (small.waves == 5)
     hipLaunchKernelGGL((k_update_w5<T>),
                        dim3(resident_grid(k_update_w5<T>, update_lds(small, true))),
