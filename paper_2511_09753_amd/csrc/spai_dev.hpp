@@ -453,14 +453,16 @@ __device__ __forceinline__ int upper_bound_int(const int* a, int n, int v) {
 template <typename T> __device__ __forceinline__ double ld(const T* p) { return (double)(*p); }
 
 // Insert up to U keys per lane (negative: none) into T[0 .. H + kOhOver), H = 2^(32 - shift).
-// Returns false if a walk ran off the end of the table (the caller then gives the
-// column to a larger tile).
+// A walk moves one slot per step and starts at a home slot below H, so capping the
+// walks at kOhOver steps keeps every probe inside the table.  Returns false (on every
+// lane) if a walk needed more steps; the caller then gives the column to a larger tile.
 template <int U>
-__device__ __forceinline__ bool oh_insert_batch(unsigned* T, int shift, int end,
-                                                const int (&key)[U]) {
+__device__ __forceinline__ bool oh_insert_batch(unsigned* T, int shift, const int (&key)[U]) {
   // The walk state is updated with selects, not branches: only the atomic itself sits
   // under a condition, so the wave runs one short loop (until no lane has a key in
-  // flight) instead of a branch per key and step.
+  // flight) instead of a branch per key and step.  A walk that found an empty slot
+  // gets max(empty, v) = empty, so placed, already present and not started all end as
+  // the empty word, which no key hashes to.
   unsigned v[U];
   int s[U];
 #pragma unroll
@@ -468,8 +470,7 @@ __device__ __forceinline__ bool oh_insert_batch(unsigned* T, int shift, int end,
     v[c] = key[c] >= 0 ? ohash(key[c]) : kOhEmpty;
     s[c] = key[c] >= 0 ? (int)(v[c] >> shift) : 0;
   }
-  bool ok = true;
-  while (true) {
+  for (int step = 0; step < kOhOver; ++step) {
     unsigned old[U];
 #pragma unroll
     for (int c = 0; c < U; ++c) {
@@ -479,17 +480,13 @@ __device__ __forceinline__ bool oh_insert_batch(unsigned* T, int shift, int end,
     bool live = false;
 #pragma unroll
     for (int c = 0; c < U; ++c) {
-      const bool fin = old[c] == kOhEmpty || old[c] == v[c];   // placed, or already there
-      const int ns = s[c] + 1;
-      const bool ovf = !fin && ns >= end;                       // walked off the table
-      ok = ok && !ovf;
-      v[c] = (fin || ovf) ? kOhEmpty : max(old[c], v[c]);       // walk on with the larger
-      s[c] = (fin || ovf) ? 0 : ns;
+      v[c] = old[c] == v[c] ? kOhEmpty : max(old[c], v[c]);   // walk on with the larger
+      s[c] += 1;
       live = live || v[c] != kOhEmpty;
     }
-    if (__ballot(live) == 0ull) break;
+    if (__ballot(live) == 0ull) return true;
   }
-  return ok;
+  return false;
 }
 
 // Compact the occupied slots of T[0 .. end) in place into keys (decoded), in slot order;

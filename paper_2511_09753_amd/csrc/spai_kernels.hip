@@ -981,14 +981,14 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
         ell_cols8(A, rr, c, cols);
         const int c0[4] = {cols[0], cols[1], cols[2], cols[3]};
         const int c1[4] = {cols[4], cols[5], cols[6], cols[7]};
-        ok = oh_insert_batch<4>(kt, ksh, kend, c0) && ok;
-        ok = oh_insert_batch<4>(kt, ksh, kend, c1) && ok;
+        ok = oh_insert_batch<4>(kt, ksh, c0) && ok;
+        ok = oh_insert_batch<4>(kt, ksh, c1) && ok;
         if (cols[7] < 0) rr = -1;                  // the row ended in this chunk
       }
     }
     {
       const int kd[1] = {lane == 0 ? (int)j : -1};
-      ok = oh_insert_batch<1>(kt, ksh, kend, kd) && ok;
+      ok = oh_insert_batch<1>(kt, ksh, kd) && ok;
     }
     const bool bad = __ballot(!ok) != 0ull;
     __syncthreads();
@@ -1406,8 +1406,8 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(5))) 
         ell_cols8(A, rr, c, cols);
         const int c0[4] = {cols[0], cols[1], cols[2], cols[3]};
         const int c1[4] = {cols[4], cols[5], cols[6], cols[7]};
-        ok = oh_insert_batch<4>(kt, ksh, kend, c0) && ok;
-        ok = oh_insert_batch<4>(kt, ksh, kend, c1) && ok;
+        ok = oh_insert_batch<4>(kt, ksh, c0) && ok;
+        ok = oh_insert_batch<4>(kt, ksh, c1) && ok;
         if (cols[7] < 0) rr = -1;
       }
     }
@@ -2463,17 +2463,17 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
     int okey[kUpdLeanOwn / SPAI_WAVE];
 #pragma unroll
     for (int k = 0; k < kUpdLeanOwn / SPAI_WAVE; ++k) okey[k] = (ovalid >> k) & 1u ? orow[k] : -1;
-    bool ok = oh_insert_batch<kUpdLeanOwn / SPAI_WAVE>(kt, ksh, kend, okey);
+    bool ok = oh_insert_batch<kUpdLeanOwn / SPAI_WAVE>(kt, ksh, okey);
 #pragma unroll
     for (int k0 = 0; k0 < NS; k0 += 4) {           // batches of four keys per lane
       int nk[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) nk[k] = slot_nbr(k0 + k) >= 0 ? nrow[k0 + k] : -1;
-      ok = oh_insert_batch<4>(kt, ksh, kend, nk) && ok;
+      ok = oh_insert_batch<4>(kt, ksh, nk) && ok;
     }
     {
       const int kd[1] = {lane == 0 ? (int)j : -1};
-      ok = oh_insert_batch<1>(kt, ksh, kend, kd) && ok;
+      ok = oh_insert_batch<1>(kt, ksh, kd) && ok;
     }
     const bool bad = __ballot(!ok) != 0ull;
     __syncthreads();
