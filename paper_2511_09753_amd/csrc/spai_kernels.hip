@@ -2459,6 +2459,9 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
     const int ksh = 32 - log2_pow2(Hc);
     const int kend = Hc + kOhOver;
     for (int i = lane; i < kend; i += SPAI_WAVE) kt[i] = kOhEmpty;
+    // the diagonal key first: the table is empty, so it sits at its home slot (the
+    // slots of an ordered table do not depend on the order of the inserts)
+    if (lane == 0) kt[ohash((int)j) >> ksh] = ohash((int)j);
     __syncthreads();
     int okey[kUpdLeanOwn / SPAI_WAVE];
 #pragma unroll
@@ -2470,10 +2473,6 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
 #pragma unroll
       for (int k = 0; k < 4; ++k) nk[k] = slot_nbr(k0 + k) >= 0 ? nrow[k0 + k] : -1;
       ok = oh_insert_batch<4>(kt, ksh, nk) && ok;
-    }
-    {
-      const int kd[1] = {lane == 0 ? (int)j : -1};
-      ok = oh_insert_batch<1>(kt, ksh, kd) && ok;
     }
     const bool bad = __ballot(!ok) != 0ull;
     __syncthreads();

@@ -581,6 +581,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_parts(const double* part, i
 
 struct RhsState {
   double bnorm, rz, pq, rr, alpha, beta;
+  double alpha_prev;                // the previous iteration's alpha (its x term may be pending)
   int active, iters, status, pad;   // status 0 running, 1 converged, 2 maxiter, 4 indefinite
 };
 
@@ -609,6 +610,7 @@ __global__ void k_set_rz(RhsState* S, const double* rz, int nrhs) {
 // alpha = (r, z) / (p, q) of one right-hand side; a non-positive (r, z) or (p, q) stops it
 // as indefinite
 __device__ void rhs_alpha(RhsState& g, double pq, int* nactive) {
+  g.alpha_prev = g.alpha;
   g.alpha = 0.0;
   if (!g.active) return;
   g.pq = pq;
@@ -623,7 +625,7 @@ __device__ void rhs_alpha(RhsState& g, double pq, int* nactive) {
 }
 
 // r -= alpha q (inactive right-hand sides have alpha = 0), fused with the per-block
-// partials of ||r||^2 for every right-hand side; x is updated later, in k_pupd
+// partials of ||r||^2 for every right-hand side; x is updated later, with p
 __global__ __launch_bounds__(kThreads) void k_axpy(double* __restrict__ rv,
                                                    const double* __restrict__ q,
                                                    const RhsState* __restrict__ S, int64_t n,
@@ -712,28 +714,84 @@ __global__ __launch_bounds__(kThreads) void k_reduce_parts_conv(const double* pa
   }
 }
 
-// x += alpha p with this iteration's alpha (zero for right-hand sides that had already
-// stopped), then p = z + beta p for the running ones: p is read once for both
-__global__ __launch_bounds__(kThreads) void k_pupd(double* __restrict__ p, double* __restrict__ x,
-                                                   const double* __restrict__ z,
-                                                   const RhsState* __restrict__ S, int64_t n,
-                                                   int nrhs, int R) {
+// The x update taken two iterations at a time (up to 64 right-hand sides): p alternates
+// between two buffers, an even iteration only forms the next p, and the odd one after it
+// adds both iterations' terms to x, first alpha_prev p_prev, then alpha p (the additions
+// and their order are those of one update per iteration, so x is the same bit for bit).
+// Reading x once per two iterations saves half a block pass per iteration.
+//
+// even iteration: pn = z + beta p for the running right-hand sides
+__global__ __launch_bounds__(kThreads) void k_pupd_p(double* __restrict__ pn,
+                                                     const double* __restrict__ p,
+                                                     const double* __restrict__ z,
+                                                     const RhsState* __restrict__ S, int64_t n,
+                                                     int nrhs, int R) {
+  const int t = threadIdx.x;
+  const int r = t % R;
+  const int rows_per = kThreads / R;
+  const int roff = t / R;
+  if (r >= nrhs || S[r].active == 0) return;
+  const double b = S[r].beta;
+  for (int64_t base = (int64_t)blockIdx.x * rows_per; base < n; base += (int64_t)gridDim.x * rows_per) {
+    const int64_t i = base + roff;
+    if (i < n) {
+      const int64_t o = i * nrhs + r;
+      pn[o] = z[o] + b * p[o];
+    }
+  }
+}
+
+// odd iteration: x += alpha_prev pp, x += alpha p; then pp = z + beta p (pp holds the even
+// iteration's p, read before it is overwritten)
+__global__ __launch_bounds__(kThreads) void k_pupd_x2(double* __restrict__ pp,
+                                                      const double* __restrict__ p,
+                                                      double* __restrict__ x,
+                                                      const double* __restrict__ z,
+                                                      const RhsState* __restrict__ S, int64_t n,
+                                                      int nrhs, int R) {
   const int t = threadIdx.x;
   const int r = t % R;
   const int rows_per = kThreads / R;
   const int roff = t / R;
   if (r >= nrhs) return;
-  const double a = S[r].alpha;
+  const double a0 = S[r].alpha_prev, a1 = S[r].alpha;
   const bool act = S[r].active != 0;
-  if (a == 0.0 && !act) return;
+  const bool upx = a0 != 0.0 || a1 != 0.0;
+  if (!upx && !act) return;
   const double b = S[r].beta;
   for (int64_t base = (int64_t)blockIdx.x * rows_per; base < n; base += (int64_t)gridDim.x * rows_per) {
     const int64_t i = base + roff;
     if (i < n) {
       const int64_t o = i * nrhs + r;
       const double po = p[o];
-      if (a != 0.0) x[o] = x[o] + a * po;
-      if (act) p[o] = z[o] + b * po;
+      if (upx) {
+        double xv = x[o];
+        if (a0 != 0.0) xv = xv + a0 * pp[o];
+        if (a1 != 0.0) xv = xv + a1 * po;
+        x[o] = xv;
+      }
+      if (act) pp[o] = z[o] + b * po;
+    }
+  }
+}
+
+// the pending x term of a solve that stopped after an even iteration: x += alpha p
+__global__ __launch_bounds__(kThreads) void k_x_flush(double* __restrict__ x,
+                                                      const double* __restrict__ p,
+                                                      const RhsState* __restrict__ S, int64_t n,
+                                                      int nrhs, int R) {
+  const int t = threadIdx.x;
+  const int r = t % R;
+  const int rows_per = kThreads / R;
+  const int roff = t / R;
+  if (r >= nrhs) return;
+  const double a = S[r].alpha;
+  if (a == 0.0) return;
+  for (int64_t base = (int64_t)blockIdx.x * rows_per; base < n; base += (int64_t)gridDim.x * rows_per) {
+    const int64_t i = base + roff;
+    if (i < n) {
+      const int64_t o = i * nrhs + r;
+      x[o] = x[o] + a * p[o];
     }
   }
 }
@@ -776,6 +834,7 @@ struct Solver {
   int nrhs;
   hipStream_t s;
   double *x, *r, *z, *p, *q, *part, *tmp;
+  double* p1 = nullptr;              // the second p buffer (up to 64 right-hand sides)
   const double* b;
   RhsState* S;
   int* nactive;
@@ -886,10 +945,13 @@ struct Solver {
     hipLaunchKernelGGL(k_reduce_parts, dim3(nrhs), dim3(kThreads), 0, s, part, kGrid, nrhs, out);
   }
 
-  // one PCG iteration; each reduction applies the scalar step that consumes it
-  void iteration(double rtol) {
+  // one PCG iteration; each reduction applies the scalar step that consumes it.  odd:
+  // the parity of the iteration's index (p in p1, and x updated for this and the previous)
+  void iteration(double rtol, int odd) {
     const dim3 gs((nrhs + 63) / 64), bs(64);
-    timed_spmm(0, A, p, q, tmp, 0);                           // q = A p, (p, q), alpha
+    const bool two = nrhs <= 64;
+    double* pc = two && odd ? p1 : p;                          // this iteration's p
+    timed_spmm(0, A, pc, q, tmp, 0);                          // q = A p, (p, q), alpha
     if (nrhs <= 64) {                                            // r update fused with ||r||^2
       hipLaunchKernelGGL(k_axpy, dim3(kGrid), dim3(kThreads), 0, s, r, q, S, n, nrhs, pow2(nrhs),
                          part);
@@ -901,9 +963,12 @@ struct Solver {
       hipLaunchKernelGGL(k_conv, gs, bs, 0, s, S, tmp, rtol, nrhs, nactive);
     }
     timed_spmm(1, M, r, z, tmp, 1);                           // z = M r, (r, z), beta
-    if (nrhs <= 64)                                              // x += alpha p, p = z + beta p
-      hipLaunchKernelGGL(k_pupd, dim3(pupd_grid), dim3(kThreads), 0, s, p, x, z, S, n, nrhs,
+    if (two && !odd)                                             // p1 = z + beta p
+      hipLaunchKernelGGL(k_pupd_p, dim3(pupd_grid), dim3(kThreads), 0, s, p1, p, z, S, n, nrhs,
                          pow2(nrhs));
+    else if (two)                                                // x += both terms, p = z + beta p1
+      hipLaunchKernelGGL(k_pupd_x2, dim3(pupd_grid), dim3(kThreads), 0, s, p, p1, x, z, S, n,
+                         nrhs, pow2(nrhs));
     else
       hipLaunchKernelGGL(k_pupd_wide, dim3(kGrid), dim3(kThreads), 0, s, p, x, z, S, n, nrhs);
   }
@@ -964,6 +1029,7 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
   S.order = order;
   const int64_t tot = S.n * nrhs;
   if ((rc = pool.alloc(&S.r, tot)) || (rc = pool.alloc(&S.z, tot)) || (rc = pool.alloc(&S.p, tot)) ||
+      (nrhs <= 64 && (rc = pool.alloc(&S.p1, tot))) ||
       (rc = pool.alloc(&S.q, tot)) ||
       (rc = pool.alloc(&S.part, (int64_t)std::max<int64_t>(kGrid, Solver::spmm_blocks(S.n)) * nrhs)) ||
       (rc = pool.alloc(&S.tmp, nrhs)) || (rc = pool.alloc(&S.S, nrhs)) || (rc = pool.alloc(&S.nactive, 1)))
@@ -1028,7 +1094,7 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
     const int k = std::min(chunk, max_iter - it);
     if (use_graph && k == chunk && !gexec) {
       if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        for (int t = 0; t < k; ++t) S.iteration(rtol);
+        for (int t = 0; t < k; ++t) S.iteration(rtol, (it + t) & 1);
         if (hipStreamEndCapture(s, &graph) != hipSuccess ||
             hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
           (void)hipGetLastError();
@@ -1045,11 +1111,14 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
     if (use_graph && k == chunk && gexec) {
       HIPCHK(hipGraphLaunch(gexec, s));
     } else {
-      for (int t = 0; t < k; ++t) S.iteration(rtol);
+      for (int t = 0; t < k; ++t) S.iteration(rtol, (it + t) & 1);
     }
     HIPCHK(hipGetLastError());
     it += k;
   }
+  if (nrhs <= 64 && (it & 1))      // the last iteration was even: its x term is pending
+    hipLaunchKernelGGL(k_x_flush, dim3(S.pupd_grid), dim3(kThreads), 0, s, S.x, S.p, S.S, S.n, nrhs,
+                       Solver::pow2(nrhs));
   // true residual ||b - A x|| / ||b||
   S.spmm(S.A, S.x, S.q, nullptr);
   S.dot(dB, dB, S.q, S.tmp);     // sum (b - Ax)^2

@@ -198,6 +198,28 @@ def test_pcg_multi_rhs_aniso(nrhs):
     assert rc == S.PCG_INDEFINITE
 
 
+@pytest.mark.parametrize("nrhs", [8, 64])
+def test_pcg_iteration_cap(nrhs):
+    """A solve stopped by its iteration cap after an odd or an even count.  For up to 64
+    right-hand sides x is updated two iterations at a time, with the last term added at
+    the end when the count is odd; X equals the oracle's PCG stopped at the same count,
+    eager (null stream) and with graph replays of full 8-iteration chunks (own stream)."""
+    import torch
+    S = _spai()
+    A = W.aniso2d(64, 1.0, 0.01)
+    ref = O.lomr(A, oracle_rule(A, "column", 3.0, True), 10)
+    B = W.rhs(A.shape[0], nrhs, W.seed_for(2, 1))
+    st = torch.cuda.Stream()
+    for cap in (1, 2, 12, 13, 21):
+        Xo, ito, sto = O.pcg_block(A, ref.M, B, rtol=1e-12, max_iter=cap)
+        assert list(ito) == [cap] * nrhs and set(sto) == {"maxiter"}
+        for opts in (None, S.Options(stream=st)):
+            X, it, _, rc = S.pcg_solve(A, ref.M, B, rtol=1e-12, max_iter=cap, options=opts)
+            assert rc == S.SPAI_MAXITER
+            assert list(it) == list(ito), (cap, it)
+            assert np.max(np.abs(X - Xo)) <= 1e-10 * np.max(np.abs(Xo)), cap
+
+
 def test_determinism():
     S = _spai()
     A = W.lognormal3d(10, 3)
