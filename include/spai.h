@@ -367,6 +367,9 @@ int spai_profile(spai_handle_t* h, double* phase_ms, int64_t* phase_calls, int64
  * On a stream other than the null stream the iterations run as replays of one HIP
  *   graph of 8 iterations (captured on first use; the host reads the count of active
  *   right-hand sides between replays); results equal the eager launches bit for bit.
+ * Device memory for the solve: n x nrhs float64 blocks r, z, q and p, and for nrhs <= 64
+ *   a second p (x is then updated once per two iterations, with the same sums), plus
+ *   per-workgroup partials; all released before the call returns.
  * Synchronises the stream.
  */
 int pcg_solve(const spai_csr_t* A, const spai_csr_t* M, int nrhs, const double* B,
