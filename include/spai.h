@@ -348,7 +348,10 @@ enum {
 /*
  * spai_profile — accumulated milliseconds and launch counts per phase (zeros unless
  *   opts.profile = 1) and the traffic counters.  Any pointer may be NULL; arrays
- *   hold SPAI_NPHASES / SPAI_NCOUNTS entries.  Synchronises the stream.
+ *   hold SPAI_NPHASES / SPAI_NCOUNTS entries.  The PCG product counts are the products
+ *   that did their work: once every right-hand side has stopped, the products left in
+ *   the last 8-iteration chunk return at once (their few microseconds stay in the
+ *   times).  Synchronises the stream.
  */
 int spai_profile(spai_handle_t* h, double* phase_ms, int64_t* phase_calls, int64_t* counts);
 

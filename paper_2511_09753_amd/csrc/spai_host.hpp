@@ -67,6 +67,10 @@ struct PcgMat {
   const int32_t* col = nullptr;
   const double* val = nullptr;
   const float* val32 = nullptr;
+  // inside the PCG iterations: a product returns at once while *gate is 0 (no right-hand
+  // side still running), and one that does its work adds 1 to *ran (null: not counted)
+  const int* gate = nullptr;
+  int* ran = nullptr;
   __device__ __forceinline__ int64_t row_begin(int64_t i) const {
     return eshift >= 0 ? (i << eshift) : beg ? beg[i] : rowptr[i];
   }

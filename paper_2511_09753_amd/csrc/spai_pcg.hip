@@ -120,6 +120,8 @@ template <typename VT, int LAY>
 __global__ __launch_bounds__(kThreads) void k_spmm_wave(Mat A, const double* X, double* Y,
                                                         int dot, int nrhs, int c0,
                                                         const int32_t* order, double* part) {
+  if (A.gate && *A.gate == 0) return;                     // every right-hand side stopped
+  if (A.ran && c0 == 0 && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(A.ran, 1);
   __shared__ double sh[kThreads];
   constexpr int WPB = kThreads / 64;
   const int lane = threadIdx.x & 63;
@@ -257,6 +259,8 @@ template <typename VT, int LAY>
 __global__ __launch_bounds__(kThreads) void k_spmm_pair(Mat A, const double* X, double* Y,
                                                         int dot, int nrhs, int c0,
                                                         const int32_t* order, double* part) {
+  if (A.gate && *A.gate == 0) return;                     // every right-hand side stopped
+  if (A.ran && c0 == 0 && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(A.ran, 1);
   constexpr int G = LAY == kLayEll ? 2 : 4;
   __shared__ double sh[kThreads];
   constexpr int WPB = kThreads / 64;
@@ -419,6 +423,8 @@ __global__ __launch_bounds__(kThreads) void k_spmm_narrow(Mat A, const double* X
                                                           const int32_t* order, double* part) {
   static_assert(narrow_chunk<R>() >= (kThreads / 64) * kRowsPerWave,
                 "no more workgroups than the partial buffer holds");
+  if (A.gate && *A.gate == 0) return;                     // every right-hand side stopped
+  if (A.ran && c0 == 0 && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(A.ran, 1);
   __shared__ double sh[kThreads];
   constexpr int G = kThreads / R;
   constexpr int RPT = narrow_rpt<R>();
@@ -629,7 +635,9 @@ __device__ void rhs_alpha(RhsState& g, double pq, int* nactive) {
 __global__ __launch_bounds__(kThreads) void k_axpy(double* __restrict__ rv,
                                                    const double* __restrict__ q,
                                                    const RhsState* __restrict__ S, int64_t n,
-                                                   int nrhs, int R, double* __restrict__ part) {
+                                                   int nrhs, int R, double* __restrict__ part,
+                                                   const int* __restrict__ gate) {
+  if (*gate == 0) return;                                  // every right-hand side stopped
   __shared__ double sh[kThreads];
   const int t = threadIdx.x;
   const int r = t % R;
@@ -830,6 +838,9 @@ __global__ __launch_bounds__(kThreads) void k_fill(double* dst, double v, int64_
 
 struct Solver {
   Mat A, M;
+  Mat Ag, Mg;                        // A and M as the iterations use them (gated, counted)
+  int* runs = nullptr;               // products that did their work, per kind (with timing)
+  int runs_seen[2] = {0, 0};
   int64_t n;
   int nrhs;
   hipStream_t s;
@@ -865,17 +876,28 @@ struct Solver {
                        S, step, nactive);
   }
   // after a synchronisation: add the recorded product times to the totals
+  // (calls: the products that did their work; a product of a solve whose right-hand sides
+  // have all stopped returns at once, and its few microseconds stay in the time)
   void collect_timing() {
     for (int i = 0; i + 1 < ev_used; i += 2) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) {
         timing->ms[ev_kind[i / 2]] += ms;
-        timing->calls[ev_kind[i / 2]] += 1;
       } else {
         (void)hipGetLastError();
       }
     }
     ev_used = 0;
+    int now[2] = {0, 0};
+    if (runs && hipMemcpyAsync(now, runs, sizeof(now), hipMemcpyDeviceToHost, s) == hipSuccess &&
+        hipStreamSynchronize(s) == hipSuccess) {
+      for (int k = 0; k < 2; ++k) {
+        timing->calls[k] += now[k] - runs_seen[k];
+        runs_seen[k] = now[k];
+      }
+    } else {
+      (void)hipGetLastError();
+    }
   }
 
   static int pow2(int w) {
@@ -951,10 +973,10 @@ struct Solver {
     const dim3 gs((nrhs + 63) / 64), bs(64);
     const bool two = nrhs <= 64;
     double* pc = two && odd ? p1 : p;                          // this iteration's p
-    timed_spmm(0, A, pc, q, tmp, 0);                          // q = A p, (p, q), alpha
+    timed_spmm(0, Ag, pc, q, tmp, 0);                         // q = A p, (p, q), alpha
     if (nrhs <= 64) {                                            // r update fused with ||r||^2
       hipLaunchKernelGGL(k_axpy, dim3(kGrid), dim3(kThreads), 0, s, r, q, S, n, nrhs, pow2(nrhs),
-                         part);
+                         part, nactive);
       hipLaunchKernelGGL(k_reduce_parts_conv, dim3(nrhs), dim3(kThreads), 0, s, part, kGrid, nrhs,
                          tmp, S, rtol, nactive);               // convergence test
     } else {
@@ -962,7 +984,7 @@ struct Solver {
       dot(r, r, nullptr, tmp);
       hipLaunchKernelGGL(k_conv, gs, bs, 0, s, S, tmp, rtol, nrhs, nactive);
     }
-    timed_spmm(1, M, r, z, tmp, 1);                           // z = M r, (r, z), beta
+    timed_spmm(1, Mg, r, z, tmp, 1);                          // z = M r, (r, z), beta
     if (two && !odd)                                             // p1 = z + beta p
       hipLaunchKernelGGL(k_pupd_p, dim3(pupd_grid), dim3(kThreads), 0, s, p1, p, z, S, n, nrhs,
                          pow2(nrhs));
@@ -1056,6 +1078,15 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
         S.timing = nullptr;
       }
   }
+  if (S.timing) {
+    if ((rc = pool.alloc(&S.runs, 2))) return rc;
+    HIPCHK(hipMemsetAsync(S.runs, 0, 2 * sizeof(int), s));
+  }
+  S.Ag = S.A;
+  S.Mg = S.M;
+  S.Ag.gate = S.Mg.gate = S.nactive;
+  S.Ag.ran = S.runs;
+  S.Mg.ran = S.runs ? S.runs + 1 : nullptr;
   HIPCHK(hipMemsetAsync(S.nactive, 0, sizeof(int), s));
   HIPCHK(hipMemsetAsync(S.S, 0, sizeof(RhsState) * nrhs, s));
   const dim3 gs((nrhs + 63) / 64), bs(64);

@@ -1165,6 +1165,33 @@ def test_pcg_graph_replay_matches_eager():
     assert rcb == rce and list(itb) == list(ite) and np.array_equal(Xb, Xe)
 
 
+def test_pcg_stopped_chunk_tail():
+    """Once every right-hand side has stopped, the products and the r update left in the
+    last 8-iteration chunk return at once: with phase timing, q = A p did its work once per
+    iteration of the longest right-hand side and z = M r once less (that iteration ends at
+    the convergence test), and the solution equals the one without timing (graph replays)
+    bit for bit."""
+    import torch
+    S = _spai()
+    A = W.lognormal3d(16, 41)
+    B = W.rhs(A.shape[0], 5, 13)
+    st = torch.cuda.Stream()
+    h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=12, options=S.Options(profile=True))
+    g = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=12, options=S.Options(stream=st))
+    h.iterate(12)
+    g.iterate(12)
+    for rtol in (1e-6, 1e-8, 1e-9):
+        _, c0, _ = h.profile()
+        X, it, _, rc = h.pcg(B, rtol=rtol)
+        _, c1, _ = h.profile()
+        Xg, itg, _, rcg = g.pcg(B, rtol=rtol)
+        assert rc == rcg == S.SPAI_OK and list(it) == list(itg) and np.array_equal(X, Xg)
+        assert c1["pcg_ax"] - c0["pcg_ax"] == max(it), (rtol, max(it))
+        assert c1["pcg_mx"] - c0["pcg_mx"] == max(it) - 1, (rtol, max(it))
+    h.close()
+    g.close()
+
+
 # ----------------------------------------------------------------------------
 # checkpoint / resume
 # ----------------------------------------------------------------------------
