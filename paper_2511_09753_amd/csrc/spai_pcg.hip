@@ -839,8 +839,9 @@ __global__ __launch_bounds__(kThreads) void k_fill(double* dst, double v, int64_
 struct Solver {
   Mat A, M;
   Mat Ag, Mg;                        // A and M as the iterations use them (gated, counted)
-  int* runs = nullptr;               // products that did their work, per kind (with timing)
+  int* runs = nullptr;               // products that did their work, per kind: nactive + 1
   int runs_seen[2] = {0, 0};
+  int ctr_host[3] = {0, 0, 0};       // the last host copy of nactive and runs
   int64_t n;
   int nrhs;
   hipStream_t s;
@@ -888,15 +889,9 @@ struct Solver {
       }
     }
     ev_used = 0;
-    int now[2] = {0, 0};
-    if (runs && hipMemcpyAsync(now, runs, sizeof(now), hipMemcpyDeviceToHost, s) == hipSuccess &&
-        hipStreamSynchronize(s) == hipSuccess) {
-      for (int k = 0; k < 2; ++k) {
-        timing->calls[k] += now[k] - runs_seen[k];
-        runs_seen[k] = now[k];
-      }
-    } else {
-      (void)hipGetLastError();
+    for (int k = 0; k < 2; ++k) {
+      timing->calls[k] += ctr_host[1 + k] - runs_seen[k];
+      runs_seen[k] = ctr_host[1 + k];
     }
   }
 
@@ -1054,7 +1049,7 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
       (nrhs <= 64 && (rc = pool.alloc(&S.p1, tot))) ||
       (rc = pool.alloc(&S.q, tot)) ||
       (rc = pool.alloc(&S.part, (int64_t)std::max<int64_t>(kGrid, Solver::spmm_blocks(S.n)) * nrhs)) ||
-      (rc = pool.alloc(&S.tmp, nrhs)) || (rc = pool.alloc(&S.S, nrhs)) || (rc = pool.alloc(&S.nactive, 1)))
+      (rc = pool.alloc(&S.tmp, nrhs)) || (rc = pool.alloc(&S.S, nrhs)) || (rc = pool.alloc(&S.nactive, 3)))
     return rc;
   S.b = dB;
   S.x = dX;
@@ -1078,16 +1073,13 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
         S.timing = nullptr;
       }
   }
-  if (S.timing) {
-    if ((rc = pool.alloc(&S.runs, 2))) return rc;
-    HIPCHK(hipMemsetAsync(S.runs, 0, 2 * sizeof(int), s));
-  }
+  if (S.timing) S.runs = S.nactive + 1;   // read with the active count in one copy
   S.Ag = S.A;
   S.Mg = S.M;
   S.Ag.gate = S.Mg.gate = S.nactive;
   S.Ag.ran = S.runs;
   S.Mg.ran = S.runs ? S.runs + 1 : nullptr;
-  HIPCHK(hipMemsetAsync(S.nactive, 0, sizeof(int), s));
+  HIPCHK(hipMemsetAsync(S.nactive, 0, 3 * sizeof(int), s));
   HIPCHK(hipMemsetAsync(S.S, 0, sizeof(RhsState) * nrhs, s));
   const dim3 gs((nrhs + 63) / 64), bs(64);
   // x_0 = 0, r = b, z = M r, p = z
@@ -1117,11 +1109,11 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
   } gguard{&graph, &gexec};
   bool use_graph = s != nullptr && !S.timing;
   while (it < max_iter) {
-    int nact = 0;
-    HIPCHK(hipMemcpyAsync(&nact, S.nactive, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(S.ctr_host, S.nactive, (S.timing ? 3 : 1) * sizeof(int),
+                          hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (S.timing) S.collect_timing();
-    if (nact == 0) break;
+    if (S.ctr_host[0] == 0) break;
     const int k = std::min(chunk, max_iter - it);
     if (use_graph && k == chunk && !gexec) {
       if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
@@ -1157,6 +1149,8 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
   HIPCHK(hipMemcpyAsync(rr.data(), S.tmp, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
   std::vector<RhsState> hs(nrhs);
   HIPCHK(hipMemcpyAsync(hs.data(), S.S, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, s));
+  if (S.timing)
+    HIPCHK(hipMemcpyAsync(S.ctr_host, S.nactive, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (S.timing) S.collect_timing();
   bool indef = false, unconv = false;
