@@ -27,6 +27,7 @@ constexpr int kThreads = 256;
 constexpr int kGrid = 2048;
 
 using Mat = PcgMat;
+typedef double d2v __attribute__((ext_vector_type(2)));   // for nontemporal 16-byte stores
 
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   const long long b = __double_as_longlong(v);
@@ -358,8 +359,12 @@ __global__ __launch_bounds__(kThreads) void k_spmm_pair(Mat A, const double* X, 
     }
     double t0 = 0.0, t1 = 0.0;          // this row's terms of the dot
     if (has && on) {
-      double2* yr = (double2*)(Y + (i * nrhs + c0 + 2 * hl));
-      *yr = make_double2(y0, y1);
+      // stored nontemporally: the next kernel reads Y once
+      d2v* yr = (d2v*)(Y + (i * nrhs + c0 + 2 * hl));
+      d2v yv;
+      yv.x = y0;
+      yv.y = y1;
+      __builtin_nontemporal_store(yv, yr);
       if (dot) {
         // a row without a diagonal entry loads X[i, :] after all
         const double2 w = found ? xd : *(const double2*)(X + (i * nrhs + c0 + 2 * hl));
@@ -633,8 +638,9 @@ __device__ void rhs_alpha(RhsState& g, double pq, int* nactive) {
 // r -= alpha q (inactive right-hand sides have alpha = 0), fused with the per-block
 // partials of ||r||^2 for every right-hand side; x is updated later, with p.  Blocks read
 // for the last time before they are written again (q here, z and x in the p updates)
-// are loaded (and x stored) nontemporally, so that they do not push out of the caches
-// what the next product gathers: 1% off the 64-right-hand-side solve at 96^3.
+// are loaded nontemporally, and x and the new p are stored so, as are the products'
+// outputs: they do not push out of the caches what a product gathers (the 64-right-hand-
+// side solve at 96^3 339 -> 330 ms; r, which the next product gathers, gained nothing).
 __global__ __launch_bounds__(kThreads) void k_axpy(double* __restrict__ rv,
                                                    const double* __restrict__ q,
                                                    const RhsState* __restrict__ S, int64_t n,
@@ -747,7 +753,7 @@ __global__ __launch_bounds__(kThreads) void k_pupd_p(double* __restrict__ pn,
     const int64_t i = base + roff;
     if (i < n) {
       const int64_t o = i * nrhs + r;
-      pn[o] = __builtin_nontemporal_load(&z[o]) + b * p[o];
+      __builtin_nontemporal_store(__builtin_nontemporal_load(&z[o]) + b * p[o], &pn[o]);
     }
   }
 }
@@ -781,7 +787,7 @@ __global__ __launch_bounds__(kThreads) void k_pupd_x2(double* __restrict__ pp,
         if (a1 != 0.0) xv = xv + a1 * po;
         __builtin_nontemporal_store(xv, &x[o]);
       }
-      if (act) pp[o] = __builtin_nontemporal_load(&z[o]) + b * po;
+      if (act) __builtin_nontemporal_store(__builtin_nontemporal_load(&z[o]) + b * po, &pp[o]);
     }
   }
 }
