@@ -242,6 +242,9 @@ int spai_reset(spai_handle_t* h);
  *   exactly symmetric, so its column storage is also its row storage).  B, X: dense
  *   n x nrhs row-major float64, device pointers when on_device = 1, else host.
  *   For a batched handle the block-diagonal system is solved.  Returns as pcg_solve.
+ *   The handle keeps the solve's device blocks (those pcg_solve allocates per call) for
+ *   the next spai_pcg with the same nrhs; one with another nrhs replaces them, and
+ *   spai_destroy frees them.
  */
 int spai_pcg(spai_handle_t* h, int nrhs, const double* B, double* X, double rtol,
              int max_iter, int* iters, double* relres, int on_device);

@@ -150,9 +150,13 @@ int DevPool::alloc_bytes(void** p, size_t bytes) {
   return SPAI_OK;
 }
 
-DevPool::~DevPool() {
+void DevPool::release() {
   for (void* p : ptrs) (void)hipFree(p);
+  ptrs.clear();
+  used = 0;
 }
+
+DevPool::~DevPool() { release(); }
 
 }  // namespace spai
 
@@ -296,6 +300,7 @@ struct Engine : EngineBase {
   std::vector<int64_t> seg_beg_h;
   // device
   DevPool pool;
+  PcgWork pcg_work;                  // spai_pcg's blocks, kept between solves of one size
   Csr A;
   Pair<T> M, P, PT;
   Cols<T> R;
@@ -688,7 +693,7 @@ struct Engine : EngineBase {
     tb(SPAI_PH_PCG);
     PcgTiming tm;
     rc = pcg_run(pa, pm, nrhs, dB, dX, rtol, max_iter, iters, relres, d_order, s,
-                 prof ? &tm : nullptr);
+                 prof ? &tm : nullptr, &pcg_work);
     te();
     if (prof) {
       ph_ms[SPAI_PH_PCG_AX] += tm.ms[0];

@@ -52,6 +52,7 @@ struct DevPool {
   int alloc(U** p, int64_t count) {
     return alloc_bytes((void**)p, sizeof(U) * (size_t)(count > 0 ? count : 1));
   }
+  void release();                    // free everything allocated so far
   ~DevPool();
 };
 
@@ -89,9 +90,18 @@ struct PcgTiming {
   int64_t calls[2] = {0, 0};
 };
 
+// the device blocks of a PCG solve, kept between solves of one size (a handle's): a solve
+// of another size replaces them, and they are freed with the owner
+struct PcgWork {
+  DevPool pool;
+  int64_t n = -1;
+  int nrhs = 0;
+  void* blk[9] = {};
+};
+
 int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double* dX, double rtol,
             int max_iter, int* iters, double* relres, const int32_t* order, hipStream_t s,
-            PcgTiming* timing);
+            PcgTiming* timing, PcgWork* work = nullptr);
 
 // extreme Ritz values of S (symmetric) after up to `steps` Lanczos steps with full
 // reorthogonalisation from the device vector dv0: out = {theta_min, theta_max, res_min,

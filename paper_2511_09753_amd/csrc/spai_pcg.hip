@@ -1037,9 +1037,10 @@ namespace spai {
 
 int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double* dX, double rtol,
             int max_iter, int* iters, double* relres, const int32_t* order, hipStream_t s,
-            PcgTiming* timing) {
+            PcgTiming* timing, PcgWork* work) {
   int rc;
-  DevPool pool;
+  DevPool local;
+  DevPool& pool = work ? work->pool : local;
   Solver S{};
   struct EvGuard {
     std::vector<hipEvent_t>* v;
@@ -1054,12 +1055,36 @@ int pcg_run(const PcgMat& A, const PcgMat& M, int nrhs, const double* dB, double
   S.s = s;
   S.order = order;
   const int64_t tot = S.n * nrhs;
-  if ((rc = pool.alloc(&S.r, tot)) || (rc = pool.alloc(&S.z, tot)) || (rc = pool.alloc(&S.p, tot)) ||
-      (nrhs <= 64 && (rc = pool.alloc(&S.p1, tot))) ||
-      (rc = pool.alloc(&S.q, tot)) ||
-      (rc = pool.alloc(&S.part, (int64_t)std::max<int64_t>(kGrid, Solver::spmm_blocks(S.n)) * nrhs)) ||
-      (rc = pool.alloc(&S.tmp, nrhs)) || (rc = pool.alloc(&S.S, nrhs)) || (rc = pool.alloc(&S.nactive, 3)))
-    return rc;
+  // every block is initialised or written before it is read in each solve, so kept
+  // blocks need no clearing beyond the state reset below
+  if (work && work->n == S.n && work->nrhs == nrhs) {
+    S.r = (double*)work->blk[0];
+    S.z = (double*)work->blk[1];
+    S.p = (double*)work->blk[2];
+    S.p1 = (double*)work->blk[3];
+    S.q = (double*)work->blk[4];
+    S.part = (double*)work->blk[5];
+    S.tmp = (double*)work->blk[6];
+    S.S = (RhsState*)work->blk[7];
+    S.nactive = (int*)work->blk[8];
+  } else {
+    if (work) {
+      work->pool.release();
+      work->n = -1;
+    }
+    if ((rc = pool.alloc(&S.r, tot)) || (rc = pool.alloc(&S.z, tot)) || (rc = pool.alloc(&S.p, tot)) ||
+        (nrhs <= 64 && (rc = pool.alloc(&S.p1, tot))) ||
+        (rc = pool.alloc(&S.q, tot)) ||
+        (rc = pool.alloc(&S.part, (int64_t)std::max<int64_t>(kGrid, Solver::spmm_blocks(S.n)) * nrhs)) ||
+        (rc = pool.alloc(&S.tmp, nrhs)) || (rc = pool.alloc(&S.S, nrhs)) || (rc = pool.alloc(&S.nactive, 3)))
+      return rc;
+    if (work) {
+      void* const b[9] = {S.r, S.z, S.p, S.p1, S.q, S.part, S.tmp, S.S, S.nactive};
+      for (int i = 0; i < 9; ++i) work->blk[i] = b[i];
+      work->n = S.n;
+      work->nrhs = nrhs;
+    }
+  }
   S.b = dB;
   S.x = dX;
   {

@@ -1165,6 +1165,31 @@ def test_pcg_graph_replay_matches_eager():
     assert rcb == rce and list(itb) == list(ite) and np.array_equal(Xb, Xe)
 
 
+def test_handle_pcg_keeps_blocks():
+    """The handle keeps its PCG blocks between solves of one size and replaces them for
+    another: solves with 6, 3, 6, 3 and 6 right-hand sides (different tolerances) each
+    match the stateless pcg_solve on the same M, and a repeated solve equals the
+    handle's first one bit for bit (nothing of an earlier solve carries over)."""
+    S = _spai()
+    A = W.lognormal3d(16, 41)
+    h = S.SPAI(A, "lomr", "global", 2.0, True, max_iter=12)
+    h.iterate(12)
+    M = h.get()
+    first = {}
+    for key in ((6, 1e-8, 3), (3, 1e-9, 4), (6, 1e-8, 3), (3, 1e-9, 4), (6, 1e-7, 5)):
+        nrhs, rtol, seed = key
+        B = W.rhs(A.shape[0], nrhs, seed)
+        X, it, _, rc = h.pcg(B, rtol=rtol)
+        Xs, its, _, rcs = S.pcg_solve(A, M, B, rtol=rtol)
+        assert rc == rcs == S.SPAI_OK and list(it) == list(its), key
+        assert np.max(np.abs(X - Xs)) <= 1e-12 * np.max(np.abs(Xs)), key
+        if key in first:
+            assert np.array_equal(X, first[key][0]) and list(it) == first[key][1], key
+        else:
+            first[key] = (X, list(it))
+    h.close()
+
+
 def test_pcg_stopped_chunk_tail():
     """Once every right-hand side has stopped, the products and the r update left in the
     last 8-iteration chunk return at once: with phase timing, q = A p did its work once per
