@@ -1035,8 +1035,10 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
           out = (T)(pi * r);
           acc_rz += (double)rt * (double)out;
         }
-        R.idx[ob + t] = u;
-        R.val[ob + t] = out;
+        // stored nontemporally: R is read again only in the next iteration, so it keeps
+        // the rows of A and the columns of M this kernel gathers in the caches
+        __builtin_nontemporal_store(u, &R.idx[ob + t]);
+        __builtin_nontemporal_store(out, &R.val[ob + t]);
         acc += (double)rt * (double)rt;
       }
     }
