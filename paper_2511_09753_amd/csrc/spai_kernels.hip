@@ -954,8 +954,8 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
       const int e = lane + k * SPAI_WAVE;
       pos[k] = e;
       const int64_t q = e < lm ? mb + e : 0;
-      row[k] = M.idx[q];
-      val[k] = M.val[q];
+      row[k] = __builtin_nontemporal_load(&M.idx[q]);   // read once here (see R below)
+      val[k] = __builtin_nontemporal_load(&M.val[q]);
     }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -1035,8 +1035,9 @@ __global__ __launch_bounds__(SPAI_WAVE) __attribute__((amdgpu_waves_per_eu(sizeo
           out = (T)(pi * r);
           acc_rz += (double)rt * (double)out;
         }
-        // stored nontemporally: R is read again only in the next iteration, so it keeps
-        // the rows of A and the columns of M this kernel gathers in the caches
+        // stored nontemporally: R is read again only in the next iteration, and the
+        // column's own entries of M are loaded so, which keeps the rows of A this kernel
+        // gathers in the caches
         __builtin_nontemporal_store(u, &R.idx[ob + t]);
         __builtin_nontemporal_store(out, &R.val[ob + t]);
         acc += (double)rt * (double)rt;
